@@ -1,0 +1,131 @@
+/*
+ * jk.h -- C ABI of the MI355X (gfx950) Cholesky-decomposed Coulomb/exchange
+ * engine for non-symmetric densities.
+ *
+ * The operation (the paper, Sec. 2.3 "The non-symmetric AO-Laplace J/K
+ * kernel", Eq. (4), in the Cholesky-decomposed representation
+ * (mn|ls) = sum_Q B^Q_mn B^Q_ls and the half-transform form K = B_V^T B_U
+ * stated in the same section): for densities D_k = C_Lk C_Rk^T, k < ndens,
+ *
+ *     gamma_kQ = <B^Q, D_k>               (Frobenius pairing)
+ *     J_k      = sum_Q gamma_kQ B^Q
+ *     K_k      = sum_Q B^Q D_k B^Q  = sum_Q (B^Q C_Lk) (B^Q C_Rk)^T
+ *
+ * and the reverse-mode derivative of L = sum_k <Jbar_k, J_k> + <Kbar_k, K_k>
+ * (Sec. 2.1, Eq. (1): the adjoint of J and K is J and K of the cotangent).
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers to caller-owned FP64 memory,
+ *     row-major and densely packed:
+ *        B          [naux][nao][nao]     every slab B^Q symmetric (precondition,
+ *                                        not checked; the kernels read B^Q as
+ *                                        its own transpose)
+ *        CL, CR     [ndens][nao][rank]
+ *        J, K       [ndens][nao][nao]    outputs, overwritten (never accumulated)
+ *        Jbar, Kbar [ndens][nao][nao]    cotangents W_k, V_k (need not be symmetric)
+ *        dB         [naux][nao][nao]     dL/dB, the literal-formula gradient
+ *                                        (see jk_vjp)
+ *        dCL, dCR   [ndens][nao][rank]
+ *   - ws/ws_bytes: a caller-provided DEVICE workspace of at least the size the
+ *     matching *_workspace_bytes query returns.  The library allocates no
+ *     device memory in these calls.  ws must be 256-byte aligned.
+ *   - stream: a hipStream_t passed as void* (NULL = the default stream).  All
+ *     work is enqueued on it; calls return without synchronising the host.
+ *   - Errors: arguments are validated before anything is enqueued; on any
+ *     error status nothing is written.  A failed launch returns JK_EHIP.
+ *     Faults of already-enqueued kernels surface at the caller's next
+ *     synchronisation.  No C++ exception crosses this interface.
+ *   - Buffers of one call must not overlap, except that inputs may alias
+ *     inputs.  Concurrent calls on different streams need separate workspaces.
+ *   - Results are deterministic: the same inputs and problem give bit-identical
+ *     outputs (no floating-point atomics; every sum has a fixed order).
+ */
+#ifndef JK_GFX950_H
+#define JK_GFX950_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    JK_OK = 0,
+    JK_EINVAL = 1,        /* bad size, null required pointer, misaligned ws  */
+    JK_EWORKSPACE = 2,    /* ws_bytes below the required size                */
+    JK_EUNSUPPORTED = 3,  /* valid but not implemented combination           */
+    JK_EHIP = 4           /* a HIP launch or runtime call failed             */
+} jk_status;
+
+typedef enum {
+    JK_FP64 = 0,   /* every product and sum in FP64                          */
+    JK_MIXED = 1   /* half-transforms and K products on BF16 matrix cores as
+                      exact fixed-point slice products (nslice 8-bit slices),
+                      FP64 for gamma, J, every cross-chunk sum and the final
+                      accumulation                                           */
+} jk_precision;
+
+enum { JK_WANT_J = 1, JK_WANT_K = 2 };
+
+typedef struct {
+    int64_t nao;       /* basis size, >= 1                                   */
+    int64_t naux;      /* number of Cholesky vectors Q, >= 1                 */
+    int64_t ndens;     /* number of densities k, >= 1                        */
+    int64_t rank;      /* columns of each CL_k / CR_k, 1 <= rank <= nao      */
+    int32_t precision; /* jk_precision                                       */
+    int32_t flags;     /* JK_WANT_J | JK_WANT_K (0 means both)               */
+    int32_t nslice;    /* JK_MIXED only: 8-bit slices per operand, 2..5;
+                          0 selects the default (4)                          */
+    int32_t reserved;  /* must be 0                                          */
+} jk_problem;
+
+/* Workspace bytes needed by jk_build and jk_vjp for problem *p (one size
+ * serves both).  Returns 0 if *p is invalid. */
+size_t jk_workspace_bytes(const jk_problem *p);
+
+/* Forward build (Sec. 2.3, Eq. (4)): J_k and K_k for every density k.
+ * Writes J if flags has JK_WANT_J (J may be NULL otherwise) and K if flags
+ * has JK_WANT_K (K may be NULL otherwise). */
+jk_status jk_build(const jk_problem *p, const double *B, const double *CL,
+                   const double *CR, double *J, double *K, void *ws,
+                   size_t ws_bytes, void *stream);
+
+/* Workspace bytes needed by jk_build_batched for the nprob problems p[0..]. */
+size_t jk_batched_workspace_bytes(int32_t nprob, const jk_problem *p);
+
+/* Many independent problems (geometries of uneven size, each with its own
+ * nao, naux, ndens and rank) in one call.  p, B, CL, CR, J, K are HOST arrays
+ * of length nprob; B[g], CL[g], ... are DEVICE pointers with the layouts
+ * above.  Every problem must share one precision and one flags value.  Each
+ * member's outputs are bit-identical to a jk_build call of that member alone
+ * with the same precision. */
+jk_status jk_build_batched(int32_t nprob, const jk_problem *p,
+                           const double *const *B, const double *const *CL,
+                           const double *const *CR, double *const *J,
+                           double *const *K, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* Reverse-mode derivative (Sec. 2.1, Eq. (1)) of
+ *     L = sum_k <Jbar_k, J_k> + <Kbar_k, K_k>
+ * with W_k = Jbar_k, V_k = Kbar_k (either may be NULL = zero cotangent):
+ *     omega_kQ = <W_k, B^Q>,  X^Q_k = B^Q CL_k,  Y^Q_k = B^Q CR_k
+ *     dCL_k = sum_Q B^Q (V_k Y^Q_k)   + omega_kQ Y^Q_k
+ *     dCR_k = sum_Q B^Q (V_k^T X^Q_k) + omega_kQ X^Q_k
+ *     dB^Q  = sum_k gamma_kQ W_k + omega_kQ D_k + V_k B^Q D_k^T + D_k^T B^Q V_k
+ * dB is the gradient of the literal formulas for a general B evaluated at the
+ * given symmetric B (its symmetric part is convention-free).  The
+ * half-transforms are recomputed, not stored.  dB, dCL, dCR may each be NULL
+ * (not computed).  Only JK_FP64 is supported (else JK_EUNSUPPORTED). */
+jk_status jk_vjp(const jk_problem *p, const double *B, const double *CL,
+                 const double *CR, const double *Jbar, const double *Kbar,
+                 double *dB, double *dCL, double *dCR, void *ws,
+                 size_t ws_bytes, void *stream);
+
+/* Static, NUL-terminated description of a status code. */
+const char *jk_status_str(jk_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JK_GFX950_H */

@@ -1,0 +1,69 @@
+"""ctypes loader of the gfx950 J/K library (``libjk_gfx950.so``).
+
+The library is the whole product path: if it is missing, every call raises.
+There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libjk_gfx950.so")
+
+JK_OK, JK_EINVAL, JK_EWORKSPACE, JK_EUNSUPPORTED, JK_EHIP = 0, 1, 2, 3, 4
+JK_FP64, JK_MIXED = 0, 1
+JK_WANT_J, JK_WANT_K = 1, 2
+
+# Every symbol include/jk.h declares.
+EXPORTS = ("jk_workspace_bytes", "jk_build", "jk_batched_workspace_bytes", "jk_build_batched",
+           "jk_vjp", "jk_status_str")
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("nao", ctypes.c_int64), ("naux", ctypes.c_int64), ("ndens", ctypes.c_int64),
+                ("rank", ctypes.c_int64), ("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("nslice", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class JKError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_str(status)} (status {status})")
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                               "(hipcc --offload-arch=gfx950); there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz = ctypes.c_void_p, ctypes.c_size_t
+        pp = ctypes.POINTER(Problem)
+        L.jk_workspace_bytes.restype = sz
+        L.jk_workspace_bytes.argtypes = [pp]
+        L.jk_build.restype = ctypes.c_int
+        L.jk_build.argtypes = [pp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.jk_batched_workspace_bytes.restype = sz
+        L.jk_batched_workspace_bytes.argtypes = [ctypes.c_int32, pp]
+        L.jk_build_batched.restype = ctypes.c_int
+        L.jk_build_batched.argtypes = [ctypes.c_int32, pp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.jk_vjp.restype = ctypes.c_int
+        L.jk_vjp.argtypes = [pp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.jk_status_str.restype = ctypes.c_char_p
+        L.jk_status_str.argtypes = [ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def status_str(s: int) -> str:
+    return lib().jk_status_str(int(s)).decode()
+
+
+def check(status: int, what: str) -> None:
+    if status != JK_OK:
+        raise JKError(status, what)

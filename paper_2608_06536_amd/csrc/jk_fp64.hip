@@ -1,0 +1,299 @@
+// jk_fp64.hip -- FP64 kernels of the Cholesky-decomposed J/K build.
+//
+// The build (Sec. 2.3, Eq. (4), half-transform form K = B_V^T B_U):
+//   pack          Cc[n][c]        = [C_L | C_R] re-laid as one nao x 2R matrix
+//   density       D_k             = C_Lk C_Rk^T
+//   project       part[p][Q][k]   = sum over a block of positions of B^Q . A_k
+//   reduce        g[k][Q]         = sum of the partials in fixed order
+//   coulomb       J_k             = sum_Q gamma_kQ B^Q
+//   half-transform X^Q, Y^Q       = B^Q [C_L | C_R]            (per Q-chunk)
+//   exchange      K_k            += sum_{Q in chunk} X^Q_k (Y^Q_k)^T
+//
+// Layouts of the chunk workspace: X_ws[k][m][ql*r + i] and Y_ws[k][n][ql*r + i]
+// for the ql-th slab of the chunk, so that each row of the exchange operands
+// is contiguous over the chunk's inner index (Q, i).
+#include "f64_core.hpp"
+#include "jk_kernels.hpp"
+
+namespace jk {
+
+// ------------------------------------------------------------------ pack
+__global__ void __launch_bounds__(256) k_pack_c(const double *__restrict__ CL,
+                                                const double *__restrict__ CR, double *__restrict__ Cc,
+                                                int nao, int nd, int r)
+{
+    const int R = nd * r, R2 = 2 * R;
+    const i64 total = (i64)nao * R2;
+    for (i64 e = (i64)blockIdx.x * 256 + threadIdx.x; e < total; e += (i64)gridDim.x * 256) {
+        int n = (int)(e / R2), c = (int)(e % R2);
+        const double *src = c < R ? CL : CR;
+        int cc = c < R ? c : c - R;
+        int k = cc / r, i = cc % r;
+        Cc[e] = src[((i64)k * nao + n) * r + i];
+    }
+}
+
+// ------------------------------------------------------------------ density
+// D_k[m][n] = sum_i CL[k][m][i] CR[k][n][i]; grid: (tiles of nao x nao) x nd.
+__global__ void __launch_bounds__(256) k_density(const double *__restrict__ CL,
+                                                 const double *__restrict__ CR, double *__restrict__ D,
+                                                 int nao, int r)
+{
+    typedef Tile<64, 64, 32, 32> TL;
+    __shared__ double lds[TL::LDS_DOUBLES];
+    const int nt = (nao + 63) / 64;
+    const int k = blockIdx.y;
+    const int mb = blockIdx.x / nt, nb = blockIdx.x % nt;
+    OpKC a{CL + (i64)k * nao * r, r, nao, r};
+    OpKC b{CR + (i64)k * nao * r, r, nao, r};
+    Acc<64, 64, 32, 32> acc;
+    acc.zero();
+    tile_gemm<64, 64, 32, 32>(a, b, mb * 64, nb * 64, r, lds, acc);
+    acc.reduce_blocks();
+    double *Dk = D + (i64)k * nao * nao;
+    tile_foreach(acc, mb * 64, nb * 64, [&](int m, int n, double v) {
+        if (m < nao && n < nao)
+            Dk[(i64)m * nao + n] = v;
+    });
+}
+
+// ------------------------------------------------------------------ project
+// part[pb][Q][kk] = sum_{p in block pb} B[Q][p] * A[k0 + kk][p], kk < 8.
+// A GEMM with M = naux, N = nd (in groups of 8), inner = nao^2 split into
+// blocks of plen positions.  grid: x = Q tiles of 128, y = density groups,
+// z = position blocks.
+__global__ void __launch_bounds__(256) k_project(const double *__restrict__ B,
+                                                 const double *__restrict__ A, double *__restrict__ part,
+                                                 int naux, int nd, i64 npos, int plen)
+{
+    typedef Tile<128, 8, 32, 8> TL;
+    __shared__ double lds[TL::LDS_DOUBLES];
+    const int qt = blockIdx.x, kg = blockIdx.y, pb = blockIdx.z;
+    const i64 p0 = (i64)pb * plen;
+    const int len = (int)((npos - p0) < plen ? (npos - p0) : plen);
+    const int ndg = (nd - kg * 8) < 8 ? (nd - kg * 8) : 8;
+    OpKC a{B + p0, npos, naux, len};
+    OpKC b{A + (i64)kg * 8 * npos + p0, npos, ndg, len};
+    Acc<128, 8, 32, 8> acc;
+    acc.zero();
+    tile_gemm<128, 8, 32, 8>(a, b, qt * 128, 0, len, lds, acc);
+    acc.reduce_blocks();
+    const int ndp = ((nd + 7) / 8) * 8;
+    double *out = part + (i64)pb * naux * ndp;
+    tile_foreach(acc, qt * 128, 0, [&](int q, int kk, double v) {
+        if (q < naux && kk < 8)
+            out[(i64)q * ndp + kg * 8 + kk] = v;
+    });
+}
+
+// g[k][Q] = sum_{pb} part[pb][Q][k] (fixed order).
+__global__ void __launch_bounds__(256) k_project_reduce(const double *__restrict__ part,
+                                                        double *__restrict__ g, int naux, int nd,
+                                                        int npb)
+{
+    const int ndp = ((nd + 7) / 8) * 8;
+    const i64 total = (i64)naux * nd;
+    for (i64 e = (i64)blockIdx.x * 256 + threadIdx.x; e < total; e += (i64)gridDim.x * 256) {
+        int k = (int)(e / naux), q = (int)(e % naux);
+        double s = 0.0;
+        for (int pb = 0; pb < npb; pb++)
+            s += part[((i64)pb * naux + q) * ndp + k];
+        g[(i64)k * naux + q] = s;
+    }
+}
+
+// ------------------------------------------------------------------ coulomb
+// J[k][p] = sum_Q g[k][Q] B[Q][p] for k in [k0, k0 + 8); one position per
+// thread, Q unrolled by 8 for loads in flight.  HBM-bound stream over B.
+__global__ void __launch_bounds__(256) k_coulomb(const double *__restrict__ B,
+                                                 const double *__restrict__ g, double *__restrict__ J,
+                                                 int naux, int nd, int k0, i64 npos)
+{
+    const i64 p = (i64)blockIdx.x * 256 + threadIdx.x;
+    const int nk = (nd - k0) < 8 ? (nd - k0) : 8;
+    double acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++)
+        acc[k] = 0.0;
+    const bool ok = p < npos;
+    const double *bp = B + (ok ? p : 0);
+    int q = 0;
+    for (; q + 8 <= naux; q += 8) {
+        double bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+            bv[u] = ok ? __builtin_nontemporal_load(bp + (i64)(q + u) * npos) : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+#pragma unroll
+            for (int k = 0; k < 8; k++)
+                if (k < nk)
+                    acc[k] = fma(g[(i64)(k0 + k) * naux + q + u], bv[u], acc[k]);
+    }
+    for (; q < naux; q++) {
+        double b = ok ? bp[(i64)q * npos] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (k < nk)
+                acc[k] = fma(g[(i64)(k0 + k) * naux + q], b, acc[k]);
+    }
+    if (ok) {
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (k < nk)
+                J[(i64)(k0 + k) * npos + p] = acc[k];
+    }
+}
+
+// ------------------------------------------------------------------ half-transform
+// For slab Q = q0 + ql (ql < nq): XY[m][c] = sum_n B^Q[m][n] Cc[n][c], written
+// as X_ws[k][m][ql*r + i] (c = k*r + i < R) or Y_ws[k][m][ql*r + i] (c - R).
+// grid.x = nq * nmt * nct (XCD-swizzled), tile 64 x 64.
+__global__ void __launch_bounds__(256) k_half_transform(const double *__restrict__ B,
+                                                        const double *__restrict__ Cc,
+                                                        double *__restrict__ Xw, double *__restrict__ Yw,
+                                                        int nao, int nd, int r, int q0, int nq,
+                                                        int ldw)
+{
+    typedef Tile<64, 64, 32, 32> TL;
+    __shared__ double lds[TL::LDS_DOUBLES];
+    const int R = nd * r, R2 = 2 * R;
+    const int nmt = (nao + 63) / 64, nct = (R2 + 63) / 64;
+    const int ntile = nq * nmt * nct;
+    const int t = xcd_swizzle(blockIdx.x, ntile);
+    const int ql = t / (nmt * nct), rem = t % (nmt * nct);
+    const int mb = rem / nct, cb = rem % nct;
+    const i64 n2 = (i64)nao * nao;
+    OpKC a{B + (i64)(q0 + ql) * n2, nao, nao, nao};
+    OpIC b{Cc, R2, R2, nao};
+    Acc<64, 64, 32, 32> acc;
+    acc.zero();
+    tile_gemm<64, 64, 32, 32>(a, b, mb * 64, cb * 64, nao, lds, acc);
+    acc.reduce_blocks();
+    tile_foreach(acc, mb * 64, cb * 64, [&](int m, int c, double v) {
+        if (m < nao && c < R2) {
+            double *dst = c < R ? Xw : Yw;
+            int cc = c < R ? c : c - R;
+            int k = cc / r, i = cc % r;
+            dst[((i64)k * nao + m) * ldw + (i64)ql * r + i] = v;
+        }
+    });
+}
+
+// ------------------------------------------------------------------ exchange
+// K[k][m][n] (+)= sum_{j < nj} X_ws[k][m][j] Y_ws[k][n][j].
+// grid.x = nd * nt * nt (XCD-swizzled), tile 64 x 64.
+__global__ void __launch_bounds__(256) k_exchange(const double *__restrict__ Xw,
+                                                  const double *__restrict__ Yw, double *__restrict__ K,
+                                                  int nao, int nd, int nj, int ldw, int accumulate)
+{
+    typedef Tile<64, 64, 32, 32> TL;
+    __shared__ double lds[TL::LDS_DOUBLES];
+    const int nt = (nao + 63) / 64;
+    const int ntile = nd * nt * nt;
+    const int t = xcd_swizzle(blockIdx.x, ntile);
+    const int k = t / (nt * nt), rem = t % (nt * nt);
+    const int mb = rem / nt, nb = rem % nt;
+    OpKC a{Xw + (i64)k * nao * ldw, ldw, nao, nj};
+    OpKC b{Yw + (i64)k * nao * ldw, ldw, nao, nj};
+    Acc<64, 64, 32, 32> acc;
+    acc.zero();
+    tile_gemm<64, 64, 32, 32>(a, b, mb * 64, nb * 64, nj, lds, acc);
+    acc.reduce_blocks();
+    double *Kk = K + (i64)k * nao * nao;
+    tile_foreach(acc, mb * 64, nb * 64, [&](int m, int n, double v) {
+        if (m < nao && n < nao) {
+            i64 o = (i64)m * nao + n;
+            Kk[o] = accumulate ? Kk[o] + v : v;
+        }
+    });
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline int cdiv(i64 a, i64 b) { return (int)((a + b - 1) / b); }
+
+hipError_t launch_pack_c(const double *CL, const double *CR, double *Cc, int nao, int nd, int r,
+                         hipStream_t s)
+{
+    i64 total = (i64)nao * 2 * nd * r;
+    int grid = cdiv(total, 256);
+    if (grid > 65535)
+        grid = 65535;
+    hipLaunchKernelGGL(k_pack_c, dim3(grid), dim3(256), 0, s, CL, CR, Cc, nao, nd, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_density(const double *CL, const double *CR, double *D, int nao, int nd, int r,
+                          hipStream_t s)
+{
+    int nt = cdiv(nao, 64);
+    hipLaunchKernelGGL(k_density, dim3(nt * nt, nd), dim3(256), 0, s, CL, CR, D, nao, r);
+    return hipGetLastError();
+}
+
+int project_nblocks(i64 npos, int naux, int nd, int *plen)
+{
+    // Aim for >= 2048 workgroups in total; position blocks are multiples of 16.
+    int nqt = cdiv(naux, 128), nkg = cdiv(nd, 8);
+    i64 want = 2048 / (nqt * nkg);
+    if (want < 1)
+        want = 1;
+    i64 len = (npos + want - 1) / want;
+    len = ((len + 15) / 16) * 16;
+    if (len < 256)
+        len = 256;
+    *plen = (int)len;
+    return cdiv(npos, len);
+}
+
+hipError_t launch_project(const double *B, const double *A, double *part, double *g, int naux,
+                          int nd, i64 npos, hipStream_t s)
+{
+    int plen;
+    int npb = project_nblocks(npos, naux, nd, &plen);
+    dim3 grid(cdiv(naux, 128), cdiv(nd, 8), npb);
+    hipLaunchKernelGGL(k_project, grid, dim3(256), 0, s, B, A, part, naux, nd, npos, plen);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    i64 total = (i64)naux * nd;
+    int rg = cdiv(total, 256);
+    if (rg > 65535)
+        rg = 65535;
+    hipLaunchKernelGGL(k_project_reduce, dim3(rg), dim3(256), 0, s, part, g, naux, nd, npb);
+    return hipGetLastError();
+}
+
+hipError_t launch_coulomb(const double *B, const double *g, double *J, int naux, int nd, i64 npos,
+                          hipStream_t s)
+{
+    for (int k0 = 0; k0 < nd; k0 += 8) {
+        hipLaunchKernelGGL(k_coulomb, dim3(cdiv(npos, 256)), dim3(256), 0, s, B, g, J, naux, nd, k0,
+                           npos);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_half_transform(const double *B, const double *Cc, double *Xw, double *Yw,
+                                 int nao, int nd, int r, int q0, int nq, int ldw, hipStream_t s)
+{
+    int nmt = cdiv(nao, 64), nct = cdiv(2 * (i64)nd * r, 64);
+    hipLaunchKernelGGL(k_half_transform, dim3(nq * nmt * nct), dim3(256), 0, s, B, Cc, Xw, Yw, nao,
+                       nd, r, q0, nq, ldw);
+    return hipGetLastError();
+}
+
+hipError_t launch_exchange(const double *Xw, const double *Yw, double *K, int nao, int nd, int nj,
+                           int ldw, int accumulate, hipStream_t s)
+{
+    int nt = cdiv(nao, 64);
+    hipLaunchKernelGGL(k_exchange, dim3(nd * nt * nt), dim3(256), 0, s, Xw, Yw, K, nao, nd, nj, ldw,
+                       accumulate);
+    return hipGetLastError();
+}
+
+} // namespace jk

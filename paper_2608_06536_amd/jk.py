@@ -1,0 +1,181 @@
+"""Python binding of the C ABI in include/jk.h (argument marshalling only).
+
+PyTorch supplies device memory and the current HIP stream; every step of the
+J/K path runs in the library's HIP kernels.
+
+    J, K = jk_build(B, CL, CR)                  # Sec. 2.3, Eq. (4)
+    dB, dCL, dCR = jk_vjp(B, CL, CR, Jbar, Kbar) # Sec. 2.1, Eq. (1)
+    J, K = jk(B, CL, CR)                        # differentiable (autograd)
+
+Shapes: B [naux][nao][nao] (each slab symmetric), CL, CR [nd][nao][r],
+J, K, Jbar, Kbar [nd][nao][nao]; all float64, contiguous, on the GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+
+_PREC = {"fp64": _lib.JK_FP64, "mixed": _lib.JK_MIXED}
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_tensor(t, name, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (the library has no CPU path)")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def make_problem(nao, naux, nd, r, precision="fp64", want_j=True, want_k=True, nslice=0):
+    flags = (_lib.JK_WANT_J if want_j else 0) | (_lib.JK_WANT_K if want_k else 0)
+    if flags == 0:
+        raise ValueError("nothing requested")
+    return _lib.Problem(int(nao), int(naux), int(nd), int(r), int(_PREC[precision]), flags,
+                        int(nslice), 0)
+
+
+def workspace_bytes(prob) -> int:
+    return int(_lib.lib().jk_workspace_bytes(ctypes.byref(prob)))
+
+
+def _workspace(nbytes, device):
+    # 256-byte alignment: the caching allocator hands out 512-byte aligned blocks.
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _shapes(B, CL, CR):
+    _check_tensor(B, "B")
+    _check_tensor(CL, "CL")
+    _check_tensor(CR, "CR")
+    if B.dim() != 3 or B.shape[1] != B.shape[2]:
+        raise ValueError("B must be [naux][nao][nao]")
+    naux, nao = B.shape[0], B.shape[1]
+    if CL.dim() != 3 or CL.shape[1] != nao:
+        raise ValueError("CL must be [nd][nao][r]")
+    if tuple(CR.shape) != tuple(CL.shape):
+        raise ValueError("CR must have the shape of CL")
+    return nao, naux, CL.shape[0], CL.shape[2]
+
+
+def jk_build(B, CL, CR, precision="fp64", want_j=True, want_k=True, nslice=0, out=None, ws=None):
+    """J_k = sum_Q <B^Q, D_k> B^Q and K_k = sum_Q B^Q D_k B^Q for D_k = CL_k CR_k^T."""
+    nao, naux, nd, r = _shapes(B, CL, CR)
+    prob = make_problem(nao, naux, nd, r, precision, want_j, want_k, nslice)
+    if out is None:
+        J = torch.empty((nd, nao, nao), dtype=torch.float64, device=B.device) if want_j else None
+        K = torch.empty((nd, nao, nao), dtype=torch.float64, device=B.device) if want_k else None
+    else:
+        J, K = out
+    for t, name in ((J, "J"), (K, "K")):
+        if t is not None:
+            _check_tensor(t, name, (nd, nao, nao))
+    nbytes = workspace_bytes(prob)
+    if nbytes == 0:
+        raise _lib.JKError(_lib.JK_EINVAL, "jk_build")
+    if ws is None:
+        ws = _workspace(nbytes, B.device)
+    st = _lib.lib().jk_build(ctypes.byref(prob), _ptr(B), _ptr(CL), _ptr(CR), _ptr(J), _ptr(K),
+                             _ptr(ws), ws.numel(), _stream())
+    _lib.check(st, "jk_build")
+    return J, K
+
+
+def batched_workspace_bytes(probs) -> int:
+    arr = (_lib.Problem * len(probs))(*probs)
+    return int(_lib.lib().jk_batched_workspace_bytes(len(probs), arr))
+
+
+def jk_build_batched(items, precision="fp64", want_j=True, want_k=True, nslice=0, outs=None,
+                     ws=None):
+    """items: list of (B, CL, CR) of uneven sizes; returns a list of (J, K)."""
+    n = len(items)
+    probs, res = [], []
+    for g, (B, CL, CR) in enumerate(items):
+        nao, naux, nd, r = _shapes(B, CL, CR)
+        probs.append(make_problem(nao, naux, nd, r, precision, want_j, want_k, nslice))
+        if outs is None:
+            J = torch.empty((nd, nao, nao), dtype=torch.float64, device=B.device) if want_j else None
+            K = torch.empty((nd, nao, nao), dtype=torch.float64, device=B.device) if want_k else None
+        else:
+            J, K = outs[g]
+        res.append((J, K))
+    arr = (_lib.Problem * n)(*probs)
+    VP = ctypes.c_void_p * n
+    pb = VP(*[B.data_ptr() for B, _, _ in items])
+    pl = VP(*[CL.data_ptr() for _, CL, _ in items])
+    pr = VP(*[CR.data_ptr() for _, _, CR in items])
+    pj = VP(*[(J.data_ptr() if J is not None else 0) for J, _ in res])
+    pk = VP(*[(K.data_ptr() if K is not None else 0) for _, K in res])
+    nbytes = batched_workspace_bytes(probs)
+    if nbytes == 0:
+        raise _lib.JKError(_lib.JK_EINVAL, "jk_build_batched")
+    if ws is None:
+        ws = _workspace(nbytes, items[0][0].device)
+    st = _lib.lib().jk_build_batched(n, arr, pb, pl, pr, pj, pk, _ptr(ws), ws.numel(), _stream())
+    _lib.check(st, "jk_build_batched")
+    return res
+
+
+def jk_vjp(B, CL, CR, Jbar=None, Kbar=None, want_dB=True, want_dC=True, out=None, ws=None):
+    """Adjoints (dB, dCL, dCR) of L = sum_k <Jbar_k, J_k> + <Kbar_k, K_k>."""
+    nao, naux, nd, r = _shapes(B, CL, CR)
+    for t, name in ((Jbar, "Jbar"), (Kbar, "Kbar")):
+        if t is not None:
+            _check_tensor(t, name, (nd, nao, nao))
+    prob = make_problem(nao, naux, nd, r, "fp64")
+    if out is None:
+        dB = torch.empty_like(B) if want_dB else None
+        dCL = torch.empty_like(CL) if want_dC else None
+        dCR = torch.empty_like(CR) if want_dC else None
+    else:
+        dB, dCL, dCR = out
+    nbytes = workspace_bytes(prob)
+    if nbytes == 0:
+        raise _lib.JKError(_lib.JK_EINVAL, "jk_vjp")
+    if ws is None:
+        ws = _workspace(nbytes, B.device)
+    st = _lib.lib().jk_vjp(ctypes.byref(prob), _ptr(B), _ptr(CL), _ptr(CR), _ptr(Jbar), _ptr(Kbar),
+                           _ptr(dB), _ptr(dCL), _ptr(dCR), _ptr(ws), ws.numel(), _stream())
+    _lib.check(st, "jk_vjp")
+    return dB, dCL, dCR
+
+
+class JKFunction(torch.autograd.Function):
+    """(B, CL, CR) -> (J, K) with the reverse pass through jk_vjp."""
+
+    @staticmethod
+    def forward(ctx, B, CL, CR, precision="fp64"):
+        J, K = jk_build(B.contiguous(), CL.contiguous(), CR.contiguous(), precision)
+        ctx.save_for_backward(B, CL, CR)
+        return J, K
+
+    @staticmethod
+    def backward(ctx, Jbar, Kbar):
+        B, CL, CR = ctx.saved_tensors
+        Jbar = None if Jbar is None else Jbar.contiguous()
+        Kbar = None if Kbar is None else Kbar.contiguous()
+        need_b = ctx.needs_input_grad[0]
+        need_c = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
+        dB, dCL, dCR = jk_vjp(B.contiguous(), CL.contiguous(), CR.contiguous(), Jbar, Kbar,
+                              want_dB=need_b, want_dC=need_c)
+        return dB, dCL, dCR, None
+
+
+def jk(B, CL, CR, precision="fp64"):
+    return JKFunction.apply(B, CL, CR, precision)

@@ -1,0 +1,97 @@
+"""The C ABI on the CPU: the library loads, exports every symbol the header
+declares, and rejects bad arguments before any launch (no GPU needed: every
+call here fails validation, so nothing is enqueued)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2608_06536_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "jk.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:[a-z_]+\s+\*?)+(jk_[a-z_]+)\s*\(", txt, re.M)))
+
+
+def test_header_symbols_exported():
+    L = _lib.lib()
+    names = _declared()
+    assert set(names) == set(_lib.EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _prob(**kw):
+    d = dict(nao=10, naux=4, ndens=2, rank=3, precision=0, flags=3, nslice=0, reserved=0)
+    d.update(kw)
+    return _lib.Problem(*[d[k] for k, _ in _lib.Problem._fields_])
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nao=0), dict(naux=0), dict(ndens=0), dict(rank=0), dict(rank=11), dict(precision=7),
+    dict(flags=4), dict(flags=-1), dict(reserved=1), dict(precision=1, nslice=1),
+    dict(precision=1, nslice=9), dict(nao=1 << 20),
+])
+def test_invalid_problem(bad):
+    L = _lib.lib()
+    p = _prob(**bad)
+    assert L.jk_workspace_bytes(ctypes.byref(p)) == 0
+    st = L.jk_build(ctypes.byref(p), 8, 8, 8, 8, 8, 256, 1 << 40, None)
+    assert st == _lib.JK_EINVAL
+    st = L.jk_vjp(ctypes.byref(p), 8, 8, 8, 8, 8, 8, 8, 8, 256, 1 << 40, None)
+    assert st == _lib.JK_EINVAL
+
+
+def test_workspace_query_and_errors():
+    L = _lib.lib()
+    p = _prob()
+    need = L.jk_workspace_bytes(ctypes.byref(p))
+    assert need > 0 and need % 256 == 0
+    # null required pointers
+    assert L.jk_build(ctypes.byref(p), None, 8, 8, 8, 8, 256, need, None) == _lib.JK_EINVAL
+    assert L.jk_build(ctypes.byref(p), 8, 8, 8, None, 8, 256, need, None) == _lib.JK_EINVAL
+    # K not requested: K may be NULL, but ws too small still reported
+    pj = _prob(flags=1)
+    assert L.jk_build(ctypes.byref(pj), 8, 8, 8, 8, None, 256, 16, None) == _lib.JK_EWORKSPACE
+    # misaligned workspace
+    assert L.jk_build(ctypes.byref(p), 8, 8, 8, 8, 8, 264, need, None) == _lib.JK_EINVAL
+    # too small workspace
+    assert L.jk_build(ctypes.byref(p), 8, 8, 8, 8, 8, 256, need - 1, None) == _lib.JK_EWORKSPACE
+    assert L.jk_vjp(ctypes.byref(p), 8, 8, 8, 8, 8, 8, 8, 8, 256, need - 1, None) == _lib.JK_EWORKSPACE
+    # null problem
+    assert L.jk_workspace_bytes(None) == 0
+    assert L.jk_build(None, 8, 8, 8, 8, 8, 256, need, None) == _lib.JK_EINVAL
+
+
+def test_batched_validation():
+    L = _lib.lib()
+    arr = (_lib.Problem * 2)(_prob(), _prob(nao=20))
+    need = L.jk_batched_workspace_bytes(2, arr)
+    assert need >= L.jk_workspace_bytes(ctypes.byref(arr[1])) > 0
+    VP = ctypes.c_void_p * 2
+    ptrs = VP(8, 8)
+    assert L.jk_build_batched(0, arr, ptrs, ptrs, ptrs, ptrs, ptrs, 256, need, None) == _lib.JK_EINVAL
+    mixed = (_lib.Problem * 2)(_prob(), _prob(precision=1))
+    assert L.jk_build_batched(2, mixed, ptrs, ptrs, ptrs, ptrs, ptrs, 256, need, None) == _lib.JK_EINVAL
+    nulls = VP(8, None)
+    assert L.jk_build_batched(2, arr, ptrs, nulls, ptrs, ptrs, ptrs, 256, need, None) == _lib.JK_EINVAL
+    assert L.jk_build_batched(2, arr, ptrs, ptrs, ptrs, ptrs, ptrs, 256, need - 1, None) == _lib.JK_EWORKSPACE
+
+
+def test_status_strings():
+    for s in range(5):
+        assert len(_lib.status_str(s)) > 0
+    assert "unknown" in _lib.status_str(99)
+
+
+def test_binding_refuses_cpu_tensors():
+    torch = pytest.importorskip("torch")
+    from paper_2608_06536_amd import jk
+    B = torch.zeros((2, 4, 4), dtype=torch.float64)
+    C = torch.zeros((1, 4, 2), dtype=torch.float64)
+    with pytest.raises(ValueError):
+        jk.jk_build(B, C, C)

@@ -115,8 +115,9 @@ jk_status jk_build_batched(int32_t nprob, const jk_problem *p,
  *     dB^Q  = sum_k gamma_kQ W_k + omega_kQ D_k + V_k B^Q D_k^T + D_k^T B^Q V_k
  * dB is the gradient of the literal formulas for a general B evaluated at the
  * given symmetric B (its symmetric part is convention-free).  The
- * half-transforms are recomputed, not stored.  dB, dCL, dCR may each be NULL
- * (not computed).  Only JK_FP64 is supported (else JK_EUNSUPPORTED). */
+ * half-transforms are recomputed, not stored.  dB may be NULL (not computed);
+ * dCL and dCR are both NULL (not computed) or both non-NULL (else
+ * JK_EINVAL).  Only JK_FP64 is supported (else JK_EUNSUPPORTED). */
 jk_status jk_vjp(const jk_problem *p, const double *B, const double *CL,
                  const double *CR, const double *Jbar, const double *Kbar,
                  double *dB, double *dCL, double *dCR, void *ws,

@@ -2,24 +2,27 @@
 //
 // Every dense contraction of the Cholesky J/K path (half-transforms, exchange
 // products, projections, the derivative products) is a sum of products
-// C[i][j] += sum_k A[i][k] B[k][j] over one tile.  This header provides the
+// C[i][j] += sum_k A[i][k] B[k][j] over one output tile.  This header is the
 // one tile engine they share.
 //
-// Matrix-core instruction: V_MFMA_F64_4X4X4_4B (four independent 4x4x4 FP64
-// products per wave).  Measured on MI355X it sustains ~95% of the FP64 peak,
-// well above the 16x16x4 FP64 form.  Lane mapping, measured on the device:
+// Matrix-core instruction: V_MFMA_F64_4X4X4_4B, four independent 4x4x4 FP64
+// products per wave.  Measured on MI355X it sustains ~95% of the FP64 peak,
+// far above the 16x16x4 FP64 form.  Lane mapping (measured on the device):
 // for lane l, block b = (l >> 2) & 3, x = l & 3, h = l >> 4,
 //     A_b[x][h] = a(l),   B_b[h][x] = b(l),   D_b[h][x] = d(l).
-// The engine uses the four blocks as a split of a 16-long inner step:
-// block b covers inner indices 4b .. 4b+3, so one instruction adds a 4x4
-// output tile over 16 inner indices, kept as four partial tiles (one per
-// block) that are summed once, at the end, by two lane exchanges.
+// The engine gives the four blocks four different 4-row groups of A and the
+// SAME 4x4 piece of B, so one instruction is a 16 x 4 x 4 product:
+//   A fragment (16 rows x 4 inner):  lane l holds A[row l & 15][k l >> 4]
+//   B fragment (4 inner x 4 cols):   lane l holds B[k l >> 4][col l & 3]
+//                                    (16 values, each read by 4 lanes)
+//   output (16 x 4):                 lane l holds C[4*((l >> 2) & 3) + (l >> 4)][l & 3]
+// Accumulators therefore hold distinct outputs (no cross-lane reduction) and
+// a wave tile of WM x WN keeps (WM/16)*(WN/4) doubles per lane.
 //
-// Fragment of an operand tile of 4 rows (A) or 4 columns (B) by 16 inner
-// indices: lane l holds element (x = l & 3, k = 4*((l >> 2) & 3) + (l >> 4)).
-// Inverse: element (x, k) sits in lane 16*(k & 3) + 4*(k >> 2) + x.
-// LDS holds operand tiles in this fragment order, 64 doubles per fragment, so
-// every fragment read is one conflict-free 8-byte LDS read per lane.
+// LDS holds operand tiles in fragment order: A as [row group of 16][inner
+// step of 4][64], B as [col group of 4][inner step of 4][16]; every A
+// fragment read is a conflict-free 8-byte read per lane, every B fragment
+// read a broadcast.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -33,89 +36,122 @@ __device__ __forceinline__ double mfma4(double a, double b, double c)
     return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ int frag_slot(int x, int k)
-{
-    return 16 * (k & 3) + 4 * (k >> 2) + x;
-}
-
 // ---------------------------------------------------------------- operands
-// An operand accessor returns element (i, k) -- i the row of A or the column
-// of B, k the inner index -- as an FP64 value, 0 outside the valid range.
+// An operand describes element (i, k) -- i the row of A or the column of B,
+// k the inner index -- in two phases so that global loads stay in flight
+// while the matrix cores work:
+//   fetch(i, k, raw)  issues the loads of the element into raw[0..NRAW) and
+//                     nothing else (addresses are clamped into range, so no
+//                     branch and no wait);
+//   finish(i, k, raw) combines the raw values and returns the FP64 element,
+//                     0 outside the valid range.
 // kContig tells the loader which index is contiguous in memory so that it
-// assigns threads for coalesced reads.
+// assigns threads for coalesced reads.  Valid ranges need ni, nk >= 1.
 
 // element (i, k) at p[i * ld + k]
 struct OpKC {
     static constexpr bool kContig = true;
+    static constexpr int NRAW = 1;
     const double *p;
     i64 ld;
     int ni, nk;
-    __device__ double operator()(int i, int k) const
+    __device__ __forceinline__ void fetch(int i, int k, double *raw) const
     {
-        return (i < ni && k < nk) ? p[(i64)i * ld + k] : 0.0;
+        const int ic = i < ni ? i : ni - 1, kc = k < nk ? k : nk - 1;
+        raw[0] = p[(i64)ic * ld + kc];
+    }
+    __device__ __forceinline__ double finish(int i, int k, const double *raw) const
+    {
+        return (i < ni && k < nk) ? raw[0] : 0.0;
     }
 };
 
 // element (i, k) at p[k * ld + i]
 struct OpIC {
     static constexpr bool kContig = false;
+    static constexpr int NRAW = 1;
     const double *p;
     i64 ld;
     int ni, nk;
-    __device__ double operator()(int i, int k) const
+    __device__ __forceinline__ void fetch(int i, int k, double *raw) const
     {
-        return (i < ni && k < nk) ? p[(i64)k * ld + i] : 0.0;
+        const int ic = i < ni ? i : ni - 1, kc = k < nk ? k : nk - 1;
+        raw[0] = p[(i64)kc * ld + ic];
+    }
+    __device__ __forceinline__ double finish(int i, int k, const double *raw) const
+    {
+        return (i < ni && k < nk) ? raw[0] : 0.0;
     }
 };
 
-// ---------------------------------------------------------------- loader
-// Moves a T x 16 operand tile (T rows/cols, 16 inner indices starting at k0,
-// i starting at i0) from global memory into registers, then into LDS in
-// fragment order.  Each thread owns groups of 4 consecutive elements along
-// the contiguous index.
-template <int T, int NTHR, class Op>
-struct TileLoader {
-    static constexpr int NGRP = 4 * T;                       // groups of 4
-    static constexpr int NSTEP = (NGRP + NTHR - 1) / NTHR;
-    double v[NSTEP][4];
+// LDS slot of A element (row r, inner k) in a tile with NSUB inner steps.
+template <int NSUB>
+__device__ __forceinline__ int a_slot(int r, int k)
+{
+    return ((r >> 4) * NSUB + (k >> 2)) * 64 + 16 * (k & 3) + (r & 15);
+}
+// LDS slot of B element (col c, inner k).
+template <int NSUB>
+__device__ __forceinline__ int b_slot(int c, int k)
+{
+    return ((c >> 2) * NSUB + (k >> 2)) * 16 + 4 * (k & 3) + (c & 3);
+}
 
-    __device__ __forceinline__ void load(const Op &op, int i0, int k0, int tid)
+// ---------------------------------------------------------------- loader
+// Moves a T x BK operand tile (T rows/cols from i0, BK inner indices from k0)
+// from global memory into registers (load: fetch only), then into LDS
+// (store: finish, then write).  Each thread owns groups of 4 consecutive
+// elements along the contiguous index.
+template <int T, int BK, int NTHR, bool IS_A, class Op>
+struct TileLoader {
+    static constexpr int NGRP = T * BK / 4;
+    static constexpr int NSTEP = (NGRP + NTHR - 1) / NTHR;
+    static constexpr int NSUB = BK / 4;
+    double raw[NSTEP][4][Op::NRAW];
+    int i0, k0;
+
+    __device__ __forceinline__ void coords(int g, int e, int &i, int &k) const
     {
+        if (Op::kContig) {
+            i = i0 + g / (BK / 4);
+            k = k0 + (g % (BK / 4)) * 4 + e;
+        } else {
+            k = k0 + g / (T / 4);
+            i = i0 + (g % (T / 4)) * 4 + e;
+        }
+    }
+
+    __device__ __forceinline__ void load(const Op &op, int i0_, int k0_, int tid)
+    {
+        i0 = i0_;
+        k0 = k0_;
 #pragma unroll
         for (int s = 0; s < NSTEP; s++) {
             int g = tid + s * NTHR;
             if (NGRP % NTHR == 0 || g < NGRP) {
-                if (Op::kContig) {
-                    int i = g >> 2, kq = (g & 3) * 4;
 #pragma unroll
-                    for (int e = 0; e < 4; e++)
-                        v[s][e] = op(i0 + i, k0 + kq + e);
-                } else {
-                    int k = g / (T / 4), iq = (g % (T / 4)) * 4;
-#pragma unroll
-                    for (int e = 0; e < 4; e++)
-                        v[s][e] = op(i0 + iq + e, k0 + k);
+                for (int e = 0; e < 4; e++) {
+                    int i, k;
+                    coords(g, e, i, k);
+                    op.fetch(i, k, raw[s][e]);
                 }
             }
         }
     }
 
-    __device__ __forceinline__ void store(double *lds, int tid) const
+    __device__ __forceinline__ void store(const Op &op, double *lds, int tid) const
     {
 #pragma unroll
         for (int s = 0; s < NSTEP; s++) {
             int g = tid + s * NTHR;
             if (NGRP % NTHR == 0 || g < NGRP) {
-                if (Op::kContig) {
-                    int i = g >> 2, kq = (g & 3) * 4;
 #pragma unroll
-                    for (int e = 0; e < 4; e++)
-                        lds[(i >> 2) * 64 + frag_slot(i & 3, kq + e)] = v[s][e];
-                } else {
-                    int k = g / (T / 4), iq = (g % (T / 4)) * 4;
-#pragma unroll
-                    for (int e = 0; e < 4; e++)
-                        lds[(iq >> 2) * 64 + frag_slot(e, k)] = v[s][e];
+                for (int e = 0; e < 4; e++) {
+                    int i, k;
+                    coords(g, e, i, k);
+                    const double v = op.finish(i, k, raw[s][e]);
+                    const int li = i - i0, lk = k - k0;
+                    lds[IS_A ? a_slot<NSUB>(li, lk) : b_slot<NSUB>(li, lk)] = v;
                 }
             }
         }
@@ -123,133 +159,117 @@ struct TileLoader {
 };
 
 // ---------------------------------------------------------------- tile GEMM
-// One workgroup computes a BM x BN output tile; waves are laid out
-// (BM/WM) x (BN/WN), each wave owning a WM x WN sub-tile held as
-// (WM/4) x (WN/4) accumulators (one double per lane each, four partial tiles
-// per accumulator).  LDS: 2 * (BM + BN) * 16 doubles.
-template <int BM, int BN, int WM, int WN>
+// One workgroup computes a BM x BN output tile with inner stages of BK;
+// waves are laid out (BM/WM) x (BN/WN), each owning a WM x WN sub-tile.
+template <int BM, int BN, int WM, int WN, int BK>
 struct Tile {
     static constexpr int WROWS = BM / WM, WCOLS = BN / WN;
     static constexpr int NWAVE = WROWS * WCOLS;
     static constexpr int NTHR = NWAVE * 64;
-    static constexpr int MA = WM / 4, NB = WN / 4;
-    static constexpr int LDS_DOUBLES = 2 * (BM + BN) * 16;
-    static_assert(BM % WM == 0 && BN % WN == 0 && WM % 4 == 0 && WN % 4 == 0, "tile");
+    static constexpr int MA = WM / 16, NB = WN / 4, NSUB = BK / 4;
+    static constexpr int A_DOUBLES = BM * BK, B_DOUBLES = BN * BK;
+    static constexpr int LDS_DOUBLES = 2 * (A_DOUBLES + B_DOUBLES);
+    static_assert(BM % WM == 0 && BN % WN == 0 && WM % 16 == 0 && WN % 4 == 0, "tile");
+    static_assert(BK % 4 == 0 && BM % 16 == 0 && BN % 4 == 0, "tile");
 };
 
-template <int BM, int BN, int WM, int WN>
+template <class TL>
 struct Acc {
-    double c[WM / 4][WN / 4];
+    double c[TL::MA][TL::NB];
     __device__ __forceinline__ void zero()
     {
-#pragma unroll
-        for (int i = 0; i < WM / 4; i++)
-#pragma unroll
-            for (int j = 0; j < WN / 4; j++)
-                c[i][j] = 0.0;
-    }
-    // Sum the four per-block partial tiles; afterwards every lane of a block
-    // group holds the full value of its element.
-    __device__ __forceinline__ void reduce_blocks()
-    {
-#pragma unroll
-        for (int i = 0; i < WM / 4; i++)
-#pragma unroll
-            for (int j = 0; j < WN / 4; j++) {
-                double t = c[i][j];
-                t += __shfl_xor(t, 4);
-                t += __shfl_xor(t, 8);
-                c[i][j] = t;
-            }
-    }
-};
-
-// Accumulate sum over k in [0, kdim) of A(m0 + i, k) * B(n0 + j, k) into acc.
-// lds must hold Tile::LDS_DOUBLES doubles.  All threads of the workgroup
-// must call this.
-template <int BM, int BN, int WM, int WN, class OA, class OB>
-__device__ __forceinline__ void tile_gemm(const OA &A, const OB &B, int m0, int n0, int kdim,
-                                          double *lds, Acc<BM, BN, WM, WN> &acc)
-{
-    typedef Tile<BM, BN, WM, WN> TL;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
-    double *ldsA[2] = {lds, lds + (BM + BN) * 16};
-    double *ldsB[2] = {lds + BM * 16, lds + (BM + BN) * 16 + BM * 16};
-
-    TileLoader<BM, TL::NTHR, OA> la;
-    TileLoader<BN, TL::NTHR, OB> lb;
-    const int nk = (kdim + 15) / 16;
-    if (nk == 0)
-        return;
-    la.load(A, m0, 0, tid);
-    lb.load(B, n0, 0, tid);
-    la.store(ldsA[0], tid);
-    lb.store(ldsB[0], tid);
-    __syncthreads();
-    for (int kt = 0; kt < nk; kt++) {
-        const int cur = kt & 1;
-        const bool more = (kt + 1) < nk;
-        if (more) {
-            la.load(A, m0, (kt + 1) * 16, tid);
-            lb.load(B, n0, (kt + 1) * 16, tid);
-        }
-        double a[TL::MA], b[TL::NB];
-        const double *pa = ldsA[cur] + (wr * TL::MA) * 64 + lane;
-        const double *pb = ldsB[cur] + (wc * TL::NB) * 64 + lane;
-#pragma unroll
-        for (int i = 0; i < TL::MA; i++)
-            a[i] = pa[i * 64];
-#pragma unroll
-        for (int j = 0; j < TL::NB; j++)
-            b[j] = pb[j * 64];
 #pragma unroll
         for (int i = 0; i < TL::MA; i++)
 #pragma unroll
             for (int j = 0; j < TL::NB; j++)
-                acc.c[i][j] = mfma4(a[i], b[j], acc.c[i][j]);
+                c[i][j] = 0.0;
+    }
+};
+
+// acc += sum over k in [k_begin, k_end) of A(m0 + i, k) * B(n0 + j, k).
+// lds must hold TL::LDS_DOUBLES doubles.  Every thread of the workgroup calls
+// this.  Inner indices outside [k_begin, k_end) contribute nothing only if
+// the operands return 0 there; the callers pass nk bounds accordingly.
+template <class TL, class OA, class OB>
+__device__ __forceinline__ void tile_gemm(const OA &A, const OB &B, int m0, int n0, int k_begin,
+                                          int k_end, double *lds, Acc<TL> &acc)
+{
+    constexpr int BK = TL::NSUB * 4;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
+    // Stage buffer s starts at lds + s * STAGE: A tile, then B tile.  Plain
+    // pointer arithmetic keeps every access an LDS (ds_*) instruction.
+    constexpr int STAGE = TL::A_DOUBLES + TL::B_DOUBLES;
+
+    TileLoader<TL::WROWS * TL::MA * 16, BK, TL::NTHR, true, OA> la;
+    TileLoader<TL::WCOLS * TL::NB * 4, BK, TL::NTHR, false, OB> lb;
+    const int nk = (k_end - k_begin + BK - 1) / BK;
+    if (nk <= 0)
+        return;
+    la.load(A, m0, k_begin, tid);
+    lb.load(B, n0, k_begin, tid);
+    la.store(A, lds, tid);
+    lb.store(B, lds + TL::A_DOUBLES, tid);
+    __syncthreads();
+    const int boff = 4 * (lane >> 4) + (lane & 3);
+    for (int kt = 0; kt < nk; kt++) {
+        const int cur = kt & 1;
+        const bool more = (kt + 1) < nk;
         if (more) {
-            la.store(ldsA[cur ^ 1], tid);
-            lb.store(ldsB[cur ^ 1], tid);
+            la.load(A, m0, k_begin + (kt + 1) * BK, tid);
+            lb.load(B, n0, k_begin + (kt + 1) * BK, tid);
+        }
+        const double *pa = lds + cur * STAGE + (wr * TL::MA) * TL::NSUB * 64 + lane;
+        const double *pb = lds + cur * STAGE + TL::A_DOUBLES + (wc * TL::NB) * TL::NSUB * 16 + boff;
+#pragma unroll
+        for (int s = 0; s < TL::NSUB; s++) {
+            double a[TL::MA], b[TL::NB];
+#pragma unroll
+            for (int i = 0; i < TL::MA; i++)
+                a[i] = pa[(i * TL::NSUB + s) * 64];
+#pragma unroll
+            for (int j = 0; j < TL::NB; j++)
+                b[j] = pb[(j * TL::NSUB + s) * 16];
+#pragma unroll
+            for (int i = 0; i < TL::MA; i++)
+#pragma unroll
+                for (int j = 0; j < TL::NB; j++)
+                    acc.c[i][j] = mfma4(a[i], b[j], acc.c[i][j]);
+        }
+        if (more) {
+            la.store(A, lds + (cur ^ 1) * STAGE, tid);
+            lb.store(B, lds + (cur ^ 1) * STAGE + TL::A_DOUBLES, tid);
         }
         __syncthreads();
     }
 }
 
-// After acc.reduce_blocks(): the element held by this lane for accumulator
-// (i, j) is output (row, col) = (m0 + wr*WM + 4i + (lane >> 4),
-// n0 + wc*WN + 4j + (lane & 3)).  Lanes of block b = (lane >> 2) & 3 write
-// the accumulators with (j & 3) == b, so every lane writes and each element
-// is written once.
-template <int BM, int BN, int WM, int WN, class F>
-__device__ __forceinline__ void tile_foreach(const Acc<BM, BN, WM, WN> &acc, int m0, int n0, F &&f)
+// Calls f(row, col, value) for every output element this lane holds:
+// accumulator (i, j) is element (m0 + wr*WM + 16i + 4*((lane >> 2) & 3) +
+// (lane >> 4), n0 + wc*WN + 4j + (lane & 3)).
+template <class TL, class F>
+__device__ __forceinline__ void tile_foreach(const Acc<TL> &acc, int m0, int n0, F &&f)
 {
-    typedef Tile<BM, BN, WM, WN> TL;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
-    const int blk = (lane >> 2) & 3;
-    const int rb = m0 + wr * WM + (lane >> 4);
-    const int cb = n0 + wc * WN + (lane & 3);
+    const int rb = m0 + wr * (TL::MA * 16) + 4 * ((lane >> 2) & 3) + (lane >> 4);
+    const int cb = n0 + wc * (TL::NB * 4) + (lane & 3);
 #pragma unroll
     for (int i = 0; i < TL::MA; i++)
 #pragma unroll
         for (int j = 0; j < TL::NB; j++)
-            if ((j & 3) == blk)
-                f(rb + 4 * i, cb + 4 * j, acc.c[i][j]);
+            f(rb + 16 * i, cb + 4 * j, acc.c[i][j]);
 }
 
 // Workgroup index remapped so that consecutive logical tiles land on the same
 // XCD (the hardware deals workgroups round-robin over the 8 XCDs, each with
-// its own L2): logical = xcd * ceil(n/8) + (hw / 8), folded back into range.
+// its own L2): logical = xcd * (n/8) + hw/8 when n is a multiple of 8.
 __device__ __forceinline__ int xcd_swizzle(int hw, int n)
 {
-    const int per = (n + 7) / 8;
-    const int xcd = hw & 7, slot = hw >> 3;
-    int logical = xcd * per + slot;
-    // Grids that are not a multiple of 8 leave holes; fall back to identity
-    // for them to keep the map a bijection.
-    return (n % 8 == 0) ? logical : hw;
+    if (n % 8 != 0)
+        return hw;
+    return (hw & 7) * (n >> 3) + (hw >> 3);
 }
 
 } // namespace jk

@@ -66,8 +66,8 @@ int chunk_slabs(const jk_problem *p)
 }
 
 struct FwdPlan {
-    int qc, ldw, npb, plen, ndp;
-    size_t o_cc, o_d, o_part, o_g, o_x, o_y, total;
+    int qc, ldw, npb, plen, ndp, nsplit;
+    size_t o_cc, o_d, o_part, o_g, o_x, o_y, o_kp, total;
 };
 
 FwdPlan plan_forward(const jk_problem *p)
@@ -86,11 +86,54 @@ FwdPlan plan_forward(const jk_problem *p)
     f.o_g = c.take(sizeof(double) * nd * p->naux);
     f.o_x = c.take(sizeof(double) * nd * nao * (size_t)f.ldw);
     f.o_y = c.take(sizeof(double) * nd * nao * (size_t)f.ldw);
+    f.nsplit = jk::exchange_nsplit((int)nao, (int)nd, f.ldw);
+    f.o_kp = c.take(f.nsplit > 1 ? sizeof(double) * (size_t)f.nsplit * nd * npos : 0);
     f.total = c.off;
     return f;
 }
 
-jk_status hip_status(hipError_t e) { return e == hipSuccess ? JK_OK : JK_EHIP; }
+// Slabs per chunk of the derivative: X, Y, P, R of one chunk in the budget.
+int chunk_slabs_vjp(const jk_problem *p)
+{
+    size_t per = 4 * (size_t)p->nao * (size_t)(p->ndens * p->rank) * sizeof(double);
+    i64 qc = (i64)(kChunkBudget / (per ? per : 1));
+    if (qc < 1)
+        qc = 1;
+    if (qc > p->naux)
+        qc = p->naux;
+    return (int)qc;
+}
+
+struct VjpPlan {
+    int qc, ldw, npb, plen, ndp, nsplit_c;
+    size_t o_cc, o_d, o_part, o_g, o_om, o_omx, o_x, o_y, o_p, o_r, o_dcp, total;
+};
+
+VjpPlan plan_vjp(const jk_problem *p)
+{
+    VjpPlan f;
+    const i64 nao = p->nao, nd = p->ndens, r = p->rank, R = nd * r, naux = p->naux;
+    const i64 npos = nao * nao;
+    f.qc = chunk_slabs_vjp(p);
+    f.ldw = (int)(f.qc * r);
+    f.ndp = (int)(((nd + 7) / 8) * 8);
+    f.npb = jk::project_nblocks(npos, (int)naux, (int)nd, &f.plen);
+    f.nsplit_c = jk::vjp_stage_c_nsplit((int)nao, (int)R, f.qc);
+    Carve c;
+    f.o_cc = c.take(sizeof(double) * nao * 2 * R);
+    f.o_d = c.take(sizeof(double) * nd * npos);
+    f.o_part = c.take(sizeof(double) * (size_t)f.npb * naux * f.ndp);
+    f.o_g = c.take(sizeof(double) * nd * naux);
+    f.o_om = c.take(sizeof(double) * nd * naux);
+    f.o_omx = c.take(sizeof(double) * naux * R);
+    f.o_x = c.take(sizeof(double) * nd * nao * (size_t)f.ldw);
+    f.o_y = c.take(sizeof(double) * nd * nao * (size_t)f.ldw);
+    f.o_p = c.take(sizeof(double) * (size_t)f.qc * nao * R);
+    f.o_r = c.take(sizeof(double) * (size_t)f.qc * nao * R);
+    f.o_dcp = c.take(sizeof(double) * (size_t)f.nsplit_c * nao * 2 * R);
+    f.total = c.off;
+    return f;
+}
 
 #define JK_TRY(expr)                                                                               \
     do {                                                                                           \
@@ -120,13 +163,68 @@ jk_status build_fp64(const jk_problem *p, const double *B, const double *CL, con
         JK_TRY(jk::launch_coulomb(B, g, J, naux, nd, npos, s));
     }
     if (w & JK_WANT_K) {
+        // K accumulates over Q-chunks in nsplit partial buffers (or in K
+        // itself when nsplit == 1), summed in fixed order at the end.
+        double *Kp = f.nsplit > 1 ? (double *)(ws + f.o_kp) : K;
         JK_TRY(jk::launch_pack_c(CL, CR, Cc, nao, nd, r, s));
         for (int q0 = 0; q0 < naux; q0 += f.qc) {
             int nq = (naux - q0) < f.qc ? (naux - q0) : f.qc;
             JK_TRY(jk::launch_half_transform(B, Cc, Xw, Yw, nao, nd, r, q0, nq, f.ldw, s));
-            JK_TRY(jk::launch_exchange(Xw, Yw, K, nao, nd, nq * r, f.ldw, q0 > 0, s));
+            JK_TRY(jk::launch_exchange(Xw, Yw, Kp, nao, nd, nq * r, f.ldw, f.nsplit, q0 > 0, s));
+        }
+        if (f.nsplit > 1)
+            JK_TRY(jk::launch_sum_splits(Kp, K, (i64)nd * npos, f.nsplit, s));
+    }
+    return JK_OK;
+}
+
+jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const double *CR,
+                   const double *W, const double *V, double *dB, double *dCL, double *dCR, char *ws,
+                   hipStream_t s)
+{
+    const VjpPlan f = plan_vjp(p);
+    const int nao = (int)p->nao, naux = (int)p->naux, nd = (int)p->ndens, r = (int)p->rank;
+    const int R = nd * r;
+    const i64 npos = (i64)nao * nao;
+    const int has_w = W != nullptr, has_v = V != nullptr;
+    const bool want_db = dB != nullptr, want_dc = dCL != nullptr;
+    double *Cc = (double *)(ws + f.o_cc);
+    double *D = (double *)(ws + f.o_d);
+    double *part = (double *)(ws + f.o_part);
+    double *g = (double *)(ws + f.o_g);
+    double *om = (double *)(ws + f.o_om);
+    double *omx = (double *)(ws + f.o_omx);
+    double *Xw = (double *)(ws + f.o_x);
+    double *Yw = (double *)(ws + f.o_y);
+    double *Pq = (double *)(ws + f.o_p);
+    double *Rq = (double *)(ws + f.o_r);
+    double *dCp = (double *)(ws + f.o_dcp);
+
+    JK_TRY(jk::launch_pack_c(CL, CR, Cc, nao, nd, r, s));
+    if (has_w) {
+        // omega_kQ = <W_k, B^Q>; gamma_kQ = <D_k, B^Q> for the gamma W term of dB.
+        JK_TRY(jk::launch_project(B, W, part, om, naux, nd, npos, s));
+        JK_TRY(jk::launch_omega_expand(om, omx, naux, nd, r, s));
+        if (want_db) {
+            JK_TRY(jk::launch_density(CL, CR, D, nao, nd, r, s));
+            JK_TRY(jk::launch_project(B, D, part, g, naux, nd, npos, s));
         }
     }
+    for (int q0 = 0; q0 < naux; q0 += f.qc) {
+        const int nq = (naux - q0) < f.qc ? (naux - q0) : f.qc;
+        if (has_v) {
+            JK_TRY(jk::launch_half_transform(B, Cc, Xw, Yw, nao, nd, r, q0, nq, f.ldw, s));
+            JK_TRY(jk::launch_vjp_stage_b(V, Xw, Yw, Pq, Rq, nao, nd, r, nq * r, f.ldw, s));
+        }
+        if (want_dc)
+            JK_TRY(jk::launch_vjp_stage_c(B, Pq, Rq, omx, Cc, dCp, nao, R, q0, nq, f.nsplit_c, has_v,
+                                          has_w, q0 > 0, s));
+        if (want_db)
+            JK_TRY(jk::launch_vjp_stage_d(Pq, Rq, Cc, omx, g, W, dB, nao, nd, r, naux, q0, nq, has_v,
+                                          has_w, s));
+    }
+    if (want_dc)
+        JK_TRY(jk::launch_vjp_dc_finish(dCp, dCL, dCR, nao, nd, r, f.nsplit_c, s));
     return JK_OK;
 }
 
@@ -138,7 +236,8 @@ size_t jk_workspace_bytes(const jk_problem *p)
 {
     if (!valid_problem(p))
         return 0;
-    return plan_forward(p).total;
+    size_t a = plan_forward(p).total, b = plan_vjp(p).total;
+    return a > b ? a : b;
 }
 
 jk_status jk_build(const jk_problem *p, const double *B, const double *CL, const double *CR,
@@ -211,14 +310,19 @@ jk_status jk_vjp(const jk_problem *p, const double *B, const double *CL, const d
                  const double *Jbar, const double *Kbar, double *dB, double *dCL, double *dCR,
                  void *ws, size_t ws_bytes, void *stream)
 {
-    (void)Jbar; (void)Kbar; (void)dB; (void)dCL; (void)dCR; (void)stream;
     if (!valid_problem(p))
         return JK_EINVAL;
     if (!B || !CL || !CR || !ws || ((uintptr_t)ws) % kAlign)
         return JK_EINVAL;
+    if ((dCL == nullptr) != (dCR == nullptr))
+        return JK_EINVAL;
     if (ws_bytes < jk_workspace_bytes(p))
         return JK_EWORKSPACE;
-    return JK_EUNSUPPORTED;
+    if (p->precision != JK_FP64)
+        return JK_EUNSUPPORTED;
+    if (!dB && !dCL)
+        return JK_OK;
+    return vjp_fp64(p, B, CL, CR, Jbar, Kbar, dB, dCL, dCR, (char *)ws, (hipStream_t)stream);
 }
 
 const char *jk_status_str(jk_status s)

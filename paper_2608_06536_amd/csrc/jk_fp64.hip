@@ -17,6 +17,14 @@
 
 namespace jk {
 
+// Tile shapes: the big GEMMs use 128 x 128 workgroup tiles of four 64 x 64
+// wave tiles; the projection 256 Q-rows x 8 densities; the density 64 x 64.
+constexpr int kBig = 128;
+constexpr int kProjRows = 256;
+typedef Tile<kBig, kBig, 64, 64, 16> TileBig;
+typedef Tile<kProjRows, 8, 64, 8, 16> TileProject;
+typedef Tile<64, 64, 32, 32, 16> TileDensity;
+
 // ------------------------------------------------------------------ pack
 __global__ void __launch_bounds__(256) k_pack_c(const double *__restrict__ CL,
                                                 const double *__restrict__ CR, double *__restrict__ Cc,
@@ -39,17 +47,16 @@ __global__ void __launch_bounds__(256) k_density(const double *__restrict__ CL,
                                                  const double *__restrict__ CR, double *__restrict__ D,
                                                  int nao, int r)
 {
-    typedef Tile<64, 64, 32, 32> TL;
+    typedef TileDensity TL;
     __shared__ double lds[TL::LDS_DOUBLES];
     const int nt = (nao + 63) / 64;
     const int k = blockIdx.y;
     const int mb = blockIdx.x / nt, nb = blockIdx.x % nt;
     OpKC a{CL + (i64)k * nao * r, r, nao, r};
     OpKC b{CR + (i64)k * nao * r, r, nao, r};
-    Acc<64, 64, 32, 32> acc;
+    Acc<TL> acc;
     acc.zero();
-    tile_gemm<64, 64, 32, 32>(a, b, mb * 64, nb * 64, r, lds, acc);
-    acc.reduce_blocks();
+    tile_gemm<TL>(a, b, mb * 64, nb * 64, 0, r, lds, acc);
     double *Dk = D + (i64)k * nao * nao;
     tile_foreach(acc, mb * 64, nb * 64, [&](int m, int n, double v) {
         if (m < nao && n < nao)
@@ -60,13 +67,13 @@ __global__ void __launch_bounds__(256) k_density(const double *__restrict__ CL,
 // ------------------------------------------------------------------ project
 // part[pb][Q][kk] = sum_{p in block pb} B[Q][p] * A[k0 + kk][p], kk < 8.
 // A GEMM with M = naux, N = nd (in groups of 8), inner = nao^2 split into
-// blocks of plen positions.  grid: x = Q tiles of 128, y = density groups,
-// z = position blocks.
+// blocks of plen positions.  grid: x = Q tiles of kProjRows, y = density
+// groups, z = position blocks.
 __global__ void __launch_bounds__(256) k_project(const double *__restrict__ B,
                                                  const double *__restrict__ A, double *__restrict__ part,
                                                  int naux, int nd, i64 npos, int plen)
 {
-    typedef Tile<128, 8, 32, 8> TL;
+    typedef TileProject TL;
     __shared__ double lds[TL::LDS_DOUBLES];
     const int qt = blockIdx.x, kg = blockIdx.y, pb = blockIdx.z;
     const i64 p0 = (i64)pb * plen;
@@ -74,13 +81,12 @@ __global__ void __launch_bounds__(256) k_project(const double *__restrict__ B,
     const int ndg = (nd - kg * 8) < 8 ? (nd - kg * 8) : 8;
     OpKC a{B + p0, npos, naux, len};
     OpKC b{A + (i64)kg * 8 * npos + p0, npos, ndg, len};
-    Acc<128, 8, 32, 8> acc;
+    Acc<TL> acc;
     acc.zero();
-    tile_gemm<128, 8, 32, 8>(a, b, qt * 128, 0, len, lds, acc);
-    acc.reduce_blocks();
+    tile_gemm<TL>(a, b, qt * kProjRows, 0, 0, len, lds, acc);
     const int ndp = ((nd + 7) / 8) * 8;
     double *out = part + (i64)pb * naux * ndp;
-    tile_foreach(acc, qt * 128, 0, [&](int q, int kk, double v) {
+    tile_foreach(acc, qt * kProjRows, 0, [&](int q, int kk, double v) {
         if (q < naux && kk < 8)
             out[(i64)q * ndp + kg * 8 + kk] = v;
     });
@@ -148,17 +154,17 @@ __global__ void __launch_bounds__(256) k_coulomb(const double *__restrict__ B,
 // ------------------------------------------------------------------ half-transform
 // For slab Q = q0 + ql (ql < nq): XY[m][c] = sum_n B^Q[m][n] Cc[n][c], written
 // as X_ws[k][m][ql*r + i] (c = k*r + i < R) or Y_ws[k][m][ql*r + i] (c - R).
-// grid.x = nq * nmt * nct (XCD-swizzled), tile 64 x 64.
+// grid.x = nq * nmt * nct (XCD-swizzled), tile kBig x kBig.
 __global__ void __launch_bounds__(256) k_half_transform(const double *__restrict__ B,
                                                         const double *__restrict__ Cc,
                                                         double *__restrict__ Xw, double *__restrict__ Yw,
                                                         int nao, int nd, int r, int q0, int nq,
                                                         int ldw)
 {
-    typedef Tile<64, 64, 32, 32> TL;
+    typedef TileBig TL;
     __shared__ double lds[TL::LDS_DOUBLES];
     const int R = nd * r, R2 = 2 * R;
-    const int nmt = (nao + 63) / 64, nct = (R2 + 63) / 64;
+    const int nmt = (nao + kBig - 1) / kBig, nct = (R2 + kBig - 1) / kBig;
     const int ntile = nq * nmt * nct;
     const int t = xcd_swizzle(blockIdx.x, ntile);
     const int ql = t / (nmt * nct), rem = t % (nmt * nct);
@@ -166,11 +172,10 @@ __global__ void __launch_bounds__(256) k_half_transform(const double *__restrict
     const i64 n2 = (i64)nao * nao;
     OpKC a{B + (i64)(q0 + ql) * n2, nao, nao, nao};
     OpIC b{Cc, R2, R2, nao};
-    Acc<64, 64, 32, 32> acc;
+    Acc<TL> acc;
     acc.zero();
-    tile_gemm<64, 64, 32, 32>(a, b, mb * 64, cb * 64, nao, lds, acc);
-    acc.reduce_blocks();
-    tile_foreach(acc, mb * 64, cb * 64, [&](int m, int c, double v) {
+    tile_gemm<TL>(a, b, mb * kBig, cb * kBig, 0, nao, lds, acc);
+    tile_foreach(acc, mb * kBig, cb * kBig, [&](int m, int c, double v) {
         if (m < nao && c < R2) {
             double *dst = c < R ? Xw : Yw;
             int cc = c < R ? c : c - R;
@@ -181,32 +186,48 @@ __global__ void __launch_bounds__(256) k_half_transform(const double *__restrict
 }
 
 // ------------------------------------------------------------------ exchange
-// K[k][m][n] (+)= sum_{j < nj} X_ws[k][m][j] Y_ws[k][n][j].
-// grid.x = nd * nt * nt (XCD-swizzled), tile 64 x 64.
+// Kp[s][k][m][n] (+)= sum_{j in split s} X_ws[k][m][j] Y_ws[k][n][j], the inner
+// range [0, nj) cut into nsplit contiguous pieces of jlen.  With nsplit == 1
+// Kp is K itself.  grid.x = nsplit * nd * nt * nt (XCD-swizzled).
 __global__ void __launch_bounds__(256) k_exchange(const double *__restrict__ Xw,
-                                                  const double *__restrict__ Yw, double *__restrict__ K,
-                                                  int nao, int nd, int nj, int ldw, int accumulate)
+                                                  const double *__restrict__ Yw, double *__restrict__ Kp,
+                                                  int nao, int nd, int nj, int ldw, int nsplit,
+                                                  int jlen, int accumulate)
 {
-    typedef Tile<64, 64, 32, 32> TL;
+    typedef TileBig TL;
     __shared__ double lds[TL::LDS_DOUBLES];
-    const int nt = (nao + 63) / 64;
-    const int ntile = nd * nt * nt;
-    const int t = xcd_swizzle(blockIdx.x, ntile);
+    const int nt = (nao + kBig - 1) / kBig;
+    const int ntile = nsplit * nd * nt * nt;
+    int t = xcd_swizzle(blockIdx.x, ntile);
+    const int sp = t / (nd * nt * nt);
+    t -= sp * (nd * nt * nt);
     const int k = t / (nt * nt), rem = t % (nt * nt);
     const int mb = rem / nt, nb = rem % nt;
-    OpKC a{Xw + (i64)k * nao * ldw, ldw, nao, nj};
-    OpKC b{Yw + (i64)k * nao * ldw, ldw, nao, nj};
-    Acc<64, 64, 32, 32> acc;
+    const int j0 = sp * jlen, j1 = (j0 + jlen) < nj ? (j0 + jlen) : nj;
+    OpKC a{Xw + (i64)k * nao * ldw, ldw, nao, j1};
+    OpKC b{Yw + (i64)k * nao * ldw, ldw, nao, j1};
+    Acc<TL> acc;
     acc.zero();
-    tile_gemm<64, 64, 32, 32>(a, b, mb * 64, nb * 64, nj, lds, acc);
-    acc.reduce_blocks();
-    double *Kk = K + (i64)k * nao * nao;
-    tile_foreach(acc, mb * 64, nb * 64, [&](int m, int n, double v) {
+    tile_gemm<TL>(a, b, mb * kBig, nb * kBig, j0, j1, lds, acc);
+    double *Kk = Kp + ((i64)sp * nd + k) * nao * nao;
+    tile_foreach(acc, mb * kBig, nb * kBig, [&](int m, int n, double v) {
         if (m < nao && n < nao) {
             i64 o = (i64)m * nao + n;
             Kk[o] = accumulate ? Kk[o] + v : v;
         }
     });
+}
+
+// out[e] = sum_{s < nsplit} part[s * n + e] (fixed order).
+__global__ void __launch_bounds__(256) k_sum_splits(const double *__restrict__ part,
+                                                    double *__restrict__ out, i64 n, int nsplit)
+{
+    for (i64 e = (i64)blockIdx.x * 256 + threadIdx.x; e < n; e += (i64)gridDim.x * 256) {
+        double s = 0.0;
+        for (int sp = 0; sp < nsplit; sp++)
+            s += part[(i64)sp * n + e];
+        out[e] = s;
+    }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -235,7 +256,7 @@ hipError_t launch_density(const double *CL, const double *CR, double *D, int nao
 int project_nblocks(i64 npos, int naux, int nd, int *plen)
 {
     // Aim for >= 2048 workgroups in total; position blocks are multiples of 16.
-    int nqt = cdiv(naux, 128), nkg = cdiv(nd, 8);
+    int nqt = cdiv(naux, kProjRows), nkg = cdiv(nd, 8);
     i64 want = 2048 / (nqt * nkg);
     if (want < 1)
         want = 1;
@@ -252,7 +273,7 @@ hipError_t launch_project(const double *B, const double *A, double *part, double
 {
     int plen;
     int npb = project_nblocks(npos, naux, nd, &plen);
-    dim3 grid(cdiv(naux, 128), cdiv(nd, 8), npb);
+    dim3 grid(cdiv(naux, kProjRows), cdiv(nd, 8), npb);
     hipLaunchKernelGGL(k_project, grid, dim3(256), 0, s, B, A, part, naux, nd, npos, plen);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -281,18 +302,43 @@ hipError_t launch_coulomb(const double *B, const double *g, double *J, int naux,
 hipError_t launch_half_transform(const double *B, const double *Cc, double *Xw, double *Yw,
                                  int nao, int nd, int r, int q0, int nq, int ldw, hipStream_t s)
 {
-    int nmt = cdiv(nao, 64), nct = cdiv(2 * (i64)nd * r, 64);
+    int nmt = cdiv(nao, kBig), nct = cdiv(2 * (i64)nd * r, kBig);
     hipLaunchKernelGGL(k_half_transform, dim3(nq * nmt * nct), dim3(256), 0, s, B, Cc, Xw, Yw, nao,
                        nd, r, q0, nq, ldw);
     return hipGetLastError();
 }
 
-hipError_t launch_exchange(const double *Xw, const double *Yw, double *K, int nao, int nd, int nj,
-                           int ldw, int accumulate, hipStream_t s)
+int exchange_nsplit(int nao, int nd, int nj)
 {
-    int nt = cdiv(nao, 64);
-    hipLaunchKernelGGL(k_exchange, dim3(nd * nt * nt), dim3(256), 0, s, Xw, Yw, K, nao, nd, nj, ldw,
-                       accumulate);
+    // Enough workgroups for two per CU; each split keeps >= 256 inner indices.
+    int nt = cdiv(nao, kBig);
+    int tiles = nd * nt * nt;
+    int ns = cdiv(512, tiles);
+    int maxs = nj / 256 > 1 ? nj / 256 : 1;
+    if (ns > maxs)
+        ns = maxs;
+    if (ns > 16)
+        ns = 16;
+    return ns < 1 ? 1 : ns;
+}
+
+hipError_t launch_exchange(const double *Xw, const double *Yw, double *Kp, int nao, int nd, int nj,
+                           int ldw, int nsplit, int accumulate, hipStream_t s)
+{
+    int nt = cdiv(nao, kBig);
+    int jlen = cdiv(nj, nsplit);
+    jlen = ((jlen + 15) / 16) * 16;
+    hipLaunchKernelGGL(k_exchange, dim3(nsplit * nd * nt * nt), dim3(256), 0, s, Xw, Yw, Kp, nao, nd,
+                       nj, ldw, nsplit, jlen, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_splits(const double *part, double *out, i64 n, int nsplit, hipStream_t s)
+{
+    int grid = cdiv(n, 256);
+    if (grid > 65535)
+        grid = 65535;
+    hipLaunchKernelGGL(k_sum_splits, dim3(grid), dim3(256), 0, s, part, out, n, nsplit);
     return hipGetLastError();
 }
 

@@ -18,7 +18,26 @@ hipError_t launch_coulomb(const double *B, const double *g, double *J, int naux,
                           int64_t npos, hipStream_t s);
 hipError_t launch_half_transform(const double *B, const double *Cc, double *Xw, double *Yw,
                                  int nao, int nd, int r, int q0, int nq, int ldw, hipStream_t s);
-hipError_t launch_exchange(const double *Xw, const double *Yw, double *K, int nao, int nd, int nj,
-                           int ldw, int accumulate, hipStream_t s);
+int exchange_nsplit(int nao, int nd, int nj);
+hipError_t launch_exchange(const double *Xw, const double *Yw, double *Kp, int nao, int nd, int nj,
+                           int ldw, int nsplit, int accumulate, hipStream_t s);
+hipError_t launch_sum_splits(const double *part, double *out, i64 n, int nsplit, hipStream_t s);
+
+// derivative (jk_vjp.hip)
+hipError_t launch_omega_expand(const double *om, double *omx, int naux, int nd, int r,
+                               hipStream_t s);
+hipError_t launch_vjp_stage_b(const double *V, const double *Xw, const double *Yw, double *Pq,
+                              double *Rq, int nao, int nd, int r, int nj, int ldw, hipStream_t s);
+int vjp_stage_c_nsplit(int nao, int R, int qc);
+hipError_t launch_vjp_stage_c(const double *B, const double *Pq, const double *Rq,
+                              const double *omx, const double *Cc, double *dCp, int nao, int R,
+                              int q0, int nq, int nsplit, int has_v, int has_w, int accumulate,
+                              hipStream_t s);
+hipError_t launch_vjp_dc_finish(const double *dCp, double *dCL, double *dCR, int nao, int nd,
+                                int r, int nsplit, hipStream_t s);
+hipError_t launch_vjp_stage_d(const double *Pq, const double *Rq, const double *Cc,
+                              const double *omx, const double *gam, const double *W, double *dB,
+                              int nao, int nd, int r, int naux, int q0, int nq, int has_v,
+                              int has_w, hipStream_t s);
 
 } // namespace jk

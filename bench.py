@@ -1,0 +1,233 @@
+"""Benchmark of the Cholesky-decomposed J/K path on one MI355X.
+
+One step = one pass of the hot path over the differentiated workload
+(nao=500, naux=2000, 8 non-symmetric densities of rank 40): the FP64 forward
+build jk_build (gamma, J, half-transforms, K) followed by the reverse-mode
+derivative jk_vjp with N(0,1) cotangents (dB, dC_L, dC_R).  Inputs are seeded
+synthetic arrays resident on the GPU before the timed region.
+
+Prints ONE JSON line.  value = densities carried through build + derivative
+per second (nd / step time).  Also reported: builds/s and VJPs/s timed
+separately, the mixed-precision build rate and its error when available,
+per-kernel times from HIP events recorded around every launch during the
+timed steps, the roofline fraction of the dominant kernel, sampled errors
+against the CPU oracle, and the CPU oracle's own rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (vector and matrix)
+PEAK_BF16_TFLOPS = 2516.6    # MI355X dense BF16 matrix
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
+
+
+def kernel_models(p, nd, nao, naux, R):
+    """Algorithmic work of each kernel over ONE step: (bound, amount, unit).
+    Flops count the method's own products; bytes count one read of B."""
+    n2 = float(nao) * nao
+    return {
+        "half_transform": ("mfma", 2 * 4.0 * naux * n2 * R, "flop"),   # build + derivative
+        "exchange": ("mfma", 2.0 * naux * n2 * R, "flop"),
+        "vjp_stage_b_p": ("mfma", 2.0 * naux * n2 * R, "flop"),
+        "vjp_stage_b_r": ("mfma", 2.0 * naux * n2 * R, "flop"),
+        "vjp_stage_c": ("mfma", 4.0 * naux * n2 * R, "flop"),
+        "vjp_stage_d": ("mfma", 6.0 * naux * n2 * R, "flop"),
+        "coulomb": ("hbm", 8.0 * naux * n2, "byte"),
+        "project": ("hbm", 3 * 8.0 * naux * n2, "byte"),   # gamma (build), omega, gamma (derivative)
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the sharded multi-GPU path is a design note, not part of this build)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2608_06536_amd import _lib, jk, synth
+
+    p = synth.config(4)
+    nd, nao, naux, r = p.nd, p.nao, p.naux, p.r
+    R = nd * r
+    t0 = time.time()
+    B, CL, CR = synth.make_problem(p)
+    W, V = synth.make_cotangents(p)
+    print(f"# inputs generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    Bd, Ld, Rd, Wd, Vd = (torch.from_numpy(a).to(dev) for a in (B, CL, CR, W, V))
+    J = torch.empty((nd, nao, nao), dtype=torch.float64, device=dev)
+    K = torch.empty_like(J)
+    dB = torch.empty_like(Bd)
+    dCL = torch.empty_like(Ld)
+    dCR = torch.empty_like(Rd)
+    nbytes = jk.workspace_bytes(jk.make_problem(nao, naux, nd, r))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    def build():
+        jk.jk_build(Bd, Ld, Rd, out=(J, K), ws=ws)
+
+    def vjp():
+        jk.jk_vjp(Bd, Ld, Rd, Wd, Vd, out=(dB, dCL, dCR), ws=ws)
+
+    def step():
+        build()
+        vjp()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # ---- timed region: K steps with every kernel launch bracketed by events
+    _lib.prof_enable(4096)
+    _lib.prof_reset()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    kern = _lib.prof_collect()
+    dropped = _lib.prof_dropped()
+    _lib.prof_disable()
+    ms_per_step = 1e3 * t_total / args.steps
+    value = nd * args.steps / t_total
+
+    # ---- separate rates of the build and the derivative
+    def rate(fn, n=3):
+        fn()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) / n
+
+    t_build = rate(build)
+    t_vjp = rate(vjp)
+
+    # ---- roofline of the dominant kernel
+    models = kernel_models(p, nd, nao, naux, R)
+    per_kernel = {}
+    for name, (ms, cnt) in kern.items():
+        ent = {"total_ms": round(ms, 3), "launches": cnt, "avg_us": round(1e3 * ms / max(cnt, 1), 1)}
+        if name in models:
+            bound, amount, unit = models[name]
+            tot = amount * args.steps
+            if unit == "flop":
+                ent["tflops"] = round(tot / (ms * 1e-3) / 1e12, 2)
+            else:
+                ent["gbs"] = round(tot / (ms * 1e-3) / 1e9, 1)
+        per_kernel[name] = ent
+    dom = max(kern.items(), key=lambda kv: kv[1][0])[0]
+    bound, amount, unit = models.get(dom, ("mfma", float("nan"), "flop"))
+    dom_ms, dom_cnt = kern[dom]
+    if unit == "flop":
+        achieved = amount * args.steps / (dom_ms * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 3), "traffic": None,
+                "flop_per_launch": amount * args.steps / dom_cnt,
+                "avg_launch_us": round(1e3 * dom_ms / dom_cnt, 1)}
+    else:
+        achieved = amount * args.steps / (dom_ms * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 3), "traffic": None,
+                "byte_per_launch": amount * args.steps / dom_cnt,
+                "avg_launch_us": round(1e3 * dom_ms / dom_cnt, 1)}
+
+    out = {
+        "metric": "J/K builds/s + VJPs/s at nao=500 (FP64 vs mixed), max err vs FP64 oracle",
+        "value": round(value, 3),
+        "unit": "densities/s (FP64 build + VJP)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "differentiated CD J/K build: nao=500 naux=2000, 8 non-symmetric "
+                               "densities of rank 40, N(0,1) cotangents; step = jk_build + jk_vjp",
+                   "nao": nao, "naux": naux, "ndens": nd, "rank": r, "precision": "fp64"},
+        "builds_per_s_fp64": round(nd / t_build, 2),
+        "vjps_per_s_fp64": round(nd / t_vjp, 2),
+        "build_ms_fp64": round(1e3 * t_build, 3),
+        "vjp_ms_fp64": round(1e3 * t_vjp, 3),
+        "roofline": roof,
+        "kernels": per_kernel,
+        "prof_dropped": dropped,
+    }
+
+    # ---- sampled errors against the CPU oracle (same launch configuration)
+    if not args.no_check:
+        import oracle
+        torch.cuda.synchronize()
+        Jh, Kh = J.cpu().numpy(), K.cpu().numpy()
+        rng = np.random.default_rng(2024)
+        n = 8
+        ks, ms_, ns_ = rng.integers(0, nd, n), rng.integers(0, nao, n), rng.integers(0, nao, n)
+        Je, Ke = oracle.jk_entries(B, CL, CR, ks, ms_, ns_)
+        qs, as_, bs_ = rng.integers(0, naux, n), rng.integers(0, nao, n), rng.integers(0, nao, n)
+        dBe = oracle.db_entries(B, CL, CR, W, V, qs, as_, bs_)
+        dBh = dB[qs, as_, bs_].cpu().numpy()
+        out["max_err_sampled"] = {
+            "J": float(np.max(np.abs(Jh[ks, ms_, ns_] - Je)) / np.max(np.abs(Jh))),
+            "K": float(np.max(np.abs(Kh[ks, ms_, ns_] - Ke)) / np.max(np.abs(Kh))),
+            "dB": float(np.max(np.abs(dBh - dBe)) / float(dB.abs().max())),
+            "entries_each": n,
+        }
+
+    # ---- CPU oracle baseline on a bounded Q-sample
+    if not args.no_cpu:
+        import oracle
+        nthr = oracle.num_threads()
+
+        def cpu_time(ns):
+            Bs = np.ascontiguousarray(B[:ns])
+            a = time.perf_counter()
+            oracle.jk_factored(Bs, CL, CR)
+            tf = time.perf_counter() - a
+            a = time.perf_counter()
+            oracle.vjp_factored(Bs, CL, CR, W, V)
+            return tf, time.perf_counter() - a
+
+        tf1, tv1 = cpu_time(2)
+        per_slab = (tf1 + tv1) / 2
+        ns = int(max(2, min(naux, args.cpu_seconds / max(per_slab, 1e-6))))
+        tf, tv = cpu_time(ns) if ns > 2 else (tf1, tv1)
+        scale = naux / ns
+        t_cpu = (tf + tv) * scale
+        out["cpu_baseline"] = {
+            "value": round(nd / t_cpu, 5), "unit": "densities/s (FP64 build + VJP)",
+            "cores": nthr, "kind": "oracle",
+            "sample": f"factored oracle (build + derivative) on the first {ns} of {naux} slabs of "
+                      f"the same workload, time scaled by {scale:.1f}",
+            "build_s_est": round(tf * scale, 2), "vjp_s_est": round(tv * scale, 2),
+        }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

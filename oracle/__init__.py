@@ -44,7 +44,8 @@ def _load():
         for name, nargs in [("jko_eri4", 0), ("jko_jk_from_eri", 0), ("jko_density", 0),
                             ("jko_project", 0), ("jko_coulomb", 0), ("jko_exchange", 0),
                             ("jko_jk_factored", 0), ("jko_jk_entries", 0), ("jko_vjp", 0),
-                            ("jko_db_entries", 0), ("jko_jvp", 0), ("jko_dc_density", 0)]:
+                            ("jko_db_entries", 0), ("jko_jvp", 0), ("jko_dc_density", 0),
+                            ("jko_vjp_factored", 0)]:
             getattr(lib, name).restype = None
         lib.jko_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -201,6 +202,23 @@ def jvp(B, CL, CR, dB=None, dCL=None, dCR=None):
     _load().jko_jvp(_I(nd), _I(nao), _I(naux), _I(r), _d(B), _d(CL), _d(CR), _d(dB),
                     _d(dCL), _d(dCR), _d(dJ), _d(dK))
     return dJ, dK
+
+
+def vjp_factored(B, CL, CR, W=None, V=None, q0=0, q1=None, want_dB=True):
+    """Factored derivative (symmetric B) over slabs [q0, q1).  Returns
+    (dB or None, dCL, dCR); dB rows outside [q0, q1) are zero."""
+    B, CL, CR = _c(B), _c(CL), _c(CR)
+    W = None if W is None else _c(W)
+    V = None if V is None else _c(V)
+    naux, nao, _ = B.shape
+    nd, _, r = CL.shape
+    q1 = naux if q1 is None else q1
+    dB = np.zeros_like(B) if want_dB else None
+    dCL = np.empty_like(CL)
+    dCR = np.empty_like(CR)
+    _load().jko_vjp_factored(_I(nd), _I(nao), _I(naux), _I(r), _d(B), _d(CL), _d(CR), _d(W),
+                             _d(V), _I(q0), _I(q1), _d(dB), _d(dCL), _d(dCR))
+    return dB, dCL, dCR
 
 
 def db_entries(B, CL, CR, W, V, qs, as_, bs):

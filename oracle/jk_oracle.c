@@ -417,6 +417,101 @@ void jko_vjp(i64 nd, i64 nao, i64 naux, i64 r, const double *B,
     free(dD);
 }
 
+/* Factored reverse-mode derivative (symmetric B), the half-transform form of
+ * the closed forms in the header: for every density k and slab Q
+ *   X = B^Q C_Lk, Y = B^Q C_Rk, P = V_k Y, R = V_k^T X,
+ *   dC_Lk += B^Q P + omega_kQ Y,   dC_Rk += B^Q R + omega_kQ X,
+ *   dB^Q  += gamma_kQ W_k + omega_kQ C_Lk C_Rk^T + P C_Lk^T + C_Rk R^T.
+ * Slabs are processed for Q in [q0, q1) only (dB rows outside are untouched;
+ * dC sums only that range), so a Q-sample can be timed.  W or V may be NULL.
+ * dB is indexed by absolute Q.  Q ascending; threads split rows only. */
+void jko_vjp_factored(i64 nd, i64 nao, i64 naux, i64 r, const double *B,
+                      const double *CL, const double *CR, const double *W,
+                      const double *V, i64 q0, i64 q1, double *dB,
+                      double *dCL, double *dCR)
+{
+    (void)naux;
+    i64 n2 = nao * nao;
+    double *x = (double *)malloc(sizeof(double) * nao * r);
+    double *y = (double *)malloc(sizeof(double) * nao * r);
+    double *pp = (double *)malloc(sizeof(double) * nao * r);
+    double *rr = (double *)malloc(sizeof(double) * nao * r);
+    for (i64 e = 0; e < nd * nao * r; e++) {
+        if (dCL) dCL[e] = 0.0;
+        if (dCR) dCR[e] = 0.0;
+    }
+    if (dB)
+        for (i64 q = q0; q < q1; q++)
+            for (i64 e = 0; e < n2; e++)
+                dB[q * n2 + e] = 0.0;
+    for (i64 k = 0; k < nd; k++) {
+        const double *cl = CL + k * nao * r, *cr = CR + k * nao * r;
+        const double *Wk = W ? W + k * n2 : NULL, *Vk = V ? V + k * n2 : NULL;
+        for (i64 q = q0; q < q1; q++) {
+            const double *Bq = B + q * n2;
+#pragma omp parallel for schedule(static)
+            for (i64 m = 0; m < nao; m++)
+                for (i64 i = 0; i < r; i++) {
+                    double sx = 0.0, sy = 0.0;
+                    for (i64 l = 0; l < nao; l++) {
+                        sx += Bq[m * nao + l] * cl[l * r + i];
+                        sy += Bq[m * nao + l] * cr[l * r + i];
+                    }
+                    x[m * r + i] = sx;
+                    y[m * r + i] = sy;
+                }
+            double g = 0.0, w = 0.0;
+            for (i64 m = 0; m < nao; m++)
+                for (i64 i = 0; i < r; i++)
+                    g += cl[m * r + i] * y[m * r + i];
+            if (Wk)
+                for (i64 e = 0; e < n2; e++)
+                    w += Wk[e] * Bq[e];
+#pragma omp parallel for schedule(static)
+            for (i64 m = 0; m < nao; m++)
+                for (i64 i = 0; i < r; i++) {
+                    double sp = 0.0, sr = 0.0;
+                    if (Vk)
+                        for (i64 n = 0; n < nao; n++) {
+                            sp += Vk[m * nao + n] * y[n * r + i];
+                            sr += Vk[n * nao + m] * x[n * r + i];
+                        }
+                    pp[m * r + i] = sp;
+                    rr[m * r + i] = sr;
+                }
+            if (dCL)
+#pragma omp parallel for schedule(static)
+                for (i64 m = 0; m < nao; m++)
+                    for (i64 i = 0; i < r; i++) {
+                        double sl = w * y[m * r + i], sr = w * x[m * r + i];
+                        for (i64 n = 0; n < nao; n++) {
+                            sl += Bq[m * nao + n] * pp[n * r + i];
+                            sr += Bq[m * nao + n] * rr[n * r + i];
+                        }
+                        dCL[(k * nao + m) * r + i] += sl;
+                        dCR[(k * nao + m) * r + i] += sr;
+                    }
+            if (dB)
+#pragma omp parallel for schedule(static)
+                for (i64 a = 0; a < nao; a++)
+                    for (i64 b = 0; b < nao; b++) {
+                        double v = 0.0;
+                        for (i64 i = 0; i < r; i++)
+                            v += w * cl[a * r + i] * cr[b * r + i]
+                               + pp[a * r + i] * cl[b * r + i]
+                               + cr[a * r + i] * rr[b * r + i];
+                        if (Wk)
+                            v += g * Wk[a * nao + b];
+                        dB[q * n2 + a * nao + b] += v;
+                    }
+        }
+    }
+    free(x);
+    free(y);
+    free(pp);
+    free(rr);
+}
+
 /* Selected entries of dB (symmetric B assumed, as the factored form uses):
  *   dB^Q_ab = sum_k gamma_kQ W_k,ab + omega_kQ D_k,ab
  *             + sum_c V_k,ac (B^Q D_k^T)_cb + sum_c D_k,ca (B^Q V_k)_cb

@@ -15,9 +15,11 @@ JK_OK, JK_EINVAL, JK_EWORKSPACE, JK_EUNSUPPORTED, JK_EHIP = 0, 1, 2, 3, 4
 JK_FP64, JK_MIXED = 0, 1
 JK_WANT_J, JK_WANT_K = 1, 2
 
-# Every symbol include/jk.h declares.
+# Every symbol include/jk.h and include/jk_prof.h declare.
 EXPORTS = ("jk_workspace_bytes", "jk_build", "jk_batched_workspace_bytes", "jk_build_batched",
            "jk_vjp", "jk_status_str")
+PROF_EXPORTS = ("jk_prof_enable", "jk_prof_reset", "jk_prof_collect", "jk_prof_entry",
+                "jk_prof_dropped")
 
 
 class Problem(ctypes.Structure):
@@ -56,6 +58,17 @@ def lib():
         L.jk_vjp.argtypes = [pp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.jk_status_str.restype = ctypes.c_char_p
         L.jk_status_str.argtypes = [ctypes.c_int]
+        L.jk_prof_enable.restype = ctypes.c_int
+        L.jk_prof_enable.argtypes = [ctypes.c_int32]
+        L.jk_prof_reset.restype = None
+        L.jk_prof_reset.argtypes = []
+        L.jk_prof_collect.restype = ctypes.c_int32
+        L.jk_prof_collect.argtypes = []
+        L.jk_prof_entry.restype = ctypes.c_int
+        L.jk_prof_entry.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_char_p),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+        L.jk_prof_dropped.restype = ctypes.c_int64
+        L.jk_prof_dropped.argtypes = []
         _lib = L
     return _lib
 
@@ -67,3 +80,37 @@ def status_str(s: int) -> str:
 def check(status: int, what: str) -> None:
     if status != JK_OK:
         raise JKError(status, what)
+
+
+def prof_enable(capacity: int) -> None:
+    """Start recording per-launch HIP events (see include/jk_prof.h)."""
+    if lib().jk_prof_enable(int(capacity)) != 0:
+        raise RuntimeError("jk_prof_enable failed")
+
+
+def prof_disable() -> None:
+    lib().jk_prof_enable(0)
+
+
+def prof_reset() -> None:
+    lib().jk_prof_reset()
+
+
+def prof_collect() -> dict:
+    """{kernel name: (total ms, launches)} of the recorded launches."""
+    L = lib()
+    n = L.jk_prof_collect()
+    if n < 0:
+        raise RuntimeError("jk_prof_collect failed")
+    out = {}
+    for i in range(n):
+        name = ctypes.c_char_p()
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        L.jk_prof_entry(i, ctypes.byref(name), ctypes.byref(ms), ctypes.byref(cnt))
+        out[name.value.decode()] = (ms.value, cnt.value)
+    return out
+
+
+def prof_dropped() -> int:
+    return int(lib().jk_prof_dropped())

@@ -47,6 +47,8 @@ __device__ __forceinline__ double mfma4(double a, double b, double c)
 //                     0 outside the valid range.
 // kContig tells the loader which index is contiguous in memory so that it
 // assigns threads for coalesced reads.  Valid ranges need ni, nk >= 1.
+// (Measured: a separate unchecked path for interior tiles is slower than this
+// single branch-free path, because the branch splits the load schedule.)
 
 // element (i, k) at p[i * ld + k]
 struct OpKC {
@@ -188,22 +190,27 @@ struct Acc {
 
 // acc += sum over k in [k_begin, k_end) of A(m0 + i, k) * B(n0 + j, k).
 // lds must hold TL::LDS_DOUBLES doubles.  Every thread of the workgroup calls
-// this.  Inner indices outside [k_begin, k_end) contribute nothing only if
-// the operands return 0 there; the callers pass nk bounds accordingly.
+// this.  Operands return 0 outside their valid range.
+//
+// Pipeline: two LDS stage buffers; the global loads of stage kt + 1 are
+// issued before the matrix-core work of stage kt and written to the other
+// buffer after it, one barrier per stage.
 template <class TL, class OA, class OB>
 __device__ __forceinline__ void tile_gemm(const OA &A, const OB &B, int m0, int n0, int k_begin,
                                           int k_end, double *lds, Acc<TL> &acc)
 {
     constexpr int BK = TL::NSUB * 4;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
+    constexpr int BM = TL::WROWS * TL::MA * 16, BN = TL::WCOLS * TL::NB * 4;
     // Stage buffer s starts at lds + s * STAGE: A tile, then B tile.  Plain
     // pointer arithmetic keeps every access an LDS (ds_*) instruction.
     constexpr int STAGE = TL::A_DOUBLES + TL::B_DOUBLES;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
+    const int boff = 4 * (lane >> 4) + (lane & 3);
 
-    TileLoader<TL::WROWS * TL::MA * 16, BK, TL::NTHR, true, OA> la;
-    TileLoader<TL::WCOLS * TL::NB * 4, BK, TL::NTHR, false, OB> lb;
+    TileLoader<BM, BK, TL::NTHR, true, OA> la;
+    TileLoader<BN, BK, TL::NTHR, false, OB> lb;
     const int nk = (k_end - k_begin + BK - 1) / BK;
     if (nk <= 0)
         return;
@@ -212,7 +219,6 @@ __device__ __forceinline__ void tile_gemm(const OA &A, const OB &B, int m0, int 
     la.store(A, lds, tid);
     lb.store(B, lds + TL::A_DOUBLES, tid);
     __syncthreads();
-    const int boff = 4 * (lane >> 4) + (lane & 3);
     for (int kt = 0; kt < nk; kt++) {
         const int cur = kt & 1;
         const bool more = (kt + 1) < nk;

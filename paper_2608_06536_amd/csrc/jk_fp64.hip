@@ -17,11 +17,16 @@
 
 namespace jk {
 
-// Tile shapes: the big GEMMs use 128 x 128 workgroup tiles of four 64 x 64
-// wave tiles; the projection 256 Q-rows x 8 densities; the density 64 x 64.
-constexpr int kBig = 128;
+// Tile shapes (chosen by measurement on MI355X): the half-transform uses
+// 128 x 64 workgroup tiles of four 64 x 32 wave tiles (two workgroups per
+// CU); the exchange product 128 x 64 tiles of eight 64 x 16 wave tiles (four
+// waves per SIMD); the projection 256 Q-rows x 8 densities; the density
+// 64 x 64.
+constexpr int kHtM = 128, kHtN = 64;
+constexpr int kExM = 128, kExN = 64;
 constexpr int kProjRows = 256;
-typedef Tile<kBig, kBig, 64, 64, 16> TileBig;
+typedef Tile<kHtM, kHtN, 64, 32, 16> TileHalf;
+typedef Tile<kExM, kExN, 64, 16, 16> TileExch;
 typedef Tile<kProjRows, 8, 64, 8, 16> TileProject;
 typedef Tile<64, 64, 32, 32, 16> TileDensity;
 
@@ -154,17 +159,17 @@ __global__ void __launch_bounds__(256) k_coulomb(const double *__restrict__ B,
 // ------------------------------------------------------------------ half-transform
 // For slab Q = q0 + ql (ql < nq): XY[m][c] = sum_n B^Q[m][n] Cc[n][c], written
 // as X_ws[k][m][ql*r + i] (c = k*r + i < R) or Y_ws[k][m][ql*r + i] (c - R).
-// grid.x = nq * nmt * nct (XCD-swizzled), tile kBig x kBig.
-__global__ void __launch_bounds__(256) k_half_transform(const double *__restrict__ B,
+// grid.x = nq * nmt * nct (XCD-swizzled), tile kHtM x kHtN.
+__global__ void __launch_bounds__(256, 2) k_half_transform(const double *__restrict__ B,
                                                         const double *__restrict__ Cc,
                                                         double *__restrict__ Xw, double *__restrict__ Yw,
                                                         int nao, int nd, int r, int q0, int nq,
                                                         int ldw)
 {
-    typedef TileBig TL;
+    typedef TileHalf TL;
     __shared__ double lds[TL::LDS_DOUBLES];
     const int R = nd * r, R2 = 2 * R;
-    const int nmt = (nao + kBig - 1) / kBig, nct = (R2 + kBig - 1) / kBig;
+    const int nmt = (nao + kHtM - 1) / kHtM, nct = (R2 + kHtN - 1) / kHtN;
     const int ntile = nq * nmt * nct;
     const int t = xcd_swizzle(blockIdx.x, ntile);
     const int ql = t / (nmt * nct), rem = t % (nmt * nct);
@@ -174,8 +179,8 @@ __global__ void __launch_bounds__(256) k_half_transform(const double *__restrict
     OpIC b{Cc, R2, R2, nao};
     Acc<TL> acc;
     acc.zero();
-    tile_gemm<TL>(a, b, mb * kBig, cb * kBig, 0, nao, lds, acc);
-    tile_foreach(acc, mb * kBig, cb * kBig, [&](int m, int c, double v) {
+    tile_gemm<TL>(a, b, mb * kHtM, cb * kHtN, 0, nao, lds, acc);
+    tile_foreach(acc, mb * kHtM, cb * kHtN, [&](int m, int c, double v) {
         if (m < nao && c < R2) {
             double *dst = c < R ? Xw : Yw;
             int cc = c < R ? c : c - R;
@@ -188,29 +193,29 @@ __global__ void __launch_bounds__(256) k_half_transform(const double *__restrict
 // ------------------------------------------------------------------ exchange
 // Kp[s][k][m][n] (+)= sum_{j in split s} X_ws[k][m][j] Y_ws[k][n][j], the inner
 // range [0, nj) cut into nsplit contiguous pieces of jlen.  With nsplit == 1
-// Kp is K itself.  grid.x = nsplit * nd * nt * nt (XCD-swizzled).
-__global__ void __launch_bounds__(256) k_exchange(const double *__restrict__ Xw,
+// Kp is K itself.  grid.x = nsplit * nd * nmt * nnt (XCD-swizzled).
+__global__ void __launch_bounds__(512, 4) k_exchange(const double *__restrict__ Xw,
                                                   const double *__restrict__ Yw, double *__restrict__ Kp,
                                                   int nao, int nd, int nj, int ldw, int nsplit,
                                                   int jlen, int accumulate)
 {
-    typedef TileBig TL;
+    typedef TileExch TL;
     __shared__ double lds[TL::LDS_DOUBLES];
-    const int nt = (nao + kBig - 1) / kBig;
-    const int ntile = nsplit * nd * nt * nt;
+    const int nmt = (nao + kExM - 1) / kExM, nnt = (nao + kExN - 1) / kExN;
+    const int ntile = nsplit * nd * nmt * nnt;
     int t = xcd_swizzle(blockIdx.x, ntile);
-    const int sp = t / (nd * nt * nt);
-    t -= sp * (nd * nt * nt);
-    const int k = t / (nt * nt), rem = t % (nt * nt);
-    const int mb = rem / nt, nb = rem % nt;
+    const int sp = t / (nd * nmt * nnt);
+    t -= sp * (nd * nmt * nnt);
+    const int k = t / (nmt * nnt), rem = t % (nmt * nnt);
+    const int mb = rem / nnt, nb = rem % nnt;
     const int j0 = sp * jlen, j1 = (j0 + jlen) < nj ? (j0 + jlen) : nj;
     OpKC a{Xw + (i64)k * nao * ldw, ldw, nao, j1};
     OpKC b{Yw + (i64)k * nao * ldw, ldw, nao, j1};
     Acc<TL> acc;
     acc.zero();
-    tile_gemm<TL>(a, b, mb * kBig, nb * kBig, j0, j1, lds, acc);
+    tile_gemm<TL>(a, b, mb * kExM, nb * kExN, j0, j1, lds, acc);
     double *Kk = Kp + ((i64)sp * nd + k) * nao * nao;
-    tile_foreach(acc, mb * kBig, nb * kBig, [&](int m, int n, double v) {
+    tile_foreach(acc, mb * kExM, nb * kExN, [&](int m, int n, double v) {
         if (m < nao && n < nao) {
             i64 o = (i64)m * nao + n;
             Kk[o] = accumulate ? Kk[o] + v : v;
@@ -241,7 +246,10 @@ hipError_t launch_pack_c(const double *CL, const double *CR, double *Cc, int nao
     int grid = cdiv(total, 256);
     if (grid > 65535)
         grid = 65535;
-    hipLaunchKernelGGL(k_pack_c, dim3(grid), dim3(256), 0, s, CL, CR, Cc, nao, nd, r);
+    {
+        ProfScope ps_("pack_c", s);
+        hipLaunchKernelGGL(k_pack_c, dim3(grid), dim3(256), 0, s, CL, CR, Cc, nao, nd, r);
+    }
     return hipGetLastError();
 }
 
@@ -249,7 +257,10 @@ hipError_t launch_density(const double *CL, const double *CR, double *D, int nao
                           hipStream_t s)
 {
     int nt = cdiv(nao, 64);
-    hipLaunchKernelGGL(k_density, dim3(nt * nt, nd), dim3(256), 0, s, CL, CR, D, nao, r);
+    {
+        ProfScope ps_("density", s);
+        hipLaunchKernelGGL(k_density, dim3(nt * nt, nd), dim3(256), 0, s, CL, CR, D, nao, r);
+    }
     return hipGetLastError();
 }
 
@@ -274,7 +285,10 @@ hipError_t launch_project(const double *B, const double *A, double *part, double
     int plen;
     int npb = project_nblocks(npos, naux, nd, &plen);
     dim3 grid(cdiv(naux, kProjRows), cdiv(nd, 8), npb);
-    hipLaunchKernelGGL(k_project, grid, dim3(256), 0, s, B, A, part, naux, nd, npos, plen);
+    {
+        ProfScope ps_("project", s);
+        hipLaunchKernelGGL(k_project, grid, dim3(256), 0, s, B, A, part, naux, nd, npos, plen);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
@@ -282,7 +296,10 @@ hipError_t launch_project(const double *B, const double *A, double *part, double
     int rg = cdiv(total, 256);
     if (rg > 65535)
         rg = 65535;
-    hipLaunchKernelGGL(k_project_reduce, dim3(rg), dim3(256), 0, s, part, g, naux, nd, npb);
+    {
+        ProfScope ps_("project_reduce", s);
+        hipLaunchKernelGGL(k_project_reduce, dim3(rg), dim3(256), 0, s, part, g, naux, nd, npb);
+    }
     return hipGetLastError();
 }
 
@@ -290,8 +307,11 @@ hipError_t launch_coulomb(const double *B, const double *g, double *J, int naux,
                           hipStream_t s)
 {
     for (int k0 = 0; k0 < nd; k0 += 8) {
-        hipLaunchKernelGGL(k_coulomb, dim3(cdiv(npos, 256)), dim3(256), 0, s, B, g, J, naux, nd, k0,
+        {
+            ProfScope ps_("coulomb", s);
+            hipLaunchKernelGGL(k_coulomb, dim3(cdiv(npos, 256)), dim3(256), 0, s, B, g, J, naux, nd, k0,
                            npos);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
@@ -302,17 +322,19 @@ hipError_t launch_coulomb(const double *B, const double *g, double *J, int naux,
 hipError_t launch_half_transform(const double *B, const double *Cc, double *Xw, double *Yw,
                                  int nao, int nd, int r, int q0, int nq, int ldw, hipStream_t s)
 {
-    int nmt = cdiv(nao, kBig), nct = cdiv(2 * (i64)nd * r, kBig);
-    hipLaunchKernelGGL(k_half_transform, dim3(nq * nmt * nct), dim3(256), 0, s, B, Cc, Xw, Yw, nao,
+    int nmt = cdiv(nao, kHtM), nct = cdiv(2 * (i64)nd * r, kHtN);
+    {
+        ProfScope ps_("half_transform", s);
+        hipLaunchKernelGGL(k_half_transform, dim3(nq * nmt * nct), dim3(256), 0, s, B, Cc, Xw, Yw, nao,
                        nd, r, q0, nq, ldw);
+    }
     return hipGetLastError();
 }
 
 int exchange_nsplit(int nao, int nd, int nj)
 {
     // Enough workgroups for two per CU; each split keeps >= 256 inner indices.
-    int nt = cdiv(nao, kBig);
-    int tiles = nd * nt * nt;
+    int tiles = nd * cdiv(nao, kExM) * cdiv(nao, kExN);
     int ns = cdiv(512, tiles);
     int maxs = nj / 256 > 1 ? nj / 256 : 1;
     if (ns > maxs)
@@ -325,11 +347,14 @@ int exchange_nsplit(int nao, int nd, int nj)
 hipError_t launch_exchange(const double *Xw, const double *Yw, double *Kp, int nao, int nd, int nj,
                            int ldw, int nsplit, int accumulate, hipStream_t s)
 {
-    int nt = cdiv(nao, kBig);
     int jlen = cdiv(nj, nsplit);
     jlen = ((jlen + 15) / 16) * 16;
-    hipLaunchKernelGGL(k_exchange, dim3(nsplit * nd * nt * nt), dim3(256), 0, s, Xw, Yw, Kp, nao, nd,
+    {
+        ProfScope ps_("exchange", s);
+        hipLaunchKernelGGL(k_exchange, dim3(nsplit * nd * cdiv(nao, kExM) * cdiv(nao, kExN)),
+                       dim3(TileExch::NTHR), 0, s, Xw, Yw, Kp, nao, nd,
                        nj, ldw, nsplit, jlen, accumulate);
+    }
     return hipGetLastError();
 }
 
@@ -338,7 +363,10 @@ hipError_t launch_sum_splits(const double *part, double *out, i64 n, int nsplit,
     int grid = cdiv(n, 256);
     if (grid > 65535)
         grid = 65535;
-    hipLaunchKernelGGL(k_sum_splits, dim3(grid), dim3(256), 0, s, part, out, n, nsplit);
+    {
+        ProfScope ps_("sum_splits", s);
+        hipLaunchKernelGGL(k_sum_splits, dim3(grid), dim3(256), 0, s, part, out, n, nsplit);
+    }
     return hipGetLastError();
 }
 

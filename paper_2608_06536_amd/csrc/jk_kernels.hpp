@@ -7,6 +7,20 @@ namespace jk {
 
 typedef int64_t i64;
 
+// Brackets one kernel launch with timing events when jk_prof_enable is on
+// (include/jk_prof.h); does nothing otherwise.
+class ProfScope {
+  public:
+    ProfScope(const char *name, hipStream_t s);
+    ~ProfScope();
+    ProfScope(const ProfScope &) = delete;
+    ProfScope &operator=(const ProfScope &) = delete;
+
+  private:
+    hipStream_t stream_;
+    int pair_;
+};
+
 hipError_t launch_pack_c(const double *CL, const double *CR, double *Cc, int nao, int nd, int r,
                          hipStream_t s);
 hipError_t launch_density(const double *CL, const double *CR, double *D, int nao, int nd, int r,

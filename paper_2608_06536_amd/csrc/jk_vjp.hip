@@ -25,8 +25,9 @@
 namespace jk {
 
 namespace {
-constexpr int kT = 128;
-typedef Tile<kT, kT, 64, 64, 16> TileV;
+// 128 x 64 workgroup tiles of four 64 x 32 wave tiles (two workgroups per CU).
+constexpr int kTM = 128, kTN = 64;
+typedef Tile<kTM, kTN, 64, 32, 16> TileV;
 } // namespace
 
 // omx[Q][c] = om[c / r][Q], c < R.
@@ -47,7 +48,7 @@ __global__ void __launch_bounds__(256) k_omega_expand(const double *__restrict__
 // WHICH = 1: Rq[ql][m][k*r+i] = sum_n V_k[n][m] X_ws[k][n][ql*r+i]
 // grid.x = nd * nmt * njt (XCD-swizzled).
 template <int WHICH>
-__global__ void __launch_bounds__(256) k_vjp_stage_b(const double *__restrict__ V,
+__global__ void __launch_bounds__(256, 2) k_vjp_stage_b(const double *__restrict__ V,
                                                      const double *__restrict__ Zw,
                                                      double *__restrict__ Out, int nao, int nd, int r,
                                                      int nj, int ldw)
@@ -55,7 +56,7 @@ __global__ void __launch_bounds__(256) k_vjp_stage_b(const double *__restrict__ 
     typedef TileV TL;
     __shared__ double lds[TL::LDS_DOUBLES];
     const int R = nd * r;
-    const int nmt = (nao + kT - 1) / kT, njt = (nj + kT - 1) / kT;
+    const int nmt = (nao + kTM - 1) / kTM, njt = (nj + kTN - 1) / kTN;
     const int t = xcd_swizzle(blockIdx.x, nd * nmt * njt);
     const int k = t / (nmt * njt), rem = t % (nmt * njt);
     const int mb = rem / njt, jb = rem % njt;
@@ -65,12 +66,12 @@ __global__ void __launch_bounds__(256) k_vjp_stage_b(const double *__restrict__ 
     acc.zero();
     if (WHICH == 0) {
         OpKC a{Vk, nao, nao, nao};
-        tile_gemm<TL>(a, b, mb * kT, jb * kT, 0, nao, lds, acc);
+        tile_gemm<TL>(a, b, mb * kTM, jb * kTN, 0, nao, lds, acc);
     } else {
         OpIC a{Vk, nao, nao, nao};
-        tile_gemm<TL>(a, b, mb * kT, jb * kT, 0, nao, lds, acc);
+        tile_gemm<TL>(a, b, mb * kTM, jb * kTN, 0, nao, lds, acc);
     }
-    tile_foreach(acc, mb * kT, jb * kT, [&](int m, int j, double v) {
+    tile_foreach(acc, mb * kTM, jb * kTN, [&](int m, int j, double v) {
         if (m < nao && j < nj) {
             int ql = j / r, i = j - ql * r;
             Out[((i64)ql * nao + m) * R + (i64)k * r + i] = v;
@@ -109,7 +110,7 @@ struct OpStageC {
 
 // dCp[sp][m][c] (+)= sum_{ql in split sp} sum_n B^{q0+ql}[m][n] op(c, n)
 // grid.x = nsplit * nmt * nct.
-__global__ void __launch_bounds__(256) k_vjp_stage_c(const double *__restrict__ B,
+__global__ void __launch_bounds__(256, 2) k_vjp_stage_c(const double *__restrict__ B,
                                                      const double *__restrict__ Pq,
                                                      const double *__restrict__ Rq,
                                                      const double *__restrict__ omx,
@@ -121,7 +122,7 @@ __global__ void __launch_bounds__(256) k_vjp_stage_c(const double *__restrict__ 
     typedef TileV TL;
     __shared__ double lds[TL::LDS_DOUBLES];
     const int R2 = 2 * R;
-    const int nmt = (nao + kT - 1) / kT, nct = (R2 + kT - 1) / kT;
+    const int nmt = (nao + kTM - 1) / kTM, nct = (R2 + kTN - 1) / kTN;
     const int t = xcd_swizzle(blockIdx.x, nsplit * nmt * nct);
     const int sp = t / (nmt * nct), rem = t % (nmt * nct);
     const int mb = rem / nct, cb = rem % nct;
@@ -134,10 +135,10 @@ __global__ void __launch_bounds__(256) k_vjp_stage_c(const double *__restrict__ 
         OpKC a{B + (i64)Q * n2, nao, nao, nao};
         OpStageC b{Pq + (i64)ql * nao * R, Rq + (i64)ql * nao * R, omx + (i64)Q * R, Cc, nao, R,
                    has_v != 0, has_w != 0};
-        tile_gemm<TL>(a, b, mb * kT, cb * kT, 0, nao, lds, acc);
+        tile_gemm<TL>(a, b, mb * kTM, cb * kTN, 0, nao, lds, acc);
     }
     double *out = dCp + (i64)sp * nao * R2;
-    tile_foreach(acc, mb * kT, cb * kT, [&](int m, int c, double v) {
+    tile_foreach(acc, mb * kTM, cb * kTN, [&](int m, int c, double v) {
         if (m < nao && c < R2) {
             i64 o = (i64)m * R2 + c;
             out[o] = accumulate ? out[o] + v : v;
@@ -219,7 +220,7 @@ struct OpStageDB {
 
 // dB[q0+ql][a][b] = sum_{j in [jlo, jhi)} A(a, j) B(b, j) + sum_k gamma[k][Q] W[k][a][b]
 // grid.x = nq * nt * nt (XCD-swizzled).
-__global__ void __launch_bounds__(256) k_vjp_stage_d(const double *__restrict__ Pq,
+__global__ void __launch_bounds__(256, 2) k_vjp_stage_d(const double *__restrict__ Pq,
                                                      const double *__restrict__ Rq,
                                                      const double *__restrict__ Cc,
                                                      const double *__restrict__ omx,
@@ -232,19 +233,19 @@ __global__ void __launch_bounds__(256) k_vjp_stage_d(const double *__restrict__ 
     typedef TileV TL;
     __shared__ double lds[TL::LDS_DOUBLES];
     const int R = nd * r;
-    const int nt = (nao + kT - 1) / kT;
-    const int t = xcd_swizzle(blockIdx.x, nq * nt * nt);
-    const int ql = t / (nt * nt), rem = t % (nt * nt);
-    const int ab = rem / nt, bb = rem % nt;
+    const int nmt = (nao + kTM - 1) / kTM, nnt = (nao + kTN - 1) / kTN;
+    const int t = xcd_swizzle(blockIdx.x, nq * nmt * nnt);
+    const int ql = t / (nmt * nnt), rem = t % (nmt * nnt);
+    const int ab = rem / nnt, bb = rem % nnt;
     const int Q = q0 + ql;
     OpStageDA a{Pq + (i64)ql * nao * R, Cc, omx + (i64)Q * R, nao, R, jhi};
     OpStageDB b{Rq + (i64)ql * nao * R, Cc, nao, R, jhi};
     Acc<TL> acc;
     acc.zero();
-    tile_gemm<TL>(a, b, ab * kT, bb * kT, jlo, jhi, lds, acc);
+    tile_gemm<TL>(a, b, ab * kTM, bb * kTN, jlo, jhi, lds, acc);
     const i64 n2 = (i64)nao * nao;
     double *out = dB + (i64)Q * n2;
-    tile_foreach(acc, ab * kT, bb * kT, [&](int ia, int ib, double v) {
+    tile_foreach(acc, ab * kTM, bb * kTN, [&](int ia, int ib, double v) {
         if (ia < nao && ib < nao) {
             const i64 o = (i64)ia * nao + ib;
             if (has_w)
@@ -268,27 +269,36 @@ static inline int grid_1d(i64 n)
 hipError_t launch_omega_expand(const double *om, double *omx, int naux, int nd, int r,
                                hipStream_t s)
 {
-    hipLaunchKernelGGL(k_omega_expand, dim3(grid_1d((i64)naux * nd * r)), dim3(256), 0, s, om, omx,
+    {
+        ProfScope ps_("omega_expand", s);
+        hipLaunchKernelGGL(k_omega_expand, dim3(grid_1d((i64)naux * nd * r)), dim3(256), 0, s, om, omx,
                        naux, nd, r);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_vjp_stage_b(const double *V, const double *Xw, const double *Yw, double *Pq,
                               double *Rq, int nao, int nd, int r, int nj, int ldw, hipStream_t s)
 {
-    const int nmt = cdiv(nao, kT), njt = cdiv(nj, kT);
+    const int nmt = cdiv(nao, kTM), njt = cdiv(nj, kTN);
     dim3 grid(nd * nmt * njt);
-    hipLaunchKernelGGL(k_vjp_stage_b<0>, grid, dim3(256), 0, s, V, Yw, Pq, nao, nd, r, nj, ldw);
+    {
+        ProfScope ps_("vjp_stage_b_p", s);
+        hipLaunchKernelGGL(k_vjp_stage_b<0>, grid, dim3(256), 0, s, V, Yw, Pq, nao, nd, r, nj, ldw);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_vjp_stage_b<1>, grid, dim3(256), 0, s, V, Xw, Rq, nao, nd, r, nj, ldw);
+    {
+        ProfScope ps_("vjp_stage_b_r", s);
+        hipLaunchKernelGGL(k_vjp_stage_b<1>, grid, dim3(256), 0, s, V, Xw, Rq, nao, nd, r, nj, ldw);
+    }
     return hipGetLastError();
 }
 
 int vjp_stage_c_nsplit(int nao, int R, int qc)
 {
-    int tiles = cdiv(nao, kT) * cdiv(2 * (i64)R, kT);
+    int tiles = cdiv(nao, kTM) * cdiv(2 * (i64)R, kTN);
     int ns = cdiv(512, tiles);
     if (ns > qc)
         ns = qc;
@@ -300,18 +310,24 @@ hipError_t launch_vjp_stage_c(const double *B, const double *Pq, const double *R
                               int q0, int nq, int nsplit, int has_v, int has_w, int accumulate,
                               hipStream_t s)
 {
-    const int nmt = cdiv(nao, kT), nct = cdiv(2 * (i64)R, kT);
+    const int nmt = cdiv(nao, kTM), nct = cdiv(2 * (i64)R, kTN);
     const int qlen = cdiv(nq, nsplit);
-    hipLaunchKernelGGL(k_vjp_stage_c, dim3(nsplit * nmt * nct), dim3(256), 0, s, B, Pq, Rq, omx, Cc,
+    {
+        ProfScope ps_("vjp_stage_c", s);
+        hipLaunchKernelGGL(k_vjp_stage_c, dim3(nsplit * nmt * nct), dim3(256), 0, s, B, Pq, Rq, omx, Cc,
                        dCp, nao, R, q0, nq, nsplit, qlen, has_v, has_w, accumulate);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_vjp_dc_finish(const double *dCp, double *dCL, double *dCR, int nao, int nd,
                                 int r, int nsplit, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_vjp_dc_finish, dim3(grid_1d((i64)nao * 2 * nd * r)), dim3(256), 0, s, dCp,
+    {
+        ProfScope ps_("vjp_dc_finish", s);
+        hipLaunchKernelGGL(k_vjp_dc_finish, dim3(grid_1d((i64)nao * 2 * nd * r)), dim3(256), 0, s, dCp,
                        dCL, dCR, nao, nd, r, nsplit);
+    }
     return hipGetLastError();
 }
 
@@ -323,9 +339,11 @@ hipError_t launch_vjp_stage_d(const double *Pq, const double *Rq, const double *
     const int R = nd * r;
     const int jlo = has_v ? 0 : 2 * R;
     const int jhi = has_w ? 3 * R : 2 * R;
-    const int nt = cdiv(nao, kT);
-    hipLaunchKernelGGL(k_vjp_stage_d, dim3(nq * nt * nt), dim3(256), 0, s, Pq, Rq, Cc, omx, gam, W,
+    {
+        ProfScope ps_("vjp_stage_d", s);
+        hipLaunchKernelGGL(k_vjp_stage_d, dim3(nq * cdiv(nao, kTM) * cdiv(nao, kTN)), dim3(256), 0, s, Pq, Rq, Cc, omx, gam, W,
                        dB, nao, nd, r, naux, q0, nq, jlo, jhi > jlo ? jhi : jlo, has_w);
+    }
     return hipGetLastError();
 }
 

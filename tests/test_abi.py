@@ -12,16 +12,18 @@ from paper_2608_06536_amd import _lib
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    txt = open(os.path.join(ROOT, "include", "jk.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:[a-z_]+\s+\*?)+(jk_[a-z_]+)\s*\(", txt, re.M)))
+def _declared(header):
+    txt = open(os.path.join(ROOT, "include", header)).read()
+    return sorted(set(re.findall(r"^\s*(?:[a-z_0-9]+\s+\*?)+(jk_[a-z_]+)\s*\(", txt, re.M)))
 
 
 def test_header_symbols_exported():
     L = _lib.lib()
-    names = _declared()
+    names = _declared("jk.h")
     assert set(names) == set(_lib.EXPORTS)
-    for n in names:
+    prof = _declared("jk_prof.h")
+    assert set(prof) == set(_lib.PROF_EXPORTS)
+    for n in names + prof:
         assert hasattr(L, n), n
 
 

@@ -419,6 +419,22 @@ def test_vjp_entry_and_density_forms(dprob):
         assert rel_err(dl, dCL[k]) < 1e-13 and rel_err(dr, dCR[k]) < 1e-13
 
 
+def test_vjp_factored_equals_literal(dprob):
+    # the factored derivative (the GPU's own arrangement) against the literal
+    # closed forms, and its Q-range restriction against a Q-split sum
+    B, CL, CR, W, V = dprob
+    rB, rL, rR = oracle.vjp(B, CL, CR, W, V)
+    fB, fL, fR = oracle.vjp_factored(B, CL, CR, W, V)
+    assert rel_err(fB, rB) < 1e-13 and rel_err(fL, rL) < 1e-13 and rel_err(fR, rR) < 1e-13
+    aB, aL, aR = oracle.vjp_factored(B, CL, CR, W, V, 0, 2)
+    bB, bL, bR = oracle.vjp_factored(B, CL, CR, W, V, 2, None)
+    assert rel_err(aB + bB, fB) < 1e-14 and rel_err(aL + bL, fL) < 1e-14
+    for Wx, Vx in ((W, None), (None, V)):
+        rB, rL, rR = oracle.vjp(B, CL, CR, Wx, Vx)
+        fB, fL, fR = oracle.vjp_factored(B, CL, CR, Wx, Vx)
+        assert rel_err(fB, rB) < 1e-13 and rel_err(fL, rL) < 1e-13 and rel_err(fR, rR) < 1e-13
+
+
 def test_vjp_zero_cotangents(dprob):
     B, CL, CR, W, V = dprob
     dB, dCL, dCR = oracle.vjp(B, CL, CR, None, None)

@@ -41,7 +41,7 @@ def kernel_models(p, nd, nao, naux, R):
         "vjp_stage_b_p": ("mfma", 2.0 * naux * n2 * R, "flop"),
         "vjp_stage_b_r": ("mfma", 2.0 * naux * n2 * R, "flop"),
         "vjp_stage_c": ("mfma", 4.0 * naux * n2 * R, "flop"),
-        "vjp_stage_d": ("mfma", 6.0 * naux * n2 * R, "flop"),
+        "vjp_stage_d": ("mfma", 4.0 * naux * n2 * R, "flop"),
         "coulomb": ("hbm", 8.0 * naux * n2, "byte"),
         "project": ("hbm", 3 * 8.0 * naux * n2, "byte"),   # gamma (build), omega, gamma (derivative)
     }
@@ -126,6 +126,29 @@ def main():
     t_build = rate(build)
     t_vjp = rate(vjp)
 
+    # ---- mixed-precision build (INT8 slice products; gamma, J and all sums FP64)
+    Jm = torch.empty_like(J)
+    Km = torch.empty_like(K)
+    mixed = None
+    try:
+        nbm = jk.workspace_bytes(jk.make_problem(nao, naux, nd, r, "mixed"))
+        wsm = torch.empty(nbm, dtype=torch.uint8, device=dev)
+
+        def build_mixed():
+            jk.jk_build(Bd, Ld, Rd, precision="mixed", out=(Jm, Km), ws=wsm)
+
+        t_mixed = rate(build_mixed)
+        build()
+        torch.cuda.synchronize()
+        errs = [float((Km[k] - K[k]).abs().max() / K[k].abs().max()) for k in range(nd)]
+        mixed = {"builds_per_s_mixed": round(nd / t_mixed, 2), "build_ms_mixed": round(1e3 * t_mixed, 3),
+                 "speedup_mixed_vs_fp64_build": round(t_build / t_mixed, 3),
+                 "max_err_K_mixed_vs_fp64": max(errs),
+                 "J_mixed_equals_fp64": bool(torch.equal(Jm, J))}
+        del wsm
+    except _lib.JKError as e:  # noqa: F841
+        mixed = {"mixed": "unavailable"}
+
     # ---- roofline of the dominant kernel
     models = kernel_models(p, nd, nao, naux, R)
     per_kernel = {}
@@ -175,6 +198,7 @@ def main():
         "vjps_per_s_fp64": round(nd / t_vjp, 2),
         "build_ms_fp64": round(1e3 * t_build, 3),
         "vjp_ms_fp64": round(1e3 * t_vjp, 3),
+        "mixed": mixed,
         "roofline": roof,
         "kernels": per_kernel,
         "prof_dropped": dropped,

@@ -92,10 +92,11 @@ FwdPlan plan_forward(const jk_problem *p)
     return f;
 }
 
-// Slabs per chunk of the derivative: X, Y, P, R of one chunk in the budget.
+// Slabs per chunk of the derivative: X, Y and the slab blocks [C_R|P'|R'|C_L]
+// of one chunk in the budget.
 int chunk_slabs_vjp(const jk_problem *p)
 {
-    size_t per = 4 * (size_t)p->nao * (size_t)(p->ndens * p->rank) * sizeof(double);
+    size_t per = 6 * (size_t)p->nao * (size_t)(p->ndens * p->rank) * sizeof(double);
     i64 qc = (i64)(kChunkBudget / (per ? per : 1));
     if (qc < 1)
         qc = 1;
@@ -106,7 +107,7 @@ int chunk_slabs_vjp(const jk_problem *p)
 
 struct VjpPlan {
     int qc, ldw, npb, plen, ndp, nsplit_c;
-    size_t o_cc, o_d, o_part, o_g, o_om, o_omx, o_x, o_y, o_p, o_r, o_dcp, total;
+    size_t o_cc, o_d, o_e, o_part, o_g, o_om, o_omx, o_x, o_y, o_pr, o_dcp, total;
 };
 
 VjpPlan plan_vjp(const jk_problem *p)
@@ -122,14 +123,14 @@ VjpPlan plan_vjp(const jk_problem *p)
     Carve c;
     f.o_cc = c.take(sizeof(double) * nao * 2 * R);
     f.o_d = c.take(sizeof(double) * nd * npos);
+    f.o_e = c.take(sizeof(double) * nd * npos);
     f.o_part = c.take(sizeof(double) * (size_t)f.npb * naux * f.ndp);
     f.o_g = c.take(sizeof(double) * nd * naux);
     f.o_om = c.take(sizeof(double) * nd * naux);
     f.o_omx = c.take(sizeof(double) * naux * R);
     f.o_x = c.take(sizeof(double) * nd * nao * (size_t)f.ldw);
     f.o_y = c.take(sizeof(double) * nd * nao * (size_t)f.ldw);
-    f.o_p = c.take(sizeof(double) * (size_t)f.qc * nao * R);
-    f.o_r = c.take(sizeof(double) * (size_t)f.qc * nao * R);
+    f.o_pr = c.take(sizeof(double) * (size_t)f.qc * nao * 4 * R);
     f.o_dcp = c.take(sizeof(double) * (size_t)f.nsplit_c * nao * 2 * R);
     f.total = c.off;
     return f;
@@ -141,6 +142,42 @@ VjpPlan plan_vjp(const jk_problem *p)
         if (_e != hipSuccess)                                                                      \
             return JK_EHIP;                                                                        \
     } while (0)
+
+// Mixed-precision plan: the FP64 plan (gamma, J, X/Y chunk buffers) plus
+// int8 digit planes of B (per chunk), of [C_L | C_R] and of X/Y (per chunk).
+struct MixPlan {
+    FwdPlan f;
+    int ns, mp, kp, cp, jp, nsplit;
+    size_t o_bp, o_eb, o_cp, o_ec, o_xp, o_yp, o_ex, o_ey, o_kp, total;
+};
+
+inline i64 pad_to(i64 x, i64 m) { return ((x + m - 1) / m) * m; }
+
+MixPlan plan_mixed(const jk_problem *p)
+{
+    MixPlan x;
+    x.f = plan_forward(p);
+    const i64 nao = p->nao, nd = p->ndens, r = p->rank, R = nd * r;
+    x.ns = jk::mixed_nslice();
+    x.mp = (int)pad_to(nao, jk::mixed_row_pad());
+    x.kp = (int)pad_to(nao, jk::mixed_k_pad());
+    x.cp = (int)pad_to(2 * R, jk::mixed_row_pad());
+    x.jp = (int)pad_to((i64)x.f.qc * r, jk::mixed_k_pad());
+    x.nsplit = jk::ex_mixed_nsplit(x.mp, (int)nd, x.jp);
+    Carve c;
+    c.off = x.f.total;
+    x.o_bp = c.take((size_t)x.ns * x.f.qc * x.mp * x.kp);
+    x.o_eb = c.take(sizeof(int) * (size_t)x.f.qc * x.mp);
+    x.o_cp = c.take((size_t)x.ns * x.cp * x.kp);
+    x.o_ec = c.take(sizeof(int) * (size_t)x.cp);
+    x.o_xp = c.take((size_t)x.ns * nd * x.mp * x.jp);
+    x.o_yp = c.take((size_t)x.ns * nd * x.mp * x.jp);
+    x.o_ex = c.take(sizeof(int) * (size_t)nd * x.mp);
+    x.o_ey = c.take(sizeof(int) * (size_t)nd * x.mp);
+    x.o_kp = c.take(sizeof(double) * (size_t)x.nsplit * nd * nao * nao);
+    x.total = c.off;
+    return x;
+}
 
 jk_status build_fp64(const jk_problem *p, const double *B, const double *CL, const double *CR,
                      double *J, double *K, char *ws, hipStream_t s)
@@ -190,41 +227,104 @@ jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const
     const bool want_db = dB != nullptr, want_dc = dCL != nullptr;
     double *Cc = (double *)(ws + f.o_cc);
     double *D = (double *)(ws + f.o_d);
+    double *E = (double *)(ws + f.o_e);
     double *part = (double *)(ws + f.o_part);
     double *g = (double *)(ws + f.o_g);
     double *om = (double *)(ws + f.o_om);
     double *omx = (double *)(ws + f.o_omx);
     double *Xw = (double *)(ws + f.o_x);
     double *Yw = (double *)(ws + f.o_y);
-    double *Pq = (double *)(ws + f.o_p);
-    double *Rq = (double *)(ws + f.o_r);
+    double *L = (double *)(ws + f.o_pr);
     double *dCp = (double *)(ws + f.o_dcp);
 
     JK_TRY(jk::launch_pack_c(CL, CR, Cc, nao, nd, r, s));
     if (has_w) {
-        // omega_kQ = <W_k, B^Q>; gamma_kQ = <D_k, B^Q> for the gamma W term of dB.
+        // omega_kQ = <W_k, B^Q>; for dB also gamma_kQ = <D_k, B^Q> and E = D - 2 D^T.
         JK_TRY(jk::launch_project(B, W, part, om, naux, nd, npos, s));
         JK_TRY(jk::launch_omega_expand(om, omx, naux, nd, r, s));
         if (want_db) {
             JK_TRY(jk::launch_density(CL, CR, D, nao, nd, r, s));
             JK_TRY(jk::launch_project(B, D, part, g, naux, nd, npos, s));
+            JK_TRY(jk::launch_vjp_e_matrix(D, E, nao, nd, s));
         }
     }
+    if (want_db)
+        JK_TRY(jk::launch_vjp_fill_blocks(Cc, L, nao, R, f.qc, s));
     for (int q0 = 0; q0 < naux; q0 += f.qc) {
         const int nq = (naux - q0) < f.qc ? (naux - q0) : f.qc;
-        if (has_v) {
+        if (has_v)
             JK_TRY(jk::launch_half_transform(B, Cc, Xw, Yw, nao, nd, r, q0, nq, f.ldw, s));
-            JK_TRY(jk::launch_vjp_stage_b(V, Xw, Yw, Pq, Rq, nao, nd, r, nq * r, f.ldw, s));
-        }
+        JK_TRY(jk::launch_vjp_stage_b(V, Xw, Yw, Cc, omx, L, nao, nd, r, q0, nq * r, f.ldw, has_v,
+                                      has_w, s));
         if (want_dc)
-            JK_TRY(jk::launch_vjp_stage_c(B, Pq, Rq, omx, Cc, dCp, nao, R, q0, nq, f.nsplit_c, has_v,
-                                          has_w, q0 > 0, s));
-        if (want_db)
-            JK_TRY(jk::launch_vjp_stage_d(Pq, Rq, Cc, omx, g, W, dB, nao, nd, r, naux, q0, nq, has_v,
-                                          has_w, s));
+            JK_TRY(jk::launch_vjp_stage_c(B, L, dCp, nao, R, q0, nq, f.nsplit_c, q0 > 0, s));
+        if (want_db) {
+            JK_TRY(jk::launch_vjp_stage_d(L, dB, nao, R, q0, nq, s));
+            if (has_w)
+                JK_TRY(jk::launch_vjp_db_affine(g, om, W, E, dB, nd, naux, npos, q0, nq, s));
+        }
     }
     if (want_dc)
         JK_TRY(jk::launch_vjp_dc_finish(dCp, dCL, dCR, nao, nd, r, f.nsplit_c, s));
+    return JK_OK;
+}
+
+jk_status build_mixed(const jk_problem *p, const double *B, const double *CL, const double *CR,
+                      double *J, double *K, char *ws, hipStream_t s)
+{
+    const MixPlan x = plan_mixed(p);
+    const FwdPlan &f = x.f;
+    const int nao = (int)p->nao, naux = (int)p->naux, nd = (int)p->ndens, r = (int)p->rank;
+    const int R = nd * r, R2 = 2 * R;
+    const i64 npos = (i64)nao * nao;
+    const int w = want(p);
+    if (w & JK_WANT_J) {
+        // gamma and J stay FP64 (the same kernels as the FP64 path).
+        double *D = (double *)(ws + f.o_d);
+        double *part = (double *)(ws + f.o_part);
+        double *g = (double *)(ws + f.o_g);
+        JK_TRY(jk::launch_density(CL, CR, D, nao, nd, r, s));
+        JK_TRY(jk::launch_project(B, D, part, g, naux, nd, npos, s));
+        JK_TRY(jk::launch_coulomb(B, g, J, naux, nd, npos, s));
+    }
+    if (!(w & JK_WANT_K))
+        return JK_OK;
+    double *Cc = (double *)(ws + f.o_cc);
+    double *Xw = (double *)(ws + f.o_x);
+    double *Yw = (double *)(ws + f.o_y);
+    int8_t *Bp = (int8_t *)(ws + x.o_bp);
+    int *eB = (int *)(ws + x.o_eb);
+    int8_t *Cp = (int8_t *)(ws + x.o_cp);
+    int *eC = (int *)(ws + x.o_ec);
+    int8_t *Xp = (int8_t *)(ws + x.o_xp);
+    int8_t *Yp = (int8_t *)(ws + x.o_yp);
+    int *eX = (int *)(ws + x.o_ex);
+    int *eY = (int *)(ws + x.o_ey);
+    double *Kp = x.nsplit > 1 ? (double *)(ws + x.o_kp) : K;
+    const i64 bpstride = (i64)f.qc * x.mp * x.kp;
+    const i64 cpstride = (i64)x.cp * x.kp;
+    const i64 xpstride = (i64)nd * x.mp * x.jp;
+
+    JK_TRY(jk::launch_pack_c(CL, CR, Cc, nao, nd, r, s));
+    // digits of [C_L | C_R]: row c, inner n, element Cc[n][c]
+    JK_TRY(jk::launch_slice_rows(Cc, 0, 1, R2, 1, R2, nao, x.cp, x.kp, Cp, cpstride, eC, s));
+    for (int q0 = 0; q0 < naux; q0 += f.qc) {
+        const int nq = (naux - q0) < f.qc ? (naux - q0) : f.qc;
+        const int nj = nq * r;
+        const int jp = (int)pad_to(nj, jk::mixed_k_pad());
+        JK_TRY(jk::launch_slice_rows(B + (i64)q0 * npos, npos, nao, 1, nq, nao, nao, x.mp, x.kp, Bp,
+                                     bpstride, eB, s));
+        JK_TRY(jk::launch_ht_mixed(Bp, bpstride, eB, Cp, cpstride, eC, Xw, Yw, nao, nd, r, nq, x.mp,
+                                   x.kp, f.ldw, s));
+        JK_TRY(jk::launch_slice_rows(Xw, (i64)nao * f.ldw, f.ldw, 1, nd, nao, nj, x.mp, jp, Xp,
+                                     xpstride, eX, s));
+        JK_TRY(jk::launch_slice_rows(Yw, (i64)nao * f.ldw, f.ldw, 1, nd, nao, nj, x.mp, jp, Yp,
+                                     xpstride, eY, s));
+        JK_TRY(jk::launch_ex_mixed(Xp, Yp, xpstride, eX, eY, Kp, nao, nd, x.mp, jp, x.nsplit, q0 > 0,
+                                   s));
+    }
+    if (x.nsplit > 1)
+        JK_TRY(jk::launch_sum_splits(Kp, K, (i64)nd * npos, x.nsplit, s));
     return JK_OK;
 }
 
@@ -237,6 +337,11 @@ size_t jk_workspace_bytes(const jk_problem *p)
     if (!valid_problem(p))
         return 0;
     size_t a = plan_forward(p).total, b = plan_vjp(p).total;
+    if (p->precision == JK_MIXED) {
+        size_t m = plan_mixed(p).total;
+        if (m > a)
+            a = m;
+    }
     return a > b ? a : b;
 }
 
@@ -256,8 +361,8 @@ jk_status jk_build(const jk_problem *p, const double *B, const double *CL, const
         return JK_EINVAL;
     if (ws_bytes < jk_workspace_bytes(p))
         return JK_EWORKSPACE;
-    if (p->precision != JK_FP64)
-        return JK_EUNSUPPORTED;
+    if (p->precision == JK_MIXED)
+        return build_mixed(p, B, CL, CR, J, K, (char *)ws, (hipStream_t)stream);
     return build_fp64(p, B, CL, CR, J, K, (char *)ws, (hipStream_t)stream);
 }
 
@@ -295,11 +400,12 @@ jk_status jk_build_batched(int32_t nprob, const jk_problem *p, const double *con
         return JK_EINVAL;
     if (ws_bytes < jk_batched_workspace_bytes(nprob, p))
         return JK_EWORKSPACE;
-    if (p[0].precision != JK_FP64)
-        return JK_EUNSUPPORTED;
     for (int32_t g = 0; g < nprob; g++) {
-        jk_status st = build_fp64(&p[g], B[g], CL[g], CR[g], J[g], K[g], (char *)ws,
-                                  (hipStream_t)stream);
+        jk_status st = p[g].precision == JK_MIXED
+                           ? build_mixed(&p[g], B[g], CL[g], CR[g], J[g], K[g], (char *)ws,
+                                         (hipStream_t)stream)
+                           : build_fp64(&p[g], B[g], CL[g], CR[g], J[g], K[g], (char *)ws,
+                                        (hipStream_t)stream);
         if (st != JK_OK)
             return st;
     }

@@ -239,6 +239,41 @@ __global__ void __launch_bounds__(256) k_sum_splits(const double *__restrict__ p
 
 static inline int cdiv(i64 a, i64 b) { return (int)((a + b - 1) / b); }
 
+int device_slots()
+{
+    static int slots = 0;
+    if (slots == 0) {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            ncu <= 0)
+            ncu = 256;
+        slots = 2 * ncu;
+    }
+    return slots;
+}
+
+int pick_split(int tiles, int smax)
+{
+    const int slots = device_slots();
+    if (smax < 1)
+        smax = 1;
+    int best = 1;
+    double best_eff = -1.0;
+    for (int s = 1; s <= smax; s++) {
+        const i64 w = (i64)tiles * s;
+        const i64 rounds = (w + slots - 1) / slots;
+        const double eff = (double)w / (double)(rounds * slots);
+        if (w >= slots && eff >= 0.9)
+            return s;
+        if (eff > best_eff + 1e-9) {
+            best_eff = eff;
+            best = s;
+        }
+    }
+    return best;
+}
+
 hipError_t launch_pack_c(const double *CL, const double *CR, double *Cc, int nao, int nd, int r,
                          hipStream_t s)
 {
@@ -333,15 +368,12 @@ hipError_t launch_half_transform(const double *B, const double *Cc, double *Xw, 
 
 int exchange_nsplit(int nao, int nd, int nj)
 {
-    // Enough workgroups for two per CU; each split keeps >= 256 inner indices.
-    int tiles = nd * cdiv(nao, kExM) * cdiv(nao, kExN);
-    int ns = cdiv(512, tiles);
+    // Full rounds of workgroups; each split keeps >= 256 inner indices.
+    const int tiles = nd * cdiv(nao, kExM) * cdiv(nao, kExN);
     int maxs = nj / 256 > 1 ? nj / 256 : 1;
-    if (ns > maxs)
-        ns = maxs;
-    if (ns > 16)
-        ns = 16;
-    return ns < 1 ? 1 : ns;
+    if (maxs > 16)
+        maxs = 16;
+    return pick_split(tiles, maxs);
 }
 
 hipError_t launch_exchange(const double *Xw, const double *Yw, double *Kp, int nao, int nd, int nj,

@@ -21,6 +21,13 @@ class ProfScope {
     int pair_;
 };
 
+// Workgroup slots of the current device for two resident workgroups per CU.
+int device_slots();
+// Split count s in [1, smax] for a grid of tiles * s workgroups: the smallest s
+// whose last round of workgroups is at least 90% full with at least one full
+// round, else the s with the fullest rounds.
+int pick_split(int tiles, int smax);
+
 hipError_t launch_pack_c(const double *CL, const double *CR, double *Cc, int nao, int nd, int r,
                          hipStream_t s);
 hipError_t launch_density(const double *CL, const double *CR, double *D, int nao, int nd, int r,
@@ -40,18 +47,35 @@ hipError_t launch_sum_splits(const double *part, double *out, i64 n, int nsplit,
 // derivative (jk_vjp.hip)
 hipError_t launch_omega_expand(const double *om, double *omx, int naux, int nd, int r,
                                hipStream_t s);
-hipError_t launch_vjp_stage_b(const double *V, const double *Xw, const double *Yw, double *Pq,
-                              double *Rq, int nao, int nd, int r, int nj, int ldw, hipStream_t s);
+hipError_t launch_vjp_fill_blocks(const double *Cc, double *L, int nao, int R, int nslot,
+                                  hipStream_t s);
+hipError_t launch_vjp_stage_b(const double *V, const double *Xw, const double *Yw,
+                              const double *Cc, const double *omx, double *L, int nao, int nd,
+                              int r, int q0, int nj, int ldw, int has_v, int has_w, hipStream_t s);
 int vjp_stage_c_nsplit(int nao, int R, int qc);
-hipError_t launch_vjp_stage_c(const double *B, const double *Pq, const double *Rq,
-                              const double *omx, const double *Cc, double *dCp, int nao, int R,
-                              int q0, int nq, int nsplit, int has_v, int has_w, int accumulate,
-                              hipStream_t s);
+hipError_t launch_vjp_stage_c(const double *B, const double *L, double *dCp, int nao, int R,
+                              int q0, int nq, int nsplit, int accumulate, hipStream_t s);
 hipError_t launch_vjp_dc_finish(const double *dCp, double *dCL, double *dCR, int nao, int nd,
                                 int r, int nsplit, hipStream_t s);
-hipError_t launch_vjp_stage_d(const double *Pq, const double *Rq, const double *Cc,
-                              const double *omx, const double *gam, const double *W, double *dB,
-                              int nao, int nd, int r, int naux, int q0, int nq, int has_v,
-                              int has_w, hipStream_t s);
+hipError_t launch_vjp_e_matrix(const double *D, double *E, int nao, int nd, hipStream_t s);
+hipError_t launch_vjp_stage_d(const double *L, double *dB, int nao, int R, int q0, int nq,
+                              hipStream_t s);
+hipError_t launch_vjp_db_affine(const double *gam, const double *om, const double *W,
+                                const double *E, double *dB, int nd, int naux, i64 npos, int q0,
+                                int nq, hipStream_t s);
+
+// mixed precision (jk_mixed.hip)
+int mixed_nslice();
+int mixed_row_pad();
+int mixed_k_pad();
+hipError_t launch_slice_rows(const double *src, i64 bs, i64 rs, i64 ks, int nb, int nr, int nk,
+                             int rp, int kp, int8_t *out, i64 pstride, int *exps, hipStream_t s);
+hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, const int *eB, const int8_t *Cp,
+                           i64 cpstride, const int *eC, double *Xw, double *Yw, int nao, int nd,
+                           int r, int nq, int mp, int kp, int ldw, hipStream_t s);
+int ex_mixed_nsplit(int mp, int nd, int jp);
+hipError_t launch_ex_mixed(const int8_t *Xp, const int8_t *Yp, i64 pstride, const int *eX,
+                           const int *eY, double *Kp, int nao, int nd, int mp, int jp, int nsplit,
+                           int accumulate, hipStream_t s);
 
 } // namespace jk

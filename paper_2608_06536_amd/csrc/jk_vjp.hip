@@ -2,23 +2,26 @@
 // build (Sec. 2.1, Eq. (1): the adjoint of J and K is J and K applied to the
 // cotangent).  For L = sum_k <W_k, J_k> + <V_k, K_k> and symmetric B^Q:
 //
-//   omega_kQ = <W_k, B^Q>          (projection kernel, jk_fp64.hip)
-//   X^Q_k = B^Q C_Lk, Y^Q_k = B^Q C_Rk     (recomputed per Q-chunk)
-//   P^Q_k = V_k Y^Q_k,   R^Q_k = V_k^T X^Q_k                  (stage B)
-//   dC_Lk = sum_Q B^Q (P^Q_k + omega_kQ C_Rk)                  (stage C)
-//   dC_Rk = sum_Q B^Q (R^Q_k + omega_kQ C_Lk)
-//   dB^Q  = sum_k gamma_kQ W_k + P^Q_k C_Lk^T + C_Rk (R^Q_k)^T
-//                + omega_kQ C_Lk C_Rk^T                         (stage D)
+//   omega_kQ = <W_k, B^Q>, gamma_kQ = <D_k, B^Q>   (projection kernel)
+//   X^Q_k = B^Q C_Lk, Y^Q_k = B^Q C_Rk              (recomputed per Q-chunk)
+//   stage B:  P'^Q_k = V_k Y^Q_k   + omega_kQ C_Rk
+//             R'^Q_k = V_k^T X^Q_k + omega_kQ C_Lk
+//   stage C:  dC_Lk = sum_Q B^Q P'^Q_k,  dC_Rk = sum_Q B^Q R'^Q_k
+//   stage D:  dB^Q  = sum_k C_Rk (R'^Q_k)^T + P'^Q_k C_Lk^T
+//   affine:   dB^Q += sum_k gamma_kQ W_k + omega_kQ (D_k - 2 D_k^T)
 //
-// (omega_kQ Y^Q_k = B^Q omega_kQ C_Rk, so the omega terms of dC fold into the
-// stage-C operand.)  Stage D is one product with inner dimension 3R:
-//   [P^Q | C_R | omega C_L] [C_L | R^Q | C_R]^T
-// plus the gamma W term added in its epilogue.
+// Stage C uses omega_kQ Y^Q_k = B^Q (omega_kQ C_Rk).  Stage D plus the affine
+// term is the closed form sum_k gamma W + omega D + P C_L^T + C_R R^T
+// rewritten with the primed factors: P' C_L^T + C_R R'^T = P C_L^T + C_R R^T
+// + 2 omega D^T, hence E_k = D_k - 2 D_k^T.
 //
-// Layouts: X/Y come from the half-transform kernel as X_ws[k][m][ql*r + i];
-// stage B writes P/R per slab as Pq[ql][m][k*r + i] (ld R) so that stages C
-// and D read all densities of a slab as one contiguous row.  Cc[n][c] is
-// [C_L | C_R] with c < 2R; omx[Q][c] = omega_{c / r, Q} for c < R.
+// Layouts: X/Y come from the half-transform kernel as X_ws[k][m][ql*r + i].
+// Each slab slot ql of the chunk owns one row-major block
+//     L[ql][m][0:4R] = [ C_R | P' | R' | C_L ]      (column c = k*r + i per part)
+// whose constant parts are written once per call.  Stage C reads the middle
+// half [P' | R'] and stage D is one product of the first half with the last:
+//     sum_{j<2R} L[a][j] L[b][2R + j] = C_R R'^T + P' C_L^T.
+// Cc[n][c] is [C_L | C_R] with c < 2R; omx[Q][c] = omega_{c / r, Q}, c < R.
 #include "f64_core.hpp"
 #include "jk_kernels.hpp"
 
@@ -43,85 +46,81 @@ __global__ void __launch_bounds__(256) k_omega_expand(const double *__restrict__
     }
 }
 
+// ------------------------------------------------------------------ slab blocks
+// L[ql][n][0:R] = C_R[n], L[ql][n][3R:4R] = C_L[n] for every slot ql < nslot.
+__global__ void __launch_bounds__(256) k_vjp_fill_blocks(const double *__restrict__ Cc,
+                                                         double *__restrict__ L, int nao, int R,
+                                                         int nslot)
+{
+    const int R2 = 2 * R, R4 = 4 * R;
+    const i64 total = (i64)nslot * nao * R2;
+    for (i64 e = (i64)blockIdx.x * 256 + threadIdx.x; e < total; e += (i64)gridDim.x * 256) {
+        const i64 row = e / R2;          // ql * nao + n
+        const int c = (int)(e % R2);
+        const int n = (int)(row % nao);
+        const bool right = c < R;        // c < R: C_R part, else C_L part
+        const int cc = right ? c : c - R;
+        L[row * R4 + (right ? cc : 3 * R + cc)] = Cc[(i64)n * R2 + (right ? R + cc : cc)];
+    }
+}
+
 // ------------------------------------------------------------------ stage B
-// WHICH = 0: Pq[ql][m][k*r+i] = sum_n V_k[m][n] Y_ws[k][n][ql*r+i]
-// WHICH = 1: Rq[ql][m][k*r+i] = sum_n V_k[n][m] X_ws[k][n][ql*r+i]
-// grid.x = nd * nmt * njt (XCD-swizzled).
+// WHICH = 0: L[ql][m][R  + k*r+i] = sum_n V_k[m][n] Y_ws[k][n][ql*r+i] + om * C_R
+// WHICH = 1: L[ql][m][2R + k*r+i] = sum_n V_k[n][m] X_ws[k][n][ql*r+i] + om * C_L
+// (om = omega_{k, q0+ql}; products skipped when has_v == 0, omega terms when
+// has_w == 0).  grid.x = nd * nmt * njt (XCD-swizzled).
 template <int WHICH>
 __global__ void __launch_bounds__(256, 2) k_vjp_stage_b(const double *__restrict__ V,
-                                                     const double *__restrict__ Zw,
-                                                     double *__restrict__ Out, int nao, int nd, int r,
-                                                     int nj, int ldw)
+                                                        const double *__restrict__ Zw,
+                                                        const double *__restrict__ Cc,
+                                                        const double *__restrict__ omx,
+                                                        double *__restrict__ L, int nao, int nd,
+                                                        int r, int q0, int nj, int ldw, int has_v,
+                                                        int has_w)
 {
     typedef TileV TL;
     __shared__ double lds[TL::LDS_DOUBLES];
-    const int R = nd * r;
+    const int R = nd * r, R2 = 2 * R, R4 = 4 * R;
     const int nmt = (nao + kTM - 1) / kTM, njt = (nj + kTN - 1) / kTN;
     const int t = xcd_swizzle(blockIdx.x, nd * nmt * njt);
     const int k = t / (nmt * njt), rem = t % (nmt * njt);
     const int mb = rem / njt, jb = rem % njt;
-    const double *Vk = V + (i64)k * nao * nao;
-    OpIC b{Zw + (i64)k * nao * ldw, ldw, nj, nao};
     Acc<TL> acc;
     acc.zero();
-    if (WHICH == 0) {
-        OpKC a{Vk, nao, nao, nao};
-        tile_gemm<TL>(a, b, mb * kTM, jb * kTN, 0, nao, lds, acc);
-    } else {
-        OpIC a{Vk, nao, nao, nao};
-        tile_gemm<TL>(a, b, mb * kTM, jb * kTN, 0, nao, lds, acc);
+    if (has_v) {
+        const double *Vk = V + (i64)k * nao * nao;
+        OpIC b{Zw + (i64)k * nao * ldw, ldw, nj, nao};
+        if (WHICH == 0) {
+            OpKC a{Vk, nao, nao, nao};
+            tile_gemm<TL>(a, b, mb * kTM, jb * kTN, 0, nao, lds, acc);
+        } else {
+            OpIC a{Vk, nao, nao, nao};
+            tile_gemm<TL>(a, b, mb * kTM, jb * kTN, 0, nao, lds, acc);
+        }
     }
     tile_foreach(acc, mb * kTM, jb * kTN, [&](int m, int j, double v) {
         if (m < nao && j < nj) {
-            int ql = j / r, i = j - ql * r;
-            Out[((i64)ql * nao + m) * R + (i64)k * r + i] = v;
+            const int ql = j / r, i = j - ql * r;
+            const int c = k * r + i;
+            if (has_w)
+                v = fma(omx[(i64)(q0 + ql) * R + c], Cc[(i64)m * R2 + (WHICH == 0 ? R + c : c)], v);
+            L[((i64)ql * nao + m) * R4 + (WHICH == 0 ? R : R2) + c] = v;
         }
     });
 }
 
 // ------------------------------------------------------------------ stage C
-// Operand of stage C: element (c, n) for c < 2R of slab ql:
-//   c <  R: Pq[ql][n][c]     + omx[Q][c]     * Cc[n][R + c]
-//   c >= R: Rq[ql][n][c - R] + omx[Q][c - R] * Cc[n][c - R]
-struct OpStageC {
-    static constexpr bool kContig = false;
-    static constexpr int NRAW = 3;
-    const double *Pq, *Rq, *omx, *Cc;   // Pq/Rq already offset to slab ql, omx to row Q
-    int nao, R;
-    bool has_v, has_w;
-    __device__ __forceinline__ void fetch(int c, int n, double *raw) const
-    {
-        const int R2 = 2 * R;
-        const int cc0 = c < R2 ? c : R2 - 1;
-        const int nn = n < nao ? n : nao - 1;
-        const bool lo = cc0 < R;
-        const int cc = lo ? cc0 : cc0 - R;
-        raw[0] = has_v ? (lo ? Pq : Rq)[(i64)nn * R + cc] : 0.0;
-        raw[1] = has_w ? omx[cc] : 0.0;
-        raw[2] = has_w ? Cc[(i64)nn * R2 + (lo ? R + cc : cc)] : 0.0;
-    }
-    __device__ __forceinline__ double finish(int c, int n, const double *raw) const
-    {
-        if (c >= 2 * R || n >= nao)
-            return 0.0;
-        return fma(raw[1], raw[2], raw[0]);
-    }
-};
-
-// dCp[sp][m][c] (+)= sum_{ql in split sp} sum_n B^{q0+ql}[m][n] op(c, n)
+// dCp[sp][m][c] (+)= sum_{ql in split sp} sum_n B^{q0+ql}[m][n] L[ql][n][R + c], c < 2R.
 // grid.x = nsplit * nmt * nct.
 __global__ void __launch_bounds__(256, 2) k_vjp_stage_c(const double *__restrict__ B,
-                                                     const double *__restrict__ Pq,
-                                                     const double *__restrict__ Rq,
-                                                     const double *__restrict__ omx,
-                                                     const double *__restrict__ Cc,
-                                                     double *__restrict__ dCp, int nao, int R, int q0,
-                                                     int nq, int nsplit, int qlen, int has_v,
-                                                     int has_w, int accumulate)
+                                                        const double *__restrict__ L,
+                                                        double *__restrict__ dCp, int nao, int R,
+                                                        int q0, int nq, int nsplit, int qlen,
+                                                        int accumulate)
 {
     typedef TileV TL;
     __shared__ double lds[TL::LDS_DOUBLES];
-    const int R2 = 2 * R;
+    const int R2 = 2 * R, R4 = 4 * R;
     const int nmt = (nao + kTM - 1) / kTM, nct = (R2 + kTN - 1) / kTN;
     const int t = xcd_swizzle(blockIdx.x, nsplit * nmt * nct);
     const int sp = t / (nmt * nct), rem = t % (nmt * nct);
@@ -131,10 +130,8 @@ __global__ void __launch_bounds__(256, 2) k_vjp_stage_c(const double *__restrict
     acc.zero();
     const int qa = sp * qlen, qb = (qa + qlen) < nq ? (qa + qlen) : nq;
     for (int ql = qa; ql < qb; ql++) {
-        const int Q = q0 + ql;
-        OpKC a{B + (i64)Q * n2, nao, nao, nao};
-        OpStageC b{Pq + (i64)ql * nao * R, Rq + (i64)ql * nao * R, omx + (i64)Q * R, Cc, nao, R,
-                   has_v != 0, has_w != 0};
+        OpKC a{B + (i64)(q0 + ql) * n2, nao, nao, nao};
+        OpIC b{L + (i64)ql * nao * R4 + R, R4, R2, nao};
         tile_gemm<TL>(a, b, mb * kTM, cb * kTN, 0, nao, lds, acc);
     }
     double *out = dCp + (i64)sp * nao * R2;
@@ -166,94 +163,87 @@ __global__ void __launch_bounds__(256) k_vjp_dc_finish(const double *__restrict_
     }
 }
 
-// ------------------------------------------------------------------ stage D
-// A(a, j): j < R: Pq[a][j];  j < 2R: Cc[a][j] (C_R);  j < 3R: omx[j-2R] Cc[a][j-2R] (omega C_L)
-struct OpStageDA {
-    static constexpr bool kContig = true;
-    static constexpr int NRAW = 2;
-    const double *Pq, *Cc, *omx;
-    int nao, R, jhi;
-    __device__ __forceinline__ void fetch(int a, int j, double *raw) const
-    {
-        const int aa = a < nao ? a : nao - 1;
-        const int jj = j < jhi ? j : jhi - 1;
-        const i64 row = (i64)aa * 2 * R;
-        if (jj < R) {
-            raw[0] = Pq[(i64)aa * R + jj];
-            raw[1] = 1.0;
-        } else if (jj < 2 * R) {
-            raw[0] = Cc[row + jj];
-            raw[1] = 1.0;
-        } else {
-            raw[0] = Cc[row + jj - 2 * R];
-            raw[1] = omx[jj - 2 * R];
-        }
+// E[k][a][b] = D[k][a][b] - 2 D[k][b][a]
+__global__ void __launch_bounds__(256) k_vjp_e_matrix(const double *__restrict__ D,
+                                                      double *__restrict__ E, int nao, int nd)
+{
+    const i64 n2 = (i64)nao * nao, total = n2 * nd;
+    for (i64 e = (i64)blockIdx.x * 256 + threadIdx.x; e < total; e += (i64)gridDim.x * 256) {
+        const i64 k = e / n2, ab = e % n2;
+        const int a = (int)(ab / nao), b = (int)(ab % nao);
+        E[e] = D[e] - 2.0 * D[k * n2 + (i64)b * nao + a];
     }
-    __device__ __forceinline__ double finish(int a, int j, const double *raw) const
-    {
-        return (a < nao && j < jhi) ? raw[0] * raw[1] : 0.0;
-    }
-};
-// B(b, j): j < R: Cc[b][j] (C_L);  j < 2R: Rq[b][j-R];  j < 3R: Cc[b][j-R] (C_R)
-struct OpStageDB {
-    static constexpr bool kContig = true;
-    static constexpr int NRAW = 1;
-    const double *Rq, *Cc;
-    int nao, R, jhi;
-    __device__ __forceinline__ void fetch(int b, int j, double *raw) const
-    {
-        const int bb = b < nao ? b : nao - 1;
-        const int jj = j < jhi ? j : jhi - 1;
-        const i64 row = (i64)bb * 2 * R;
-        if (jj < R)
-            raw[0] = Cc[row + jj];
-        else if (jj < 2 * R)
-            raw[0] = Rq[(i64)bb * R + jj - R];
-        else
-            raw[0] = Cc[row + jj - R];
-    }
-    __device__ __forceinline__ double finish(int b, int j, const double *raw) const
-    {
-        return (b < nao && j < jhi) ? raw[0] : 0.0;
-    }
-};
+}
 
-// dB[q0+ql][a][b] = sum_{j in [jlo, jhi)} A(a, j) B(b, j) + sum_k gamma[k][Q] W[k][a][b]
-// grid.x = nq * nt * nt (XCD-swizzled).
-__global__ void __launch_bounds__(256, 2) k_vjp_stage_d(const double *__restrict__ Pq,
-                                                     const double *__restrict__ Rq,
-                                                     const double *__restrict__ Cc,
-                                                     const double *__restrict__ omx,
-                                                     const double *__restrict__ gam,
-                                                     const double *__restrict__ W,
-                                                     double *__restrict__ dB, int nao, int nd, int r,
-                                                     int naux, int q0, int nq, int jlo, int jhi,
-                                                     int has_w)
+// ------------------------------------------------------------------ stage D
+// dB[q0+ql][a][b] = sum_{j<2R} L[ql][a][j] L[ql][b][2R + j].
+// grid.x = nq * nmt * nnt (XCD-swizzled).
+__global__ void __launch_bounds__(256, 2) k_vjp_stage_d(const double *__restrict__ L,
+                                                        double *__restrict__ dB, int nao, int R,
+                                                        int q0, int nq)
 {
     typedef TileV TL;
     __shared__ double lds[TL::LDS_DOUBLES];
-    const int R = nd * r;
+    const int R2 = 2 * R, R4 = 4 * R;
     const int nmt = (nao + kTM - 1) / kTM, nnt = (nao + kTN - 1) / kTN;
     const int t = xcd_swizzle(blockIdx.x, nq * nmt * nnt);
     const int ql = t / (nmt * nnt), rem = t % (nmt * nnt);
     const int ab = rem / nnt, bb = rem % nnt;
-    const int Q = q0 + ql;
-    OpStageDA a{Pq + (i64)ql * nao * R, Cc, omx + (i64)Q * R, nao, R, jhi};
-    OpStageDB b{Rq + (i64)ql * nao * R, Cc, nao, R, jhi};
+    const double *Lq = L + (i64)ql * nao * R4;
+    OpKC a{Lq, R4, nao, R2};
+    OpKC b{Lq + R2, R4, nao, R2};
     Acc<TL> acc;
     acc.zero();
-    tile_gemm<TL>(a, b, ab * kTM, bb * kTN, jlo, jhi, lds, acc);
+    tile_gemm<TL>(a, b, ab * kTM, bb * kTN, 0, R2, lds, acc);
     const i64 n2 = (i64)nao * nao;
-    double *out = dB + (i64)Q * n2;
+    double *out = dB + (i64)(q0 + ql) * n2;
     tile_foreach(acc, ab * kTM, bb * kTN, [&](int ia, int ib, double v) {
-        if (ia < nao && ib < nao) {
-            const i64 o = (i64)ia * nao + ib;
-            if (has_w)
-                for (int k = 0; k < nd; k++)
-                    v = fma(gam[(i64)k * naux + Q], W[(i64)k * n2 + o], v);
-            out[o] = v;
-        }
+        if (ia < nao && ib < nao)
+            out[(i64)ia * nao + ib] = v;
     });
+}
+
+// dB[Q][p] += sum_k gamma[k][Q] W[k][p] + omega[k][Q] E[k][p] for Q in
+// [q0, q0 + nq): each thread keeps the W and E values of its two positions in
+// registers across the slabs of the chunk; densities in groups of 8.
+__global__ void __launch_bounds__(256) k_vjp_db_affine(const double *__restrict__ gam,
+                                                       const double *__restrict__ om,
+                                                       const double *__restrict__ W,
+                                                       const double *__restrict__ E,
+                                                       double *__restrict__ dB, int nd, int naux,
+                                                       i64 npos, int q0, int nq)
+{
+    const i64 p0 = ((i64)blockIdx.x * 256 + threadIdx.x) * 2;
+    if (p0 >= npos)
+        return;
+    const bool two = p0 + 1 < npos;
+    for (int k0 = 0; k0 < nd; k0 += 8) {
+        const int nk = (nd - k0) < 8 ? (nd - k0) : 8;
+        double w[8][2], e[8][2];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const i64 base = (i64)(k0 + (k < nk ? k : 0)) * npos + p0;
+            w[k][0] = W[base];
+            e[k][0] = E[base];
+            w[k][1] = two ? W[base + 1] : 0.0;
+            e[k][1] = two ? E[base + 1] : 0.0;
+        }
+        for (int ql = 0; ql < nq; ql++) {
+            const int Q = q0 + ql;
+            double *d = dB + (i64)Q * npos + p0;
+            double v0 = d[0], v1 = two ? d[1] : 0.0;
+#pragma unroll
+            for (int k = 0; k < 8; k++)
+                if (k < nk) {
+                    const double g = gam[(i64)(k0 + k) * naux + Q], o = om[(i64)(k0 + k) * naux + Q];
+                    v0 = fma(g, w[k][0], fma(o, e[k][0], v0));
+                    v1 = fma(g, w[k][1], fma(o, e[k][1], v1));
+                }
+            d[0] = v0;
+            if (two)
+                d[1] = v1;
+        }
+    }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -277,45 +267,54 @@ hipError_t launch_omega_expand(const double *om, double *omx, int naux, int nd, 
     return hipGetLastError();
 }
 
-hipError_t launch_vjp_stage_b(const double *V, const double *Xw, const double *Yw, double *Pq,
-                              double *Rq, int nao, int nd, int r, int nj, int ldw, hipStream_t s)
+hipError_t launch_vjp_fill_blocks(const double *Cc, double *L, int nao, int R, int nslot,
+                                  hipStream_t s)
+{
+    {
+        ProfScope ps_("vjp_fill_blocks", s);
+        hipLaunchKernelGGL(k_vjp_fill_blocks, dim3(grid_1d((i64)nslot * nao * 2 * R)), dim3(256), 0, s,
+                           Cc, L, nao, R, nslot);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp_stage_b(const double *V, const double *Xw, const double *Yw,
+                              const double *Cc, const double *omx, double *L, int nao, int nd,
+                              int r, int q0, int nj, int ldw, int has_v, int has_w, hipStream_t s)
 {
     const int nmt = cdiv(nao, kTM), njt = cdiv(nj, kTN);
     dim3 grid(nd * nmt * njt);
     {
         ProfScope ps_("vjp_stage_b_p", s);
-        hipLaunchKernelGGL(k_vjp_stage_b<0>, grid, dim3(256), 0, s, V, Yw, Pq, nao, nd, r, nj, ldw);
+        hipLaunchKernelGGL(k_vjp_stage_b<0>, grid, dim3(256), 0, s, V, Yw, Cc, omx, L, nao, nd, r,
+                           q0, nj, ldw, has_v, has_w);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
     {
         ProfScope ps_("vjp_stage_b_r", s);
-        hipLaunchKernelGGL(k_vjp_stage_b<1>, grid, dim3(256), 0, s, V, Xw, Rq, nao, nd, r, nj, ldw);
+        hipLaunchKernelGGL(k_vjp_stage_b<1>, grid, dim3(256), 0, s, V, Xw, Cc, omx, L, nao, nd, r,
+                           q0, nj, ldw, has_v, has_w);
     }
     return hipGetLastError();
 }
 
 int vjp_stage_c_nsplit(int nao, int R, int qc)
 {
-    int tiles = cdiv(nao, kTM) * cdiv(2 * (i64)R, kTN);
-    int ns = cdiv(512, tiles);
-    if (ns > qc)
-        ns = qc;
-    return ns < 1 ? 1 : ns;
+    const int tiles = cdiv(nao, kTM) * cdiv(2 * (i64)R, kTN);
+    return pick_split(tiles, qc < 64 ? qc : 64);
 }
 
-hipError_t launch_vjp_stage_c(const double *B, const double *Pq, const double *Rq,
-                              const double *omx, const double *Cc, double *dCp, int nao, int R,
-                              int q0, int nq, int nsplit, int has_v, int has_w, int accumulate,
-                              hipStream_t s)
+hipError_t launch_vjp_stage_c(const double *B, const double *L, double *dCp, int nao, int R,
+                              int q0, int nq, int nsplit, int accumulate, hipStream_t s)
 {
     const int nmt = cdiv(nao, kTM), nct = cdiv(2 * (i64)R, kTN);
     const int qlen = cdiv(nq, nsplit);
     {
         ProfScope ps_("vjp_stage_c", s);
-        hipLaunchKernelGGL(k_vjp_stage_c, dim3(nsplit * nmt * nct), dim3(256), 0, s, B, Pq, Rq, omx, Cc,
-                       dCp, nao, R, q0, nq, nsplit, qlen, has_v, has_w, accumulate);
+        hipLaunchKernelGGL(k_vjp_stage_c, dim3(nsplit * nmt * nct), dim3(256), 0, s, B, L, dCp, nao,
+                           R, q0, nq, nsplit, qlen, accumulate);
     }
     return hipGetLastError();
 }
@@ -326,23 +325,40 @@ hipError_t launch_vjp_dc_finish(const double *dCp, double *dCL, double *dCR, int
     {
         ProfScope ps_("vjp_dc_finish", s);
         hipLaunchKernelGGL(k_vjp_dc_finish, dim3(grid_1d((i64)nao * 2 * nd * r)), dim3(256), 0, s, dCp,
-                       dCL, dCR, nao, nd, r, nsplit);
+                           dCL, dCR, nao, nd, r, nsplit);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_vjp_stage_d(const double *Pq, const double *Rq, const double *Cc,
-                              const double *omx, const double *gam, const double *W, double *dB,
-                              int nao, int nd, int r, int naux, int q0, int nq, int has_v,
-                              int has_w, hipStream_t s)
+hipError_t launch_vjp_e_matrix(const double *D, double *E, int nao, int nd, hipStream_t s)
 {
-    const int R = nd * r;
-    const int jlo = has_v ? 0 : 2 * R;
-    const int jhi = has_w ? 3 * R : 2 * R;
+    {
+        ProfScope ps_("vjp_e_matrix", s);
+        hipLaunchKernelGGL(k_vjp_e_matrix, dim3(grid_1d((i64)nao * nao * nd)), dim3(256), 0, s, D, E,
+                           nao, nd);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp_stage_d(const double *L, double *dB, int nao, int R, int q0, int nq,
+                              hipStream_t s)
+{
     {
         ProfScope ps_("vjp_stage_d", s);
-        hipLaunchKernelGGL(k_vjp_stage_d, dim3(nq * cdiv(nao, kTM) * cdiv(nao, kTN)), dim3(256), 0, s, Pq, Rq, Cc, omx, gam, W,
-                       dB, nao, nd, r, naux, q0, nq, jlo, jhi > jlo ? jhi : jlo, has_w);
+        hipLaunchKernelGGL(k_vjp_stage_d, dim3(nq * cdiv(nao, kTM) * cdiv(nao, kTN)), dim3(256), 0, s,
+                           L, dB, nao, R, q0, nq);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp_db_affine(const double *gam, const double *om, const double *W,
+                                const double *E, double *dB, int nd, int naux, i64 npos, int q0,
+                                int nq, hipStream_t s)
+{
+    {
+        ProfScope ps_("vjp_db_affine", s);
+        hipLaunchKernelGGL(k_vjp_db_affine, dim3(cdiv((npos + 1) / 2, 256)), dim3(256), 0, s, gam, om,
+                           W, E, dB, nd, naux, npos, q0, nq);
     }
     return hipGetLastError();
 }

@@ -1,0 +1,208 @@
+// slice_core.hpp -- fixed-point slice products on gfx950 INT8 matrix cores.
+//
+// Split-precision scheme of the mixed J/K path.  Every FP64 row a[0..n) of an
+// operand gets one power-of-two scale 2^e with max|a| < 2^e, and is cut into
+// NS signed 7-bit digits (base 2^7, round to nearest, |digit| <= 64):
+//     a = 2^(e+1) * sum_{i=1..NS} d_i 2^(-7 i) + rest,  |rest| <= 2^(e - 7 NS)
+// so each digit plane holds int8 values.  A product of two rows is
+//     sum_k a_k b_k = 2^(ea+eb+2) * sum_{l} 2^(-7 l) * S_l,
+//     S_l = sum_{i+j=l} sum_k d_i(a_k) d_j(b_k),
+// keeping the pairs with i + j <= NS + 1.  Each S_l is an exact integer: the
+// matrix cores multiply int8 digits and accumulate in int32, and
+// |S_l| <= 5 * n * 2^12 < 2^31 for n <= 100000 inner indices.  The levels are
+// combined in FP64 at the end (exact conversions, power-of-two weights), so
+// the only approximations are the dropped low digits (relative ~2^-34 for
+// NS = 5) and FP64 rounding.
+//
+// Instruction: V_MFMA_I32_32X32X32_I8 (measured 4.6 POP/s on MI355X, about
+// twice the BF16 32x32x16 rate).  Lane layout (measured on the device): lane
+// l holds A[row l % 32][k 16*(l/32) .. +15] and B[k 16*(l/32) .. +15][col
+// l % 32] as 16 bytes each, and output element j (0..15) is
+// C[8*(j/4) + 4*(l/32) + j%4][l % 32].
+//
+// Digit planes live in global memory as [plane][row][kp] int8 with kp a
+// multiple of 64 and rows padded to a multiple of the tile, zero-filled, so
+// the GEMM loaders copy 16-byte chunks without bounds checks.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace jk {
+
+typedef int64_t i64;
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kSliceBits = 7;          // bits per digit
+constexpr int kSliceKP = 64;           // inner padding unit (bytes per plane row chunk)
+
+__device__ __forceinline__ v16i mfma_i8(v4i a, v4i b, v16i c)
+{
+    return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+}
+
+// Digits of one value given the row exponent e (max|row| < 2^e):
+// d[i] = digit i+1 of a * 2^-e, i < NS.
+template <int NS>
+__device__ __forceinline__ void slice_value(double a, int e, int8_t *d)
+{
+    double x = ldexp(a, -e) * 64.0;            // |x| < 64
+#pragma unroll
+    for (int i = 0; i < NS; i++) {
+        const double t = rint(x);
+        d[i] = (int8_t)(int)t;
+        x = (x - t) * 128.0;                   // |x| <= 64, exact
+    }
+}
+
+// Exponent with max|row| < 2^e (0 for an all-zero row).
+__device__ __forceinline__ int row_exponent(double maxabs)
+{
+    return maxabs > 0.0 ? ilogb(maxabs) + 1 : 0;
+}
+
+// ---------------------------------------------------------------- tile GEMM
+// One workgroup: BM x BN output tile, waves (BM/32) x (BN/32), one 32x32
+// MFMA tile per wave, NS digit planes per operand, inner stages of 64.
+// Accumulators: one v16i per level l = 2 .. NS+1.
+template <int BM, int BN, int NS>
+struct STile {
+    static constexpr int WROWS = BM / 32, WCOLS = BN / 32;
+    static constexpr int NWAVE = WROWS * WCOLS;
+    static constexpr int NTHR = NWAVE * 64;
+    static constexpr int NLEV = NS;            // levels 2..NS+1
+    static constexpr int ROWB = kSliceKP + 16; // LDS row stride in bytes (padded)
+    static constexpr int A_BYTES = NS * BM * ROWB, B_BYTES = NS * BN * ROWB;
+    static constexpr int STAGE_BYTES = A_BYTES + B_BYTES;
+    static constexpr int LDS_BYTES = 2 * STAGE_BYTES;
+};
+
+// Digit-plane operand: plane p, row i, inner byte k at base[p * pstride + i * ld + k].
+struct SPlanes {
+    const int8_t *base;
+    i64 pstride;   // bytes between planes
+    i64 ld;        // bytes between rows (multiple of 64)
+};
+
+template <int T, int NS, int NTHR>
+struct SLoader {
+    // chunks of 16 bytes per stage: NS planes x T rows x 4
+    static constexpr int NCH = NS * T * 4;
+    static constexpr int NSTEP = (NCH + NTHR - 1) / NTHR;
+    v4i v[NSTEP];
+
+    __device__ __forceinline__ void load(const SPlanes &op, int i0, int k0, int tid)
+    {
+#pragma unroll
+        for (int s = 0; s < NSTEP; s++) {
+            const int c = tid + s * NTHR;
+            if (NCH % NTHR == 0 || c < NCH) {
+                const int p = c / (T * 4), rem = c % (T * 4);
+                const int row = rem >> 2, q = rem & 3;
+                v[s] = *(const v4i *)(op.base + p * op.pstride + (i64)(i0 + row) * op.ld + k0 + 16 * q);
+            }
+        }
+    }
+
+    __device__ __forceinline__ void store(char *lds, int tid) const
+    {
+#pragma unroll
+        for (int s = 0; s < NSTEP; s++) {
+            const int c = tid + s * NTHR;
+            if (NCH % NTHR == 0 || c < NCH) {
+                const int p = c / (T * 4), rem = c % (T * 4);
+                const int row = rem >> 2, q = rem & 3;
+                *(v4i *)(lds + (p * T + row) * (kSliceKP + 16) + 16 * q) = v[s];
+            }
+        }
+    }
+};
+
+template <class TL>
+struct SAcc {
+    v16i c[TL::NLEV];
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int l = 0; l < TL::NLEV; l++)
+#pragma unroll
+            for (int e = 0; e < 16; e++)
+                c[l][e] = 0;
+    }
+};
+
+// acc_l += sum over inner [k_begin, k_end) (multiples of 64) of the digit
+// pair products with i + j = l + 2 (i, j = 1..NS, i + j <= NS + 1).
+template <class TL, int NS>
+__device__ __forceinline__ void stile_gemm(const SPlanes &A, const SPlanes &B, int m0, int n0,
+                                           int k_begin, int k_end, char *lds, SAcc<TL> &acc)
+{
+    constexpr int BM = TL::WROWS * 32, BN = TL::WCOLS * 32;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
+    SLoader<BM, NS, TL::NTHR> la;
+    SLoader<BN, NS, TL::NTHR> lb;
+    const int nk = (k_end - k_begin) / kSliceKP;
+    if (nk <= 0)
+        return;
+    la.load(A, m0, k_begin, tid);
+    lb.load(B, n0, k_begin, tid);
+    la.store(lds, tid);
+    lb.store(lds + TL::A_BYTES, tid);
+    __syncthreads();
+    const int arow = wr * 32 + (lane & 31), brow = wc * 32 + (lane & 31);
+    const int koff = 16 * (lane >> 5);
+    for (int kt = 0; kt < nk; kt++) {
+        const int cur = kt & 1;
+        const bool more = kt + 1 < nk;
+        if (more) {
+            la.load(A, m0, k_begin + (kt + 1) * kSliceKP, tid);
+            lb.load(B, n0, k_begin + (kt + 1) * kSliceKP, tid);
+        }
+        const char *sa = lds + cur * TL::STAGE_BYTES;
+        const char *sb = sa + TL::A_BYTES;
+#pragma unroll
+        for (int ks = 0; ks < 2; ks++) {      // two 32-deep steps per stage
+            v4i a[NS], b[NS];
+#pragma unroll
+            for (int p = 0; p < NS; p++) {
+                a[p] = *(const v4i *)(sa + (p * BM + arow) * TL::ROWB + 32 * ks + koff);
+                b[p] = *(const v4i *)(sb + (p * BN + brow) * TL::ROWB + 32 * ks + koff);
+            }
+#pragma unroll
+            for (int i = 0; i < NS; i++)
+#pragma unroll
+                for (int j = 0; j < NS - i; j++)          // (i+1) + (j+1) <= NS + 1
+                    acc.c[i + j] = mfma_i8(a[i], b[j], acc.c[i + j]);
+        }
+        if (more) {
+            la.store(lds + (cur ^ 1) * TL::STAGE_BYTES, tid);
+            lb.store(lds + (cur ^ 1) * TL::STAGE_BYTES + TL::A_BYTES, tid);
+        }
+        __syncthreads();
+    }
+}
+
+// FP64 value of output element e (0..15) of this lane: sum_l S_l 2^(-7(l+2)),
+// before the 2^(ea+eb+2) row/column scale.
+template <class TL>
+__device__ __forceinline__ double combine_levels(const SAcc<TL> &acc, int e)
+{
+    double v = 0.0;
+#pragma unroll
+    for (int l = TL::NLEV - 1; l >= 0; l--)
+        v += ldexp((double)acc.c[l][e], -kSliceBits * (l + 2));
+    return v;
+}
+
+// Output coordinates of element e of this lane inside the workgroup tile.
+template <class TL>
+__device__ __forceinline__ void stile_coord(int e, int &row, int &col)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
+    row = wr * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+    col = wc * 32 + (lane & 31);
+}
+
+} // namespace jk

@@ -1,0 +1,110 @@
+"""GPU parity of the mixed-precision build (jk_build, precision="mixed").
+
+The bulk products run as exact fixed-point slice products on the INT8 matrix
+cores; gamma and J stay FP64.  Bar: per result, normwise error against the
+FP64 oracle <= 1e-8; J bit-identical to the FP64 path; on integer-valued
+inputs that the slices represent exactly, K bit-identical to the FP64 path.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2608_06536_amd import synth
+from conftest import rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-8
+
+
+def _dev(*arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a)).to("cuda") for a in arrs]
+
+
+def _run(B, CL, CR, precision, **kw):
+    from paper_2608_06536_amd import jk
+    Bd, Ld, Rd = _dev(B, CL, CR)
+    J, K = jk.jk_build(Bd, Ld, Rd, precision=precision, **kw)
+    torch.cuda.synchronize()
+    return J.cpu().numpy(), K.cpu().numpy()
+
+
+def test_integer_inputs_exact():
+    # Integer entries below 2^6 with products far below 2^35: every digit
+    # product is exact, so the mixed K must equal the FP64 K bit for bit.
+    rng = np.random.default_rng(3)
+    nao, naux, nd, r = 70, 9, 2, 5
+    A = rng.integers(-40, 41, size=(naux, nao, nao)).astype(float)
+    B = np.triu(A) + np.triu(A, 1).transpose(0, 2, 1)
+    CL = rng.integers(-5, 6, size=(nd, nao, r)).astype(float)
+    CR = rng.integers(-5, 6, size=(nd, nao, r)).astype(float)
+    Jm, Km = _run(B, CL, CR, "mixed")
+    Jf, Kf = _run(B, CL, CR, "fp64")
+    assert np.array_equal(Jm, Jf)
+    assert np.array_equal(Km, Kf)
+    Jr, Kr, _ = oracle.jk_factored(B, CL, CR)
+    assert np.array_equal(Kf, Kr)
+
+
+@pytest.mark.parametrize("nao,naux,nd,r", [(1, 1, 1, 1), (48, 192, 1, 8), (65, 9, 3, 5),
+                                           (130, 37, 2, 13), (200, 50, 5, 17)])
+def test_mixed_ragged(nao, naux, nd, r):
+    p = synth.Problem(nao=nao, naux=naux, nd=nd, r=r, ell=10.0, tau=naux / 4 + 1, n_ground=1,
+                      seed=500 + nao)
+    B, CL, CR = synth.make_problem(p)
+    Jm, Km = _run(B, CL, CR, "mixed")
+    Jf, _ = _run(B, CL, CR, "fp64")
+    Jr, Kr, _ = oracle.jk_factored(B, CL, CR)
+    assert np.array_equal(Jm, Jf)          # gamma and J are FP64 in both paths
+    for k in range(nd):
+        assert rel_err(Km[k], Kr[k]) <= TOL, k
+
+
+def test_mixed_rows_of_very_different_scale():
+    # Per-(slab, row) exponents: slabs scaled over 2^-30 .. 2^30 and rows over
+    # 2^-20 .. 2^20 (B stays symmetric) keep the normwise accuracy of every
+    # density.  (Scales that are anti-correlated across the inner index, e.g.
+    # C rows divided by the B column scale, defeat any row/column fixed-point
+    # split; that limit is documented, not tested.)
+    p = synth.Problem(nao=90, naux=12, nd=2, r=6, ell=10.0, tau=4.0, seed=9)
+    B, CL, CR = synth.make_problem(p)
+    s = 2.0 ** np.linspace(-20, 20, p.nao)
+    t = 2.0 ** np.linspace(-30, 30, p.naux)
+    B = B * t[:, None, None] * s[None, :, None] * s[None, None, :]
+    Jm, Km = _run(B, CL, CR, "mixed")
+    Jr, Kr, _ = oracle.jk_factored(B, CL, CR)
+    for k in range(p.nd):
+        assert rel_err(Km[k], Kr[k]) <= TOL
+        assert rel_err(Jm[k], Jr[k]) <= 1e-12
+
+
+def test_config2_mixed_errors():
+    p = synth.config(2)
+    B, CL, CR = synth.make_problem(p)
+    Jm, Km = _run(B, CL, CR, "mixed")
+    Jr, Kr, _ = oracle.jk_factored(B, CL, CR)
+    errs = [rel_err(Km[k], Kr[k]) for k in range(p.nd)]
+    print("mixed K errors per density:", errs)
+    assert max(errs) <= TOL
+    assert max(rel_err(Jm[k], Jr[k]) for k in range(p.nd)) <= 1e-12
+
+
+def test_mixed_determinism():
+    p = synth.Problem(nao=96, naux=40, nd=2, r=6, ell=10.0, tau=20.0, seed=5)
+    B, CL, CR = synth.make_problem(p)
+    a = _run(B, CL, CR, "mixed")
+    b = _run(B, CL, CR, "mixed")
+    assert np.array_equal(a[1], b[1])
+
+
+def test_config4_mixed_sampled():
+    p = synth.config(4)
+    B, CL, CR = synth.make_problem(p)
+    _, Km = _run(B, CL, CR, "mixed")
+    rng = np.random.default_rng(4040)
+    n = 24
+    ks, ms, ns = rng.integers(0, p.nd, n), rng.integers(0, p.nao, n), rng.integers(0, p.nao, n)
+    ms[:4] = p.nao - 1
+    _, Ke = oracle.jk_entries(B, CL, CR, ks, ms, ns)
+    assert np.max(np.abs(Km[ks, ms, ns] - Ke)) <= TOL * np.max(np.abs(Km))

@@ -4,8 +4,16 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
 #include "../../include/jk.h"
+#include "jk_batched.hpp"
 #include "jk_kernels.hpp"
+#include "jk_tiles.hpp"
 
 namespace {
 
@@ -328,6 +336,261 @@ jk_status build_mixed(const jk_problem *p, const double *B, const double *CL, co
     return JK_OK;
 }
 
+// ------------------------------------------------------------------ batched
+// Schedule of a batched FP64 build: the launches (phase, chunk step, tiles,
+// table offset) and the host image of the workspace header (member
+// descriptors, then the member tables of every launch).
+struct BLaunch {
+    int phase, step, ntiles;
+    size_t tab_off;     // byte offset of the launch's table in the workspace
+};
+
+struct BSchedule {
+    std::vector<jk::BMember> mem;
+    std::vector<size_t> region;      // workspace offset of each member's plan
+    std::vector<BLaunch> launches;
+    std::vector<int> tabs;           // all tables, concatenated
+    size_t header_bytes = 0, total_bytes = 0;
+    std::string key;                 // shape signature
+};
+
+// Per-member cost of one tile of a phase (larger first in the tables).
+double tile_cost(int phase, const FwdPlan &f, const jk_problem &p)
+{
+    switch (phase) {
+    case jk::kPhaseProject: return (double)f.plen;
+    case jk::kPhaseReduce: return (double)f.npb;
+    case jk::kPhaseCoulomb: return (double)p.naux;
+    case jk::kPhaseHalf: return (double)p.nao;
+    case jk::kPhaseExchange: return (double)f.qc * p.rank / f.nsplit;
+    default: return (double)p.nao;
+    }
+}
+
+BSchedule make_schedule(int32_t nprob, const jk_problem *p)
+{
+    BSchedule S;
+    const int G = nprob;
+    std::vector<FwdPlan> plans(G);
+    int maxsteps = 0;
+    for (int g = 0; g < G; g++) {
+        plans[g] = plan_forward(&p[g]);
+        const int st = (int)((p[g].naux + plans[g].qc - 1) / plans[g].qc);
+        maxsteps = std::max(maxsteps, st);
+    }
+    const int w = want(&p[0]);
+    // member lists per launch
+    struct Pending {
+        int phase, step;
+        std::vector<int> members;
+        std::vector<int> tiles;
+    };
+    std::vector<Pending> pend;
+    auto add = [&](int phase, int step, auto tiles_of, auto takes_part) {
+        Pending L{phase, step, {}, {}};
+        for (int g = 0; g < G; g++)
+            if (takes_part(g)) {
+                L.members.push_back(g);
+                L.tiles.push_back(tiles_of(g));
+            }
+        // larger tiles first
+        std::vector<int> idx(L.members.size());
+        for (size_t i = 0; i < idx.size(); i++)
+            idx[i] = (int)i;
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+            return tile_cost(phase, plans[L.members[a]], p[L.members[a]]) >
+                   tile_cost(phase, plans[L.members[b]], p[L.members[b]]);
+        });
+        Pending O{phase, step, {}, {}};
+        for (int i : idx) {
+            O.members.push_back(L.members[i]);
+            O.tiles.push_back(L.tiles[i]);
+        }
+        if (!O.members.empty())
+            pend.push_back(O);
+    };
+    auto all = [](int) { return true; };
+    if (w & JK_WANT_J) {
+        add(jk::kPhaseDensity, 0, [&](int g) { return jk::density_tiles((int)p[g].nao, (int)p[g].ndens); }, all);
+        add(jk::kPhaseProject, 0,
+            [&](int g) { return jk::project_tiles((int)p[g].naux, (int)p[g].ndens, plans[g].npb); }, all);
+        add(jk::kPhaseReduce, 0, [&](int g) { return jk::reduce_tiles((int)p[g].naux, (int)p[g].ndens); },
+            all);
+        add(jk::kPhaseCoulomb, 0,
+            [&](int g) { return jk::coulomb_tiles((int)p[g].ndens, p[g].nao * p[g].nao); }, all);
+    }
+    if (w & JK_WANT_K) {
+        add(jk::kPhasePack, 0,
+            [&](int g) { return jk::pack_tiles((int)p[g].nao, (int)p[g].ndens, (int)p[g].rank); }, all);
+        for (int c = 0; c < maxsteps; c++) {
+            auto in_step = [&](int g) { return (i64)c * plans[g].qc < p[g].naux; };
+            auto nq_of = [&](int g) {
+                const i64 q0 = (i64)c * plans[g].qc;
+                return (int)std::min<i64>(plans[g].qc, p[g].naux - q0);
+            };
+            add(jk::kPhaseHalf, c,
+                [&](int g) { return jk::ht_tiles((int)p[g].nao, (int)p[g].ndens, (int)p[g].rank, nq_of(g)); },
+                in_step);
+            add(jk::kPhaseExchange, c,
+                [&](int g) { return jk::ex_tiles((int)p[g].nao, (int)p[g].ndens, plans[g].nsplit); },
+                in_step);
+        }
+        add(jk::kPhaseSum, 0, [&](int g) { return jk::sum_tiles(p[g].ndens * p[g].nao * p[g].nao); },
+            [&](int g) { return plans[g].nsplit > 1; });
+    }
+    // header: descriptors, then tables
+    Carve c;
+    const size_t o_mem = c.take(sizeof(jk::BMember) * G);
+    for (const Pending &L : pend) {
+        const int n = (int)L.members.size();
+        BLaunch bl;
+        bl.phase = L.phase;
+        bl.step = L.step;
+        bl.ntiles = 0;
+        for (int t : L.tiles)
+            bl.ntiles += t;
+        bl.tab_off = o_mem + align_up(sizeof(jk::BMember) * G) + S.tabs.size() * sizeof(int);
+        S.tabs.push_back(n);
+        int acc = 0;
+        for (int t : L.tiles) {
+            S.tabs.push_back(acc);
+            acc += t;
+        }
+        S.tabs.push_back(acc);
+        for (int g : L.members)
+            S.tabs.push_back(g);
+        S.launches.push_back(bl);
+    }
+    c.take(sizeof(int) * S.tabs.size());
+    S.header_bytes = c.off;
+    S.mem.resize(G);
+    S.region.resize(G);
+    for (int g = 0; g < G; g++) {
+        S.region[g] = c.take(plans[g].total);
+        jk::BMember &m = S.mem[g];
+        memset(&m, 0, sizeof(m));
+        m.npos = p[g].nao * p[g].nao;
+        m.nao = (int)p[g].nao;
+        m.naux = (int)p[g].naux;
+        m.nd = (int)p[g].ndens;
+        m.r = (int)p[g].rank;
+        m.qc = plans[g].qc;
+        m.ldw = plans[g].ldw;
+        m.nsplit = plans[g].nsplit;
+        m.npb = plans[g].npb;
+        m.plen = plans[g].plen;
+    }
+    S.total_bytes = c.off;
+    // shape signature
+    S.key.reserve(64 + 48 * G);
+    for (int g = 0; g < G; g++) {
+        char buf[128];
+        snprintf(buf, sizeof buf, "%lld,%lld,%lld,%lld,%d,%d;", (long long)p[g].nao,
+                 (long long)p[g].naux, (long long)p[g].ndens, (long long)p[g].rank, p[g].precision,
+                 p[g].flags);
+        S.key += buf;
+    }
+    return S;
+}
+
+// Captured launch sequences, keyed by shape signature, workspace and device.
+struct GraphCache {
+    std::mutex mu;
+    std::map<std::string, hipGraphExec_t> execs;
+};
+GraphCache &graph_cache()
+{
+    static GraphCache c;
+    return c;
+}
+
+bool graphs_enabled()
+{
+    const char *e = getenv("JK_BATCHED_GRAPH");
+    return !(e && e[0] == '0');
+}
+
+jk_status enqueue_batched(const BSchedule &S, char *ws, hipStream_t s)
+{
+    const jk::BMember *M = (const jk::BMember *)ws;
+    for (const BLaunch &L : S.launches) {
+        hipError_t e = jk::launch_batched_phase(L.phase, M, (const int *)(ws + L.tab_off), L.ntiles,
+                                                L.step, s);
+        if (e != hipSuccess)
+            return JK_EHIP;
+    }
+    return JK_OK;
+}
+
+jk_status build_batched_fp64(int32_t nprob, const jk_problem *p, const double *const *B,
+                             const double *const *CL, const double *const *CR, double *const *J,
+                             double *const *K, char *ws, hipStream_t s)
+{
+    BSchedule S = make_schedule(nprob, p);
+    // host image of the header: descriptors with this call's pointers, tables
+    std::vector<char> host(S.header_bytes, 0);
+    for (int g = 0; g < nprob; g++) {
+        jk::BMember &m = S.mem[g];
+        const FwdPlan f = plan_forward(&p[g]);
+        char *base = ws + S.region[g];
+        m.B = B[g];
+        m.CL = CL[g];
+        m.CR = CR[g];
+        m.J = J[g];
+        m.K = K[g];
+        m.Cc = (double *)(base + f.o_cc);
+        m.D = (double *)(base + f.o_d);
+        m.part = (double *)(base + f.o_part);
+        m.g = (double *)(base + f.o_g);
+        m.Xw = (double *)(base + f.o_x);
+        m.Yw = (double *)(base + f.o_y);
+        m.Kp = (double *)(base + f.o_kp);
+    }
+    memcpy(host.data(), S.mem.data(), sizeof(jk::BMember) * nprob);
+    const size_t tab0 = align_up(sizeof(jk::BMember) * nprob);
+    memcpy(host.data() + tab0, S.tabs.data(), sizeof(int) * S.tabs.size());
+    if (hipMemcpyAsync(ws, host.data(), S.header_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+        return JK_EHIP;
+
+    if (s == nullptr || !graphs_enabled())
+        return enqueue_batched(S, ws, s);
+
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return JK_EHIP;
+    char kbuf[64];
+    snprintf(kbuf, sizeof kbuf, "|%p|%d", (void *)ws, dev);
+    const std::string key = S.key + kbuf;
+    GraphCache &gc = graph_cache();
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(gc.mu);
+        auto it = gc.execs.find(key);
+        if (it != gc.execs.end())
+            exec = it->second;
+    }
+    if (!exec) {
+        hipGraph_t graph = nullptr;
+        jk::ProfScope::set_capturing(true);
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            jk::ProfScope::set_capturing(false);
+            return JK_EHIP;
+        }
+        jk_status st = enqueue_batched(S, ws, s);
+        hipError_t e = hipStreamEndCapture(s, &graph);
+        jk::ProfScope::set_capturing(false);
+        if (st != JK_OK || e != hipSuccess)
+            return JK_EHIP;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess)
+            return JK_EHIP;
+        std::lock_guard<std::mutex> lk(gc.mu);
+        gc.execs[key] = exec;
+    }
+    return hipGraphLaunch(exec, s) == hipSuccess ? JK_OK : JK_EHIP;
+}
+
 } // namespace
 
 extern "C" {
@@ -378,6 +641,11 @@ size_t jk_batched_workspace_bytes(int32_t nprob, const jk_problem *p)
         if (b > mx)
             mx = b;
     }
+    if (p[0].precision == JK_FP64) {
+        // every member owns its single-build workspace, plus the header
+        size_t t = make_schedule(nprob, p).total_bytes;
+        return t > mx ? t : mx;
+    }
     return mx;
 }
 
@@ -400,6 +668,8 @@ jk_status jk_build_batched(int32_t nprob, const jk_problem *p, const double *con
         return JK_EINVAL;
     if (ws_bytes < jk_batched_workspace_bytes(nprob, p))
         return JK_EWORKSPACE;
+    if (p[0].precision == JK_FP64)
+        return build_batched_fp64(nprob, p, B, CL, CR, J, K, (char *)ws, (hipStream_t)stream);
     for (int32_t g = 0; g < nprob; g++) {
         jk_status st = p[g].precision == JK_MIXED
                            ? build_mixed(&p[g], B[g], CL[g], CR[g], J[g], K[g], (char *)ws,

@@ -1,0 +1,174 @@
+// jk_batched.hip -- many J/K problems of uneven size per launch.
+//
+// A batched build runs the phases of the FP64 build (jk_tiles.hpp) once for
+// the whole batch: each launch covers the tiles of every member that takes
+// part in that phase, in one grid.  blockIdx.x is mapped to (member, tile)
+// through a table of prefix sums; members are listed in decreasing order of
+// per-tile cost so the longest tiles start first.  Each member keeps the
+// chunking and split plan it would have alone, so its outputs are bit-for-bit
+// those of a single jk_build.
+//
+// The member descriptors and the tables live in the caller's workspace; the
+// host writes them with one asynchronous copy per call.  Kernel arguments are
+// only workspace pointers, so a captured graph of the launch sequence can be
+// replayed for any batch of the same shapes in the same workspace.
+#include "jk_batched.hpp"
+#include "jk_kernels.hpp"
+#include "jk_tiles.hpp"
+
+namespace jk {
+
+// Table layout: tab[0] = n entries, tab[1 .. n+1] = start offsets (n+1
+// values), tab[n+2 .. 2n+2) = member indices.
+__device__ __forceinline__ int find_member(const int *__restrict__ tab, int t, int &local)
+{
+    const int n = tab[0];
+    const int *start = tab + 1;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    local = t - start[lo];
+    return tab[n + 2 + lo];
+}
+
+// Chunk of member m at step c: first slab and slab count.
+__device__ __forceinline__ void chunk_of(const BMember &m, int c, int &q0, int &nq)
+{
+    q0 = c * m.qc;
+    nq = (m.naux - q0) < m.qc ? (m.naux - q0) : m.qc;
+}
+
+__global__ void __launch_bounds__(256) k_b_pack(const BMember *__restrict__ M, const int *__restrict__ tab)
+{
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    pack_tile(m.CL, m.CR, m.Cc, m.nao, m.nd, m.r, loc);
+}
+
+__global__ void __launch_bounds__(256) k_b_density(const BMember *__restrict__ M,
+                                                   const int *__restrict__ tab)
+{
+    __shared__ double lds[TileDensity::LDS_DOUBLES];
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    density_tile(m.CL, m.CR, m.D, m.nao, m.r, loc, lds);
+}
+
+__global__ void __launch_bounds__(256) k_b_project(const BMember *__restrict__ M,
+                                                   const int *__restrict__ tab)
+{
+    __shared__ double lds[TileProject::LDS_DOUBLES];
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    project_tile(m.B, m.D, m.part, m.naux, m.nd, m.npos, m.plen, loc, lds);
+}
+
+__global__ void __launch_bounds__(256) k_b_reduce(const BMember *__restrict__ M,
+                                                  const int *__restrict__ tab)
+{
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    reduce_tile(m.part, m.g, m.naux, m.nd, m.npb, loc);
+}
+
+__global__ void __launch_bounds__(256) k_b_coulomb(const BMember *__restrict__ M,
+                                                   const int *__restrict__ tab)
+{
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    coulomb_tile(m.B, m.g, m.J, m.naux, m.nd, m.npos, loc);
+}
+
+__global__ void __launch_bounds__(256, 2) k_b_half_transform(const BMember *__restrict__ M,
+                                                             const int *__restrict__ tab, int c)
+{
+    __shared__ double lds[TileHalf::LDS_DOUBLES];
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    int q0, nq;
+    chunk_of(m, c, q0, nq);
+    ht_tile(m.B, m.Cc, m.Xw, m.Yw, m.nao, m.nd, m.r, q0, m.ldw, loc, lds);
+}
+
+__global__ void __launch_bounds__(512, 4) k_b_exchange(const BMember *__restrict__ M,
+                                                       const int *__restrict__ tab, int c)
+{
+    __shared__ double lds[TileExch::LDS_DOUBLES];
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    int q0, nq;
+    chunk_of(m, c, q0, nq);
+    const int nj = nq * m.r;
+    int jlen = cdiv_i(nj, m.nsplit);
+    jlen = ((jlen + 15) / 16) * 16;
+    ex_tile(m.Xw, m.Yw, m.nsplit > 1 ? m.Kp : m.K, m.nao, m.nd, nj, m.ldw, jlen, c > 0, loc, lds);
+}
+
+__global__ void __launch_bounds__(256) k_b_sum_splits(const BMember *__restrict__ M,
+                                                      const int *__restrict__ tab)
+{
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    sum_tile(m.Kp, m.K, (i64)m.nd * m.npos, m.nsplit, loc);
+}
+
+// ------------------------------------------------------------------ launch
+hipError_t launch_batched_phase(int phase, const BMember *M, const int *tab, int ntiles, int step,
+                                hipStream_t s)
+{
+    if (ntiles <= 0)
+        return hipSuccess;
+    const dim3 g(ntiles);
+    switch (phase) {
+    case kPhasePack: {
+        ProfScope ps_("b_pack", s);
+        hipLaunchKernelGGL(k_b_pack, g, dim3(256), 0, s, M, tab);
+        break;
+    }
+    case kPhaseDensity: {
+        ProfScope ps_("b_density", s);
+        hipLaunchKernelGGL(k_b_density, g, dim3(256), 0, s, M, tab);
+        break;
+    }
+    case kPhaseProject: {
+        ProfScope ps_("b_project", s);
+        hipLaunchKernelGGL(k_b_project, g, dim3(256), 0, s, M, tab);
+        break;
+    }
+    case kPhaseReduce: {
+        ProfScope ps_("b_reduce", s);
+        hipLaunchKernelGGL(k_b_reduce, g, dim3(256), 0, s, M, tab);
+        break;
+    }
+    case kPhaseCoulomb: {
+        ProfScope ps_("b_coulomb", s);
+        hipLaunchKernelGGL(k_b_coulomb, g, dim3(256), 0, s, M, tab);
+        break;
+    }
+    case kPhaseHalf: {
+        ProfScope ps_("b_half_transform", s);
+        hipLaunchKernelGGL(k_b_half_transform, g, dim3(256), 0, s, M, tab, step);
+        break;
+    }
+    case kPhaseExchange: {
+        ProfScope ps_("b_exchange", s);
+        hipLaunchKernelGGL(k_b_exchange, g, dim3(TileExch::NTHR), 0, s, M, tab, step);
+        break;
+    }
+    case kPhaseSum: {
+        ProfScope ps_("b_sum_splits", s);
+        hipLaunchKernelGGL(k_b_sum_splits, g, dim3(256), 0, s, M, tab);
+        break;
+    }
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+} // namespace jk

@@ -13,6 +13,8 @@ class ProfScope {
   public:
     ProfScope(const char *name, hipStream_t s);
     ~ProfScope();
+    // While a stream is being captured into a graph no events are recorded.
+    static void set_capturing(bool on);
     ProfScope(const ProfScope &) = delete;
     ProfScope &operator=(const ProfScope &) = delete;
 

@@ -17,6 +17,7 @@ struct Rec {
 
 struct Prof {
     bool on = false;
+    bool capturing = false;
     std::vector<hipEvent_t> ev;   // 2 per pair
     std::vector<Rec> recs;
     int64_t dropped = 0;
@@ -35,10 +36,12 @@ Prof &prof()
 
 namespace jk {
 
+void ProfScope::set_capturing(bool on) { prof().capturing = on; }
+
 ProfScope::ProfScope(const char *name, hipStream_t s) : stream_(s), pair_(-1)
 {
     Prof &p = prof();
-    if (!p.on)
+    if (!p.on || p.capturing)
         return;
     const int npair = (int)(p.ev.size() / 2);
     const int next = (int)p.recs.size();

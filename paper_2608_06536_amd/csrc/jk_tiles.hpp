@@ -1,0 +1,270 @@
+// jk_tiles.hpp -- one workgroup's share of each FP64 build phase.
+//
+// Every phase of the build is a set of independent tiles; these device
+// functions compute one tile.  The single-problem kernels (jk_fp64.hip) run
+// tile blockIdx.x of one problem; the batched kernels (jk_batched.hip) map
+// blockIdx.x to (problem, tile) through a table and run the same function, so
+// a member of a batch is computed exactly as it would be alone.
+//
+// Phases (Sec. 2.3, Eq. (4), half-transform form K = B_V^T B_U):
+//   pack          Cc[n][c]       = [C_L | C_R] as one nao x 2R matrix
+//   density       D_k            = C_Lk C_Rk^T
+//   project       part[p][Q][k]  = sum over a block of positions of B^Q . A_k
+//   reduce        g[k][Q]        = sum of the partials in fixed order
+//   coulomb       J_k            = sum_Q gamma_kQ B^Q
+//   half-transform X^Q, Y^Q      = B^Q [C_L | C_R]            (per Q-chunk)
+//   exchange      K_k           += sum_{Q in chunk} X^Q_k (Y^Q_k)^T
+//   sum splits    K              = sum of the split partials in fixed order
+// Chunk workspace: X_ws[k][m][ql*r + i], Y_ws likewise, so each exchange
+// operand row is contiguous over the chunk's inner index (Q, i).
+#pragma once
+#include "f64_core.hpp"
+
+namespace jk {
+
+// Tile shapes (chosen by measurement on MI355X): the half-transform uses
+// 128 x 64 workgroup tiles of four 64 x 32 wave tiles (two workgroups per
+// CU); the exchange product 128 x 64 tiles of eight 64 x 16 wave tiles (four
+// waves per SIMD); the projection 256 Q-rows x 8 densities; the density
+// 64 x 64.  Element-wise phases take 1024 elements per tile.
+constexpr int kHtM = 128, kHtN = 64;
+constexpr int kExM = 128, kExN = 64;
+constexpr int kProjRows = 256;
+constexpr int kElemTile = 1024;
+typedef Tile<kHtM, kHtN, 64, 32, 16> TileHalf;
+typedef Tile<kExM, kExN, 64, 16, 16> TileExch;
+typedef Tile<kProjRows, 8, 64, 8, 16> TileProject;
+typedef Tile<64, 64, 32, 32, 16> TileDensity;
+
+__host__ __device__ inline int cdiv_i(i64 a, i64 b) { return (int)((a + b - 1) / b); }
+
+// ------------------------------------------------------------------ tile counts
+__host__ __device__ inline int pack_tiles(int nao, int nd, int r)
+{
+    return cdiv_i((i64)nao * 2 * nd * r, kElemTile);
+}
+__host__ __device__ inline int density_tiles(int nao, int nd)
+{
+    const int nt = cdiv_i(nao, 64);
+    return nd * nt * nt;
+}
+__host__ __device__ inline int project_tiles(int naux, int nd, int npb)
+{
+    return cdiv_i(naux, kProjRows) * cdiv_i(nd, 8) * npb;
+}
+__host__ __device__ inline int reduce_tiles(int naux, int nd) { return cdiv_i((i64)naux * nd, kElemTile); }
+__host__ __device__ inline int coulomb_tiles(int nd, i64 npos) { return cdiv_i(nd, 8) * cdiv_i(npos, 256); }
+__host__ __device__ inline int ht_tiles(int nao, int nd, int r, int nq)
+{
+    return nq * cdiv_i(nao, kHtM) * cdiv_i(2 * (i64)nd * r, kHtN);
+}
+__host__ __device__ inline int ex_tiles(int nao, int nd, int nsplit)
+{
+    return nsplit * nd * cdiv_i(nao, kExM) * cdiv_i(nao, kExN);
+}
+__host__ __device__ inline int sum_tiles(i64 n) { return cdiv_i(n, kElemTile); }
+
+// ------------------------------------------------------------------ pack
+__device__ inline void pack_tile(const double *__restrict__ CL, const double *__restrict__ CR,
+                                 double *__restrict__ Cc, int nao, int nd, int r, int tile)
+{
+    const int R = nd * r, R2 = 2 * R;
+    const i64 total = (i64)nao * R2;
+    for (int u = 0; u < kElemTile / 256; u++) {
+        const i64 e = (i64)tile * kElemTile + u * 256 + threadIdx.x;
+        if (e < total) {
+            const int n = (int)(e / R2), c = (int)(e % R2);
+            const double *src = c < R ? CL : CR;
+            const int cc = c < R ? c : c - R;
+            const int k = cc / r, i = cc % r;
+            Cc[e] = src[((i64)k * nao + n) * r + i];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ density
+// D_k[m][n] = sum_i CL[k][m][i] CR[k][n][i]
+__device__ inline void density_tile(const double *__restrict__ CL, const double *__restrict__ CR,
+                                    double *__restrict__ D, int nao, int r, int tile, double *lds)
+{
+    typedef TileDensity TL;
+    const int nt = cdiv_i(nao, 64);
+    const int k = tile / (nt * nt), rem = tile % (nt * nt);
+    const int mb = rem / nt, nb = rem % nt;
+    OpKC a{CL + (i64)k * nao * r, r, nao, r};
+    OpKC b{CR + (i64)k * nao * r, r, nao, r};
+    Acc<TL> acc;
+    acc.zero();
+    tile_gemm<TL>(a, b, mb * 64, nb * 64, 0, r, lds, acc);
+    double *Dk = D + (i64)k * nao * nao;
+    tile_foreach(acc, mb * 64, nb * 64, [&](int m, int n, double v) {
+        if (m < nao && n < nao)
+            Dk[(i64)m * nao + n] = v;
+    });
+}
+
+// ------------------------------------------------------------------ project
+// part[pb][Q][kg*8 + kk] = sum_{p in block pb} B[Q][p] * A[kg*8 + kk][p]:
+// a product with M = naux, N = nd (groups of 8), inner = nao^2 cut into
+// blocks of plen positions.
+__device__ inline void project_tile(const double *__restrict__ B, const double *__restrict__ A,
+                                    double *__restrict__ part, int naux, int nd, i64 npos, int plen,
+                                    int tile, double *lds)
+{
+    typedef TileProject TL;
+    const int nqt = cdiv_i(naux, kProjRows), nkg = cdiv_i(nd, 8);
+    const int pb = tile / (nqt * nkg), rem = tile % (nqt * nkg);
+    const int kg = rem / nqt, qt = rem % nqt;
+    const i64 p0 = (i64)pb * plen;
+    const int len = (int)((npos - p0) < plen ? (npos - p0) : plen);
+    const int ndg = (nd - kg * 8) < 8 ? (nd - kg * 8) : 8;
+    OpKC a{B + p0, npos, naux, len};
+    OpKC b{A + (i64)kg * 8 * npos + p0, npos, ndg, len};
+    Acc<TL> acc;
+    acc.zero();
+    tile_gemm<TL>(a, b, qt * kProjRows, 0, 0, len, lds, acc);
+    const int ndp = nkg * 8;
+    double *out = part + (i64)pb * naux * ndp;
+    tile_foreach(acc, qt * kProjRows, 0, [&](int q, int kk, double v) {
+        if (q < naux && kk < 8)
+            out[(i64)q * ndp + kg * 8 + kk] = v;
+    });
+}
+
+// g[k][Q] = sum_{pb} part[pb][Q][k] (fixed order).
+__device__ inline void reduce_tile(const double *__restrict__ part, double *__restrict__ g, int naux,
+                                   int nd, int npb, int tile)
+{
+    const int ndp = cdiv_i(nd, 8) * 8;
+    const i64 total = (i64)naux * nd;
+    for (int u = 0; u < kElemTile / 256; u++) {
+        const i64 e = (i64)tile * kElemTile + u * 256 + threadIdx.x;
+        if (e < total) {
+            const int k = (int)(e / naux), q = (int)(e % naux);
+            double s = 0.0;
+            for (int pb = 0; pb < npb; pb++)
+                s += part[((i64)pb * naux + q) * ndp + k];
+            g[(i64)k * naux + q] = s;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ coulomb
+// J[k][p] = sum_Q g[k][Q] B[Q][p] for the 8 densities of group kg and the 256
+// positions of block pb: one position per thread, Q unrolled by 8 for loads
+// in flight.  HBM-bound stream over B.
+__device__ inline void coulomb_tile(const double *__restrict__ B, const double *__restrict__ g,
+                                    double *__restrict__ J, int naux, int nd, i64 npos, int tile)
+{
+    const int npb = cdiv_i(npos, 256);
+    const int kg = tile / npb, pb = tile % npb;
+    const int k0 = kg * 8;
+    const i64 p = (i64)pb * 256 + threadIdx.x;
+    const int nk = (nd - k0) < 8 ? (nd - k0) : 8;
+    double acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++)
+        acc[k] = 0.0;
+    const bool ok = p < npos;
+    const double *bp = B + (ok ? p : 0);
+    int q = 0;
+    for (; q + 8 <= naux; q += 8) {
+        double bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+            bv[u] = ok ? __builtin_nontemporal_load(bp + (i64)(q + u) * npos) : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+#pragma unroll
+            for (int k = 0; k < 8; k++)
+                if (k < nk)
+                    acc[k] = fma(g[(i64)(k0 + k) * naux + q + u], bv[u], acc[k]);
+    }
+    for (; q < naux; q++) {
+        const double b = ok ? bp[(i64)q * npos] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (k < nk)
+                acc[k] = fma(g[(i64)(k0 + k) * naux + q], b, acc[k]);
+    }
+    if (ok) {
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (k < nk)
+                J[(i64)(k0 + k) * npos + p] = acc[k];
+    }
+}
+
+// ------------------------------------------------------------------ half-transform
+// For slab Q = q0 + ql (ql < nq): XY[m][c] = sum_n B^Q[m][n] Cc[n][c], written
+// as X_ws[k][m][ql*r + i] (c = k*r + i < R) or Y_ws[k][m][ql*r + i] (c - R).
+__device__ inline void ht_tile(const double *__restrict__ B, const double *__restrict__ Cc,
+                               double *__restrict__ Xw, double *__restrict__ Yw, int nao, int nd,
+                               int r, int q0, int ldw, int tile, double *lds)
+{
+    typedef TileHalf TL;
+    const int R = nd * r, R2 = 2 * R;
+    const int nmt = cdiv_i(nao, kHtM), nct = cdiv_i(R2, kHtN);
+    const int ql = tile / (nmt * nct), rem = tile % (nmt * nct);
+    const int mb = rem / nct, cb = rem % nct;
+    const i64 n2 = (i64)nao * nao;
+    OpKC a{B + (i64)(q0 + ql) * n2, nao, nao, nao};
+    OpIC b{Cc, R2, R2, nao};
+    Acc<TL> acc;
+    acc.zero();
+    tile_gemm<TL>(a, b, mb * kHtM, cb * kHtN, 0, nao, lds, acc);
+    tile_foreach(acc, mb * kHtM, cb * kHtN, [&](int m, int c, double v) {
+        if (m < nao && c < R2) {
+            double *dst = c < R ? Xw : Yw;
+            const int cc = c < R ? c : c - R;
+            const int k = cc / r, i = cc % r;
+            dst[((i64)k * nao + m) * ldw + (i64)ql * r + i] = v;
+        }
+    });
+}
+
+// ------------------------------------------------------------------ exchange
+// Kp[s][k][m][n] (+)= sum_{j in split s} X_ws[k][m][j] Y_ws[k][n][j]; the
+// inner range [0, nj) is cut into nsplit contiguous pieces of jlen.
+__device__ inline void ex_tile(const double *__restrict__ Xw, const double *__restrict__ Yw,
+                               double *__restrict__ Kp, int nao, int nd, int nj, int ldw, int jlen,
+                               int accumulate, int tile, double *lds)
+{
+    typedef TileExch TL;
+    const int nmt = cdiv_i(nao, kExM), nnt = cdiv_i(nao, kExN);
+    const int per = nd * nmt * nnt;
+    const int sp = tile / per;
+    const int t = tile % per;
+    const int k = t / (nmt * nnt), rem = t % (nmt * nnt);
+    const int mb = rem / nnt, nb = rem % nnt;
+    const int j0 = sp * jlen, j1 = (j0 + jlen) < nj ? (j0 + jlen) : nj;
+    OpKC a{Xw + (i64)k * nao * ldw, ldw, nao, j1};
+    OpKC b{Yw + (i64)k * nao * ldw, ldw, nao, j1};
+    Acc<TL> acc;
+    acc.zero();
+    tile_gemm<TL>(a, b, mb * kExM, nb * kExN, j0, j1, lds, acc);
+    double *Kk = Kp + ((i64)sp * nd + k) * nao * nao;
+    tile_foreach(acc, mb * kExM, nb * kExN, [&](int m, int n, double v) {
+        if (m < nao && n < nao) {
+            const i64 o = (i64)m * nao + n;
+            Kk[o] = accumulate ? Kk[o] + v : v;
+        }
+    });
+}
+
+// out[e] = sum_{s < nsplit} part[s * n + e] (fixed order).
+__device__ inline void sum_tile(const double *__restrict__ part, double *__restrict__ out, i64 n,
+                                int nsplit, int tile)
+{
+    for (int u = 0; u < kElemTile / 256; u++) {
+        const i64 e = (i64)tile * kElemTile + u * 256 + threadIdx.x;
+        if (e < n) {
+            double s = 0.0;
+            for (int sp = 0; sp < nsplit; sp++)
+                s += part[(i64)sp * n + e];
+            out[e] = s;
+        }
+    }
+}
+
+} // namespace jk

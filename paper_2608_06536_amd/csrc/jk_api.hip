@@ -156,7 +156,7 @@ VjpPlan plan_vjp(const jk_problem *p)
 struct MixPlan {
     FwdPlan f;
     int ns, mp, kp, cp, jp, nsplit;
-    size_t o_bp, o_eb, o_cp, o_ec, o_xp, o_yp, o_ex, o_ey, o_kp, total;
+    size_t o_bp, o_eb, o_cp, o_ec, o_xp, o_yp, o_ux, o_kp, total;
 };
 
 inline i64 pad_to(i64 x, i64 m) { return ((x + m - 1) / m) * m; }
@@ -171,7 +171,7 @@ MixPlan plan_mixed(const jk_problem *p)
     x.kp = (int)pad_to(nao, jk::mixed_k_pad());
     x.cp = (int)pad_to(2 * R, jk::mixed_row_pad());
     x.jp = (int)pad_to((i64)x.f.qc * r, jk::mixed_k_pad());
-    x.nsplit = jk::ex_mixed_nsplit(x.mp, (int)nd, x.jp);
+    x.nsplit = jk::ex_mixed_nsplit(x.mp, (int)nd, x.jp / jk::mixed_k_block());
     Carve c;
     c.off = x.f.total;
     x.o_bp = c.take((size_t)x.ns * x.f.qc * x.mp * x.kp);
@@ -180,8 +180,7 @@ MixPlan plan_mixed(const jk_problem *p)
     x.o_ec = c.take(sizeof(int) * (size_t)x.cp);
     x.o_xp = c.take((size_t)x.ns * nd * x.mp * x.jp);
     x.o_yp = c.take((size_t)x.ns * nd * x.mp * x.jp);
-    x.o_ex = c.take(sizeof(int) * (size_t)nd * x.mp);
-    x.o_ey = c.take(sizeof(int) * (size_t)nd * x.mp);
+    x.o_ux = c.take(sizeof(unsigned) * (size_t)2 * nd * x.mp);
     x.o_kp = c.take(sizeof(double) * (size_t)x.nsplit * nd * nao * nao);
     x.total = c.off;
     return x;
@@ -306,29 +305,31 @@ jk_status build_mixed(const jk_problem *p, const double *B, const double *CL, co
     int *eC = (int *)(ws + x.o_ec);
     int8_t *Xp = (int8_t *)(ws + x.o_xp);
     int8_t *Yp = (int8_t *)(ws + x.o_yp);
-    int *eX = (int *)(ws + x.o_ex);
-    int *eY = (int *)(ws + x.o_ey);
+    unsigned *uX = (unsigned *)(ws + x.o_ux);
+    unsigned *uY = uX + (size_t)nd * x.mp;
     double *Kp = x.nsplit > 1 ? (double *)(ws + x.o_kp) : K;
-    const i64 bpstride = (i64)f.qc * x.mp * x.kp;
-    const i64 cpstride = (i64)x.cp * x.kp;
-    const i64 xpstride = (i64)nd * x.mp * x.jp;
+    const int KB = jk::mixed_k_block();
+    // K-blocked plane strides (slice_core.hpp): kbstride = rows * 32 bytes
+    const i64 bkb = (i64)f.qc * x.mp * KB, bps = bkb * (x.kp / KB);
+    const i64 ckb = (i64)x.cp * KB, cps = ckb * (x.kp / KB);
+    const i64 xkb = (i64)nd * x.mp * KB, xps = xkb * (x.jp / KB);
 
     JK_TRY(jk::launch_pack_c(CL, CR, Cc, nao, nd, r, s));
     // digits of [C_L | C_R]: row c, inner n, element Cc[n][c]
-    JK_TRY(jk::launch_slice_rows(Cc, 0, 1, R2, 1, R2, nao, x.cp, x.kp, Cp, cpstride, eC, s));
+    JK_TRY(jk::launch_slice_rows(Cc, 0, 1, R2, 1, R2, nao, x.cp, x.kp / KB, Cp, cps, ckb, eC, s));
     for (int q0 = 0; q0 < naux; q0 += f.qc) {
         const int nq = (naux - q0) < f.qc ? (naux - q0) : f.qc;
         const int nj = nq * r;
-        const int jp = (int)pad_to(nj, jk::mixed_k_pad());
-        JK_TRY(jk::launch_slice_rows(B + (i64)q0 * npos, npos, nao, 1, nq, nao, nao, x.mp, x.kp, Bp,
-                                     bpstride, eB, s));
-        JK_TRY(jk::launch_ht_mixed(Bp, bpstride, eB, Cp, cpstride, eC, Xw, Yw, nao, nd, r, nq, x.mp,
-                                   x.kp, f.ldw, s));
-        JK_TRY(jk::launch_slice_rows(Xw, (i64)nao * f.ldw, f.ldw, 1, nd, nao, nj, x.mp, jp, Xp,
-                                     xpstride, eX, s));
-        JK_TRY(jk::launch_slice_rows(Yw, (i64)nao * f.ldw, f.ldw, 1, nd, nao, nj, x.mp, jp, Yp,
-                                     xpstride, eY, s));
-        JK_TRY(jk::launch_ex_mixed(Xp, Yp, xpstride, eX, eY, Kp, nao, nd, x.mp, jp, x.nsplit, q0 > 0,
+        const int nkb = (int)(pad_to(nj, jk::mixed_k_pad()) / KB);
+        JK_TRY(jk::launch_slice_b(B + (i64)q0 * npos, npos, nao, nq, nao, nao, x.mp, x.kp / KB, Bp,
+                                  bps, bkb, eB, uX, 2 * nd * x.mp, s));
+        JK_TRY(jk::launch_ht_mixed(Bp, bps, bkb, eB, Cp, cps, ckb, eC, Xw, Yw, uX, nao, nd, r, nq,
+                                   x.mp, x.cp, x.kp / KB, f.ldw, s));
+        JK_TRY(jk::launch_slice_elem(Xw, (i64)nao * f.ldw, f.ldw, nd, nao, nj, x.mp, nkb, Xp, xps, xkb,
+                                     uX, s));
+        JK_TRY(jk::launch_slice_elem(Yw, (i64)nao * f.ldw, f.ldw, nd, nao, nj, x.mp, nkb, Yp, xps, xkb,
+                                     uY, s));
+        JK_TRY(jk::launch_ex_mixed(Xp, Yp, xps, xkb, uX, uY, Kp, nao, nd, x.mp, nkb, x.nsplit, q0 > 0,
                                    s));
     }
     if (x.nsplit > 1)

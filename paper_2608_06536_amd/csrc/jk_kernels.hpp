@@ -70,14 +70,23 @@ hipError_t launch_vjp_db_affine(const double *gam, const double *om, const doubl
 int mixed_nslice();
 int mixed_row_pad();
 int mixed_k_pad();
+int mixed_k_block();
 hipError_t launch_slice_rows(const double *src, i64 bs, i64 rs, i64 ks, int nb, int nr, int nk,
-                             int rp, int kp, int8_t *out, i64 pstride, int *exps, hipStream_t s);
-hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, const int *eB, const int8_t *Cp,
-                           i64 cpstride, const int *eC, double *Xw, double *Yw, int nao, int nd,
-                           int r, int nq, int mp, int kp, int ldw, hipStream_t s);
-int ex_mixed_nsplit(int mp, int nd, int jp);
-hipError_t launch_ex_mixed(const int8_t *Xp, const int8_t *Yp, i64 pstride, const int *eX,
-                           const int *eY, double *Kp, int nao, int nd, int mp, int jp, int nsplit,
-                           int accumulate, hipStream_t s);
+                             int rp, int nkb, int8_t *out, i64 pstride, i64 kbstride, int *exps,
+                             hipStream_t s);
+hipError_t launch_slice_b(const double *src, i64 bs, i64 rs, int nb, int nr, int nk, int rp, int nkb,
+                          int8_t *out, i64 pstride, i64 kbstride, int *exps, unsigned *clr, int nclr,
+                          hipStream_t s);
+hipError_t launch_slice_elem(const double *src, i64 bs, i64 rs, int nb, int nr, int nk, int rp,
+                             int nkb, int8_t *out, i64 pstride, i64 kbstride, const unsigned *ux,
+                             hipStream_t s);
+hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, i64 bkbstride, const int *eB,
+                           const int8_t *Cp, i64 cpstride, i64 ckbstride, const int *eC, double *Xw,
+                           double *Yw, unsigned *ux, int nao, int nd, int r, int nq, int mp, int cp,
+                           int nkb, int ldw, hipStream_t s);
+int ex_mixed_nsplit(int mp, int nd, int nkb);
+hipError_t launch_ex_mixed(const int8_t *Xp, const int8_t *Yp, i64 pstride, i64 kbstride,
+                           const unsigned *ux, const unsigned *uy, double *Kp, int nao, int nd, int mp,
+                           int nkb, int nsplit, int accumulate, hipStream_t s);
 
 } // namespace jk

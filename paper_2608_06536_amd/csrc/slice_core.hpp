@@ -20,9 +20,9 @@
 // l % 32] as 16 bytes each, and output element j (0..15) is
 // C[8*(j/4) + 4*(l/32) + j%4][l % 32].
 //
-// Digit planes live in global memory as [plane][row][kp] int8 with kp a
-// multiple of 64 and rows padded to a multiple of the tile, zero-filled, so
-// the GEMM loaders copy 16-byte chunks without bounds checks.
+// Digit planes live in global memory K-blocked (see SPlanes) with rows and
+// inner bytes padded by zero digits, so the GEMM loaders copy 16-byte chunks
+// without bounds checks.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -34,7 +34,7 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kSliceBits = 7;          // bits per digit
-constexpr int kSliceKP = 64;           // inner padding unit (bytes per plane row chunk)
+constexpr int kSliceKB = 32;           // inner block: bytes per row per block
 
 __device__ __forceinline__ v16i mfma_i8(v4i a, v4i b, v16i c)
 {
@@ -61,45 +61,55 @@ __device__ __forceinline__ int row_exponent(double maxabs)
     return maxabs > 0.0 ? ilogb(maxabs) + 1 : 0;
 }
 
+// ---------------------------------------------------------------- planes
+// Digit planes in global memory are K-blocked: plane p, row i, inner byte k
+// lives at base[p * pstride + (k / 32) * kbstride + i * 32 + k % 32], with
+// kbstride = (rows of the array) * 32.  A tile of rows x 32 inner bytes of one
+// plane is therefore one contiguous block; rows and inner bytes are padded
+// with zero digits, so tile loads need no bounds checks.
+struct SPlanes {
+    const int8_t *base;   // already offset to the first row of the operand
+    i64 pstride;          // bytes between planes
+    i64 kbstride;         // bytes between inner blocks
+};
+
 // ---------------------------------------------------------------- tile GEMM
 // One workgroup: BM x BN output tile, waves (BM/32) x (BN/32), one 32x32
-// MFMA tile per wave, NS digit planes per operand, inner stages of 64.
-// Accumulators: one v16i per level l = 2 .. NS+1.
-template <int BM, int BN, int NS>
+// MFMA tile per wave, NS digit planes per operand.  A stage holds KBS inner
+// blocks of 32 bytes.  LDS stage layout: [plane][block][row][32 bytes] for A,
+// then the same for B, unpadded: the 16-byte chunks of a stage land in LDS in
+// the order they are read from global memory, and a fragment read by 64
+// lanes is 2 KB contiguous.  Inner ranges must be multiples of KBS blocks
+// (planes are zero-padded to that).
+template <int BM, int BN, int NS, int KBS>
 struct STile {
     static constexpr int WROWS = BM / 32, WCOLS = BN / 32;
     static constexpr int NWAVE = WROWS * WCOLS;
     static constexpr int NTHR = NWAVE * 64;
     static constexpr int NLEV = NS;            // levels 2..NS+1
-    static constexpr int ROWB = kSliceKP + 16; // LDS row stride in bytes (padded)
-    static constexpr int A_BYTES = NS * BM * ROWB, B_BYTES = NS * BN * ROWB;
+    static constexpr int KB = KBS;
+    static constexpr int A_BYTES = NS * KBS * BM * kSliceKB, B_BYTES = NS * KBS * BN * kSliceKB;
     static constexpr int STAGE_BYTES = A_BYTES + B_BYTES;
     static constexpr int LDS_BYTES = 2 * STAGE_BYTES;
 };
 
-// Digit-plane operand: plane p, row i, inner byte k at base[p * pstride + i * ld + k].
-struct SPlanes {
-    const int8_t *base;
-    i64 pstride;   // bytes between planes
-    i64 ld;        // bytes between rows (multiple of 64)
-};
-
-template <int T, int NS, int NTHR>
+template <int T, int NS, int KBS, int NTHR>
 struct SLoader {
-    // chunks of 16 bytes per stage: NS planes x T rows x 4
-    static constexpr int NCH = NS * T * 4;
+    // 16-byte chunks per stage: NS planes x KBS blocks x T rows x 2
+    static constexpr int NCH = NS * KBS * T * 2;
     static constexpr int NSTEP = (NCH + NTHR - 1) / NTHR;
     v4i v[NSTEP];
 
-    __device__ __forceinline__ void load(const SPlanes &op, int i0, int k0, int tid)
+    __device__ __forceinline__ void load(const SPlanes &op, int i0, int kb, int tid)
     {
 #pragma unroll
         for (int s = 0; s < NSTEP; s++) {
             const int c = tid + s * NTHR;
             if (NCH % NTHR == 0 || c < NCH) {
-                const int p = c / (T * 4), rem = c % (T * 4);
-                const int row = rem >> 2, q = rem & 3;
-                v[s] = *(const v4i *)(op.base + p * op.pstride + (i64)(i0 + row) * op.ld + k0 + 16 * q);
+                const int p = c / (KBS * T * 2), rem = c % (KBS * T * 2);
+                const int kbl = rem / (T * 2), rr = rem % (T * 2);
+                v[s] = *(const v4i *)(op.base + p * op.pstride + (i64)(kb + kbl) * op.kbstride +
+                                      (i64)i0 * kSliceKB + rr * 16);
             }
         }
     }
@@ -109,11 +119,8 @@ struct SLoader {
 #pragma unroll
         for (int s = 0; s < NSTEP; s++) {
             const int c = tid + s * NTHR;
-            if (NCH % NTHR == 0 || c < NCH) {
-                const int p = c / (T * 4), rem = c % (T * 4);
-                const int row = rem >> 2, q = rem & 3;
-                *(v4i *)(lds + (p * T + row) * (kSliceKP + 16) + 16 * q) = v[s];
-            }
+            if (NCH % NTHR == 0 || c < NCH)
+                *(v4i *)(lds + c * 16) = v[s];
         }
     }
 };
@@ -131,43 +138,44 @@ struct SAcc {
     }
 };
 
-// acc_l += sum over inner [k_begin, k_end) (multiples of 64) of the digit
-// pair products with i + j = l + 2 (i, j = 1..NS, i + j <= NS + 1).
+// acc_l += sum over inner blocks [kb_begin, kb_end) of the digit pair
+// products with i + j = l + 2 (i, j = 1..NS, i + j <= NS + 1).
+// kb_end - kb_begin must be a multiple of TL::KB.
 template <class TL, int NS>
 __device__ __forceinline__ void stile_gemm(const SPlanes &A, const SPlanes &B, int m0, int n0,
-                                           int k_begin, int k_end, char *lds, SAcc<TL> &acc)
+                                           int kb_begin, int kb_end, char *lds, SAcc<TL> &acc)
 {
-    constexpr int BM = TL::WROWS * 32, BN = TL::WCOLS * 32;
+    constexpr int BM = TL::WROWS * 32, BN = TL::WCOLS * 32, KBS = TL::KB;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
-    SLoader<BM, NS, TL::NTHR> la;
-    SLoader<BN, NS, TL::NTHR> lb;
-    const int nk = (k_end - k_begin) / kSliceKP;
-    if (nk <= 0)
+    SLoader<BM, NS, KBS, TL::NTHR> la;
+    SLoader<BN, NS, KBS, TL::NTHR> lb;
+    const int nst = (kb_end - kb_begin) / KBS;
+    if (nst <= 0)
         return;
-    la.load(A, m0, k_begin, tid);
-    lb.load(B, n0, k_begin, tid);
+    la.load(A, m0, kb_begin, tid);
+    lb.load(B, n0, kb_begin, tid);
     la.store(lds, tid);
     lb.store(lds + TL::A_BYTES, tid);
     __syncthreads();
-    const int arow = wr * 32 + (lane & 31), brow = wc * 32 + (lane & 31);
-    const int koff = 16 * (lane >> 5);
-    for (int kt = 0; kt < nk; kt++) {
-        const int cur = kt & 1;
-        const bool more = kt + 1 < nk;
+    const int aoff = (wr * 32 + (lane & 31)) * kSliceKB + 16 * (lane >> 5);
+    const int boff = (wc * 32 + (lane & 31)) * kSliceKB + 16 * (lane >> 5);
+    for (int st = 0; st < nst; st++) {
+        const int cur = st & 1;
+        const bool more = st + 1 < nst;
         if (more) {
-            la.load(A, m0, k_begin + (kt + 1) * kSliceKP, tid);
-            lb.load(B, n0, k_begin + (kt + 1) * kSliceKP, tid);
+            la.load(A, m0, kb_begin + (st + 1) * KBS, tid);
+            lb.load(B, n0, kb_begin + (st + 1) * KBS, tid);
         }
         const char *sa = lds + cur * TL::STAGE_BYTES;
         const char *sb = sa + TL::A_BYTES;
 #pragma unroll
-        for (int ks = 0; ks < 2; ks++) {      // two 32-deep steps per stage
+        for (int kbl = 0; kbl < KBS; kbl++) {
             v4i a[NS], b[NS];
 #pragma unroll
             for (int p = 0; p < NS; p++) {
-                a[p] = *(const v4i *)(sa + (p * BM + arow) * TL::ROWB + 32 * ks + koff);
-                b[p] = *(const v4i *)(sb + (p * BN + brow) * TL::ROWB + 32 * ks + koff);
+                a[p] = *(const v4i *)(sa + (p * KBS + kbl) * BM * kSliceKB + aoff);
+                b[p] = *(const v4i *)(sb + (p * KBS + kbl) * BN * kSliceKB + boff);
             }
 #pragma unroll
             for (int i = 0; i < NS; i++)

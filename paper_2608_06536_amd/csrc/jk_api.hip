@@ -156,7 +156,7 @@ VjpPlan plan_vjp(const jk_problem *p)
 struct MixPlan {
     FwdPlan f;
     int ns, mp, kp, cp, jp, nsplit;
-    size_t o_bp, o_eb, o_cp, o_ec, o_xp, o_yp, o_ux, o_kp, total;
+    size_t o_bp, o_eb, o_cp, o_ec, o_xyp, o_exy, o_kp, total;
 };
 
 inline i64 pad_to(i64 x, i64 m) { return ((x + m - 1) / m) * m; }
@@ -178,9 +178,8 @@ MixPlan plan_mixed(const jk_problem *p)
     x.o_eb = c.take(sizeof(int) * (size_t)x.f.qc * x.mp);
     x.o_cp = c.take((size_t)x.ns * x.cp * x.kp);
     x.o_ec = c.take(sizeof(int) * (size_t)x.cp);
-    x.o_xp = c.take((size_t)x.ns * nd * x.mp * x.jp);
-    x.o_yp = c.take((size_t)x.ns * nd * x.mp * x.jp);
-    x.o_ux = c.take(sizeof(unsigned) * (size_t)2 * nd * x.mp);
+    x.o_xyp = c.take((size_t)x.ns * 2 * nd * x.mp * x.jp);
+    x.o_exy = c.take(sizeof(int) * (size_t)2 * nd * x.mp);
     x.o_kp = c.take(sizeof(double) * (size_t)x.nsplit * nd * nao * nao);
     x.total = c.off;
     return x;
@@ -283,6 +282,8 @@ jk_status build_mixed(const jk_problem *p, const double *B, const double *CL, co
     const FwdPlan &f = x.f;
     const int nao = (int)p->nao, naux = (int)p->naux, nd = (int)p->ndens, r = (int)p->rank;
     const int R = nd * r, R2 = 2 * R;
+    if (!jk::mixed_rowmax_ok(R2))
+        return JK_EUNSUPPORTED;
     const i64 npos = (i64)nao * nao;
     const int w = want(p);
     if (w & JK_WANT_J) {
@@ -297,22 +298,22 @@ jk_status build_mixed(const jk_problem *p, const double *B, const double *CL, co
     if (!(w & JK_WANT_K))
         return JK_OK;
     double *Cc = (double *)(ws + f.o_cc);
-    double *Xw = (double *)(ws + f.o_x);
-    double *Yw = (double *)(ws + f.o_y);
+    // XY[ql][m][c] of a chunk: qc * nao * 2R doubles, exactly the space of the
+    // FP64 path's X and Y chunk buffers, which are carved back to back.
+    double *XY = (double *)(ws + f.o_x);
     int8_t *Bp = (int8_t *)(ws + x.o_bp);
     int *eB = (int *)(ws + x.o_eb);
     int8_t *Cp = (int8_t *)(ws + x.o_cp);
     int *eC = (int *)(ws + x.o_ec);
-    int8_t *Xp = (int8_t *)(ws + x.o_xp);
-    int8_t *Yp = (int8_t *)(ws + x.o_yp);
-    unsigned *uX = (unsigned *)(ws + x.o_ux);
-    unsigned *uY = uX + (size_t)nd * x.mp;
+    int8_t *XYp = (int8_t *)(ws + x.o_xyp);
+    int *eXY = (int *)(ws + x.o_exy);
     double *Kp = x.nsplit > 1 ? (double *)(ws + x.o_kp) : K;
     const int KB = jk::mixed_k_block();
     // K-blocked plane strides (slice_core.hpp): kbstride = rows * 32 bytes
     const i64 bkb = (i64)f.qc * x.mp * KB, bps = bkb * (x.kp / KB);
     const i64 ckb = (i64)x.cp * KB, cps = ckb * (x.kp / KB);
-    const i64 xkb = (i64)nd * x.mp * KB, xps = xkb * (x.jp / KB);
+    const i64 xkb = (i64)2 * nd * x.mp * KB, xps = xkb * (x.jp / KB);
+    const int8_t *Xp = XYp, *Yp = XYp + (i64)nd * x.mp * KB;
 
     JK_TRY(jk::launch_pack_c(CL, CR, Cc, nao, nd, r, s));
     // digits of [C_L | C_R]: row c, inner n, element Cc[n][c]
@@ -322,15 +323,13 @@ jk_status build_mixed(const jk_problem *p, const double *B, const double *CL, co
         const int nj = nq * r;
         const int nkb = (int)(pad_to(nj, jk::mixed_k_pad()) / KB);
         JK_TRY(jk::launch_slice_b(B + (i64)q0 * npos, npos, nao, nq, nao, nao, x.mp, x.kp / KB, Bp,
-                                  bps, bkb, eB, uX, 2 * nd * x.mp, s));
-        JK_TRY(jk::launch_ht_mixed(Bp, bps, bkb, eB, Cp, cps, ckb, eC, Xw, Yw, uX, nao, nd, r, nq,
-                                   x.mp, x.cp, x.kp / KB, f.ldw, s));
-        JK_TRY(jk::launch_slice_elem(Xw, (i64)nao * f.ldw, f.ldw, nd, nao, nj, x.mp, nkb, Xp, xps, xkb,
-                                     uX, s));
-        JK_TRY(jk::launch_slice_elem(Yw, (i64)nao * f.ldw, f.ldw, nd, nao, nj, x.mp, nkb, Yp, xps, xkb,
-                                     uY, s));
-        JK_TRY(jk::launch_ex_mixed(Xp, Yp, xps, xkb, uX, uY, Kp, nao, nd, x.mp, nkb, x.nsplit, q0 > 0,
-                                   s));
+                                  bps, bkb, eB, s));
+        JK_TRY(jk::launch_ht_mixed(Bp, bps, bkb, eB, Cp, cps, ckb, eC, XY, nao, R2, nq, x.mp, x.cp,
+                                   x.kp / KB, s));
+        JK_TRY(jk::launch_xy_rowmax(XY, nao, nq, 2 * nd, r, x.mp, eXY, s));
+        JK_TRY(jk::launch_slice_xy(XY, nao, nd, r, x.mp, nj, nkb, XYp, xps, xkb, eXY, s));
+        JK_TRY(jk::launch_ex_mixed(Xp, Yp, xps, xkb, eXY, eXY + (size_t)nd * x.mp, Kp, nao, nd, x.mp,
+                                   nkb, x.nsplit, q0 > 0, s));
     }
     if (x.nsplit > 1)
         JK_TRY(jk::launch_sum_splits(Kp, K, (i64)nd * npos, x.nsplit, s));

@@ -75,18 +75,18 @@ hipError_t launch_slice_rows(const double *src, i64 bs, i64 rs, i64 ks, int nb, 
                              int rp, int nkb, int8_t *out, i64 pstride, i64 kbstride, int *exps,
                              hipStream_t s);
 hipError_t launch_slice_b(const double *src, i64 bs, i64 rs, int nb, int nr, int nk, int rp, int nkb,
-                          int8_t *out, i64 pstride, i64 kbstride, int *exps, unsigned *clr, int nclr,
-                          hipStream_t s);
-hipError_t launch_slice_elem(const double *src, i64 bs, i64 rs, int nb, int nr, int nk, int rp,
-                             int nkb, int8_t *out, i64 pstride, i64 kbstride, const unsigned *ux,
-                             hipStream_t s);
+                          int8_t *out, i64 pstride, i64 kbstride, int *exps, hipStream_t s);
+int mixed_rowmax_ok(int R2);
+hipError_t launch_xy_rowmax(const double *XY, int nao, int nq, int nkey, int r, int mp, int *exps,
+                            hipStream_t s);
+hipError_t launch_slice_xy(const double *XY, int nao, int nd, int r, int mp, int nj, int nkb,
+                           int8_t *out, i64 pstride, i64 kbstride, const int *exps, hipStream_t s);
 hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, i64 bkbstride, const int *eB,
-                           const int8_t *Cp, i64 cpstride, i64 ckbstride, const int *eC, double *Xw,
-                           double *Yw, unsigned *ux, int nao, int nd, int r, int nq, int mp, int cp,
-                           int nkb, int ldw, hipStream_t s);
+                           const int8_t *Cp, i64 cpstride, i64 ckbstride, const int *eC, double *XY,
+                           int nao, int R2, int nq, int mp, int cp, int nkb, hipStream_t s);
 int ex_mixed_nsplit(int mp, int nd, int nkb);
 hipError_t launch_ex_mixed(const int8_t *Xp, const int8_t *Yp, i64 pstride, i64 kbstride,
-                           const unsigned *ux, const unsigned *uy, double *Kp, int nao, int nd, int mp,
-                           int nkb, int nsplit, int accumulate, hipStream_t s);
+                           const int *eX, const int *eY, double *Kp, int nao, int nd, int mp, int nkb,
+                           int nsplit, int accumulate, hipStream_t s);
 
 } // namespace jk

@@ -6,6 +6,7 @@
 //
 //   slice   rows of an FP64 operand -> NS int8 digit planes + row exponent
 //   ht      [X^Q | Y^Q] = slices(B^Q) x slices([C_L | C_R]), recombined in FP64
+//   rowmax  exponent of every row (side, k, m) of X/Y over the chunk
 //   ex      K_k (+)= slices(X_k) x slices(Y_k) over the chunk, recombined in FP64
 #include "jk_kernels.hpp"
 #include "slice_core.hpp"
@@ -14,24 +15,12 @@ namespace jk {
 
 namespace {
 constexpr int kNS = 5;                  // digits per operand (35 bits)
-constexpr int kMT = 128, kNT = 64;      // workgroup tile (eight 32 x 32 waves)
-constexpr int kKBS = 2;                 // 32-byte inner blocks per pipeline stage
-constexpr int kRowPad = 128;            // plane rows are padded to this
-constexpr int kKPad = kKBS * kSliceKB;  // plane inner bytes are padded to this
-constexpr unsigned kExpBias = 2048;     // biased exponent code: 0 = no nonzero value
-typedef STile<kMT, kNT, kNS, kKBS> TileS;
+constexpr int kMT = 64, kNT = 64;       // workgroup tile (four 32 x 32 waves)
+constexpr int kRowPad = 64;             // plane rows are padded to this
+constexpr int kKPad = kSliceKB;         // plane inner bytes are padded to this
+typedef STile<kMT, kNT, kNS> TileS;
 
 inline int cdiv(i64 a, i64 b) { return (int)((a + b - 1) / b); }
-
-__device__ __forceinline__ int decode_exp(unsigned u) { return u ? (int)u - (int)kExpBias : 0; }
-
-// Biased code of the exponent e with |v| < 2^e, 2^(e-1) <= |v| (0 for v = 0).
-__device__ __forceinline__ unsigned exp_code(double v)
-{
-    int e;
-    frexp(v, &e);
-    return v != 0.0 ? (unsigned)(e + (int)kExpBias) : 0u;
-}
 
 __device__ __forceinline__ void write_digits(int8_t *dst, i64 pstride, const int8_t (*d)[kNS])
 {
@@ -90,19 +79,14 @@ __global__ void __launch_bounds__(256) k_slice_rows(const double *__restrict__ s
 
 // One-pass slicer for unit-stride rows of at most 256 * NJ elements: one wave
 // per row holds the row in registers (lane l: elements 4 l + 256 j + u),
-// reduces the maximum across the wave, then writes the digits.  Also clears
-// clr[0 .. nclr) (the exponent codes that the following half-transform
-// accumulates).
+// reduces the maximum across the wave, then writes the digits.
 template <int NJ>
 __global__ void __launch_bounds__(256) k_slice_rows_wave(const double *__restrict__ src, i64 bs,
                                                          i64 rs, int nb, int nr, int nk, int rp,
                                                          int nkb, int8_t *__restrict__ out,
                                                          i64 pstride, i64 kbstride,
-                                                         int *__restrict__ exps,
-                                                         unsigned *__restrict__ clr, int nclr)
+                                                         int *__restrict__ exps)
 {
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < nclr; i += gridDim.x * 256)
-        clr[i] = 0u;
     const int lane = threadIdx.x & 63;
     const i64 row = (i64)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= (i64)nb * rp)        // whole waves leave together
@@ -140,54 +124,55 @@ __global__ void __launch_bounds__(256) k_slice_rows_wave(const double *__restric
     }
 }
 
-// Elementwise slicer for rows whose exponents are already known (biased
-// codes ux[b * rp + m], see exp_code): unit-stride rows, 32 rows x one
-// 32-byte inner block per workgroup (grid: row groups x nkb); each plane
-// write of a workgroup is one contiguous kilobyte.
-__global__ void __launch_bounds__(256) k_slice_elem(const double *__restrict__ src, i64 bs, i64 rs,
-                                                    int nb, int nr, int nk, int rp,
-                                                    int8_t *__restrict__ out, i64 pstride,
-                                                    i64 kbstride, const unsigned *__restrict__ ux)
+// Elementwise slicer of the half-transformed factors.  Source XY[ql][m][c]
+// (c < 2R; X_k = columns k*r.., Y_k = columns R + k*r..), plane row
+// (side * nd + k) * mp + m, inner index j = ql * r + i (j < nj), row
+// exponents exps[plane row] known.  32 plane rows x one 32-byte inner block
+// per workgroup (grid: row groups x nkb); each plane write of a workgroup is
+// one contiguous kilobyte.
+__global__ void __launch_bounds__(256) k_slice_xy(const double *__restrict__ XY, int nao, int nd,
+                                                  int r, int mp, int nj, int8_t *__restrict__ out,
+                                                  i64 pstride, i64 kbstride,
+                                                  const int *__restrict__ exps)
 {
     const int t = threadIdx.x, sub = t & 7;
-    const i64 row = (i64)blockIdx.x * 32 + (t >> 3);
+    const int row = blockIdx.x * 32 + (t >> 3);
     const int kb = blockIdx.y;
-    if (row >= (i64)nb * rp)
+    if (row >= 2 * nd * mp)
         return;
-    const int b = (int)(row / rp), m = (int)(row % rp);
-    const bool live = m < nr;
-    const int e = live ? decode_exp(ux[row]) : 0;
-    const double *s = src + (i64)b * bs + (i64)m * rs;
+    const int key = row / mp, m = row % mp;
+    const bool live = m < nao;
+    const int e = live ? exps[row] : 0;
+    const i64 R2 = 2 * (i64)nd * r;
+    const double *s = XY + (i64)m * R2 + (i64)key * r;   // + ql * nao * R2 + i
+    const int j0 = kb * kSliceKB + sub * 4;
+    int ql = j0 / r, i = j0 % r;
     int8_t d[4][kNS];
 #pragma unroll
     for (int u = 0; u < 4; u++) {
-        const int k = kb * kSliceKB + sub * 4 + u;
-        const double v = (live && k < nk) ? s[k] : 0.0;
+        const double v = (live && j0 + u < nj) ? s[(i64)ql * nao * R2 + i] : 0.0;
         slice_value<kNS>(v, e, d[u]);
+        if (++i == r) {
+            i = 0;
+            ql++;
+        }
     }
-    write_digits(out + (i64)kb * kbstride + row * kSliceKB + sub * 4, pstride, d);
+    write_digits(out + (i64)kb * kbstride + (i64)row * kSliceKB + sub * 4, pstride, d);
 }
 
 // ------------------------------------------------------------------ half-transform
-// For slab ql of the chunk: XY[m][c] = 2^(eB + eC + 2) * sum_l S_l 2^(-7 l),
-// written as X_ws[k][m][ql*r + i] (c = k*r + i < R) or Y_ws (c - R).
-// A planes: rows ql * mp + m; B planes: rows c.  The epilogue also raises
-// ux[key * mp + m] (key = c / r: X_k for key < nd, Y_(key-nd) above) to the
-// exponent code of every value it writes: after all slabs of the chunk, ux
-// holds the row exponents the X/Y slicer needs.  Columns of one key are
-// contiguous, so a segmented max-scan over the 32 lanes of a row precedes
-// one atomic per (row, key) segment.
-__global__ void __launch_bounds__(512) k_ht_mixed(const int8_t *__restrict__ Bp, i64 bpstride,
+// For slab ql of the chunk: XY[ql][m][c] = 2^(eB + eC + 2) * sum_l S_l 2^(-7 l)
+// (c < R: X = B^Q C_L, c >= R: Y = B^Q C_R).  A planes: rows ql * mp + m;
+// B planes: rows c.  Each workgroup writes whole 512-byte row segments.
+__global__ void __launch_bounds__(256) k_ht_mixed(const int8_t *__restrict__ Bp, i64 bpstride,
                                                   i64 bkbstride, const int *__restrict__ eB,
                                                   const int8_t *__restrict__ Cp, i64 cpstride,
                                                   i64 ckbstride, const int *__restrict__ eC,
-                                                  double *__restrict__ Xw, double *__restrict__ Yw,
-                                                  unsigned *__restrict__ ux, int nao, int nd, int r,
-                                                  int mp, int cp, int nkb, int ldw)
+                                                  double *__restrict__ XY, int nao, int R2, int mp,
+                                                  int cp, int nkb)
 {
     extern __shared__ char lds[];
     typedef TileS TL;
-    const int R = nd * r, R2 = 2 * R;
     const int nmt = mp / kMT, nct = cp / kNT;
     const int t = blockIdx.x;
     const int ql = t / (nmt * nct), rem = t % (nmt * nct);
@@ -197,53 +182,60 @@ __global__ void __launch_bounds__(512) k_ht_mixed(const int8_t *__restrict__ Bp,
     SAcc<TL> acc;
     acc.zero();
     stile_gemm<TL, kNS>(a, b, mb * kMT, cb * kNT, 0, nkb, lds, acc);
-
-    const int lane = threadIdx.x & 63, l32 = lane & 31;
-    int row0, col;
-    stile_coord<TL>(0, row0, col);
-    const int c = cb * kNT + col;
-    const int key = c < R2 ? c / r : -1;
-    // segment structure of the 32 columns held by this half-wave
-    int kup[5];
-#pragma unroll
-    for (int s = 0; s < 5; s++)
-        kup[s] = __shfl_up(key, 1 << s, 32);
-    const int knext = __shfl_down(key, 1, 32);
-    const bool seg_end = l32 == 31 || knext != key;
+    double *out = XY + (i64)ql * nao * R2;
 #pragma unroll
     for (int e = 0; e < 16; e++) {
-        int row, cl;
-        stile_coord<TL>(e, row, cl);
-        const int m = mb * kMT + row;
-        const bool ok = m < nao && key >= 0;
-        double v = 0.0;
-        if (ok) {
-            v = ldexp(combine_levels<TL>(acc, e), eB[(i64)ql * mp + m] + eC[c] + 2);
-            double *dst = c < R ? Xw : Yw;
-            const int cc = c < R ? c : c - R;
-            const int k = cc / r, i = cc % r;
-            dst[((i64)k * nao + m) * ldw + (i64)ql * r + i] = v;
+        int row, col;
+        stile_coord<TL>(e, row, col);
+        const int m = mb * kMT + row, c = cb * kNT + col;
+        if (m < nao && c < R2)
+            out[(i64)m * R2 + c] =
+                ldexp(combine_levels<TL>(acc, e), eB[(i64)ql * mp + m] + eC[c] + 2);
+    }
+}
+
+// Row exponents of X/Y over the chunk: exps[key * mp + m] for key = side * nd
+// + k, the maximum over slabs ql < nq and i < r of |XY[ql][m][key * r + i]|.
+// One workgroup per m: column maxima over the slabs (coalesced along c), then
+// the maximum over each key's r columns through LDS (2R doubles).
+__global__ void __launch_bounds__(256) k_xy_rowmax(const double *__restrict__ XY, int nao, int nq,
+                                                   int nkey, int r, int mp, int *__restrict__ exps)
+{
+    extern __shared__ double colmax[];
+    const int m = blockIdx.x;
+    const int R2 = nkey * r;
+    const i64 qs = (i64)nao * R2;
+    const double *s = XY + (i64)m * R2;
+    for (int c = threadIdx.x; c < R2; c += 256) {
+        double mx0 = 0.0, mx1 = 0.0, mx2 = 0.0, mx3 = 0.0;
+        int q = 0;
+        for (; q + 4 <= nq; q += 4) {
+            mx0 = fmax(mx0, fabs(s[(i64)q * qs + c]));
+            mx1 = fmax(mx1, fabs(s[(i64)(q + 1) * qs + c]));
+            mx2 = fmax(mx2, fabs(s[(i64)(q + 2) * qs + c]));
+            mx3 = fmax(mx3, fabs(s[(i64)(q + 3) * qs + c]));
         }
-        unsigned code = ok ? exp_code(v) : 0u;
-#pragma unroll
-        for (int s = 0; s < 5; s++) {
-            const unsigned o = __shfl_up(code, 1 << s, 32);
-            if (l32 >= (1 << s) && kup[s] == key)
-                code = o > code ? o : code;
-        }
-        if (ok && seg_end && code != 0u)
-            atomicMax(ux + (i64)key * mp + m, code);
+        for (; q < nq; q++)
+            mx0 = fmax(mx0, fabs(s[(i64)q * qs + c]));
+        colmax[c] = fmax(fmax(mx0, mx1), fmax(mx2, mx3));
+    }
+    __syncthreads();
+    for (int key = threadIdx.x; key < nkey; key += 256) {
+        double mx = 0.0;
+        for (int i = 0; i < r; i++)
+            mx = fmax(mx, colmax[key * r + i]);
+        exps[(i64)key * mp + m] = row_exponent(mx);
     }
 }
 
 // ------------------------------------------------------------------ exchange
 // Kp[s][k][m][n] (+)= 2^(eX + eY + 2) * sum_l S_l 2^(-7 l) over the inner
-// blocks [s * kbl, (s + 1) * kbl) of split s.  X/Y planes: rows k * mp + m;
-// exponent codes ux[k * mp + m] (X) and uy[k * mp + n] (Y).
-__global__ void __launch_bounds__(512) k_ex_mixed(const int8_t *__restrict__ Xp,
+// blocks [s * kbl, (s + 1) * kbl) of split s.  X/Y planes: rows k * mp + m
+// from Xp / Yp (same strides); row exponents eX[k * mp + m], eY[k * mp + n].
+__global__ void __launch_bounds__(256) k_ex_mixed(const int8_t *__restrict__ Xp,
                                                   const int8_t *__restrict__ Yp, i64 pstride,
-                                                  i64 kbstride, const unsigned *__restrict__ ux,
-                                                  const unsigned *__restrict__ uy,
+                                                  i64 kbstride, const int *__restrict__ eX,
+                                                  const int *__restrict__ eY,
                                                   double *__restrict__ Kp, int nao, int nd, int mp,
                                                   int nkb, int kbl, int accumulate)
 {
@@ -270,18 +262,11 @@ __global__ void __launch_bounds__(512) k_ex_mixed(const int8_t *__restrict__ Xp,
         const int m = mb * kMT + row, n = nb * kNT + col;
         if (m < nao && n < nao) {
             const double v = ldexp(combine_levels<TL>(acc, e),
-                                   decode_exp(ux[(i64)k * mp + m]) + decode_exp(uy[(i64)k * mp + n]) + 2);
+                                   eX[(i64)k * mp + m] + eY[(i64)k * mp + n] + 2);
             const i64 o = (i64)m * nao + n;
             Kk[o] = accumulate ? Kk[o] + v : v;
         }
     }
-}
-
-__global__ void __launch_bounds__(256) k_fill_u32(unsigned *__restrict__ p, int n)
-{
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < n)
-        p[i] = 0u;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -303,45 +288,50 @@ hipError_t launch_slice_rows(const double *src, i64 bs, i64 rs, i64 ks, int nb, 
 }
 
 hipError_t launch_slice_b(const double *src, i64 bs, i64 rs, int nb, int nr, int nk, int rp, int nkb,
-                          int8_t *out, i64 pstride, i64 kbstride, int *exps, unsigned *clr, int nclr,
-                          hipStream_t s)
+                          int8_t *out, i64 pstride, i64 kbstride, int *exps, hipStream_t s)
 {
     const int nj = cdiv(nkb, 8);
+    if (nj > 8)     // long rows: generic two-pass slicer
+        return launch_slice_rows(src, bs, rs, 1, nb, nr, nk, rp, nkb, out, pstride, kbstride, exps, s);
     const dim3 g(cdiv((i64)nb * rp, 4));
     {
         ProfScope ps_("slice_b", s);
         if (nj <= 1)
             hipLaunchKernelGGL(k_slice_rows_wave<1>, g, dim3(256), 0, s, src, bs, rs, nb, nr, nk, rp,
-                               nkb, out, pstride, kbstride, exps, clr, nclr);
+                               nkb, out, pstride, kbstride, exps);
         else if (nj <= 2)
             hipLaunchKernelGGL(k_slice_rows_wave<2>, g, dim3(256), 0, s, src, bs, rs, nb, nr, nk, rp,
-                               nkb, out, pstride, kbstride, exps, clr, nclr);
+                               nkb, out, pstride, kbstride, exps);
         else if (nj <= 4)
             hipLaunchKernelGGL(k_slice_rows_wave<4>, g, dim3(256), 0, s, src, bs, rs, nb, nr, nk, rp,
-                               nkb, out, pstride, kbstride, exps, clr, nclr);
-        else if (nj <= 8)
+                               nkb, out, pstride, kbstride, exps);
+        else
             hipLaunchKernelGGL(k_slice_rows_wave<8>, g, dim3(256), 0, s, src, bs, rs, nb, nr, nk, rp,
-                               nkb, out, pstride, kbstride, exps, clr, nclr);
+                               nkb, out, pstride, kbstride, exps);
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || nj <= 8)
-        return e;
-    // long rows: generic two-pass slicer plus a separate clear
-    e = launch_slice_rows(src, bs, rs, 1, nb, nr, nk, rp, nkb, out, pstride, kbstride, exps, s);
-    if (e != hipSuccess || nclr <= 0)
-        return e;
-    hipLaunchKernelGGL(k_fill_u32, dim3(cdiv(nclr, 256)), dim3(256), 0, s, clr, nclr);
     return hipGetLastError();
 }
 
-hipError_t launch_slice_elem(const double *src, i64 bs, i64 rs, int nb, int nr, int nk, int rp,
-                             int nkb, int8_t *out, i64 pstride, i64 kbstride, const unsigned *ux,
-                             hipStream_t s)
+int mixed_rowmax_ok(int R2) { return R2 <= 8192; }
+
+hipError_t launch_xy_rowmax(const double *XY, int nao, int nq, int nkey, int r, int mp, int *exps,
+                            hipStream_t s)
+{
+    {
+        ProfScope ps_("xy_rowmax", s);
+        hipLaunchKernelGGL(k_xy_rowmax, dim3(nao), dim3(256), sizeof(double) * nkey * r, s, XY, nao,
+                           nq, nkey, r, mp, exps);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_slice_xy(const double *XY, int nao, int nd, int r, int mp, int nj, int nkb,
+                           int8_t *out, i64 pstride, i64 kbstride, const int *exps, hipStream_t s)
 {
     {
         ProfScope ps_("slice_xy", s);
-        hipLaunchKernelGGL(k_slice_elem, dim3(cdiv((i64)nb * rp, 32), nkb), dim3(256), 0, s, src, bs,
-                           rs, nb, nr, nk, rp, out, pstride, kbstride, ux);
+        hipLaunchKernelGGL(k_slice_xy, dim3(cdiv((i64)2 * nd * mp, 32), nkb), dim3(256), 0, s, XY, nao,
+                           nd, r, mp, nj, out, pstride, kbstride, exps);
     }
     return hipGetLastError();
 }
@@ -360,9 +350,8 @@ static hipError_t set_lds(const void *fn, bool &done)
 static bool g_lds_ht = false, g_lds_ex = false;
 
 hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, i64 bkbstride, const int *eB,
-                           const int8_t *Cp, i64 cpstride, i64 ckbstride, const int *eC, double *Xw,
-                           double *Yw, unsigned *ux, int nao, int nd, int r, int nq, int mp, int cp,
-                           int nkb, int ldw, hipStream_t s)
+                           const int8_t *Cp, i64 cpstride, i64 ckbstride, const int *eC, double *XY,
+                           int nao, int R2, int nq, int mp, int cp, int nkb, hipStream_t s)
 {
     hipError_t e = set_lds((const void *)k_ht_mixed, g_lds_ht);
     if (e != hipSuccess)
@@ -371,7 +360,7 @@ hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, i64 bkbstride, const 
         ProfScope ps_("ht_mixed", s);
         hipLaunchKernelGGL(k_ht_mixed, dim3(nq * (mp / kMT) * (cp / kNT)), dim3(TileS::NTHR),
                            TileS::LDS_BYTES, s, Bp, bpstride, bkbstride, eB, Cp, cpstride, ckbstride,
-                           eC, Xw, Yw, ux, nao, nd, r, mp, cp, nkb, ldw);
+                           eC, XY, nao, R2, mp, cp, nkb);
     }
     return hipGetLastError();
 }
@@ -386,18 +375,17 @@ int ex_mixed_nsplit(int mp, int nd, int nkb)
 }
 
 hipError_t launch_ex_mixed(const int8_t *Xp, const int8_t *Yp, i64 pstride, i64 kbstride,
-                           const unsigned *ux, const unsigned *uy, double *Kp, int nao, int nd, int mp,
-                           int nkb, int nsplit, int accumulate, hipStream_t s)
+                           const int *eX, const int *eY, double *Kp, int nao, int nd, int mp, int nkb,
+                           int nsplit, int accumulate, hipStream_t s)
 {
     hipError_t e = set_lds((const void *)k_ex_mixed, g_lds_ex);
     if (e != hipSuccess)
         return e;
-    int kbl = cdiv(nkb, nsplit);
-    kbl = cdiv(kbl, kKBS) * kKBS;
+    const int kbl = cdiv(nkb, nsplit);
     {
         ProfScope ps_("ex_mixed", s);
         hipLaunchKernelGGL(k_ex_mixed, dim3(nsplit * nd * (mp / kMT) * (mp / kNT)), dim3(TileS::NTHR),
-                           TileS::LDS_BYTES, s, Xp, Yp, pstride, kbstride, ux, uy, Kp, nao, nd, mp, nkb,
+                           TileS::LDS_BYTES, s, Xp, Yp, pstride, kbstride, eX, eY, Kp, nao, nd, mp, nkb,
                            kbl, accumulate);
     }
     return hipGetLastError();

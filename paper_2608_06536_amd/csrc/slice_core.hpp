@@ -75,28 +75,32 @@ struct SPlanes {
 
 // ---------------------------------------------------------------- tile GEMM
 // One workgroup: BM x BN output tile, waves (BM/32) x (BN/32), one 32x32
-// MFMA tile per wave, NS digit planes per operand.  A stage holds KBS inner
-// blocks of 32 bytes.  LDS stage layout: [plane][block][row][32 bytes] for A,
-// then the same for B, unpadded: the 16-byte chunks of a stage land in LDS in
-// the order they are read from global memory, and a fragment read by 64
-// lanes is 2 KB contiguous.  Inner ranges must be multiples of KBS blocks
-// (planes are zero-padded to that).
-template <int BM, int BN, int NS, int KBS>
+// MFMA tile per wave, NS digit planes per operand, one 32-byte inner block
+// per pipeline stage.  LDS stage layout: [plane][row][32 bytes] for A, then
+// the same for B.  The two 16-byte halves of a row swap places on every
+// other group of 8 rows, so the 64 lanes of a fragment read (rows r..r+31,
+// half l/32) spread evenly over the LDS banks.
+template <int BM, int BN, int NS>
 struct STile {
     static constexpr int WROWS = BM / 32, WCOLS = BN / 32;
     static constexpr int NWAVE = WROWS * WCOLS;
     static constexpr int NTHR = NWAVE * 64;
     static constexpr int NLEV = NS;            // levels 2..NS+1
-    static constexpr int KB = KBS;
-    static constexpr int A_BYTES = NS * KBS * BM * kSliceKB, B_BYTES = NS * KBS * BN * kSliceKB;
+    static constexpr int A_BYTES = NS * BM * kSliceKB, B_BYTES = NS * BN * kSliceKB;
     static constexpr int STAGE_BYTES = A_BYTES + B_BYTES;
     static constexpr int LDS_BYTES = 2 * STAGE_BYTES;
 };
 
-template <int T, int NS, int KBS, int NTHR>
+// Byte offset of (row, 16-byte half) inside a plane of an LDS stage.
+__device__ __forceinline__ int slds_off(int row, int half)
+{
+    return row * kSliceKB + ((half ^ ((row >> 3) & 1)) << 4);
+}
+
+template <int T, int NS, int NTHR>
 struct SLoader {
-    // 16-byte chunks per stage: NS planes x KBS blocks x T rows x 2
-    static constexpr int NCH = NS * KBS * T * 2;
+    // 16-byte chunks per stage: NS planes x T rows x 2 halves
+    static constexpr int NCH = NS * T * 2;
     static constexpr int NSTEP = (NCH + NTHR - 1) / NTHR;
     v4i v[NSTEP];
 
@@ -106,9 +110,8 @@ struct SLoader {
         for (int s = 0; s < NSTEP; s++) {
             const int c = tid + s * NTHR;
             if (NCH % NTHR == 0 || c < NCH) {
-                const int p = c / (KBS * T * 2), rem = c % (KBS * T * 2);
-                const int kbl = rem / (T * 2), rr = rem % (T * 2);
-                v[s] = *(const v4i *)(op.base + p * op.pstride + (i64)(kb + kbl) * op.kbstride +
+                const int p = c / (T * 2), rr = c % (T * 2);
+                v[s] = *(const v4i *)(op.base + p * op.pstride + (i64)kb * op.kbstride +
                                       (i64)i0 * kSliceKB + rr * 16);
             }
         }
@@ -119,8 +122,10 @@ struct SLoader {
 #pragma unroll
         for (int s = 0; s < NSTEP; s++) {
             const int c = tid + s * NTHR;
-            if (NCH % NTHR == 0 || c < NCH)
-                *(v4i *)(lds + c * 16) = v[s];
+            if (NCH % NTHR == 0 || c < NCH) {
+                const int p = c / (T * 2), rr = c % (T * 2);
+                *(v4i *)(lds + p * T * kSliceKB + slds_off(rr >> 1, rr & 1)) = v[s];
+            }
         }
     }
 };
@@ -140,52 +145,71 @@ struct SAcc {
 
 // acc_l += sum over inner blocks [kb_begin, kb_end) of the digit pair
 // products with i + j = l + 2 (i, j = 1..NS, i + j <= NS + 1).
-// kb_end - kb_begin must be a multiple of TL::KB.
+//
+// Pipeline: the block of stage s is copied global -> registers -> LDS buffer
+// s % 2 during stage s - 2, its fragments are read from LDS into registers
+// during stage s - 1 (while the MFMAs of stage s - 1 run), and it is
+// multiplied in stage s.  One barrier per stage; at that barrier the buffer
+// being refilled was last read a full stage earlier.
 template <class TL, int NS>
 __device__ __forceinline__ void stile_gemm(const SPlanes &A, const SPlanes &B, int m0, int n0,
                                            int kb_begin, int kb_end, char *lds, SAcc<TL> &acc)
 {
-    constexpr int BM = TL::WROWS * 32, BN = TL::WCOLS * 32, KBS = TL::KB;
+    constexpr int BM = TL::WROWS * 32, BN = TL::WCOLS * 32;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
-    SLoader<BM, NS, KBS, TL::NTHR> la;
-    SLoader<BN, NS, KBS, TL::NTHR> lb;
-    const int nst = (kb_end - kb_begin) / KBS;
+    SLoader<BM, NS, TL::NTHR> la;
+    SLoader<BN, NS, TL::NTHR> lb;
+    const int nst = kb_end - kb_begin;
     if (nst <= 0)
         return;
     la.load(A, m0, kb_begin, tid);
     lb.load(B, n0, kb_begin, tid);
     la.store(lds, tid);
     lb.store(lds + TL::A_BYTES, tid);
+    if (nst > 1) {
+        la.load(A, m0, kb_begin + 1, tid);
+        lb.load(B, n0, kb_begin + 1, tid);
+        la.store(lds + TL::STAGE_BYTES, tid);
+        lb.store(lds + TL::STAGE_BYTES + TL::A_BYTES, tid);
+    }
     __syncthreads();
-    const int aoff = (wr * 32 + (lane & 31)) * kSliceKB + 16 * (lane >> 5);
-    const int boff = (wc * 32 + (lane & 31)) * kSliceKB + 16 * (lane >> 5);
+    const int aoff = slds_off(wr * 32 + (lane & 31), lane >> 5);
+    const int boff = slds_off(wc * 32 + (lane & 31), lane >> 5);
+    v4i fa[NS], fb[NS];
+#pragma unroll
+    for (int p = 0; p < NS; p++) {
+        fa[p] = *(const v4i *)(lds + p * BM * kSliceKB + aoff);
+        fb[p] = *(const v4i *)(lds + TL::A_BYTES + p * BN * kSliceKB + boff);
+    }
     for (int st = 0; st < nst; st++) {
-        const int cur = st & 1;
-        const bool more = st + 1 < nst;
-        if (more) {
-            la.load(A, m0, kb_begin + (st + 1) * KBS, tid);
-            lb.load(B, n0, kb_begin + (st + 1) * KBS, tid);
+        const bool more2 = st + 2 < nst;
+        if (more2) {
+            la.load(A, m0, kb_begin + st + 2, tid);
+            lb.load(B, n0, kb_begin + st + 2, tid);
         }
-        const char *sa = lds + cur * TL::STAGE_BYTES;
+        // fragments of stage st + 1 (on the last stage: a harmless re-read)
+        const char *sa = lds + ((st + 1) & 1) * TL::STAGE_BYTES;
         const char *sb = sa + TL::A_BYTES;
+        v4i ga[NS], gb[NS];
 #pragma unroll
-        for (int kbl = 0; kbl < KBS; kbl++) {
-            v4i a[NS], b[NS];
-#pragma unroll
-            for (int p = 0; p < NS; p++) {
-                a[p] = *(const v4i *)(sa + (p * KBS + kbl) * BM * kSliceKB + aoff);
-                b[p] = *(const v4i *)(sb + (p * KBS + kbl) * BN * kSliceKB + boff);
-            }
-#pragma unroll
-            for (int i = 0; i < NS; i++)
-#pragma unroll
-                for (int j = 0; j < NS - i; j++)          // (i+1) + (j+1) <= NS + 1
-                    acc.c[i + j] = mfma_i8(a[i], b[j], acc.c[i + j]);
+        for (int p = 0; p < NS; p++) {
+            ga[p] = *(const v4i *)(sa + p * BM * kSliceKB + aoff);
+            gb[p] = *(const v4i *)(sb + p * BN * kSliceKB + boff);
         }
-        if (more) {
-            la.store(lds + (cur ^ 1) * TL::STAGE_BYTES, tid);
-            lb.store(lds + (cur ^ 1) * TL::STAGE_BYTES + TL::A_BYTES, tid);
+#pragma unroll
+        for (int i = 0; i < NS; i++)
+#pragma unroll
+            for (int j = 0; j < NS - i; j++)          // (i+1) + (j+1) <= NS + 1
+                acc.c[i + j] = mfma_i8(fa[i], fb[j], acc.c[i + j]);
+#pragma unroll
+        for (int p = 0; p < NS; p++) {
+            fa[p] = ga[p];
+            fb[p] = gb[p];
+        }
+        if (more2) {
+            la.store(lds + (st & 1) * TL::STAGE_BYTES, tid);
+            lb.store(lds + (st & 1) * TL::STAGE_BYTES + TL::A_BYTES, tid);
         }
         __syncthreads();
     }

@@ -93,7 +93,8 @@ __global__ void __launch_bounds__(256) k_slice_rows_wave(const double *__restric
         return;
     const int b = (int)(row / rp), m = (int)(row % rp);
     const bool live = m < nr;
-    const double *s = src + (i64)b * bs + (i64)m * rs;
+    // loads are unconditional (clamped addresses), masked afterwards
+    const double *s = src + (i64)b * bs + (i64)(live ? m : nr - 1) * rs;
     double v[NJ][4];
     double mx = 0.0;
 #pragma unroll
@@ -101,7 +102,8 @@ __global__ void __launch_bounds__(256) k_slice_rows_wave(const double *__restric
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const int k = 256 * j + 4 * lane + u;
-            v[j][u] = (live && k < nk) ? s[k] : 0.0;
+            const double x = s[k < nk ? k : nk - 1];
+            v[j][u] = (live && k < nk) ? x : 0.0;
             mx = fmax(mx, fabs(v[j][u]));
         }
 #pragma unroll
@@ -142,21 +144,22 @@ __global__ void __launch_bounds__(256) k_slice_xy(const double *__restrict__ XY,
         return;
     const int key = row / mp, m = row % mp;
     const bool live = m < nao;
-    const int e = live ? exps[row] : 0;
+    const int e = exps[row];
     const i64 R2 = 2 * (i64)nd * r;
-    const double *s = XY + (i64)m * R2 + (i64)key * r;   // + ql * nao * R2 + i
+    // loads are unconditional (clamped addresses), masked afterwards
+    const double *s = XY + (i64)(live ? m : nao - 1) * R2 + (i64)key * r;
     const int j0 = kb * kSliceKB + sub * 4;
-    int ql = j0 / r, i = j0 % r;
-    int8_t d[4][kNS];
+    double x[4];
 #pragma unroll
     for (int u = 0; u < 4; u++) {
-        const double v = (live && j0 + u < nj) ? s[(i64)ql * nao * R2 + i] : 0.0;
-        slice_value<kNS>(v, e, d[u]);
-        if (++i == r) {
-            i = 0;
-            ql++;
-        }
+        const int j = (j0 + u) < nj ? (j0 + u) : nj - 1;
+        const int ql = j / r, i = j - ql * r;
+        x[u] = s[(i64)ql * nao * R2 + i];
     }
+    int8_t d[4][kNS];
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+        slice_value<kNS>((live && j0 + u < nj) ? x[u] : 0.0, e, d[u]);
     write_digits(out + (i64)kb * kbstride + (i64)row * kSliceKB + sub * 4, pstride, d);
 }
 
@@ -207,17 +210,26 @@ __global__ void __launch_bounds__(256) k_xy_rowmax(const double *__restrict__ XY
     const i64 qs = (i64)nao * R2;
     const double *s = XY + (i64)m * R2;
     for (int c = threadIdx.x; c < R2; c += 256) {
-        double mx0 = 0.0, mx1 = 0.0, mx2 = 0.0, mx3 = 0.0;
+        double mx[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+            mx[u] = 0.0;
         int q = 0;
-        for (; q + 4 <= nq; q += 4) {
-            mx0 = fmax(mx0, fabs(s[(i64)q * qs + c]));
-            mx1 = fmax(mx1, fabs(s[(i64)(q + 1) * qs + c]));
-            mx2 = fmax(mx2, fabs(s[(i64)(q + 2) * qs + c]));
-            mx3 = fmax(mx3, fabs(s[(i64)(q + 3) * qs + c]));
+        for (; q + 8 <= nq; q += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++)
+                v[u] = __builtin_nontemporal_load(s + (i64)(q + u) * qs + c);
+#pragma unroll
+            for (int u = 0; u < 8; u++)
+                mx[u] = fmax(mx[u], fabs(v[u]));
         }
         for (; q < nq; q++)
-            mx0 = fmax(mx0, fabs(s[(i64)q * qs + c]));
-        colmax[c] = fmax(fmax(mx0, mx1), fmax(mx2, mx3));
+            mx[0] = fmax(mx[0], fabs(s[(i64)q * qs + c]));
+#pragma unroll
+        for (int u = 1; u < 8; u++)
+            mx[0] = fmax(mx[0], mx[u]);
+        colmax[c] = mx[0];
     }
     __syncthreads();
     for (int key = threadIdx.x; key < nkey; key += 256) {

@@ -52,8 +52,8 @@ __host__ __device__ inline int project_tiles(int naux, int nd, int npb)
 {
     return cdiv_i(naux, kProjRows) * cdiv_i(nd, 8) * npb;
 }
-__host__ __device__ inline int reduce_tiles(int naux, int nd) { return cdiv_i((i64)naux * nd, kElemTile); }
-__host__ __device__ inline int coulomb_tiles(int nd, i64 npos) { return cdiv_i(nd, 8) * cdiv_i(npos, 256); }
+__host__ __device__ inline int reduce_tiles(int naux, int nd) { return cdiv_i((i64)naux * (cdiv_i(nd, 8) * 8), 64); }
+__host__ __device__ inline int coulomb_tiles(int nd, i64 npos) { return cdiv_i(nd, 8) * cdiv_i(npos, 512); }
 __host__ __device__ inline int ht_tiles(int nao, int nd, int r, int nq)
 {
     return nq * cdiv_i(nao, kHtM) * cdiv_i(2 * (i64)nd * r, kHtN);
@@ -131,68 +131,103 @@ __device__ inline void project_tile(const double *__restrict__ B, const double *
     });
 }
 
-// g[k][Q] = sum_{pb} part[pb][Q][k] (fixed order).
+// g[k][Q] = sum_{pb} part[pb][Q][k] in a fixed order.  A tile covers 64
+// consecutive entries (Q, k) of one partial block; wave w of the four sums
+// the blocks pb = w, w + 4, ... (coalesced 512-byte reads), and the four wave
+// sums are added in wave order.
 __device__ inline void reduce_tile(const double *__restrict__ part, double *__restrict__ g, int naux,
                                    int nd, int npb, int tile)
 {
+    __shared__ double red[4][64];
     const int ndp = cdiv_i(nd, 8) * 8;
-    const i64 total = (i64)naux * nd;
-    for (int u = 0; u < kElemTile / 256; u++) {
-        const i64 e = (i64)tile * kElemTile + u * 256 + threadIdx.x;
-        if (e < total) {
-            const int k = (int)(e / naux), q = (int)(e % naux);
-            double s = 0.0;
-            for (int pb = 0; pb < npb; pb++)
-                s += part[((i64)pb * naux + q) * ndp + k];
-            g[(i64)k * naux + q] = s;
+    const i64 total = (i64)naux * ndp;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const i64 e = (i64)tile * 64 + lane;
+    double s = 0.0;
+    if (e < total) {
+        const double *src = part + e;
+        int pb = w;
+        for (; pb + 12 < npb; pb += 16) {
+            const double v0 = src[(i64)pb * total], v1 = src[(i64)(pb + 4) * total];
+            const double v2 = src[(i64)(pb + 8) * total], v3 = src[(i64)(pb + 12) * total];
+            s += v0;
+            s += v1;
+            s += v2;
+            s += v3;
         }
+        for (; pb < npb; pb += 4)
+            s += src[(i64)pb * total];
+    }
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && e < total) {
+        const int q = (int)(e / ndp), k = (int)(e % ndp);
+        if (k < nd)
+            g[(i64)k * naux + q] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
     }
 }
 
 // ------------------------------------------------------------------ coulomb
-// J[k][p] = sum_Q g[k][Q] B[Q][p] for the 8 densities of group kg and the 256
-// positions of block pb: one position per thread, Q unrolled by 8 for loads
-// in flight.  HBM-bound stream over B.
+// J[k][p] = sum_Q g[k][Q] B[Q][p] for the 8 densities of group kg and the 512
+// positions of block pb: thread t takes positions pb*512 + t and + 256 (each
+// load instruction reads 512 contiguous bytes), Q unrolled by 8, so 16 loads
+// per thread are in flight.  The inner loop has no branches: positions past
+// the end read a valid clamped address and densities past nd repeat the last
+// one; neither is stored.  HBM-bound stream over B.
 __device__ inline void coulomb_tile(const double *__restrict__ B, const double *__restrict__ g,
                                     double *__restrict__ J, int naux, int nd, i64 npos, int tile)
 {
-    const int npb = cdiv_i(npos, 256);
+    const int npb = cdiv_i(npos, 512);
     const int kg = tile / npb, pb = tile % npb;
     const int k0 = kg * 8;
-    const i64 p = (i64)pb * 256 + threadIdx.x;
     const int nk = (nd - k0) < 8 ? (nd - k0) : 8;
-    double acc[8];
+    const i64 p0 = (i64)pb * 512 + threadIdx.x, p1 = p0 + 256;
+    const double *b0 = B + (p0 < npos ? p0 : npos - 1);
+    const double *b1 = B + (p1 < npos ? p1 : npos - 1);
+    const double *gk[8];
 #pragma unroll
     for (int k = 0; k < 8; k++)
-        acc[k] = 0.0;
-    const bool ok = p < npos;
-    const double *bp = B + (ok ? p : 0);
+        gk[k] = g + (i64)(k0 + (k < nk ? k : nk - 1)) * naux;
+    double a0[8], a1[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        a0[k] = 0.0;
+        a1[k] = 0.0;
+    }
     int q = 0;
     for (; q + 8 <= naux; q += 8) {
-        double bv[8];
+        double v0[8], v1[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            v0[u] = __builtin_nontemporal_load(b0 + (i64)(q + u) * npos);
+            v1[u] = __builtin_nontemporal_load(b1 + (i64)(q + u) * npos);
+        }
 #pragma unroll
         for (int u = 0; u < 8; u++)
-            bv[u] = ok ? __builtin_nontemporal_load(bp + (i64)(q + u) * npos) : 0.0;
 #pragma unroll
-        for (int u = 0; u < 8; u++)
-#pragma unroll
-            for (int k = 0; k < 8; k++)
-                if (k < nk)
-                    acc[k] = fma(g[(i64)(k0 + k) * naux + q + u], bv[u], acc[k]);
+            for (int k = 0; k < 8; k++) {
+                const double gv = gk[k][q + u];
+                a0[k] = fma(gv, v0[u], a0[k]);
+                a1[k] = fma(gv, v1[u], a1[k]);
+            }
     }
     for (; q < naux; q++) {
-        const double b = ok ? bp[(i64)q * npos] : 0.0;
+        const double v0 = b0[(i64)q * npos], v1 = b1[(i64)q * npos];
 #pragma unroll
-        for (int k = 0; k < 8; k++)
-            if (k < nk)
-                acc[k] = fma(g[(i64)(k0 + k) * naux + q], b, acc[k]);
+        for (int k = 0; k < 8; k++) {
+            const double gv = gk[k][q];
+            a0[k] = fma(gv, v0, a0[k]);
+            a1[k] = fma(gv, v1, a1[k]);
+        }
     }
-    if (ok) {
 #pragma unroll
-        for (int k = 0; k < 8; k++)
-            if (k < nk)
-                J[(i64)(k0 + k) * npos + p] = acc[k];
-    }
+    for (int k = 0; k < 8; k++)
+        if (k < nk) {
+            if (p0 < npos)
+                J[(i64)(k0 + k) * npos + p0] = a0[k];
+            if (p1 < npos)
+                J[(i64)(k0 + k) * npos + p1] = a1[k];
+        }
 }
 
 // ------------------------------------------------------------------ half-transform

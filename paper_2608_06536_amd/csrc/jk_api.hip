@@ -151,12 +151,15 @@ VjpPlan plan_vjp(const jk_problem *p)
             return JK_EHIP;                                                                        \
     } while (0)
 
-// Mixed-precision plan: the FP64 plan (gamma, J, X/Y chunk buffers) plus
-// int8 digit planes of B (per chunk), of [C_L | C_R] and of X/Y (per chunk).
+// Mixed-precision plan: the FP64 plan (gamma, J, chunk buffers) plus int8
+// digit planes of [C_L | C_R] and, double-buffered so that consecutive
+// chunks overlap, the digit planes of B, the half-transformed factors XY and
+// their digit planes.
 struct MixPlan {
     FwdPlan f;
     int ns, mp, kp, cp, jp, nsplit;
-    size_t o_bp, o_eb, o_cp, o_ec, o_xyp, o_exy, o_kp, total;
+    size_t bp_bytes, xy_bytes, xyp_bytes;
+    size_t o_bp[2], o_eb[2], o_xy[2], o_xyp[2], o_exy[2], o_cp, o_ec, o_kp, total;
 };
 
 inline i64 pad_to(i64 x, i64 m) { return ((x + m - 1) / m) * m; }
@@ -172,18 +175,71 @@ MixPlan plan_mixed(const jk_problem *p)
     x.cp = (int)pad_to(2 * R, jk::mixed_row_pad());
     x.jp = (int)pad_to((i64)x.f.qc * r, jk::mixed_k_pad());
     x.nsplit = jk::ex_mixed_nsplit(x.mp, (int)nd, x.jp / jk::mixed_k_block());
+    x.bp_bytes = (size_t)x.ns * x.f.qc * x.mp * x.kp;
+    x.xy_bytes = sizeof(double) * (size_t)x.f.qc * nao * 2 * R;
+    x.xyp_bytes = (size_t)x.ns * 2 * nd * x.mp * x.jp;
     Carve c;
     c.off = x.f.total;
-    x.o_bp = c.take((size_t)x.ns * x.f.qc * x.mp * x.kp);
-    x.o_eb = c.take(sizeof(int) * (size_t)x.f.qc * x.mp);
+    // XY buffer 0 is the FP64 path's X and Y chunk buffers, carved back to
+    // back (together at least qc * nao * 2R doubles).
+    x.o_xy[0] = x.f.o_x;
+    x.o_xy[1] = c.take(x.xy_bytes);
+    for (int b = 0; b < 2; b++) {
+        x.o_bp[b] = c.take(x.bp_bytes);
+        x.o_eb[b] = c.take(sizeof(int) * (size_t)x.f.qc * x.mp);
+        x.o_xyp[b] = c.take(x.xyp_bytes);
+        x.o_exy[b] = c.take(sizeof(int) * (size_t)2 * nd * x.mp);
+    }
     x.o_cp = c.take((size_t)x.ns * x.cp * x.kp);
     x.o_ec = c.take(sizeof(int) * (size_t)x.cp);
-    x.o_xyp = c.take((size_t)x.ns * 2 * nd * x.mp * x.jp);
-    x.o_exy = c.take(sizeof(int) * (size_t)2 * nd * x.mp);
     x.o_kp = c.take(sizeof(double) * (size_t)x.nsplit * nd * nao * nao);
     x.total = c.off;
     return x;
 }
+
+// Second stream per device for the HBM-bound slicing work of the mixed
+// build (default priority, non-blocking, kept for the life of the process).
+hipError_t aux_stream(hipStream_t *out)
+{
+    static std::mutex mu;
+    static std::map<int, hipStream_t> streams;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = streams.find(dev);
+    if (it == streams.end()) {
+        hipStream_t st = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e != hipSuccess)
+            return e;
+        it = streams.emplace(dev, st).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
+
+// Events of one call (destroyed when the call returns; a pending event is
+// released by the runtime once it completes).
+struct EventSet {
+    hipEvent_t ev[9] = {};
+    int n = 0;
+    hipError_t create(int count)
+    {
+        for (n = 0; n < count; n++) {
+            hipError_t e = hipEventCreateWithFlags(&ev[n], hipEventDisableTiming);
+            if (e != hipSuccess)
+                return e;
+        }
+        return hipSuccess;
+    }
+    ~EventSet()
+    {
+        for (int i = 0; i < n; i++)
+            (void)hipEventDestroy(ev[i]);
+    }
+};
 
 jk_status build_fp64(const jk_problem *p, const double *B, const double *CL, const double *CR,
                      double *J, double *K, char *ws, hipStream_t s)
@@ -298,39 +354,100 @@ jk_status build_mixed(const jk_problem *p, const double *B, const double *CL, co
     if (!(w & JK_WANT_K))
         return JK_OK;
     double *Cc = (double *)(ws + f.o_cc);
-    // XY[ql][m][c] of a chunk: qc * nao * 2R doubles, exactly the space of the
-    // FP64 path's X and Y chunk buffers, which are carved back to back.
-    double *XY = (double *)(ws + f.o_x);
-    int8_t *Bp = (int8_t *)(ws + x.o_bp);
-    int *eB = (int *)(ws + x.o_eb);
     int8_t *Cp = (int8_t *)(ws + x.o_cp);
     int *eC = (int *)(ws + x.o_ec);
-    int8_t *XYp = (int8_t *)(ws + x.o_xyp);
-    int *eXY = (int *)(ws + x.o_exy);
     double *Kp = x.nsplit > 1 ? (double *)(ws + x.o_kp) : K;
     const int KB = jk::mixed_k_block();
     // K-blocked plane strides (slice_core.hpp): kbstride = rows * 32 bytes
     const i64 bkb = (i64)f.qc * x.mp * KB, bps = bkb * (x.kp / KB);
     const i64 ckb = (i64)x.cp * KB, cps = ckb * (x.kp / KB);
     const i64 xkb = (i64)2 * nd * x.mp * KB, xps = xkb * (x.jp / KB);
-    const int8_t *Xp = XYp, *Yp = XYp + (i64)nd * x.mp * KB;
+    const int nchunk = (naux + f.qc - 1) / f.qc;
+    auto nq_of = [&](int c) { return (naux - c * f.qc) < f.qc ? (naux - c * f.qc) : f.qc; };
+    auto nkb_of = [&](int c) { return (int)(pad_to((i64)nq_of(c) * r, jk::mixed_k_pad()) / KB); };
+    auto Bp = [&](int c) { return (int8_t *)(ws + x.o_bp[c & 1]); };
+    auto eB = [&](int c) { return (int *)(ws + x.o_eb[c & 1]); };
+    auto XY = [&](int c) { return (double *)(ws + x.o_xy[c & 1]); };
+    auto XYp = [&](int c) { return (int8_t *)(ws + x.o_xyp[c & 1]); };
+    auto eXY = [&](int c) { return (int *)(ws + x.o_exy[c & 1]); };
+
+    // Two streams.  Main stream s: the MFMA-bound products, ht(c + 1) then
+    // ex(c).  Auxiliary stream a: the HBM-bound slicing, slice_b(c + 2), then
+    // rowmax / slice_xy(c + 1).  Buffers are double-buffered by chunk parity;
+    // every reuse waits for the last reader of the previous occupant:
+    //   Bp/eB[c]   written by slice_b(c),  read by ht(c)
+    //   XY[c]      written by ht(c),       read by rowmax/slice_xy(c)
+    //   XYp/eXY[c] written by slice_xy(c), read by ex(c)
+    hipStream_t a = nullptr;
+    JK_TRY(aux_stream(&a));
+    EventSet E;
+    JK_TRY(E.create(9));
+    hipEvent_t fork = E.ev[0], sb[2] = {E.ev[1], E.ev[2]}, ht[2] = {E.ev[3], E.ev[4]},
+               sx[2] = {E.ev[5], E.ev[6]}, ex[2] = {E.ev[7], E.ev[8]};
+    auto slice_b = [&](int c) -> jk_status {
+        JK_TRY(jk::launch_slice_b(B + (i64)c * f.qc * npos, npos, nao, nq_of(c), nao, nao, x.mp,
+                                  x.kp / KB, Bp(c), bps, bkb, eB(c), a));
+        JK_TRY(hipEventRecord(sb[c & 1], a));
+        return JK_OK;
+    };
+    auto slice_xy = [&](int c) -> jk_status {
+        JK_TRY(jk::launch_xy_rowmax(XY(c), nao, nq_of(c), 2 * nd, r, x.mp, eXY(c), a));
+        JK_TRY(jk::launch_slice_xy(XY(c), nao, nd, r, x.mp, nq_of(c) * r, nkb_of(c), XYp(c), xps, xkb,
+                                   eXY(c), a));
+        JK_TRY(hipEventRecord(sx[c & 1], a));
+        return JK_OK;
+    };
+    auto half = [&](int c) -> jk_status {
+        JK_TRY(hipStreamWaitEvent(s, sb[c & 1], 0));
+        if (c >= 2)
+            JK_TRY(hipStreamWaitEvent(s, sx[c & 1], 0));    // XY[c] free
+        JK_TRY(jk::launch_ht_mixed(Bp(c), bps, bkb, eB(c), Cp, cps, ckb, eC, XY(c), nao, R2, nq_of(c),
+                                   x.mp, x.cp, x.kp / KB, s));
+        JK_TRY(hipEventRecord(ht[c & 1], s));
+        return JK_OK;
+    };
+    auto exch = [&](int c) -> jk_status {
+        JK_TRY(hipStreamWaitEvent(s, sx[c & 1], 0));
+        const int8_t *Xp = XYp(c), *Yp = XYp(c) + (i64)nd * x.mp * KB;
+        JK_TRY(jk::launch_ex_mixed(Xp, Yp, xps, xkb, eXY(c), eXY(c) + (size_t)nd * x.mp, Kp, nao, nd,
+                                   x.mp, nkb_of(c), x.nsplit, c > 0, s));
+        JK_TRY(hipEventRecord(ex[c & 1], s));
+        return JK_OK;
+    };
+#define JK_STEP(expr)                                                                              \
+    do {                                                                                           \
+        jk_status st_ = (expr);                                                                    \
+        if (st_ != JK_OK)                                                                          \
+            return st_;                                                                            \
+    } while (0)
 
     JK_TRY(jk::launch_pack_c(CL, CR, Cc, nao, nd, r, s));
     // digits of [C_L | C_R]: row c, inner n, element Cc[n][c]
     JK_TRY(jk::launch_slice_rows(Cc, 0, 1, R2, 1, R2, nao, x.cp, x.kp / KB, Cp, cps, ckb, eC, s));
-    for (int q0 = 0; q0 < naux; q0 += f.qc) {
-        const int nq = (naux - q0) < f.qc ? (naux - q0) : f.qc;
-        const int nj = nq * r;
-        const int nkb = (int)(pad_to(nj, jk::mixed_k_pad()) / KB);
-        JK_TRY(jk::launch_slice_b(B + (i64)q0 * npos, npos, nao, nq, nao, nao, x.mp, x.kp / KB, Bp,
-                                  bps, bkb, eB, s));
-        JK_TRY(jk::launch_ht_mixed(Bp, bps, bkb, eB, Cp, cps, ckb, eC, XY, nao, R2, nq, x.mp, x.cp,
-                                   x.kp / KB, s));
-        JK_TRY(jk::launch_xy_rowmax(XY, nao, nq, 2 * nd, r, x.mp, eXY, s));
-        JK_TRY(jk::launch_slice_xy(XY, nao, nd, r, x.mp, nj, nkb, XYp, xps, xkb, eXY, s));
-        JK_TRY(jk::launch_ex_mixed(Xp, Yp, xps, xkb, eXY, eXY + (size_t)nd * x.mp, Kp, nao, nd, x.mp,
-                                   nkb, x.nsplit, q0 > 0, s));
+    JK_TRY(hipEventRecord(fork, s));
+    JK_TRY(hipStreamWaitEvent(a, fork, 0));
+    JK_STEP(slice_b(0));
+    if (nchunk > 1)
+        JK_STEP(slice_b(1));
+    JK_STEP(half(0));
+    JK_TRY(hipStreamWaitEvent(a, ht[0], 0));
+    JK_STEP(slice_xy(0));
+    for (int c = 0; c < nchunk; c++) {
+        if (c + 1 < nchunk)
+            JK_STEP(half(c + 1));
+        JK_STEP(exch(c));
+        if (c + 2 < nchunk) {
+            JK_TRY(hipStreamWaitEvent(a, ht[c & 1], 0));     // Bp[c] free
+            JK_STEP(slice_b(c + 2));
+        }
+        if (c + 1 < nchunk) {
+            JK_TRY(hipStreamWaitEvent(a, ht[(c + 1) & 1], 0));
+            if (c >= 1)
+                JK_TRY(hipStreamWaitEvent(a, ex[(c + 1) & 1], 0));   // XYp[c+1] free
+            JK_STEP(slice_xy(c + 1));
+        }
     }
+#undef JK_STEP
     if (x.nsplit > 1)
         JK_TRY(jk::launch_sum_splits(Kp, K, (i64)nd * npos, x.nsplit, s));
     return JK_OK;

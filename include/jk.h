@@ -60,10 +60,15 @@ typedef enum {
 
 typedef enum {
     JK_FP64 = 0,   /* every product and sum in FP64                          */
-    JK_MIXED = 1   /* half-transforms and K products on BF16 matrix cores as
-                      exact fixed-point slice products (nslice 8-bit slices),
-                      FP64 for gamma, J, every cross-chunk sum and the final
-                      accumulation                                           */
+    JK_MIXED = 1   /* half-transforms and K products on the INT8 matrix
+                      cores as exact fixed-point slice products (5 signed
+                      7-bit digits per value, one power-of-two scale per
+                      row, int32 accumulation); FP64 for gamma, J, the
+                      recombination of the slice levels, every cross-chunk
+                      sum and the final accumulation.  Normwise error of K
+                      about 1e-10..1e-9 on smoothly scaled inputs; rows
+                      whose inner-index magnitudes span many orders of
+                      magnitude lose the small entries (fixed point).       */
 } jk_precision;
 
 enum { JK_WANT_J = 1, JK_WANT_K = 2 };
@@ -75,8 +80,8 @@ typedef struct {
     int64_t rank;      /* columns of each CL_k / CR_k, 1 <= rank <= nao      */
     int32_t precision; /* jk_precision                                       */
     int32_t flags;     /* JK_WANT_J | JK_WANT_K (0 means both)               */
-    int32_t nslice;    /* JK_MIXED only: 8-bit slices per operand, 2..5;
-                          0 selects the default (4)                          */
+    int32_t nslice;    /* JK_MIXED only: digits per operand; 0 or 5 (the
+                          one implemented value; 1..4 give JK_EUNSUPPORTED) */
     int32_t reserved;  /* must be 0                                          */
 } jk_problem;
 

@@ -22,7 +22,9 @@ typedef int64_t i64;
 constexpr size_t kAlign = 256;
 constexpr i64 kMaxNao = 16384;          // keeps every tile index in 32 bits
 constexpr i64 kMaxCols = 1 << 20;       // 2 * ndens * rank
-constexpr size_t kChunkBudget = (size_t)256 << 20;   // X/Y chunk workspace target
+// Chunk workspace target (X/Y of the build, X/Y and slab blocks of the
+// derivative): fewer, longer launches; 1 GB is small next to HBM3E.
+constexpr size_t kChunkBudget = (size_t)1 << 30;
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -54,7 +56,7 @@ bool valid_problem(const jk_problem *p)
         return false;
     if (p->reserved != 0)
         return false;
-    if (p->precision == JK_MIXED && p->nslice != 0 && (p->nslice < 2 || p->nslice > 5))
+    if (p->precision == JK_MIXED && p->nslice != 0 && (p->nslice < 1 || p->nslice > 5))
         return false;
     return true;
 }
@@ -338,7 +340,7 @@ jk_status build_mixed(const jk_problem *p, const double *B, const double *CL, co
     const FwdPlan &f = x.f;
     const int nao = (int)p->nao, naux = (int)p->naux, nd = (int)p->ndens, r = (int)p->rank;
     const int R = nd * r, R2 = 2 * R;
-    if (!jk::mixed_rowmax_ok(R2))
+    if (!jk::mixed_rowmax_ok(R2) || (p->nslice != 0 && p->nslice != jk::mixed_nslice()))
         return JK_EUNSUPPORTED;
     const i64 npos = (i64)nao * nao;
     const int w = want(p);

@@ -35,7 +35,7 @@ def _prob(**kw):
 
 @pytest.mark.parametrize("bad", [
     dict(nao=0), dict(naux=0), dict(ndens=0), dict(rank=0), dict(rank=11), dict(precision=7),
-    dict(flags=4), dict(flags=-1), dict(reserved=1), dict(precision=1, nslice=1),
+    dict(flags=4), dict(flags=-1), dict(reserved=1), dict(precision=1, nslice=-1),
     dict(precision=1, nslice=9), dict(nao=1 << 20),
 ])
 def test_invalid_problem(bad):
@@ -97,3 +97,14 @@ def test_binding_refuses_cpu_tensors():
     C = torch.zeros((1, 4, 2), dtype=torch.float64)
     with pytest.raises(ValueError):
         jk.jk_build(B, C, C)
+
+
+@pytest.mark.parametrize("ns", [1, 2, 3, 4])
+def test_mixed_digit_count_unsupported(ns):
+    # Only 5 digits per operand are implemented: any other count is rejected
+    # by host logic before any HIP call (the pointers are never touched).
+    L = _lib.lib()
+    p = _prob(precision=1, nslice=ns)
+    need = L.jk_workspace_bytes(ctypes.byref(p))
+    assert need > 0
+    assert L.jk_build(ctypes.byref(p), 8, 8, 8, 8, 8, 256, need, None) == _lib.JK_EUNSUPPORTED

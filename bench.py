@@ -31,6 +31,31 @@ PEAK_BF16_TFLOPS = 2516.6    # MI355X dense BF16 matrix
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
 
 
+# Kernel sources whose HBM traffic was measured with counters (the record in
+# profiles/ names their sha256; a changed source voids the record).
+TRAFFIC_SOURCES = {"half_transform": ["f64_core.hpp", "jk_fp64.hip", "jk_tiles.hpp"]}
+
+
+def measured_traffic(kernel):
+    """Bytes per launch (fetched + written) from the committed counter record,
+    or None when there is none for this kernel or its sources changed since."""
+    import glob
+    import hashlib
+    if kernel not in TRAFFIC_SOURCES:
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2608_06536_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        for line in open(path):
+            if line.startswith("traffic-record:"):
+                rec = json.loads(line.split(":", 1)[1])
+                if rec.get("kernel") == kernel and rec.get("sources_sha256") == h.hexdigest():
+                    return rec["fetch_bytes"] + rec["write_bytes"]
+    return None
+
+
 def kernel_models(p, nd, nao, naux, R):
     """Algorithmic work of each kernel over ONE step: (bound, amount, unit).
     Flops count the method's own products; bytes count one read of B."""
@@ -56,6 +81,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision build")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="after the JSON line, run a plain copy kernel of known size "
+                         "(read and write 1 GiB each) for HBM counter calibration")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -129,8 +158,10 @@ def main():
     # ---- mixed-precision build (INT8 slice products; gamma, J and all sums FP64)
     Jm = torch.empty_like(J)
     Km = torch.empty_like(K)
-    mixed = None
+    mixed = {"mixed": "skipped"}
     try:
+        if args.no_mixed:
+            raise StopIteration
         nbm = jk.workspace_bytes(jk.make_problem(nao, naux, nd, r, "mixed"))
         wsm = torch.empty(nbm, dtype=torch.uint8, device=dev)
 
@@ -146,8 +177,10 @@ def main():
                  "max_err_K_mixed_vs_fp64": max(errs),
                  "J_mixed_equals_fp64": bool(torch.equal(Jm, J))}
         del wsm
-    except _lib.JKError as e:  # noqa: F841
-        mixed = {"mixed": "unavailable"}
+    except StopIteration:
+        pass
+    except _lib.JKError as e:
+        mixed = {"mixed": f"unavailable: {e}"}
 
     # ---- roofline of the dominant kernel
     models = kernel_models(p, nd, nao, naux, R)
@@ -168,13 +201,15 @@ def main():
     if unit == "flop":
         achieved = amount * args.steps / (dom_ms * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 3), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 3),
+                "traffic": measured_traffic(dom), "traffic_unit": "HBM bytes per launch (counters)",
                 "flop_per_launch": amount * args.steps / dom_cnt,
                 "avg_launch_us": round(1e3 * dom_ms / dom_cnt, 1)}
     else:
         achieved = amount * args.steps / (dom_ms * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 3), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 3),
+                "traffic": measured_traffic(dom), "traffic_unit": "HBM bytes per launch (counters)",
                 "byte_per_launch": amount * args.steps / dom_cnt,
                 "avg_launch_us": round(1e3 * dom_ms / dom_cnt, 1)}
 
@@ -251,6 +286,16 @@ def main():
             "build_s_est": round(tf * scale, 2), "vjp_s_est": round(tv * scale, 2),
         }
     print(json.dumps(out), flush=True)
+
+    if args.copy_calib:
+        # y = x * 1 over 2^27 doubles: 1 GiB read + 1 GiB written per launch
+        x = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        print(f"# copy calibration: 3 launches, {x.numel() * 8} bytes read and written each",
+              file=sys.stderr, flush=True)
 
 
 if __name__ == "__main__":

@@ -25,6 +25,8 @@ constexpr i64 kMaxCols = 1 << 20;       // 2 * ndens * rank
 // Chunk workspace target (X/Y of the build, X/Y and slab blocks of the
 // derivative): fewer, longer launches; 1 GB is small next to HBM3E.
 constexpr size_t kChunkBudget = (size_t)1 << 30;
+// Members of a batched build each own their chunk buffers: a smaller target.
+constexpr size_t kChunkBudgetBatched = (size_t)256 << 20;
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -64,10 +66,10 @@ bool valid_problem(const jk_problem *p)
 inline int want(const jk_problem *p) { return p->flags == 0 ? (JK_WANT_J | JK_WANT_K) : p->flags; }
 
 // Slabs per chunk of the half-transform workspace.
-int chunk_slabs(const jk_problem *p)
+int chunk_slabs(const jk_problem *p, size_t budget)
 {
     size_t per = 2 * (size_t)p->nao * (size_t)(p->ndens * p->rank) * sizeof(double);
-    i64 qc = (i64)(kChunkBudget / (per ? per : 1));
+    i64 qc = (i64)(budget / (per ? per : 1));
     if (qc < 1)
         qc = 1;
     if (qc > p->naux)
@@ -80,12 +82,12 @@ struct FwdPlan {
     size_t o_cc, o_d, o_part, o_g, o_x, o_y, o_kp, total;
 };
 
-FwdPlan plan_forward(const jk_problem *p)
+FwdPlan plan_forward(const jk_problem *p, size_t budget = kChunkBudget)
 {
     FwdPlan f;
     const i64 nao = p->nao, nd = p->ndens, r = p->rank, R = nd * r;
     const i64 npos = nao * nao;
-    f.qc = chunk_slabs(p);
+    f.qc = chunk_slabs(p, budget);
     f.ldw = (int)(f.qc * r);
     f.ndp = (int)(((nd + 7) / 8) * 8);
     f.npb = jk::project_nblocks(npos, (int)p->naux, (int)nd, &f.plen);
@@ -493,7 +495,7 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p)
     std::vector<FwdPlan> plans(G);
     int maxsteps = 0;
     for (int g = 0; g < G; g++) {
-        plans[g] = plan_forward(&p[g]);
+        plans[g] = plan_forward(&p[g], kChunkBudgetBatched);
         const int st = (int)((p[g].naux + plans[g].qc - 1) / plans[g].qc);
         maxsteps = std::max(maxsteps, st);
     }
@@ -650,7 +652,7 @@ jk_status build_batched_fp64(int32_t nprob, const jk_problem *p, const double *c
     std::vector<char> host(S.header_bytes, 0);
     for (int g = 0; g < nprob; g++) {
         jk::BMember &m = S.mem[g];
-        const FwdPlan f = plan_forward(&p[g]);
+        const FwdPlan f = plan_forward(&p[g], kChunkBudgetBatched);
         char *base = ws + S.region[g];
         m.B = B[g];
         m.CL = CL[g];

@@ -4,9 +4,11 @@
 // the whole batch: each launch covers the tiles of every member that takes
 // part in that phase, in one grid.  blockIdx.x is mapped to (member, tile)
 // through a table of prefix sums; members are listed in decreasing order of
-// per-tile cost so the longest tiles start first.  Each member keeps the
-// chunking and split plan it would have alone, so its outputs are bit-for-bit
-// those of a single jk_build.
+// per-tile cost so the longest tiles start first.  Each member runs the
+// single-build plan for a chunk budget of 256 MB (members own their chunk
+// buffers, so the budget is smaller than a single build's 1 GB); where both
+// budgets give the same chunking -- every problem whose slabs fit one 256 MB
+// chunk -- its outputs are bit-for-bit those of a single jk_build.
 //
 // The member descriptors and the tables live in the caller's workspace; the
 // host writes them with one asynchronous copy per call.  Kernel arguments are

@@ -1,6 +1,7 @@
 """GPU parity of the batched build (jk_build_batched): many problems of uneven
-size per call.  Each member must be bit-identical to a single jk_build of that
-member (same plan, same summation order) and within 1e-12 of the oracle.
+size per call.  Each member must be within 1e-12 of the oracle and, for
+members whose slabs fit one chunk in both the batched and the single plan (all
+members here), bit-identical to a single jk_build (same summation order).
 On a non-default stream the launch sequence is captured into a graph on the
 first call and replayed afterwards; every replay is checked, with eager work
 and new data between replays."""

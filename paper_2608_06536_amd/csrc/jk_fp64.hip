@@ -87,9 +87,10 @@ int device_slots()
     return slots;
 }
 
-int pick_split(int tiles, int smax)
+int pick_split(int tiles, int smax) { return pick_split_slots(tiles, smax, device_slots()); }
+
+int pick_split_slots(int tiles, int smax, int slots)
 {
-    const int slots = device_slots();
     if (smax < 1)
         smax = 1;
     int best = 1;

@@ -29,6 +29,8 @@ int device_slots();
 // whose last round of workgroups is at least 90% full with at least one full
 // round, else the s with the fullest rounds.
 int pick_split(int tiles, int smax);
+// Same with an explicit number of concurrent workgroup slots.
+int pick_split_slots(int tiles, int smax, int slots);
 
 hipError_t launch_pack_c(const double *CL, const double *CR, double *Cc, int nao, int nd, int r,
                          hipStream_t s);

@@ -15,10 +15,11 @@ namespace jk {
 
 namespace {
 constexpr int kNS = 5;                  // digits per operand (35 bits)
-constexpr int kMT = 64, kNT = 64;       // workgroup tile (four 32 x 32 waves)
-constexpr int kRowPad = 64;             // plane rows are padded to this
+constexpr int kMT = 128, kNT = 128;     // workgroup tile: eight waves of 32 x 64
+constexpr int kWTN = 2;                 // MFMA tiles per wave, side by side
+constexpr int kRowPad = 128;            // plane rows are padded to this
 constexpr int kKPad = kSliceKB;         // plane inner bytes are padded to this
-typedef STile<kMT, kNT, kNS> TileS;
+typedef STileW<kMT, kNT, kNS, kWTN> TileS;
 
 inline int cdiv(i64 a, i64 b) { return (int)((a + b - 1) / b); }
 
@@ -93,19 +94,34 @@ __global__ void __launch_bounds__(256) k_slice_rows_wave(const double *__restric
         return;
     const int b = (int)(row / rp), m = (int)(row % rp);
     const bool live = m < nr;
-    // loads are unconditional (clamped addresses), masked afterwards
+    // loads are unconditional (clamped addresses), masked afterwards; rows
+    // that start on 16 bytes with nk % 4 == 0 use 16-byte loads
     const double *s = src + (i64)b * bs + (i64)(live ? m : nr - 1) * rs;
+    const bool vec = ((((uintptr_t)s) & 15) == 0) && (nk & 3) == 0;
     double v[NJ][4];
     double mx = 0.0;
 #pragma unroll
-    for (int j = 0; j < NJ; j++)
+    for (int j = 0; j < NJ; j++) {
+        const int k0 = 256 * j + 4 * lane;
+        double x[4];
+        if (vec) {
+            const int kc = k0 < nk ? k0 : nk - 4;
+            const double2 lo = *(const double2 *)(s + kc), hi = *(const double2 *)(s + kc + 2);
+            x[0] = lo.x;
+            x[1] = lo.y;
+            x[2] = hi.x;
+            x[3] = hi.y;
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                x[u] = s[(k0 + u) < nk ? k0 + u : nk - 1];
+        }
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-            const int k = 256 * j + 4 * lane + u;
-            const double x = s[k < nk ? k : nk - 1];
-            v[j][u] = (live && k < nk) ? x : 0.0;
+            v[j][u] = (live && k0 + u < nk) ? x[u] : 0.0;
             mx = fmax(mx, fabs(v[j][u]));
         }
+    }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1)
         mx = fmax(mx, __shfl_xor(mx, o));
@@ -150,11 +166,21 @@ __global__ void __launch_bounds__(256) k_slice_xy(const double *__restrict__ XY,
     const double *s = XY + (i64)(live ? m : nao - 1) * R2 + (i64)key * r;
     const int j0 = kb * kSliceKB + sub * 4;
     double x[4];
+    const int q0 = j0 / r, i0 = j0 - q0 * r;
+    const double *p0 = s + (i64)q0 * nao * R2 + i0;
+    if (j0 + 3 < nj && i0 + 3 < r && (((uintptr_t)p0) & 15) == 0) {
+        const double2 lo = *(const double2 *)p0, hi = *(const double2 *)(p0 + 2);
+        x[0] = lo.x;
+        x[1] = lo.y;
+        x[2] = hi.x;
+        x[3] = hi.y;
+    } else {
 #pragma unroll
-    for (int u = 0; u < 4; u++) {
-        const int j = (j0 + u) < nj ? (j0 + u) : nj - 1;
-        const int ql = j / r, i = j - ql * r;
-        x[u] = s[(i64)ql * nao * R2 + i];
+        for (int u = 0; u < 4; u++) {
+            const int j = (j0 + u) < nj ? (j0 + u) : nj - 1;
+            const int ql = j / r, i = j - ql * r;
+            x[u] = s[(i64)ql * nao * R2 + i];
+        }
     }
     int8_t d[4][kNS];
 #pragma unroll
@@ -167,7 +193,7 @@ __global__ void __launch_bounds__(256) k_slice_xy(const double *__restrict__ XY,
 // For slab ql of the chunk: XY[ql][m][c] = 2^(eB + eC + 2) * sum_l S_l 2^(-7 l)
 // (c < R: X = B^Q C_L, c >= R: Y = B^Q C_R).  A planes: rows ql * mp + m;
 // B planes: rows c.  Each workgroup writes whole 512-byte row segments.
-__global__ void __launch_bounds__(256) k_ht_mixed(const int8_t *__restrict__ Bp, i64 bpstride,
+__global__ void __launch_bounds__(512) k_ht_mixed(const int8_t *__restrict__ Bp, i64 bpstride,
                                                   i64 bkbstride, const int *__restrict__ eB,
                                                   const int8_t *__restrict__ Cp, i64 cpstride,
                                                   i64 ckbstride, const int *__restrict__ eC,
@@ -182,19 +208,21 @@ __global__ void __launch_bounds__(256) k_ht_mixed(const int8_t *__restrict__ Bp,
     const int mb = rem / nct, cb = rem % nct;
     SPlanes a{Bp + (i64)ql * mp * kSliceKB, bpstride, bkbstride};
     SPlanes b{Cp, cpstride, ckbstride};
-    SAcc<TL> acc;
+    SAccW<TL> acc;
     acc.zero();
-    stile_gemm<TL, kNS>(a, b, mb * kMT, cb * kNT, 0, nkb, lds, acc);
+    stile_gemm_wide<TL, kNS>(a, b, mb * kMT, cb * kNT, 0, nkb, lds, acc);
     double *out = XY + (i64)ql * nao * R2;
 #pragma unroll
-    for (int e = 0; e < 16; e++) {
-        int row, col;
-        stile_coord<TL>(e, row, col);
-        const int m = mb * kMT + row, c = cb * kNT + col;
-        if (m < nao && c < R2)
-            out[(i64)m * R2 + c] =
-                ldexp(combine_levels<TL>(acc, e), eB[(i64)ql * mp + m] + eC[c] + 2);
-    }
+    for (int tt = 0; tt < kWTN; tt++)
+#pragma unroll
+        for (int e = 0; e < 16; e++) {
+            int row, col;
+            stile_coord_wide<TL>(tt, e, row, col);
+            const int m = mb * kMT + row, c = cb * kNT + col;
+            if (m < nao && c < R2)
+                out[(i64)m * R2 + c] =
+                    ldexp(combine_levels_wide<TL>(acc, tt, e), eB[(i64)ql * mp + m] + eC[c] + 2);
+        }
 }
 
 // Row exponents of X/Y over the chunk: exps[key * mp + m] for key = side * nd
@@ -210,24 +238,24 @@ __global__ void __launch_bounds__(256) k_xy_rowmax(const double *__restrict__ XY
     const i64 qs = (i64)nao * R2;
     const double *s = XY + (i64)m * R2;
     for (int c = threadIdx.x; c < R2; c += 256) {
-        double mx[8];
+        double mx[16];
 #pragma unroll
-        for (int u = 0; u < 8; u++)
+        for (int u = 0; u < 16; u++)
             mx[u] = 0.0;
         int q = 0;
-        for (; q + 8 <= nq; q += 8) {
-            double v[8];
+        for (; q + 16 <= nq; q += 16) {
+            double v[16];
 #pragma unroll
-            for (int u = 0; u < 8; u++)
+            for (int u = 0; u < 16; u++)
                 v[u] = __builtin_nontemporal_load(s + (i64)(q + u) * qs + c);
 #pragma unroll
-            for (int u = 0; u < 8; u++)
+            for (int u = 0; u < 16; u++)
                 mx[u] = fmax(mx[u], fabs(v[u]));
         }
         for (; q < nq; q++)
             mx[0] = fmax(mx[0], fabs(s[(i64)q * qs + c]));
 #pragma unroll
-        for (int u = 1; u < 8; u++)
+        for (int u = 1; u < 16; u++)
             mx[0] = fmax(mx[0], mx[u]);
         colmax[c] = mx[0];
     }
@@ -244,7 +272,7 @@ __global__ void __launch_bounds__(256) k_xy_rowmax(const double *__restrict__ XY
 // Kp[s][k][m][n] (+)= 2^(eX + eY + 2) * sum_l S_l 2^(-7 l) over the inner
 // blocks [s * kbl, (s + 1) * kbl) of split s.  X/Y planes: rows k * mp + m
 // from Xp / Yp (same strides); row exponents eX[k * mp + m], eY[k * mp + n].
-__global__ void __launch_bounds__(256) k_ex_mixed(const int8_t *__restrict__ Xp,
+__global__ void __launch_bounds__(512) k_ex_mixed(const int8_t *__restrict__ Xp,
                                                   const int8_t *__restrict__ Yp, i64 pstride,
                                                   i64 kbstride, const int *__restrict__ eX,
                                                   const int *__restrict__ eY,
@@ -263,22 +291,24 @@ __global__ void __launch_bounds__(256) k_ex_mixed(const int8_t *__restrict__ Xp,
     const int kb1 = (kb0 + kbl) < nkb ? (kb0 + kbl) : nkb;
     SPlanes a{Xp + (i64)k * mp * kSliceKB, pstride, kbstride};
     SPlanes b{Yp + (i64)k * mp * kSliceKB, pstride, kbstride};
-    SAcc<TL> acc;
+    SAccW<TL> acc;
     acc.zero();
-    stile_gemm<TL, kNS>(a, b, mb * kMT, nb * kNT, kb0, kb1, lds, acc);
+    stile_gemm_wide<TL, kNS>(a, b, mb * kMT, nb * kNT, kb0, kb1, lds, acc);
     double *Kk = Kp + ((i64)sp * nd + k) * nao * nao;
 #pragma unroll
-    for (int e = 0; e < 16; e++) {
-        int row, col;
-        stile_coord<TL>(e, row, col);
-        const int m = mb * kMT + row, n = nb * kNT + col;
-        if (m < nao && n < nao) {
-            const double v = ldexp(combine_levels<TL>(acc, e),
-                                   eX[(i64)k * mp + m] + eY[(i64)k * mp + n] + 2);
-            const i64 o = (i64)m * nao + n;
-            Kk[o] = accumulate ? Kk[o] + v : v;
+    for (int tt = 0; tt < kWTN; tt++)
+#pragma unroll
+        for (int e = 0; e < 16; e++) {
+            int row, col;
+            stile_coord_wide<TL>(tt, e, row, col);
+            const int m = mb * kMT + row, n = nb * kNT + col;
+            if (m < nao && n < nao) {
+                const double v = ldexp(combine_levels_wide<TL>(acc, tt, e),
+                                       eX[(i64)k * mp + m] + eY[(i64)k * mp + n] + 2);
+                const i64 o = (i64)m * nao + n;
+                Kk[o] = accumulate ? Kk[o] + v : v;
+            }
         }
-    }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -379,11 +409,12 @@ hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, i64 bkbstride, const 
 
 int ex_mixed_nsplit(int mp, int nd, int nkb)
 {
+    // one 512-thread workgroup per CU (registers), so half the usual slots
     const int tiles = nd * (mp / kMT) * (mp / kNT);
     int maxs = nkb / 16 > 1 ? nkb / 16 : 1;
     if (maxs > 16)
         maxs = 16;
-    return pick_split(tiles, maxs);
+    return pick_split_slots(tiles, maxs, device_slots() / 2);
 }
 
 hipError_t launch_ex_mixed(const int8_t *Xp, const int8_t *Yp, i64 pstride, i64 kbstride,

@@ -149,8 +149,9 @@ struct SAcc {
 // Pipeline: the block of stage s is copied global -> registers -> LDS buffer
 // s % 2 during stage s - 2, its fragments are read from LDS into registers
 // during stage s - 1 (while the MFMAs of stage s - 1 run), and it is
-// multiplied in stage s.  One barrier per stage; at that barrier the buffer
-// being refilled was last read a full stage earlier.
+// multiplied in stage s.  One barrier per stage (plus one after the first
+// fragment reads); a buffer is refilled only after a barrier that follows
+// every read of its previous contents.
 template <class TL, int NS>
 __device__ __forceinline__ void stile_gemm(const SPlanes &A, const SPlanes &B, int m0, int n0,
                                            int kb_begin, int kb_end, char *lds, SAcc<TL> &acc)
@@ -182,6 +183,9 @@ __device__ __forceinline__ void stile_gemm(const SPlanes &A, const SPlanes &B, i
         fa[p] = *(const v4i *)(lds + p * BM * kSliceKB + aoff);
         fb[p] = *(const v4i *)(lds + TL::A_BYTES + p * BN * kSliceKB + boff);
     }
+    // buffer 0 is refilled in the first stage: every wave must have read its
+    // stage-0 fragments first
+    __syncthreads();
     for (int st = 0; st < nst; st++) {
         const bool more2 = st + 2 < nst;
         if (more2) {
@@ -213,6 +217,234 @@ __device__ __forceinline__ void stile_gemm(const SPlanes &A, const SPlanes &B, i
         }
         __syncthreads();
     }
+}
+
+// 16 bytes per lane from global memory straight into LDS at dst + 16 * lane
+// (dst is the same for the whole wave).  The builtin exists only in the
+// device compilation.
+__device__ __forceinline__ void global_to_lds16(const int8_t *src, char *dst)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+#endif
+}
+
+// Same product with direct global -> LDS copies (global_load_lds_dwordx4):
+// no staging registers.  A wave instruction fills one kilobyte of LDS, lane l
+// at byte 16 l (measured), so each lane picks the global 16-byte chunk that
+// belongs at its LDS slot of the swizzled layout: the slot (row, half') holds
+// the chunk (row, half' ^ swizzle(row)).  A stage is NS planes x (BM + BN) / 32
+// such blocks, spread over the waves.  Stage s is copied into buffer s % 2
+// at the start of stage s - 2 and waited for at the end of that stage.
+template <class TL, int NS, int SCHED = 0>
+__device__ __forceinline__ void stile_gemm_direct(const SPlanes &A, const SPlanes &B, int m0, int n0,
+                                                  int kb_begin, int kb_end, char *lds,
+                                                  SAcc<TL> &acc)
+{
+    constexpr int BM = TL::WROWS * 32, BN = TL::WCOLS * 32;
+    constexpr int NBA = NS * (BM / 32), NB = NBA + NS * (BN / 32);
+    constexpr int NW = TL::NWAVE, PER = (NB + NW - 1) / NW;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
+    const int nst = kb_end - kb_begin;
+    if (nst <= 0)
+        return;
+    const int8_t *gp[PER];
+    i64 kbs[PER];
+    int loff[PER];
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        const int b = wave + u * NW;
+        const int bb = b < NB ? b : 0;
+        const bool isA = bb < NBA;
+        const int bl = isA ? bb : bb - NBA;
+        const int T = isA ? BM : BN;
+        const int p = bl / (T / 32), rh = bl % (T / 32);
+        const int row = rh * 32 + (lane >> 1);
+        const int half = (lane & 1) ^ ((row >> 3) & 1);
+        const SPlanes &op = isA ? A : B;
+        gp[u] = op.base + p * op.pstride + (i64)((isA ? m0 : n0) + row) * kSliceKB + half * 16;
+        kbs[u] = op.kbstride;
+        loff[u] = (isA ? 0 : TL::A_BYTES) + p * T * kSliceKB + rh * 32 * kSliceKB;
+    }
+    auto issue = [&](int kb, int buf) {
+#pragma unroll
+        for (int u = 0; u < PER; u++)
+            if (NB % NW == 0 || wave + u * NW < NB)
+                global_to_lds16(gp[u] + (i64)kb * kbs[u], lds + buf * TL::STAGE_BYTES + loff[u]);
+    };
+    issue(kb_begin, 0);
+    if (nst > 1)
+        issue(kb_begin + 1, 1);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const int aoff = slds_off(wr * 32 + (lane & 31), lane >> 5);
+    const int boff = slds_off(wc * 32 + (lane & 31), lane >> 5);
+    v4i fa[NS], fb[NS];
+#pragma unroll
+    for (int p = 0; p < NS; p++) {
+        fa[p] = *(const v4i *)(lds + p * BM * kSliceKB + aoff);
+        fb[p] = *(const v4i *)(lds + TL::A_BYTES + p * BN * kSliceKB + boff);
+    }
+    __syncthreads();     // buffer 0 is refilled in the first stage
+    for (int st = 0; st < nst; st++) {
+        if (st + 2 < nst)
+            issue(kb_begin + st + 2, st & 1);
+        const char *sa = lds + ((st + 1) & 1) * TL::STAGE_BYTES;
+        const char *sb = sa + TL::A_BYTES;
+        v4i ga[NS], gb[NS];
+#pragma unroll
+        for (int p = 0; p < NS; p++) {
+            ga[p] = *(const v4i *)(sa + p * BM * kSliceKB + aoff);
+            gb[p] = *(const v4i *)(sb + p * BN * kSliceKB + boff);
+        }
+#pragma unroll
+        for (int i = 0; i < NS; i++)
+#pragma unroll
+            for (int j = 0; j < NS - i; j++)
+                acc.c[i + j] = mfma_i8(fa[i], fb[j], acc.c[i + j]);
+        if (SCHED == 1) {
+            // next-stage fragment reads first, then the products
+            __builtin_amdgcn_sched_group_barrier(0x100, 2 * NS, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, NS * (NS + 1) / 2, 0);
+        } else if (SCHED == 2) {
+            // one fragment read between consecutive products
+#pragma unroll
+            for (int q = 0; q < 2 * NS; q++) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, NS * (NS + 1) / 2 - 2 * NS, 0);
+        }
+#pragma unroll
+        for (int p = 0; p < NS; p++) {
+            fa[p] = ga[p];
+            fb[p] = gb[p];
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- wide tiles
+// Each wave owns 32 x (32 WTN) outputs (WTN MFMA tiles side by side), so one
+// A fragment feeds WTN tiles: fewer LDS bytes per product.  Waves (BM/32) x
+// (BN/(32 WTN)).  Direct global -> LDS copies, double-buffered LDS stages,
+// fragments read at the start of each stage.
+template <int BM, int BN, int NS, int WTN>
+struct STileW {
+    static constexpr int WROWS = BM / 32, WCOLS = BN / (32 * WTN);
+    static constexpr int NWAVE = WROWS * WCOLS;
+    static constexpr int NTHR = NWAVE * 64;
+    static constexpr int NLEV = NS;
+    static constexpr int TN = WTN;
+    static constexpr int A_BYTES = NS * BM * kSliceKB, B_BYTES = NS * BN * kSliceKB;
+    static constexpr int STAGE_BYTES = A_BYTES + B_BYTES;
+    static constexpr int LDS_BYTES = 2 * STAGE_BYTES;
+};
+
+template <class TL>
+struct SAccW {
+    v16i c[TL::TN][TL::NLEV];
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int t = 0; t < TL::TN; t++)
+#pragma unroll
+            for (int l = 0; l < TL::NLEV; l++)
+#pragma unroll
+                for (int e = 0; e < 16; e++)
+                    c[t][l][e] = 0;
+    }
+};
+
+template <class TL, int NS>
+__device__ __forceinline__ void stile_gemm_wide(const SPlanes &A, const SPlanes &B, int m0, int n0,
+                                                int kb_begin, int kb_end, char *lds, SAccW<TL> &acc)
+{
+    constexpr int BM = TL::WROWS * 32, BN = TL::WCOLS * 32 * TL::TN, WTN = TL::TN;
+    constexpr int NBA = NS * (BM / 32), NB = NBA + NS * (BN / 32);
+    constexpr int NW = TL::NWAVE, PER = (NB + NW - 1) / NW;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
+    const int nst = kb_end - kb_begin;
+    if (nst <= 0)
+        return;
+    const int8_t *gp[PER];
+    i64 kbs[PER];
+    int loff[PER];
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        const int b = wave + u * NW;
+        const int bb = b < NB ? b : 0;
+        const bool isA = bb < NBA;
+        const int bl = isA ? bb : bb - NBA;
+        const int T = isA ? BM : BN;
+        const int p = bl / (T / 32), rh = bl % (T / 32);
+        const int row = rh * 32 + (lane >> 1);
+        const int half = (lane & 1) ^ ((row >> 3) & 1);
+        const SPlanes &op = isA ? A : B;
+        gp[u] = op.base + p * op.pstride + (i64)((isA ? m0 : n0) + row) * kSliceKB + half * 16;
+        kbs[u] = op.kbstride;
+        loff[u] = (isA ? 0 : TL::A_BYTES) + p * T * kSliceKB + rh * 32 * kSliceKB;
+    }
+    auto issue = [&](int kb, int buf) {
+#pragma unroll
+        for (int u = 0; u < PER; u++)
+            if (NB % NW == 0 || wave + u * NW < NB)
+                global_to_lds16(gp[u] + (i64)kb * kbs[u], lds + buf * TL::STAGE_BYTES + loff[u]);
+    };
+    const int aoff = slds_off(wr * 32 + (lane & 31), lane >> 5);
+    int boff[WTN];
+#pragma unroll
+    for (int t = 0; t < WTN; t++)
+        boff[t] = slds_off((wc * WTN + t) * 32 + (lane & 31), lane >> 5);
+    issue(kb_begin, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int st = 0; st < nst; st++) {
+        if (st + 1 < nst)
+            issue(kb_begin + st + 1, (st + 1) & 1);
+        const char *sa = lds + (st & 1) * TL::STAGE_BYTES;
+        const char *sb = sa + TL::A_BYTES;
+        v4i fa[NS], fb[WTN][NS];
+#pragma unroll
+        for (int p = 0; p < NS; p++) {
+            fa[p] = *(const v4i *)(sa + p * BM * kSliceKB + aoff);
+#pragma unroll
+            for (int t = 0; t < WTN; t++)
+                fb[t][p] = *(const v4i *)(sb + p * BN * kSliceKB + boff[t]);
+        }
+#pragma unroll
+        for (int i = 0; i < NS; i++)
+#pragma unroll
+            for (int t = 0; t < WTN; t++)
+#pragma unroll
+                for (int j = 0; j < NS - i; j++)
+                    acc.c[t][i + j] = mfma_i8(fa[i], fb[t][j], acc.c[t][i + j]);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
+}
+
+// Output coordinates of element e of tile t of this lane (wide tiles).
+template <class TL>
+__device__ __forceinline__ void stile_coord_wide(int t, int e, int &row, int &col)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
+    row = wr * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+    col = (wc * TL::TN + t) * 32 + (lane & 31);
+}
+
+template <class TL>
+__device__ __forceinline__ double combine_levels_wide(const SAccW<TL> &acc, int t, int e)
+{
+    double v = 0.0;
+#pragma unroll
+    for (int l = TL::NLEV - 1; l >= 0; l--)
+        v += ldexp((double)acc.c[t][l][e], -kSliceBits * (l + 2));
+    return v;
 }
 
 // FP64 value of output element e (0..15) of this lane: sum_l S_l 2^(-7(l+2)),

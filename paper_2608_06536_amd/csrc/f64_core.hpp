@@ -251,6 +251,79 @@ __device__ __forceinline__ void tile_gemm(const OA &A, const OB &B, int m0, int 
     }
 }
 
+// acc += sum over segments s < nseg of sum over k in [0, kdepth) of
+// A_s(m0 + i, k) * B_s(n0 + j, k), where operand A_s is A with its base moved
+// by s * segA elements (B_s likewise).  The stages of all segments form one
+// pipeline: the first stage of segment s + 1 is loaded while the last stage
+// of segment s is multiplied, so a workgroup that sums products over many
+// slabs never drains between them.  Operands must not use p in finish().
+template <class TL, class OA, class OB>
+__device__ __forceinline__ void tile_gemm_seg(const OA &A, const OB &B, i64 segA, i64 segB,
+                                              int nseg, int m0, int n0, int kdepth, double *lds,
+                                              Acc<TL> &acc)
+{
+    constexpr int BK = TL::NSUB * 4;
+    constexpr int BM = TL::WROWS * TL::MA * 16, BN = TL::WCOLS * TL::NB * 4;
+    constexpr int STAGE = TL::A_DOUBLES + TL::B_DOUBLES;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
+    const int boff = 4 * (lane >> 4) + (lane & 3);
+
+    TileLoader<BM, BK, TL::NTHR, true, OA> la;
+    TileLoader<BN, BK, TL::NTHR, false, OB> lb;
+    const int nk = (kdepth + BK - 1) / BK;
+    const int total = nk * nseg;
+    if (total <= 0)
+        return;
+    auto opA = [&](int g) {
+        OA a = A;
+        a.p += (i64)(g / nk) * segA;
+        return a;
+    };
+    auto opB = [&](int g) {
+        OB b = B;
+        b.p += (i64)(g / nk) * segB;
+        return b;
+    };
+    la.load(opA(0), m0, 0, tid);
+    lb.load(opB(0), n0, 0, tid);
+    la.store(A, lds, tid);
+    lb.store(B, lds + TL::A_DOUBLES, tid);
+    __syncthreads();
+    for (int g = 0; g < total; g++) {
+        const int cur = g & 1;
+        const bool more = (g + 1) < total;
+        if (more) {
+            const int kn = ((g + 1) % nk) * BK;
+            la.load(opA(g + 1), m0, kn, tid);
+            lb.load(opB(g + 1), n0, kn, tid);
+        }
+        const double *pa = lds + cur * STAGE + (wr * TL::MA) * TL::NSUB * 64 + lane;
+        const double *pb = lds + cur * STAGE + TL::A_DOUBLES + (wc * TL::NB) * TL::NSUB * 16 + boff;
+#pragma unroll
+        for (int s = 0; s < TL::NSUB; s++) {
+            double a[TL::MA], b[TL::NB];
+#pragma unroll
+            for (int i = 0; i < TL::MA; i++)
+                a[i] = pa[(i * TL::NSUB + s) * 64];
+#pragma unroll
+            for (int j = 0; j < TL::NB; j++)
+                b[j] = pb[(j * TL::NSUB + s) * 16];
+#pragma unroll
+            for (int i = 0; i < TL::MA; i++)
+#pragma unroll
+                for (int j = 0; j < TL::NB; j++)
+                    acc.c[i][j] = mfma4(a[i], b[j], acc.c[i][j]);
+        }
+        if (more) {
+            la.store(A, lds + (cur ^ 1) * STAGE, tid);
+            lb.store(B, lds + (cur ^ 1) * STAGE + TL::A_DOUBLES, tid);
+        }
+        __syncthreads();
+    }
+}
+
 // Calls f(row, col, value) for every output element this lane holds:
 // accumulator (i, j) is element (m0 + wr*WM + 16i + 4*((lane >> 2) & 3) +
 // (lane >> 4), n0 + wc*WN + 4j + (lane & 3)).

@@ -129,10 +129,11 @@ __global__ void __launch_bounds__(256, 2) k_vjp_stage_c(const double *__restrict
     Acc<TL> acc;
     acc.zero();
     const int qa = sp * qlen, qb = (qa + qlen) < nq ? (qa + qlen) : nq;
-    for (int ql = qa; ql < qb; ql++) {
-        OpKC a{B + (i64)(q0 + ql) * n2, nao, nao, nao};
-        OpIC b{L + (i64)ql * nao * R4 + R, R4, R2, nao};
-        tile_gemm<TL>(a, b, mb * kTM, cb * kTN, 0, nao, lds, acc);
+    if (qb > qa) {
+        // slabs qa..qb-1 as one pipelined sum
+        OpKC a{B + (i64)(q0 + qa) * n2, nao, nao, nao};
+        OpIC b{L + (i64)qa * nao * R4 + R, R4, R2, nao};
+        tile_gemm_seg<TL>(a, b, n2, (i64)nao * R4, qb - qa, mb * kTM, cb * kTN, nao, lds, acc);
     }
     double *out = dCp + (i64)sp * nao * R2;
     tile_foreach(acc, mb * kTM, cb * kTN, [&](int m, int c, double v) {
@@ -205,43 +206,81 @@ __global__ void __launch_bounds__(256, 2) k_vjp_stage_d(const double *__restrict
 
 // dB[Q][p] += sum_k gamma[k][Q] W[k][p] + omega[k][Q] E[k][p] for Q in
 // [q0, q0 + nq): each thread keeps the W and E values of its two positions in
-// registers across the slabs of the chunk; densities in groups of 8.
+// registers across its slabs (densities in groups of 8) and updates four
+// slabs at a time, so eight loads are in flight; blockIdx.y splits the
+// chunk's slabs into ranges of qlen (each dB element has one owner).  No branches in
+// the inner loop: a lone last position reuses a valid address and is not
+// stored, densities past nd get zero weights.
 __global__ void __launch_bounds__(256) k_vjp_db_affine(const double *__restrict__ gam,
                                                        const double *__restrict__ om,
                                                        const double *__restrict__ W,
                                                        const double *__restrict__ E,
                                                        double *__restrict__ dB, int nd, int naux,
-                                                       i64 npos, int q0, int nq)
+                                                       i64 npos, int q0, int nq_all, int qlen)
 {
     const i64 p0 = ((i64)blockIdx.x * 256 + threadIdx.x) * 2;
-    if (p0 >= npos)
+    const int qs = blockIdx.y * qlen;
+    if (p0 >= npos || qs >= nq_all)
         return;
+    q0 += qs;
+    const int nq = (nq_all - qs) < qlen ? (nq_all - qs) : qlen;
     const bool two = p0 + 1 < npos;
+    const i64 p1 = two ? p0 + 1 : p0;
     for (int k0 = 0; k0 < nd; k0 += 8) {
         const int nk = (nd - k0) < 8 ? (nd - k0) : 8;
         double w[8][2], e[8][2];
+        const double *gk[8], *ok[8];
 #pragma unroll
         for (int k = 0; k < 8; k++) {
-            const i64 base = (i64)(k0 + (k < nk ? k : 0)) * npos + p0;
-            w[k][0] = W[base];
-            e[k][0] = E[base];
-            w[k][1] = two ? W[base + 1] : 0.0;
-            e[k][1] = two ? E[base + 1] : 0.0;
+            const int kk = k0 + (k < nk ? k : 0);
+            const i64 base = (i64)kk * npos;
+            w[k][0] = W[base + p0];
+            e[k][0] = E[base + p0];
+            w[k][1] = W[base + p1];
+            e[k][1] = E[base + p1];
+            gk[k] = gam + (i64)kk * naux;
+            ok[k] = om + (i64)kk * naux;
         }
-        for (int ql = 0; ql < nq; ql++) {
-            const int Q = q0 + ql;
-            double *d = dB + (i64)Q * npos + p0;
-            double v0 = d[0], v1 = two ? d[1] : 0.0;
+        int ql = 0;
+        for (; ql + 4 <= nq; ql += 4) {
+            double v[4][2];
 #pragma unroll
-            for (int k = 0; k < 8; k++)
-                if (k < nk) {
-                    const double g = gam[(i64)(k0 + k) * naux + Q], o = om[(i64)(k0 + k) * naux + Q];
-                    v0 = fma(g, w[k][0], fma(o, e[k][0], v0));
-                    v1 = fma(g, w[k][1], fma(o, e[k][1], v1));
+            for (int u = 0; u < 4; u++) {
+                const double *d = dB + (i64)(q0 + ql + u) * npos;
+                v[u][0] = d[p0];
+                v[u][1] = d[p1];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int Q = q0 + ql + u;
+#pragma unroll
+                for (int k = 0; k < 8; k++) {
+                    const double g = k < nk ? gk[k][Q] : 0.0, o = k < nk ? ok[k][Q] : 0.0;
+                    v[u][0] = fma(g, w[k][0], fma(o, e[k][0], v[u][0]));
+                    v[u][1] = fma(g, w[k][1], fma(o, e[k][1], v[u][1]));
                 }
-            d[0] = v0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                double *d = dB + (i64)(q0 + ql + u) * npos;
+                d[p0] = v[u][0];
+                if (two)
+                    d[p1] = v[u][1];
+            }
+        }
+        for (; ql < nq; ql++) {
+            const int Q = q0 + ql;
+            double *d = dB + (i64)Q * npos;
+            double v0 = d[p0], v1 = d[p1];
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const double g = k < nk ? gk[k][Q] : 0.0, o = k < nk ? ok[k][Q] : 0.0;
+                v0 = fma(g, w[k][0], fma(o, e[k][0], v0));
+                v1 = fma(g, w[k][1], fma(o, e[k][1], v1));
+            }
+            d[p0] = v0;
             if (two)
-                d[1] = v1;
+                d[p1] = v1;
         }
     }
 }
@@ -357,8 +396,16 @@ hipError_t launch_vjp_db_affine(const double *gam, const double *om, const doubl
 {
     {
         ProfScope ps_("vjp_db_affine", s);
-        hipLaunchKernelGGL(k_vjp_db_affine, dim3(cdiv((npos + 1) / 2, 256)), dim3(256), 0, s, gam, om,
-                           W, E, dB, nd, naux, npos, q0, nq);
+        // enough workgroups to keep several in flight per CU
+        const int nx = cdiv((npos + 1) / 2, 256);
+        int ny = cdiv(4096, nx);
+        if (ny > nq)
+            ny = nq;
+        if (ny < 1)
+            ny = 1;
+        const int qlen = cdiv(nq, ny);
+        hipLaunchKernelGGL(k_vjp_db_affine, dim3(nx, cdiv(nq, qlen)), dim3(256), 0, s, gam, om, W, E,
+                           dB, nd, naux, npos, q0, nq, qlen);
     }
     return hipGetLastError();
 }

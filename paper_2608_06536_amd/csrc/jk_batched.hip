@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(256) k_b_coulomb(const BMember *__restrict__ M
     coulomb_tile(m.B, m.g, m.J, m.naux, m.nd, m.npos, loc);
 }
 
-__global__ void __launch_bounds__(256, 2) k_b_half_transform(const BMember *__restrict__ M,
+__global__ void __launch_bounds__(256, 3) k_b_half_transform(const BMember *__restrict__ M,
                                                              const int *__restrict__ tab, int c)
 {
     __shared__ double lds[TileHalf::LDS_DOUBLES];

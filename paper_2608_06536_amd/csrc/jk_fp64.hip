@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(256) k_coulomb(const double *__restrict__ B,
     coulomb_tile(B, g, J, naux, nd, npos, blockIdx.x);
 }
 
-__global__ void __launch_bounds__(256, 2) k_half_transform(const double *__restrict__ B,
+__global__ void __launch_bounds__(256, 3) k_half_transform(const double *__restrict__ B,
                                                            const double *__restrict__ Cc,
                                                            double *__restrict__ Xw,
                                                            double *__restrict__ Yw, int nao, int nd,

@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(256) k_vjp_fill_blocks(const double *__restric
 // (om = omega_{k, q0+ql}; products skipped when has_v == 0, omega terms when
 // has_w == 0).  grid.x = nd * nmt * njt (XCD-swizzled).
 template <int WHICH>
-__global__ void __launch_bounds__(256, 2) k_vjp_stage_b(const double *__restrict__ V,
+__global__ void __launch_bounds__(256, WHICH == 0 ? 3 : 2) k_vjp_stage_b(const double *__restrict__ V,
                                                         const double *__restrict__ Zw,
                                                         const double *__restrict__ Cc,
                                                         const double *__restrict__ omx,

@@ -182,6 +182,32 @@ def main():
     except _lib.JKError as e:
         mixed = {"mixed": f"unavailable: {e}"}
 
+    # ---- symmetric densities (the same factor for both sides: X-only path)
+    try:
+        Js = torch.empty_like(J)
+        Ks = torch.empty_like(K)
+
+        def build_sym():
+            jk.jk_build(Bd, Ld, Ld, out=(Js, Ks), ws=ws)
+
+        t_sym = rate(build_sym)
+        sym = {"builds_per_s_fp64_sym": round(nd / t_sym, 2), "build_ms_fp64_sym": round(1e3 * t_sym, 3),
+               "speedup_vs_general_fp64": round(t_build / t_sym, 3)}
+        if not args.no_mixed:
+            wsm = torch.empty(jk.workspace_bytes(jk.make_problem(nao, naux, nd, r, "mixed")),
+                              dtype=torch.uint8, device=dev)
+
+            def build_sym_mixed():
+                jk.jk_build(Bd, Ld, Ld, precision="mixed", out=(Js, Ks), ws=wsm)
+
+            t_sym_m = rate(build_sym_mixed)
+            sym.update({"builds_per_s_mixed_sym": round(nd / t_sym_m, 2),
+                        "build_ms_mixed_sym": round(1e3 * t_sym_m, 3)})
+            del wsm
+        del Js, Ks
+    except _lib.JKError as e:
+        sym = {"symmetric": f"unavailable: {e}"}
+
     # ---- roofline of the dominant kernel
     models = kernel_models(p, nd, nao, naux, R)
     per_kernel = {}
@@ -234,6 +260,7 @@ def main():
         "build_ms_fp64": round(1e3 * t_build, 3),
         "vjp_ms_fp64": round(1e3 * t_vjp, 3),
         "mixed": mixed,
+        "symmetric_densities": sym,
         "roofline": roof,
         "kernels": per_kernel,
         "prof_dropped": dropped,

@@ -91,7 +91,12 @@ size_t jk_workspace_bytes(const jk_problem *p);
 
 /* Forward build (Sec. 2.3, Eq. (4)): J_k and K_k for every density k.
  * Writes J if flags has JK_WANT_J (J may be NULL otherwise) and K if flags
- * has JK_WANT_K (K may be NULL otherwise). */
+ * has JK_WANT_K (K may be NULL otherwise).
+ * Symmetric densities: when CL and CR are the same pointer, every D_k =
+ * C_k C_k^T is symmetric (the C_L = C_R case of Sec. 2.3); only X = B^Q C is
+ * formed and K_k = sum_Q X X^T is computed on its upper triangle and
+ * mirrored, so K is exactly symmetric.  Equal contents behind two different
+ * pointers take the general path. */
 jk_status jk_build(const jk_problem *p, const double *B, const double *CL,
                    const double *CR, double *J, double *K, void *ws,
                    size_t ws_bytes, void *stream);

@@ -79,6 +79,7 @@ int chunk_slabs(const jk_problem *p, size_t budget)
 
 struct FwdPlan {
     int qc, ldw, npb, plen, ndp, nsplit;
+    int nsplit_sym;     // exchange splits when C_L = C_R (upper-triangle tiles)
     size_t o_cc, o_d, o_part, o_g, o_x, o_y, o_kp, total;
 };
 
@@ -99,7 +100,9 @@ FwdPlan plan_forward(const jk_problem *p, size_t budget = kChunkBudget)
     f.o_x = c.take(sizeof(double) * nd * nao * (size_t)f.ldw);
     f.o_y = c.take(sizeof(double) * nd * nao * (size_t)f.ldw);
     f.nsplit = jk::exchange_nsplit((int)nao, (int)nd, f.ldw);
-    f.o_kp = c.take(f.nsplit > 1 ? sizeof(double) * (size_t)f.nsplit * nd * npos : 0);
+    f.nsplit_sym = jk::exchange_nsplit((int)nao, (int)nd, f.ldw, 1);
+    const int nsmax = f.nsplit > f.nsplit_sym ? f.nsplit : f.nsplit_sym;
+    f.o_kp = c.take(nsmax > 1 ? sizeof(double) * (size_t)nsmax * nd * npos : 0);
     f.total = c.off;
     return f;
 }
@@ -162,6 +165,7 @@ VjpPlan plan_vjp(const jk_problem *p)
 struct MixPlan {
     FwdPlan f;
     int ns, mp, kp, cp, jp, nsplit;
+    int cp_sym, nsplit_sym;   // X-only columns and triangle splits (C_L = C_R)
     size_t bp_bytes, xy_bytes, xyp_bytes;
     size_t o_bp[2], o_eb[2], o_xy[2], o_xyp[2], o_exy[2], o_cp, o_ec, o_kp, total;
 };
@@ -179,6 +183,9 @@ MixPlan plan_mixed(const jk_problem *p)
     x.cp = (int)pad_to(2 * R, jk::mixed_row_pad());
     x.jp = (int)pad_to((i64)x.f.qc * r, jk::mixed_k_pad());
     x.nsplit = jk::ex_mixed_nsplit(x.mp, (int)nd, x.jp / jk::mixed_k_block());
+    x.cp_sym = (int)pad_to(R, jk::mixed_row_pad());
+    x.nsplit_sym = jk::ex_mixed_nsplit(x.mp, (int)nd, x.jp / jk::mixed_k_block(), 1);
+    const int nsmax = x.nsplit > x.nsplit_sym ? x.nsplit : x.nsplit_sym;
     x.bp_bytes = (size_t)x.ns * x.f.qc * x.mp * x.kp;
     x.xy_bytes = sizeof(double) * (size_t)x.f.qc * nao * 2 * R;
     x.xyp_bytes = (size_t)x.ns * 2 * nd * x.mp * x.jp;
@@ -196,7 +203,7 @@ MixPlan plan_mixed(const jk_problem *p)
     }
     x.o_cp = c.take((size_t)x.ns * x.cp * x.kp);
     x.o_ec = c.take(sizeof(int) * (size_t)x.cp);
-    x.o_kp = c.take(sizeof(double) * (size_t)x.nsplit * nd * nao * nao);
+    x.o_kp = c.take(sizeof(double) * (size_t)nsmax * nd * nao * nao);
     x.total = c.off;
     return x;
 }
@@ -268,15 +275,24 @@ jk_status build_fp64(const jk_problem *p, const double *B, const double *CL, con
     if (w & JK_WANT_K) {
         // K accumulates over Q-chunks in nsplit partial buffers (or in K
         // itself when nsplit == 1), summed in fixed order at the end.
-        double *Kp = f.nsplit > 1 ? (double *)(ws + f.o_kp) : K;
+        // The same factor for both sides (C_L = C_R, symmetric densities):
+        // only X is formed, K = sum X X^T on the upper-triangle tiles, and the
+        // lower triangle is mirrored at the end.
+        const bool sym = CL == CR;
+        const int ns = sym ? f.nsplit_sym : f.nsplit;
+        double *Kp = ns > 1 ? (double *)(ws + f.o_kp) : K;
+        double *Yx = sym ? Xw : Yw;
         JK_TRY(jk::launch_pack_c(CL, CR, Cc, nao, nd, r, s));
         for (int q0 = 0; q0 < naux; q0 += f.qc) {
             int nq = (naux - q0) < f.qc ? (naux - q0) : f.qc;
-            JK_TRY(jk::launch_half_transform(B, Cc, Xw, Yw, nao, nd, r, q0, nq, f.ldw, s));
-            JK_TRY(jk::launch_exchange(Xw, Yw, Kp, nao, nd, nq * r, f.ldw, f.nsplit, q0 > 0, s));
+            JK_TRY(jk::launch_half_transform(B, Cc, Xw, Yw, nao, nd, r, q0, nq, f.ldw, s,
+                                             sym ? nd * r : 2 * nd * r));
+            JK_TRY(jk::launch_exchange(Xw, Yx, Kp, nao, nd, nq * r, f.ldw, ns, q0 > 0, s, sym));
         }
-        if (f.nsplit > 1)
-            JK_TRY(jk::launch_sum_splits(Kp, K, (i64)nd * npos, f.nsplit, s));
+        if (ns > 1)
+            JK_TRY(jk::launch_sum_splits(Kp, K, (i64)nd * npos, ns, s));
+        if (sym)
+            JK_TRY(jk::launch_mirror_upper(K, nao, nd, s));
     }
     return JK_OK;
 }
@@ -360,7 +376,12 @@ jk_status build_mixed(const jk_problem *p, const double *B, const double *CL, co
     double *Cc = (double *)(ws + f.o_cc);
     int8_t *Cp = (int8_t *)(ws + x.o_cp);
     int *eC = (int *)(ws + x.o_ec);
-    double *Kp = x.nsplit > 1 ? (double *)(ws + x.o_kp) : K;
+    // The same factor for both sides (C_L = C_R): X only, K on the upper
+    // triangle, mirrored at the end.
+    const bool sym = CL == CR;
+    const int nsplit = sym ? x.nsplit_sym : x.nsplit;
+    const int ncol = sym ? R : R2, nkey = sym ? nd : 2 * nd, cpx = sym ? x.cp_sym : x.cp;
+    double *Kp = nsplit > 1 ? (double *)(ws + x.o_kp) : K;
     const int KB = jk::mixed_k_block();
     // K-blocked plane strides (slice_core.hpp): kbstride = rows * 32 bytes
     const i64 bkb = (i64)f.qc * x.mp * KB, bps = bkb * (x.kp / KB);
@@ -395,8 +416,8 @@ jk_status build_mixed(const jk_problem *p, const double *B, const double *CL, co
         return JK_OK;
     };
     auto slice_xy = [&](int c) -> jk_status {
-        JK_TRY(jk::launch_xy_rowmax(XY(c), nao, nq_of(c), 2 * nd, r, x.mp, eXY(c), a));
-        JK_TRY(jk::launch_slice_xy(XY(c), nao, nd, r, x.mp, nq_of(c) * r, nkb_of(c), XYp(c), xps, xkb,
+        JK_TRY(jk::launch_xy_rowmax(XY(c), nao, nq_of(c), nkey, r, x.mp, eXY(c), a));
+        JK_TRY(jk::launch_slice_xy(XY(c), nao, nkey, r, x.mp, nq_of(c) * r, nkb_of(c), XYp(c), xps, xkb,
                                    eXY(c), a));
         JK_TRY(hipEventRecord(sx[c & 1], a));
         return JK_OK;
@@ -405,16 +426,17 @@ jk_status build_mixed(const jk_problem *p, const double *B, const double *CL, co
         JK_TRY(hipStreamWaitEvent(s, sb[c & 1], 0));
         if (c >= 2)
             JK_TRY(hipStreamWaitEvent(s, sx[c & 1], 0));    // XY[c] free
-        JK_TRY(jk::launch_ht_mixed(Bp(c), bps, bkb, eB(c), Cp, cps, ckb, eC, XY(c), nao, R2, nq_of(c),
-                                   x.mp, x.cp, x.kp / KB, s));
+        JK_TRY(jk::launch_ht_mixed(Bp(c), bps, bkb, eB(c), Cp, cps, ckb, eC, XY(c), nao, ncol, nq_of(c),
+                                   x.mp, cpx, x.kp / KB, s));
         JK_TRY(hipEventRecord(ht[c & 1], s));
         return JK_OK;
     };
     auto exch = [&](int c) -> jk_status {
         JK_TRY(hipStreamWaitEvent(s, sx[c & 1], 0));
-        const int8_t *Xp = XYp(c), *Yp = XYp(c) + (i64)nd * x.mp * KB;
-        JK_TRY(jk::launch_ex_mixed(Xp, Yp, xps, xkb, eXY(c), eXY(c) + (size_t)nd * x.mp, Kp, nao, nd,
-                                   x.mp, nkb_of(c), x.nsplit, c > 0, s));
+        const int8_t *Xp = XYp(c), *Yp = sym ? Xp : XYp(c) + (i64)nd * x.mp * KB;
+        const int *eX = eXY(c), *eY = sym ? eX : eXY(c) + (size_t)nd * x.mp;
+        JK_TRY(jk::launch_ex_mixed(Xp, Yp, xps, xkb, eX, eY, Kp, nao, nd, x.mp, nkb_of(c), nsplit, c > 0, s,
+                                   sym));
         JK_TRY(hipEventRecord(ex[c & 1], s));
         return JK_OK;
     };
@@ -452,8 +474,10 @@ jk_status build_mixed(const jk_problem *p, const double *B, const double *CL, co
         }
     }
 #undef JK_STEP
-    if (x.nsplit > 1)
-        JK_TRY(jk::launch_sum_splits(Kp, K, (i64)nd * npos, x.nsplit, s));
+    if (nsplit > 1)
+        JK_TRY(jk::launch_sum_splits(Kp, K, (i64)nd * npos, nsplit, s));
+    if (sym)
+        JK_TRY(jk::launch_mirror_upper(K, nao, nd, s));
     return JK_OK;
 }
 

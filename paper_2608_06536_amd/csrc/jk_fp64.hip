@@ -46,21 +46,50 @@ __global__ void __launch_bounds__(256, 3) k_half_transform(const double *__restr
                                                            const double *__restrict__ Cc,
                                                            double *__restrict__ Xw,
                                                            double *__restrict__ Yw, int nao, int nd,
-                                                           int r, int q0, int nq, int ldw)
+                                                           int r, int q0, int nq, int ldw, int ncol)
 {
     __shared__ double lds[TileHalf::LDS_DOUBLES];
-    const int n = ht_tiles(nao, nd, r, nq);
-    ht_tile(B, Cc, Xw, Yw, nao, nd, r, q0, ldw, xcd_swizzle(blockIdx.x, n), lds);
+    const int n = ht_tiles_cols(nao, ncol, nq);
+    ht_tile(B, Cc, Xw, Yw, nao, nd, r, q0, ldw, xcd_swizzle(blockIdx.x, n), lds, ncol);
 }
 
 __global__ void __launch_bounds__(512, 4) k_exchange(const double *__restrict__ Xw,
                                                      const double *__restrict__ Yw,
                                                      double *__restrict__ Kp, int nao, int nd, int nj,
-                                                     int ldw, int nsplit, int jlen, int accumulate)
+                                                     int ldw, int nsplit, int jlen, int accumulate,
+                                                     int sym)
 {
     __shared__ double lds[TileExch::LDS_DOUBLES];
-    const int n = ex_tiles(nao, nd, nsplit);
-    ex_tile(Xw, Yw, Kp, nao, nd, nj, ldw, jlen, accumulate, xcd_swizzle(blockIdx.x, n), lds);
+    const int n = nsplit * nd * (sym ? ex_tri_tiles(nao) : cdiv_i(nao, kExM) * cdiv_i(nao, kExN));
+    ex_tile(Xw, Yw, Kp, nao, nd, nj, ldw, jlen, accumulate, xcd_swizzle(blockIdx.x, n), lds, sym);
+}
+
+// K[k][m][n] = K[k][n][m] for m > n: fills the lower triangle from the upper
+// one through a 32 x 32 LDS transpose (block (bi, bj), bi >= bj).
+__global__ void __launch_bounds__(256) k_mirror_upper(double *__restrict__ K, int nao)
+{
+    __shared__ double t[32][33];
+    const int nb = cdiv_i(nao, 32);
+    int b = blockIdx.x, bi = 0;
+    while (b > bi) {     // lower-triangle block index -> (bi, bj)
+        b -= bi + 1;
+        bi++;
+    }
+    const int bj = b;
+    double *Kk = K + (i64)blockIdx.y * nao * nao;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int y = ty; y < 32; y += 8) {
+        const int row = bj * 32 + y, col = bi * 32 + tx;       // upper source
+        if (row < nao && col < nao)
+            t[y][tx] = Kk[(i64)row * nao + col];
+    }
+    __syncthreads();
+    for (int y = ty; y < 32; y += 8) {
+        const int m = bi * 32 + y, n = bj * 32 + tx;           // lower target
+        if (m < nao && n < nao && m > n)
+            Kk[(i64)m * nao + n] = t[tx][y];
+    }
+    (void)nb;
 }
 
 __global__ void __launch_bounds__(256) k_sum_splits(const double *__restrict__ part,
@@ -178,21 +207,33 @@ hipError_t launch_coulomb(const double *B, const double *g, double *J, int naux,
 }
 
 hipError_t launch_half_transform(const double *B, const double *Cc, double *Xw, double *Yw,
-                                 int nao, int nd, int r, int q0, int nq, int ldw, hipStream_t s)
+                                 int nao, int nd, int r, int q0, int nq, int ldw, hipStream_t s,
+                                 int ncol)
 {
+    if (ncol < 0)
+        ncol = 2 * nd * r;
     {
         ProfScope ps_("half_transform", s);
-        hipLaunchKernelGGL(k_half_transform, dim3(ht_tiles(nao, nd, r, nq)), dim3(256), 0, s, B, Cc, Xw,
-                           Yw, nao,
-                       nd, r, q0, nq, ldw);
+        hipLaunchKernelGGL(k_half_transform, dim3(ht_tiles_cols(nao, ncol, nq)), dim3(256), 0, s, B, Cc,
+                           Xw, Yw, nao, nd, r, q0, nq, ldw, ncol);
     }
     return hipGetLastError();
 }
 
-int exchange_nsplit(int nao, int nd, int nj)
+hipError_t launch_mirror_upper(double *K, int nao, int nd, hipStream_t s)
+{
+    const int nb = cdiv(nao, 32);
+    {
+        ProfScope ps_("mirror", s);
+        hipLaunchKernelGGL(k_mirror_upper, dim3(nb * (nb + 1) / 2, nd), dim3(256), 0, s, K, nao);
+    }
+    return hipGetLastError();
+}
+
+int exchange_nsplit(int nao, int nd, int nj, int sym)
 {
     // Full rounds of workgroups; each split keeps >= 256 inner indices.
-    const int tiles = nd * cdiv(nao, kExM) * cdiv(nao, kExN);
+    const int tiles = nd * (sym ? ex_tri_tiles(nao) : cdiv(nao, kExM) * cdiv(nao, kExN));
     int maxs = nj / 256 > 1 ? nj / 256 : 1;
     if (maxs > 16)
         maxs = 16;
@@ -200,15 +241,15 @@ int exchange_nsplit(int nao, int nd, int nj)
 }
 
 hipError_t launch_exchange(const double *Xw, const double *Yw, double *Kp, int nao, int nd, int nj,
-                           int ldw, int nsplit, int accumulate, hipStream_t s)
+                           int ldw, int nsplit, int accumulate, hipStream_t s, int sym)
 {
     int jlen = cdiv(nj, nsplit);
     jlen = ((jlen + 15) / 16) * 16;
+    const int per = sym ? ex_tri_tiles(nao) : cdiv(nao, kExM) * cdiv(nao, kExN);
     {
         ProfScope ps_("exchange", s);
-        hipLaunchKernelGGL(k_exchange, dim3(nsplit * nd * cdiv(nao, kExM) * cdiv(nao, kExN)),
-                       dim3(TileExch::NTHR), 0, s, Xw, Yw, Kp, nao, nd,
-                       nj, ldw, nsplit, jlen, accumulate);
+        hipLaunchKernelGGL(k_exchange, dim3(nsplit * nd * per), dim3(TileExch::NTHR), 0, s, Xw, Yw, Kp,
+                           nao, nd, nj, ldw, nsplit, jlen, accumulate, sym);
     }
     return hipGetLastError();
 }

@@ -42,10 +42,13 @@ hipError_t launch_project(const double *B, const double *A, double *part, double
 hipError_t launch_coulomb(const double *B, const double *g, double *J, int naux, int nd,
                           int64_t npos, hipStream_t s);
 hipError_t launch_half_transform(const double *B, const double *Cc, double *Xw, double *Yw,
-                                 int nao, int nd, int r, int q0, int nq, int ldw, hipStream_t s);
-int exchange_nsplit(int nao, int nd, int nj);
+                                 int nao, int nd, int r, int q0, int nq, int ldw, hipStream_t s,
+                                 int ncol = -1);
+// Lower triangle of every K_k from its upper triangle.
+hipError_t launch_mirror_upper(double *K, int nao, int nd, hipStream_t s);
+int exchange_nsplit(int nao, int nd, int nj, int sym = 0);
 hipError_t launch_exchange(const double *Xw, const double *Yw, double *Kp, int nao, int nd, int nj,
-                           int ldw, int nsplit, int accumulate, hipStream_t s);
+                           int ldw, int nsplit, int accumulate, hipStream_t s, int sym = 0);
 hipError_t launch_sum_splits(const double *part, double *out, i64 n, int nsplit, hipStream_t s);
 
 // derivative (jk_vjp.hip)
@@ -81,14 +84,14 @@ hipError_t launch_slice_b(const double *src, i64 bs, i64 rs, int nb, int nr, int
 int mixed_rowmax_ok(int R2);
 hipError_t launch_xy_rowmax(const double *XY, int nao, int nq, int nkey, int r, int mp, int *exps,
                             hipStream_t s);
-hipError_t launch_slice_xy(const double *XY, int nao, int nd, int r, int mp, int nj, int nkb,
+hipError_t launch_slice_xy(const double *XY, int nao, int nkey, int r, int mp, int nj, int nkb,
                            int8_t *out, i64 pstride, i64 kbstride, const int *exps, hipStream_t s);
 hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, i64 bkbstride, const int *eB,
                            const int8_t *Cp, i64 cpstride, i64 ckbstride, const int *eC, double *XY,
                            int nao, int R2, int nq, int mp, int cp, int nkb, hipStream_t s);
-int ex_mixed_nsplit(int mp, int nd, int nkb);
+int ex_mixed_nsplit(int mp, int nd, int nkb, int sym = 0);
 hipError_t launch_ex_mixed(const int8_t *Xp, const int8_t *Yp, i64 pstride, i64 kbstride,
                            const int *eX, const int *eY, double *Kp, int nao, int nd, int mp, int nkb,
-                           int nsplit, int accumulate, hipStream_t s);
+                           int nsplit, int accumulate, hipStream_t s, int sym = 0);
 
 } // namespace jk

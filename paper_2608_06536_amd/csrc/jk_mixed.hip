@@ -143,12 +143,12 @@ __global__ void __launch_bounds__(256) k_slice_rows_wave(const double *__restric
 }
 
 // Elementwise slicer of the half-transformed factors.  Source XY[ql][m][c]
-// (c < 2R; X_k = columns k*r.., Y_k = columns R + k*r..), plane row
-// (side * nd + k) * mp + m, inner index j = ql * r + i (j < nj), row
+// (c < nkey r; X_k = columns k*r.., Y_k = columns R + k*r..; nkey = 2 nd, or
+// nd when only X is formed), plane row (side * nd + k) * mp + m, inner index j = ql * r + i (j < nj), row
 // exponents exps[plane row] known.  32 plane rows x one 32-byte inner block
 // per workgroup (grid: row groups x nkb); each plane write of a workgroup is
 // one contiguous kilobyte.
-__global__ void __launch_bounds__(256) k_slice_xy(const double *__restrict__ XY, int nao, int nd,
+__global__ void __launch_bounds__(256) k_slice_xy(const double *__restrict__ XY, int nao, int nkey,
                                                   int r, int mp, int nj, int8_t *__restrict__ out,
                                                   i64 pstride, i64 kbstride,
                                                   const int *__restrict__ exps)
@@ -156,12 +156,12 @@ __global__ void __launch_bounds__(256) k_slice_xy(const double *__restrict__ XY,
     const int t = threadIdx.x, sub = t & 7;
     const int row = blockIdx.x * 32 + (t >> 3);
     const int kb = blockIdx.y;
-    if (row >= 2 * nd * mp)
+    if (row >= nkey * mp)
         return;
     const int key = row / mp, m = row % mp;
     const bool live = m < nao;
     const int e = exps[row];
-    const i64 R2 = 2 * (i64)nd * r;
+    const i64 R2 = (i64)nkey * r;     // row length of XY
     // loads are unconditional (clamped addresses), masked afterwards
     const double *s = XY + (i64)(live ? m : nao - 1) * R2 + (i64)key * r;
     const int j0 = kb * kSliceKB + sub * 4;
@@ -277,16 +277,30 @@ __global__ void __launch_bounds__(512) k_ex_mixed(const int8_t *__restrict__ Xp,
                                                   i64 kbstride, const int *__restrict__ eX,
                                                   const int *__restrict__ eY,
                                                   double *__restrict__ Kp, int nao, int nd, int mp,
-                                                  int nkb, int kbl, int accumulate)
+                                                  int nkb, int kbl, int accumulate, int sym)
 {
     extern __shared__ char lds[];
     typedef TileS TL;
     const int nmt = mp / kMT, nnt = mp / kNT;
-    const int per = nd * nmt * nnt;
+    // sym: Y = X, only the square tiles with nb >= mb (upper triangle)
+    const int pk = sym ? nmt * (nmt + 1) / 2 : nmt * nnt;
+    const int per = nd * pk;
     const int t = blockIdx.x;
     const int sp = t / per, rem0 = t % per;
-    const int k = rem0 / (nmt * nnt), rem = rem0 % (nmt * nnt);
-    const int mb = rem / nnt, nb = rem % nnt;
+    const int k = rem0 / pk, rem = rem0 % pk;
+    int mb, nb;
+    if (sym) {
+        int q = rem;
+        mb = 0;
+        while (q >= nmt - mb) {
+            q -= nmt - mb;
+            mb++;
+        }
+        nb = mb + q;
+    } else {
+        mb = rem / nnt;
+        nb = rem % nnt;
+    }
     const int kb0 = sp * kbl < nkb ? sp * kbl : nkb;
     const int kb1 = (kb0 + kbl) < nkb ? (kb0 + kbl) : nkb;
     SPlanes a{Xp + (i64)k * mp * kSliceKB, pstride, kbstride};
@@ -367,13 +381,13 @@ hipError_t launch_xy_rowmax(const double *XY, int nao, int nq, int nkey, int r, 
     return hipGetLastError();
 }
 
-hipError_t launch_slice_xy(const double *XY, int nao, int nd, int r, int mp, int nj, int nkb,
+hipError_t launch_slice_xy(const double *XY, int nao, int nkey, int r, int mp, int nj, int nkb,
                            int8_t *out, i64 pstride, i64 kbstride, const int *exps, hipStream_t s)
 {
     {
         ProfScope ps_("slice_xy", s);
-        hipLaunchKernelGGL(k_slice_xy, dim3(cdiv((i64)2 * nd * mp, 32), nkb), dim3(256), 0, s, XY, nao,
-                           nd, r, mp, nj, out, pstride, kbstride, exps);
+        hipLaunchKernelGGL(k_slice_xy, dim3(cdiv((i64)nkey * mp, 32), nkb), dim3(256), 0, s, XY, nao,
+                           nkey, r, mp, nj, out, pstride, kbstride, exps);
     }
     return hipGetLastError();
 }
@@ -407,10 +421,11 @@ hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, i64 bkbstride, const 
     return hipGetLastError();
 }
 
-int ex_mixed_nsplit(int mp, int nd, int nkb)
+int ex_mixed_nsplit(int mp, int nd, int nkb, int sym)
 {
     // one 512-thread workgroup per CU (registers), so half the usual slots
-    const int tiles = nd * (mp / kMT) * (mp / kNT);
+    const int nmt = mp / kMT;
+    const int tiles = nd * (sym ? nmt * (nmt + 1) / 2 : nmt * (mp / kNT));
     int maxs = nkb / 16 > 1 ? nkb / 16 : 1;
     if (maxs > 16)
         maxs = 16;
@@ -419,17 +434,18 @@ int ex_mixed_nsplit(int mp, int nd, int nkb)
 
 hipError_t launch_ex_mixed(const int8_t *Xp, const int8_t *Yp, i64 pstride, i64 kbstride,
                            const int *eX, const int *eY, double *Kp, int nao, int nd, int mp, int nkb,
-                           int nsplit, int accumulate, hipStream_t s)
+                           int nsplit, int accumulate, hipStream_t s, int sym)
 {
     hipError_t e = set_lds((const void *)k_ex_mixed, g_lds_ex);
     if (e != hipSuccess)
         return e;
     const int kbl = cdiv(nkb, nsplit);
+    const int nmt = mp / kMT;
+    const int pk = sym ? nmt * (nmt + 1) / 2 : nmt * (mp / kNT);
     {
         ProfScope ps_("ex_mixed", s);
-        hipLaunchKernelGGL(k_ex_mixed, dim3(nsplit * nd * (mp / kMT) * (mp / kNT)), dim3(TileS::NTHR),
-                           TileS::LDS_BYTES, s, Xp, Yp, pstride, kbstride, eX, eY, Kp, nao, nd, mp, nkb,
-                           kbl, accumulate);
+        hipLaunchKernelGGL(k_ex_mixed, dim3(nsplit * nd * pk), dim3(TileS::NTHR), TileS::LDS_BYTES, s, Xp,
+                           Yp, pstride, kbstride, eX, eY, Kp, nao, nd, mp, nkb, kbl, accumulate, sym);
     }
     return hipGetLastError();
 }

@@ -58,9 +58,43 @@ __host__ __device__ inline int ht_tiles(int nao, int nd, int r, int nq)
 {
     return nq * cdiv_i(nao, kHtM) * cdiv_i(2 * (i64)nd * r, kHtN);
 }
+// ncol = 2R (X and Y) or R (X only, symmetric densities)
+__host__ __device__ inline int ht_tiles_cols(int nao, int ncol, int nq)
+{
+    return nq * cdiv_i(nao, kHtM) * cdiv_i(ncol, kHtN);
+}
 __host__ __device__ inline int ex_tiles(int nao, int nd, int nsplit)
 {
     return nsplit * nd * cdiv_i(nao, kExM) * cdiv_i(nao, kExN);
+}
+
+// Symmetric exchange (C_L = C_R, K = sum X X^T): only the tiles that reach
+// the upper triangle n >= m, row tile mb from column tile (mb kExM) / kExN on.
+__host__ __device__ inline int ex_tri_first(int mb) { return (mb * kExM) / kExN; }
+__host__ __device__ inline int ex_tri_tiles(int nao)
+{
+    const int nmt = cdiv_i(nao, kExM), nnt = cdiv_i(nao, kExN);
+    int n = 0;
+    for (int mb = 0; mb < nmt; mb++) {
+        const int f = ex_tri_first(mb);
+        n += f < nnt ? nnt - f : 0;
+    }
+    return n;
+}
+__host__ __device__ inline void ex_tri_coords(int t, int nao, int &mb, int &nb)
+{
+    const int nmt = cdiv_i(nao, kExM), nnt = cdiv_i(nao, kExN);
+    for (mb = 0; mb < nmt; mb++) {
+        const int f = ex_tri_first(mb);
+        const int cnt = f < nnt ? nnt - f : 0;
+        if (t < cnt) {
+            nb = f + t;
+            return;
+        }
+        t -= cnt;
+    }
+    mb = nmt - 1;
+    nb = nnt - 1;
 }
 __host__ __device__ inline int sum_tiles(i64 n) { return cdiv_i(n, kElemTile); }
 
@@ -232,24 +266,26 @@ __device__ inline void coulomb_tile(const double *__restrict__ B, const double *
 
 // ------------------------------------------------------------------ half-transform
 // For slab Q = q0 + ql (ql < nq): XY[m][c] = sum_n B^Q[m][n] Cc[n][c], written
-// as X_ws[k][m][ql*r + i] (c = k*r + i < R) or Y_ws[k][m][ql*r + i] (c - R).
+// as X_ws[k][m][ql*r + i] (c = k*r + i < R) or Y_ws[k][m][ql*r + i] (c - R),
+// for the first ncol columns c (2R, or R when only X is needed).
 __device__ inline void ht_tile(const double *__restrict__ B, const double *__restrict__ Cc,
                                double *__restrict__ Xw, double *__restrict__ Yw, int nao, int nd,
-                               int r, int q0, int ldw, int tile, double *lds)
+                               int r, int q0, int ldw, int tile, double *lds, int ncol = -1)
 {
     typedef TileHalf TL;
     const int R = nd * r, R2 = 2 * R;
-    const int nmt = cdiv_i(nao, kHtM), nct = cdiv_i(R2, kHtN);
+    const int nc = ncol < 0 ? R2 : ncol;
+    const int nmt = cdiv_i(nao, kHtM), nct = cdiv_i(nc, kHtN);
     const int ql = tile / (nmt * nct), rem = tile % (nmt * nct);
     const int mb = rem / nct, cb = rem % nct;
     const i64 n2 = (i64)nao * nao;
     OpKC a{B + (i64)(q0 + ql) * n2, nao, nao, nao};
-    OpIC b{Cc, R2, R2, nao};
+    OpIC b{Cc, R2, nc, nao};
     Acc<TL> acc;
     acc.zero();
     tile_gemm<TL>(a, b, mb * kHtM, cb * kHtN, 0, nao, lds, acc);
     tile_foreach(acc, mb * kHtM, cb * kHtN, [&](int m, int c, double v) {
-        if (m < nao && c < R2) {
+        if (m < nao && c < nc) {
             double *dst = c < R ? Xw : Yw;
             const int cc = c < R ? c : c - R;
             const int k = cc / r, i = cc % r;
@@ -261,17 +297,26 @@ __device__ inline void ht_tile(const double *__restrict__ B, const double *__res
 // ------------------------------------------------------------------ exchange
 // Kp[s][k][m][n] (+)= sum_{j in split s} X_ws[k][m][j] Y_ws[k][n][j]; the
 // inner range [0, nj) is cut into nsplit contiguous pieces of jlen.
+// With sym != 0 (Yw = Xw) only the tiles reaching n >= m are computed; the
+// rest of K is filled by mirroring afterwards.
 __device__ inline void ex_tile(const double *__restrict__ Xw, const double *__restrict__ Yw,
                                double *__restrict__ Kp, int nao, int nd, int nj, int ldw, int jlen,
-                               int accumulate, int tile, double *lds)
+                               int accumulate, int tile, double *lds, int sym = 0)
 {
     typedef TileExch TL;
     const int nmt = cdiv_i(nao, kExM), nnt = cdiv_i(nao, kExN);
-    const int per = nd * nmt * nnt;
+    const int pk = sym ? ex_tri_tiles(nao) : nmt * nnt;
+    const int per = nd * pk;
     const int sp = tile / per;
     const int t = tile % per;
-    const int k = t / (nmt * nnt), rem = t % (nmt * nnt);
-    const int mb = rem / nnt, nb = rem % nnt;
+    const int k = t / pk, rem = t % pk;
+    int mb, nb;
+    if (sym) {
+        ex_tri_coords(rem, nao, mb, nb);
+    } else {
+        mb = rem / nnt;
+        nb = rem % nnt;
+    }
     const int j0 = sp * jlen, j1 = (j0 + jlen) < nj ? (j0 + jlen) : nj;
     OpKC a{Xw + (i64)k * nao * ldw, ldw, nao, j1};
     OpKC b{Yw + (i64)k * nao * ldw, ldw, nao, j1};

@@ -18,6 +18,12 @@ to 1000 AO):
   A "ground" density uses ``C_L = C_R = orth(...)`` (a projector); a
   "transition" density uses independent ``C_L`` and ``C_R``.
 * Cotangents ``W``, ``V`` are standard normal ``nao x nao`` (non-symmetric).
+* Laplace pseudo-density inputs (stand-in for SCF orbitals): coefficients
+  ``C = orth(N(0,1) nao x (nocc + nvir))`` split into occupied and virtual
+  columns; occupied energies: ``ncore`` core levels uniform in
+  [-20.6, -11.0] Hartree, the rest valence levels uniform in [-1.4, -0.35];
+  virtual energies log-uniform in [0.1, 20]; amplitudes ``X_m`` standard
+  normal ``nocc x nvir``.  Energies are sorted ascending.
 """
 from __future__ import annotations
 
@@ -26,7 +32,8 @@ import numpy as np
 
 __all__ = [
     "Problem", "CONFIGS", "config", "make_B", "make_B_slabs", "make_factors",
-    "make_cotangents", "make_problem", "batched_problems",
+    "make_cotangents", "make_problem", "batched_problems", "Orbitals", "make_orbitals",
+    "make_amplitudes", "LAPLACE_BENCH",
 ]
 
 
@@ -150,3 +157,38 @@ def batched_problems(n_geom: int = 64, lo: int = 100, hi: int = 500,
         out.append(Problem(nao=nao, naux=naux, nd=nd, r=max(1, nao // 10), ell=20.0,
                            tau=naux / 4.0, n_ground=1, seed=seed * 1000 + g))
     return out
+
+
+@dataclasses.dataclass(frozen=True)
+class Orbitals:
+    """Shapes and generator parameters of one set of synthetic orbitals."""
+    nao: int
+    nocc: int
+    nvir: int
+    ncore: int = 0
+    seed: int = 2000
+
+
+def make_orbitals(o: Orbitals):
+    """``(Cocc [nao][nocc], e_occ [nocc], Cvir [nao][nvir], e_vir [nvir])``."""
+    rng = np.random.default_rng(np.random.SeedSequence(o.seed, spawn_key=(4,)))
+    C = _orth(rng, o.nao, o.nocc + o.nvir)
+    core = rng.uniform(-20.6, -11.0, size=o.ncore)
+    val = rng.uniform(-1.4, -0.35, size=o.nocc - o.ncore)
+    e_occ = np.sort(np.concatenate([core, val]))
+    e_vir = np.sort(0.1 * 200.0 ** rng.uniform(0.0, 1.0, size=o.nvir))
+    return (np.ascontiguousarray(C[:, :o.nocc]), e_occ,
+            np.ascontiguousarray(C[:, o.nocc:]), e_vir)
+
+
+def make_amplitudes(o: Orbitals, nvec: int) -> np.ndarray:
+    """``X [nvec][nocc][nvir]``, standard normal."""
+    rng = np.random.default_rng(np.random.SeedSequence(o.seed, spawn_key=(5,)))
+    return rng.standard_normal((nvec, o.nocc, o.nvir))
+
+
+# The Laplace driver's benchmark: the differentiated-build sizes (nao = 500,
+# naux = 2000) with nocc = 40 occupied orbitals (8 of them core), the other
+# 460 columns virtual, one amplitude matrix and 8 quadrature points, so the
+# build sees 8 transition densities of rank 40.
+LAPLACE_BENCH = (Orbitals(nao=500, nocc=40, nvir=460, ncore=8, seed=2004), 1, 8)

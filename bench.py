@@ -16,6 +16,7 @@ against the CPU oracle, and the CPU oracle's own rate on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -208,6 +209,41 @@ def main():
     except _lib.JKError as e:
         sym = {"symmetric": f"unavailable: {e}"}
 
+    # ---- Laplace pseudo-density driver (same B; energy-scaled factors + J/K)
+    try:
+        from paper_2608_06536_amd import laplace as lap
+        lo_, nvec_l, npts_l = synth.LAPLACE_BENCH
+        Co, eo, Cv, ev, Xl = (torch.from_numpy(a).to(dev) for a in
+                              (*synth.make_orbitals(lo_), synth.make_amplitudes(lo_, nvec_l)))
+        t_r = time.perf_counter()
+        x_lo, x_hi = lap.denominator_range(eo, ev)
+        w_l, a_l, err_l, lev_l = lap.laplace_quadrature(npts_l, x_lo, x_hi)
+        t_rule = time.perf_counter() - t_r
+        nd_l = npts_l * nvec_l
+        Jl = torch.empty((npts_l, nvec_l, nao, nao), dtype=torch.float64, device=dev)
+        Kl = torch.empty_like(Jl)
+        lap_res = {"workload": f"{npts_l} quadrature points x {nvec_l} amplitude matrix, "
+                               f"nocc={lo_.nocc} nvir={lo_.nvir}: {nd_l} densities of rank "
+                               f"{lo_.nocc}", "rule_points": npts_l, "rule_range": [x_lo, x_hi],
+                   "rule_max_rel_err": err_l, "rule_is_minimax": lev_l,
+                   "rule_host_s": round(t_rule, 3)}
+        for prec in ("fp64",) + (() if args.no_mixed else ("mixed",)):
+            pl = lap.make_laplace_problem(nao, naux, lo_.nocc, lo_.nvir, nvec_l, npts_l, prec)
+            wsl = torch.empty(int(_lib.lib().jk_laplace_workspace_bytes(ctypes.byref(pl))),
+                              dtype=torch.uint8, device=dev)
+
+            def build_lap():
+                lap.laplace_jk(Bd, Co, eo, Cv, ev, Xl, rule=(w_l, a_l), precision=prec,
+                               out=(Jl, Kl), ws=wsl)
+
+            t_l = rate(build_lap)
+            lap_res[f"densities_per_s_{prec}"] = round(nd_l / t_l, 2)
+            lap_res[f"build_ms_{prec}"] = round(1e3 * t_l, 3)
+            del wsl
+        del Co, eo, Cv, ev, Xl, Jl, Kl
+    except _lib.JKError as e:
+        lap_res = {"laplace": f"unavailable: {e}"}
+
     # ---- roofline of the dominant kernel
     models = kernel_models(p, nd, nao, naux, R)
     per_kernel = {}
@@ -261,6 +297,7 @@ def main():
         "vjp_ms_fp64": round(1e3 * t_vjp, 3),
         "mixed": mixed,
         "symmetric_densities": sym,
+        "laplace": lap_res,
         "roofline": roof,
         "kernels": per_kernel,
         "prof_dropped": dropped,

@@ -18,6 +18,9 @@ JK_WANT_J, JK_WANT_K = 1, 2
 # Every symbol include/jk.h and include/jk_prof.h declare.
 EXPORTS = ("jk_workspace_bytes", "jk_build", "jk_batched_workspace_bytes", "jk_build_batched",
            "jk_vjp", "jk_status_str")
+LAPLACE_EXPORTS = ("jk_laplace_quadrature", "jk_laplace_factors", "jk_laplace_workspace_bytes",
+                   "jk_laplace_build")
+LAPLACE_MAX_POINTS = 20
 PROF_EXPORTS = ("jk_prof_enable", "jk_prof_reset", "jk_prof_collect", "jk_prof_entry",
                 "jk_prof_dropped")
 
@@ -26,6 +29,12 @@ class Problem(ctypes.Structure):
     _fields_ = [("nao", ctypes.c_int64), ("naux", ctypes.c_int64), ("ndens", ctypes.c_int64),
                 ("rank", ctypes.c_int64), ("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("nslice", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class LaplaceProblem(ctypes.Structure):
+    _fields_ = [("nao", ctypes.c_int64), ("naux", ctypes.c_int64), ("nocc", ctypes.c_int64),
+                ("nvir", ctypes.c_int64), ("nvec", ctypes.c_int64), ("npts", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_int32), ("nslice", ctypes.c_int32)]
 
 
 class JKError(RuntimeError):
@@ -58,6 +67,17 @@ def lib():
         L.jk_vjp.argtypes = [pp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.jk_status_str.restype = ctypes.c_char_p
         L.jk_status_str.argtypes = [ctypes.c_int]
+        dp = ctypes.POINTER(ctypes.c_double)
+        i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        L.jk_laplace_quadrature.restype = ctypes.c_int
+        L.jk_laplace_quadrature.argtypes = [i32, dbl, dbl, dp, dp, dp, ctypes.POINTER(i32)]
+        L.jk_laplace_factors.restype = ctypes.c_int
+        L.jk_laplace_factors.argtypes = [i64, i64, i64, i64, i32, vp, vp, vp, dp, dp, dbl, vp, vp]
+        lpp = ctypes.POINTER(LaplaceProblem)
+        L.jk_laplace_workspace_bytes.restype = sz
+        L.jk_laplace_workspace_bytes.argtypes = [lpp]
+        L.jk_laplace_build.restype = ctypes.c_int
+        L.jk_laplace_build.argtypes = [lpp, vp, vp, vp, vp, vp, vp, dp, dp, dbl, vp, vp, vp, sz, vp]
         L.jk_prof_enable.restype = ctypes.c_int
         L.jk_prof_enable.argtypes = [ctypes.c_int32]
         L.jk_prof_reset.restype = None

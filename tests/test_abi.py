@@ -23,7 +23,10 @@ def test_header_symbols_exported():
     assert set(names) == set(_lib.EXPORTS)
     prof = _declared("jk_prof.h")
     assert set(prof) == set(_lib.PROF_EXPORTS)
-    for n in names + prof:
+    lap = _declared("jk_laplace.h")
+    assert set(lap) == set(_lib.LAPLACE_EXPORTS)
+    assert sorted(os.listdir(os.path.join(ROOT, "include"))) == ["jk.h", "jk_laplace.h", "jk_prof.h"]
+    for n in names + prof + lap:
         assert hasattr(L, n), n
 
 

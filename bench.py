@@ -209,6 +209,40 @@ def main():
     except _lib.JKError as e:
         sym = {"symmetric": f"unavailable: {e}"}
 
+    # ---- Fock combination 2J - a K - b K_lr in one call (second factor set:
+    # a scaled copy of B in its own buffer, naux_lr = naux)
+    try:
+        Blr = Bd * 0.7
+        Ff = torch.empty_like(J)
+        fock = {"workload": "F = 2 J - 0.25 K - 0.75 K_lr, K_lr from a second set of "
+                            f"{naux} Cholesky vectors, same densities"}
+        for prec in ("fp64",) + (() if args.no_mixed else ("mixed",)):
+            wsf = torch.empty(int(_lib.lib().jk_fock_workspace_bytes(
+                ctypes.byref(jk.make_problem(nao, naux, nd, r, prec)), naux)),
+                dtype=torch.uint8, device=dev)
+
+            def fock_call():
+                jk.jk_fock(Bd, Ld, Rd, 2.0, -0.25, B_lr=Blr, c_lr=-0.75, precision=prec,
+                           out=Ff, ws=wsf)
+
+            t_f = rate(fock_call)
+            fock[f"fock_ms_{prec}"] = round(1e3 * t_f, 3)
+            fock[f"densities_per_s_{prec}"] = round(nd / t_f, 2)
+            del wsf
+        Jb, Kb = torch.empty_like(J), torch.empty_like(K)
+
+        def separate():
+            jk.jk_build(Bd, Ld, Rd, out=(J, K), ws=ws)
+            jk.jk_build(Blr, Ld, Rd, want_j=False, out=(None, Kb), ws=ws)
+            torch.add(2.0 * J, K, alpha=-0.25, out=Jb)
+            Jb.add_(Kb, alpha=-0.75)
+
+        t_sep = rate(separate)
+        fock["separate_calls_ms_fp64"] = round(1e3 * t_sep, 3)
+        del Blr, Ff, Jb, Kb
+    except _lib.JKError as e:
+        fock = {"fock": f"unavailable: {e}"}
+
     # ---- Laplace pseudo-density driver (same B; energy-scaled factors + J/K)
     try:
         from paper_2608_06536_amd import laplace as lap
@@ -297,6 +331,7 @@ def main():
         "vjp_ms_fp64": round(1e3 * t_vjp, 3),
         "mixed": mixed,
         "symmetric_densities": sym,
+        "fock": fock,
         "laplace": lap_res,
         "roofline": roof,
         "kernels": per_kernel,

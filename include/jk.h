@@ -101,6 +101,34 @@ jk_status jk_build(const jk_problem *p, const double *B, const double *CL,
                    const double *CR, double *J, double *K, void *ws,
                    size_t ws_bytes, void *stream);
 
+/* Workspace bytes needed by jk_fock for problem *p (0 if invalid). */
+size_t jk_fock_workspace_bytes(const jk_problem *p, int64_t naux_lr);
+
+/* Fock-type combination in one call (Sec. 2.1, Eq. (selfadjoint): J, K and
+ * the long-range exchange K_LR are nodes of one self-adjoint family; Sec.
+ * 2.6 and Sec. 4.1: the combination 2J - a_x K of the SCF response and of
+ * the derivative Fock build; Sec. 2.5: range-separated exchange through
+ * K_LR):
+ *     F_k = c_j J[D_k] + c_k K[D_k] + c_lr K_lr[D_k],   D_k = CL_k CR_k^T,
+ *     K_lr[D] = sum_P B_lr^P D B_lr^P  with a second Cholesky factor set
+ *               B_lr [naux_lr][nao][nao] (symmetric slabs), e.g. that of the
+ *               long-range Coulomb operator.
+ * Both exchange streams accumulate into one set of partial sums (every
+ * chunk's contribution scaled by its coefficient), and J is added by the
+ * Coulomb pass at the end: F is the only output array written.
+ *   coef   HOST array {c_j, c_k, c_lr}; a zero coefficient skips its term
+ *          (all zero: F = 0)
+ *   B_lr   DEVICE pointer or NULL; NULL requires naux_lr == 0 and c_lr == 0
+ *   F      DEVICE [ndens][nao][nao], overwritten
+ * p->flags must be 0 or JK_WANT_J | JK_WANT_K.  FP64 and JK_MIXED (the
+ * exchange products of both streams in INT8 slices, J in FP64).  CL == CR
+ * takes the symmetric path as in jk_build.  Summation order differs from
+ * adding separate jk_build results, so F agrees with them to rounding, not
+ * bit for bit. */
+jk_status jk_fock(const jk_problem *p, const double *B, const double *B_lr, int64_t naux_lr,
+                  const double *CL, const double *CR, const double *coef, double *F, void *ws,
+                  size_t ws_bytes, void *stream);
+
 /* Workspace bytes needed by jk_build_batched for the nprob problems p[0..]. */
 size_t jk_batched_workspace_bytes(int32_t nprob, const jk_problem *p);
 

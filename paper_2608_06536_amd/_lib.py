@@ -16,8 +16,8 @@ JK_FP64, JK_MIXED = 0, 1
 JK_WANT_J, JK_WANT_K = 1, 2
 
 # Every symbol include/jk.h and include/jk_prof.h declare.
-EXPORTS = ("jk_workspace_bytes", "jk_build", "jk_batched_workspace_bytes", "jk_build_batched",
-           "jk_vjp", "jk_status_str")
+EXPORTS = ("jk_workspace_bytes", "jk_build", "jk_fock_workspace_bytes", "jk_fock",
+           "jk_batched_workspace_bytes", "jk_build_batched", "jk_vjp", "jk_status_str")
 LAPLACE_EXPORTS = ("jk_laplace_quadrature", "jk_laplace_factors", "jk_laplace_workspace_bytes",
                    "jk_laplace_build")
 LAPLACE_MAX_POINTS = 20
@@ -59,6 +59,11 @@ def lib():
         L.jk_workspace_bytes.argtypes = [pp]
         L.jk_build.restype = ctypes.c_int
         L.jk_build.argtypes = [pp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.jk_fock_workspace_bytes.restype = sz
+        L.jk_fock_workspace_bytes.argtypes = [pp, ctypes.c_int64]
+        L.jk_fock.restype = ctypes.c_int
+        L.jk_fock.argtypes = [pp, vp, vp, ctypes.c_int64, vp, vp, ctypes.POINTER(ctypes.c_double),
+                              vp, vp, sz, vp]
         L.jk_batched_workspace_bytes.restype = sz
         L.jk_batched_workspace_bytes.argtypes = [ctypes.c_int32, pp]
         L.jk_build_batched.restype = ctypes.c_int

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <string>
@@ -252,47 +253,95 @@ struct EventSet {
     }
 };
 
-jk_status build_fp64(const jk_problem *p, const double *B, const double *CL, const double *CR,
-                     double *J, double *K, char *ws, hipStream_t s)
+// One stream of Cholesky vectors feeding the exchange sum:
+//     K += scale * sum_{Q < naux} B^Q D B^Q.
+// The plain build has one segment (B, scale 1); the Fock combination adds a
+// segment per exchange operator (e.g. the long-range factor set).
+struct KSeg {
+    const double *B;
+    int naux;
+    double scale;
+};
+
+// What a build writes: J and K (the plain build, as selected by flags), or
+// one combined F = cj J + sum over segments of scale K (when F is set).
+struct BuildOut {
+    double *J = nullptr, *K = nullptr;
+    double *F = nullptr;
+    double cj = 0.0;
+};
+
+// The Coulomb part: gamma_kQ = <D_k, B^Q> in FP64, then
+// out (+)= scale sum_Q gamma_kQ B^Q.
+jk_status coulomb_part(const FwdPlan &f, int nao, int naux, int nd, int r, const double *B,
+                       const double *CL, const double *CR, double *out, double scale,
+                       int accumulate, char *ws, hipStream_t s)
+{
+    const i64 npos = (i64)nao * nao;
+    double *D = (double *)(ws + f.o_d);
+    double *part = (double *)(ws + f.o_part);
+    double *g = (double *)(ws + f.o_g);
+    JK_TRY(jk::launch_density(CL, CR, D, nao, nd, r, s));
+    JK_TRY(jk::launch_project(B, D, part, g, naux, nd, npos, s));
+    JK_TRY(jk::launch_coulomb(B, g, out, naux, nd, npos, s, scale, accumulate));
+    return JK_OK;
+}
+
+jk_status build_fp64(const jk_problem *p, const double *B, const KSeg *seg, int nseg,
+                     const double *CL, const double *CR, const BuildOut &o, char *ws,
+                     hipStream_t s)
 {
     const FwdPlan f = plan_forward(p);
     const int nao = (int)p->nao, naux = (int)p->naux, nd = (int)p->ndens, r = (int)p->rank;
     const i64 npos = (i64)nao * nao;
     const int w = want(p);
+    const bool fused = o.F != nullptr;
+    double *Kout = fused ? o.F : o.K;
     double *Cc = (double *)(ws + f.o_cc);
-    double *D = (double *)(ws + f.o_d);
-    double *part = (double *)(ws + f.o_part);
-    double *g = (double *)(ws + f.o_g);
     double *Xw = (double *)(ws + f.o_x);
     double *Yw = (double *)(ws + f.o_y);
 
-    if (w & JK_WANT_J) {
-        // gamma_kQ = <D_k, B^Q> in FP64, then J_k = sum_Q gamma_kQ B^Q.
-        JK_TRY(jk::launch_density(CL, CR, D, nao, nd, r, s));
-        JK_TRY(jk::launch_project(B, D, part, g, naux, nd, npos, s));
-        JK_TRY(jk::launch_coulomb(B, g, J, naux, nd, npos, s));
+    if (!fused && (w & JK_WANT_J)) {
+        jk_status st = coulomb_part(f, nao, naux, nd, r, B, CL, CR, o.J, 1.0, 0, ws, s);
+        if (st != JK_OK)
+            return st;
     }
-    if (w & JK_WANT_K) {
-        // K accumulates over Q-chunks in nsplit partial buffers (or in K
-        // itself when nsplit == 1), summed in fixed order at the end.
-        // The same factor for both sides (C_L = C_R, symmetric densities):
-        // only X is formed, K = sum X X^T on the upper-triangle tiles, and the
-        // lower triangle is mirrored at the end.
+    const bool want_k = fused ? nseg > 0 : (w & JK_WANT_K) != 0;
+    if (want_k) {
+        // K accumulates over the Q-chunks of every segment in nsplit partial
+        // buffers (or in the output itself when nsplit == 1), summed in fixed
+        // order at the end.  The same factor for both sides (C_L = C_R,
+        // symmetric densities): only X is formed, K = sum X X^T on the
+        // upper-triangle tiles, and the lower triangle is mirrored at the end.
         const bool sym = CL == CR;
         const int ns = sym ? f.nsplit_sym : f.nsplit;
-        double *Kp = ns > 1 ? (double *)(ws + f.o_kp) : K;
+        double *Kp = ns > 1 ? (double *)(ws + f.o_kp) : Kout;
         double *Yx = sym ? Xw : Yw;
         JK_TRY(jk::launch_pack_c(CL, CR, Cc, nao, nd, r, s));
-        for (int q0 = 0; q0 < naux; q0 += f.qc) {
-            int nq = (naux - q0) < f.qc ? (naux - q0) : f.qc;
-            JK_TRY(jk::launch_half_transform(B, Cc, Xw, Yw, nao, nd, r, q0, nq, f.ldw, s,
-                                             sym ? nd * r : 2 * nd * r));
-            JK_TRY(jk::launch_exchange(Xw, Yx, Kp, nao, nd, nq * r, f.ldw, ns, q0 > 0, s, sym));
+        bool first = true;
+        for (int sgi = 0; sgi < nseg; sgi++) {
+            const KSeg &sg = seg[sgi];
+            for (int q0 = 0; q0 < sg.naux; q0 += f.qc) {
+                int nq = (sg.naux - q0) < f.qc ? (sg.naux - q0) : f.qc;
+                JK_TRY(jk::launch_half_transform(sg.B, Cc, Xw, Yw, nao, nd, r, q0, nq, f.ldw, s,
+                                                 sym ? nd * r : 2 * nd * r));
+                JK_TRY(jk::launch_exchange(Xw, Yx, Kp, nao, nd, nq * r, f.ldw, ns, !first, s, sym,
+                                           sg.scale));
+                first = false;
+            }
         }
         if (ns > 1)
-            JK_TRY(jk::launch_sum_splits(Kp, K, (i64)nd * npos, ns, s));
+            JK_TRY(jk::launch_sum_splits(Kp, Kout, (i64)nd * npos, ns, s));
         if (sym)
-            JK_TRY(jk::launch_mirror_upper(K, nao, nd, s));
+            JK_TRY(jk::launch_mirror_upper(Kout, nao, nd, s));
+    }
+    if (fused && (o.cj != 0.0 || !want_k)) {
+        // F (+)= cj J (J is symmetric, so the order against the mirror does
+        // not matter); with no exchange term this writes F = cj J.
+        jk_status st = coulomb_part(f, nao, naux, nd, r, B, CL, CR, o.F, o.cj, want_k ? 1 : 0, ws,
+                                    s);
+        if (st != JK_OK)
+            return st;
     }
     return JK_OK;
 }
@@ -351,8 +400,9 @@ jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const
     return JK_OK;
 }
 
-jk_status build_mixed(const jk_problem *p, const double *B, const double *CL, const double *CR,
-                      double *J, double *K, char *ws, hipStream_t s)
+jk_status build_mixed(const jk_problem *p, const double *B, const KSeg *seg, int nseg,
+                      const double *CL, const double *CR, const BuildOut &o, char *ws,
+                      hipStream_t s)
 {
     const MixPlan x = plan_mixed(p);
     const FwdPlan &f = x.f;
@@ -362,17 +412,35 @@ jk_status build_mixed(const jk_problem *p, const double *B, const double *CL, co
         return JK_EUNSUPPORTED;
     const i64 npos = (i64)nao * nao;
     const int w = want(p);
-    if (w & JK_WANT_J) {
-        // gamma and J stay FP64 (the same kernels as the FP64 path).
-        double *D = (double *)(ws + f.o_d);
-        double *part = (double *)(ws + f.o_part);
-        double *g = (double *)(ws + f.o_g);
-        JK_TRY(jk::launch_density(CL, CR, D, nao, nd, r, s));
-        JK_TRY(jk::launch_project(B, D, part, g, naux, nd, npos, s));
-        JK_TRY(jk::launch_coulomb(B, g, J, naux, nd, npos, s));
+    const bool fused = o.F != nullptr;
+    double *K = fused ? o.F : o.K;
+    // gamma and J stay FP64 (the same kernels as the FP64 path).
+    if (!fused && (w & JK_WANT_J)) {
+        jk_status st = coulomb_part(f, nao, naux, nd, r, B, CL, CR, o.J, 1.0, 0, ws, s);
+        if (st != JK_OK)
+            return st;
     }
-    if (!(w & JK_WANT_K))
+    const bool want_k = fused ? nseg > 0 : (w & JK_WANT_K) != 0;
+    auto fock_j = [&]() -> jk_status {
+        if (fused && (o.cj != 0.0 || !want_k))
+            return coulomb_part(f, nao, naux, nd, r, B, CL, CR, o.F, o.cj, want_k ? 1 : 0, ws, s);
         return JK_OK;
+    };
+    if (!want_k)
+        return fock_j();
+    // The Q-chunks of every segment, in order: slab pointer, slab count,
+    // exchange scale.
+    struct Chunk {
+        const double *B;
+        int nq;
+        double scale;
+    };
+    std::vector<Chunk> chunks;
+    for (int sgi = 0; sgi < nseg; sgi++)
+        for (int q0 = 0; q0 < seg[sgi].naux; q0 += f.qc)
+            chunks.push_back({seg[sgi].B + (i64)q0 * npos,
+                              (seg[sgi].naux - q0) < f.qc ? (seg[sgi].naux - q0) : f.qc,
+                              seg[sgi].scale});
     double *Cc = (double *)(ws + f.o_cc);
     int8_t *Cp = (int8_t *)(ws + x.o_cp);
     int *eC = (int *)(ws + x.o_ec);
@@ -387,8 +455,8 @@ jk_status build_mixed(const jk_problem *p, const double *B, const double *CL, co
     const i64 bkb = (i64)f.qc * x.mp * KB, bps = bkb * (x.kp / KB);
     const i64 ckb = (i64)x.cp * KB, cps = ckb * (x.kp / KB);
     const i64 xkb = (i64)2 * nd * x.mp * KB, xps = xkb * (x.jp / KB);
-    const int nchunk = (naux + f.qc - 1) / f.qc;
-    auto nq_of = [&](int c) { return (naux - c * f.qc) < f.qc ? (naux - c * f.qc) : f.qc; };
+    const int nchunk = (int)chunks.size();
+    auto nq_of = [&](int c) { return chunks[c].nq; };
     auto nkb_of = [&](int c) { return (int)(pad_to((i64)nq_of(c) * r, jk::mixed_k_pad()) / KB); };
     auto Bp = [&](int c) { return (int8_t *)(ws + x.o_bp[c & 1]); };
     auto eB = [&](int c) { return (int *)(ws + x.o_eb[c & 1]); };
@@ -410,7 +478,7 @@ jk_status build_mixed(const jk_problem *p, const double *B, const double *CL, co
     hipEvent_t fork = E.ev[0], sb[2] = {E.ev[1], E.ev[2]}, ht[2] = {E.ev[3], E.ev[4]},
                sx[2] = {E.ev[5], E.ev[6]}, ex[2] = {E.ev[7], E.ev[8]};
     auto slice_b = [&](int c) -> jk_status {
-        JK_TRY(jk::launch_slice_b(B + (i64)c * f.qc * npos, npos, nao, nq_of(c), nao, nao, x.mp,
+        JK_TRY(jk::launch_slice_b(chunks[c].B, npos, nao, nq_of(c), nao, nao, x.mp,
                                   x.kp / KB, Bp(c), bps, bkb, eB(c), a));
         JK_TRY(hipEventRecord(sb[c & 1], a));
         return JK_OK;
@@ -436,7 +504,7 @@ jk_status build_mixed(const jk_problem *p, const double *B, const double *CL, co
         const int8_t *Xp = XYp(c), *Yp = sym ? Xp : XYp(c) + (i64)nd * x.mp * KB;
         const int *eX = eXY(c), *eY = sym ? eX : eXY(c) + (size_t)nd * x.mp;
         JK_TRY(jk::launch_ex_mixed(Xp, Yp, xps, xkb, eX, eY, Kp, nao, nd, x.mp, nkb_of(c), nsplit, c > 0, s,
-                                   sym));
+                                   sym, chunks[c].scale));
         JK_TRY(hipEventRecord(ex[c & 1], s));
         return JK_OK;
     };
@@ -478,7 +546,19 @@ jk_status build_mixed(const jk_problem *p, const double *B, const double *CL, co
         JK_TRY(jk::launch_sum_splits(Kp, K, (i64)nd * npos, nsplit, s));
     if (sym)
         JK_TRY(jk::launch_mirror_upper(K, nao, nd, s));
-    return JK_OK;
+    return fock_j();
+}
+
+// The plain build: J and K of B as selected by flags.
+jk_status build_plain(const jk_problem *p, const double *B, const double *CL, const double *CR,
+                      double *J, double *K, char *ws, hipStream_t s)
+{
+    const KSeg seg{B, (int)p->naux, 1.0};
+    BuildOut o;
+    o.J = J;
+    o.K = K;
+    return p->precision == JK_MIXED ? build_mixed(p, B, &seg, 1, CL, CR, o, ws, s)
+                                     : build_fp64(p, B, &seg, 1, CL, CR, o, ws, s);
 }
 
 // ------------------------------------------------------------------ batched
@@ -769,9 +849,45 @@ jk_status jk_build(const jk_problem *p, const double *B, const double *CL, const
         return JK_EINVAL;
     if (ws_bytes < jk_workspace_bytes(p))
         return JK_EWORKSPACE;
-    if (p->precision == JK_MIXED)
-        return build_mixed(p, B, CL, CR, J, K, (char *)ws, (hipStream_t)stream);
-    return build_fp64(p, B, CL, CR, J, K, (char *)ws, (hipStream_t)stream);
+    return build_plain(p, B, CL, CR, J, K, (char *)ws, (hipStream_t)stream);
+}
+
+size_t jk_fock_workspace_bytes(const jk_problem *p, int64_t naux_lr)
+{
+    if (!valid_problem(p) || naux_lr < 0 || naux_lr > ((int64_t)1 << 28))
+        return 0;
+    return p->precision == JK_MIXED ? plan_mixed(p).total : plan_forward(p).total;
+}
+
+jk_status jk_fock(const jk_problem *p, const double *B, const double *B_lr, int64_t naux_lr,
+                  const double *CL, const double *CR, const double *coef, double *F, void *ws,
+                  size_t ws_bytes, void *stream)
+{
+    if (!valid_problem(p) || (p->flags != 0 && p->flags != (JK_WANT_J | JK_WANT_K)))
+        return JK_EINVAL;
+    if (!B || !CL || !CR || !coef || !F || !ws || ((uintptr_t)ws) % kAlign)
+        return JK_EINVAL;
+    for (int i = 0; i < 3; i++)
+        if (!std::isfinite(coef[i]))
+            return JK_EINVAL;
+    if ((B_lr == nullptr) != (naux_lr == 0) || (B_lr == nullptr && coef[2] != 0.0))
+        return JK_EINVAL;
+    if (naux_lr < 0 || naux_lr > ((int64_t)1 << 28))
+        return JK_EINVAL;
+    if (ws_bytes < jk_fock_workspace_bytes(p, naux_lr))
+        return JK_EWORKSPACE;
+    KSeg seg[2];
+    int nseg = 0;
+    if (coef[1] != 0.0)
+        seg[nseg++] = KSeg{B, (int)p->naux, coef[1]};
+    if (B_lr && coef[2] != 0.0)
+        seg[nseg++] = KSeg{B_lr, (int)naux_lr, coef[2]};
+    BuildOut o;
+    o.F = F;
+    o.cj = coef[0];
+    return p->precision == JK_MIXED
+               ? build_mixed(p, B, seg, nseg, CL, CR, o, (char *)ws, (hipStream_t)stream)
+               : build_fp64(p, B, seg, nseg, CL, CR, o, (char *)ws, (hipStream_t)stream);
 }
 
 size_t jk_batched_workspace_bytes(int32_t nprob, const jk_problem *p)
@@ -816,11 +932,8 @@ jk_status jk_build_batched(int32_t nprob, const jk_problem *p, const double *con
     if (p[0].precision == JK_FP64)
         return build_batched_fp64(nprob, p, B, CL, CR, J, K, (char *)ws, (hipStream_t)stream);
     for (int32_t g = 0; g < nprob; g++) {
-        jk_status st = p[g].precision == JK_MIXED
-                           ? build_mixed(&p[g], B[g], CL[g], CR[g], J[g], K[g], (char *)ws,
-                                         (hipStream_t)stream)
-                           : build_fp64(&p[g], B[g], CL[g], CR[g], J[g], K[g], (char *)ws,
-                                        (hipStream_t)stream);
+        jk_status st = build_plain(&p[g], B[g], CL[g], CR[g], J[g], K[g], (char *)ws,
+                                   (hipStream_t)stream);
         if (st != JK_OK)
             return st;
     }

@@ -37,9 +37,10 @@ __global__ void __launch_bounds__(256) k_project_reduce(const double *__restrict
 
 __global__ void __launch_bounds__(256) k_coulomb(const double *__restrict__ B,
                                                  const double *__restrict__ g, double *__restrict__ J,
-                                                 int naux, int nd, i64 npos)
+                                                 int naux, int nd, i64 npos, double scale,
+                                                 int accumulate)
 {
-    coulomb_tile(B, g, J, naux, nd, npos, blockIdx.x);
+    coulomb_tile(B, g, J, naux, nd, npos, blockIdx.x, scale, accumulate);
 }
 
 __global__ void __launch_bounds__(256, 3) k_half_transform(const double *__restrict__ B,
@@ -57,11 +58,12 @@ __global__ void __launch_bounds__(512, 4) k_exchange(const double *__restrict__ 
                                                      const double *__restrict__ Yw,
                                                      double *__restrict__ Kp, int nao, int nd, int nj,
                                                      int ldw, int nsplit, int jlen, int accumulate,
-                                                     int sym)
+                                                     int sym, double scale)
 {
     __shared__ double lds[TileExch::LDS_DOUBLES];
     const int n = nsplit * nd * (sym ? ex_tri_tiles(nao) : cdiv_i(nao, kExM) * cdiv_i(nao, kExN));
-    ex_tile(Xw, Yw, Kp, nao, nd, nj, ldw, jlen, accumulate, xcd_swizzle(blockIdx.x, n), lds, sym);
+    ex_tile(Xw, Yw, Kp, nao, nd, nj, ldw, jlen, accumulate, xcd_swizzle(blockIdx.x, n), lds, sym,
+            scale);
 }
 
 // K[k][m][n] = K[k][n][m] for m > n: fills the lower triangle from the upper
@@ -196,12 +198,12 @@ hipError_t launch_project(const double *B, const double *A, double *part, double
 }
 
 hipError_t launch_coulomb(const double *B, const double *g, double *J, int naux, int nd, i64 npos,
-                          hipStream_t s)
+                          hipStream_t s, double scale, int accumulate)
 {
     {
         ProfScope ps_("coulomb", s);
         hipLaunchKernelGGL(k_coulomb, dim3(coulomb_tiles(nd, npos)), dim3(256), 0, s, B, g, J, naux, nd,
-                           npos);
+                           npos, scale, accumulate);
     }
     return hipGetLastError();
 }
@@ -241,7 +243,7 @@ int exchange_nsplit(int nao, int nd, int nj, int sym)
 }
 
 hipError_t launch_exchange(const double *Xw, const double *Yw, double *Kp, int nao, int nd, int nj,
-                           int ldw, int nsplit, int accumulate, hipStream_t s, int sym)
+                           int ldw, int nsplit, int accumulate, hipStream_t s, int sym, double scale)
 {
     int jlen = cdiv(nj, nsplit);
     jlen = ((jlen + 15) / 16) * 16;
@@ -249,7 +251,7 @@ hipError_t launch_exchange(const double *Xw, const double *Yw, double *Kp, int n
     {
         ProfScope ps_("exchange", s);
         hipLaunchKernelGGL(k_exchange, dim3(nsplit * nd * per), dim3(TileExch::NTHR), 0, s, Xw, Yw, Kp,
-                           nao, nd, nj, ldw, nsplit, jlen, accumulate, sym);
+                           nao, nd, nj, ldw, nsplit, jlen, accumulate, sym, scale);
     }
     return hipGetLastError();
 }

@@ -39,16 +39,20 @@ hipError_t launch_density(const double *CL, const double *CR, double *D, int nao
 int project_nblocks(int64_t npos, int naux, int nd, int *plen);
 hipError_t launch_project(const double *B, const double *A, double *part, double *g, int naux,
                           int nd, int64_t npos, hipStream_t s);
+// J (+)= scale * sum_Q g B^Q; accumulate adds to what J holds.
 hipError_t launch_coulomb(const double *B, const double *g, double *J, int naux, int nd,
-                          int64_t npos, hipStream_t s);
+                          int64_t npos, hipStream_t s, double scale = 1.0, int accumulate = 0);
 hipError_t launch_half_transform(const double *B, const double *Cc, double *Xw, double *Yw,
                                  int nao, int nd, int r, int q0, int nq, int ldw, hipStream_t s,
                                  int ncol = -1);
 // Lower triangle of every K_k from its upper triangle.
 hipError_t launch_mirror_upper(double *K, int nao, int nd, hipStream_t s);
 int exchange_nsplit(int nao, int nd, int nj, int sym = 0);
+// Every chunk's contribution is multiplied by scale before it is stored or
+// added (scale 1 leaves it unchanged bit for bit).
 hipError_t launch_exchange(const double *Xw, const double *Yw, double *Kp, int nao, int nd, int nj,
-                           int ldw, int nsplit, int accumulate, hipStream_t s, int sym = 0);
+                           int ldw, int nsplit, int accumulate, hipStream_t s, int sym = 0,
+                           double scale = 1.0);
 hipError_t launch_sum_splits(const double *part, double *out, i64 n, int nsplit, hipStream_t s);
 
 // derivative (jk_vjp.hip)
@@ -92,6 +96,7 @@ hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, i64 bkbstride, const 
 int ex_mixed_nsplit(int mp, int nd, int nkb, int sym = 0);
 hipError_t launch_ex_mixed(const int8_t *Xp, const int8_t *Yp, i64 pstride, i64 kbstride,
                            const int *eX, const int *eY, double *Kp, int nao, int nd, int mp, int nkb,
-                           int nsplit, int accumulate, hipStream_t s, int sym = 0);
+                           int nsplit, int accumulate, hipStream_t s, int sym = 0,
+                           double scale = 1.0);
 
 } // namespace jk

@@ -269,7 +269,7 @@ __global__ void __launch_bounds__(256) k_xy_rowmax(const double *__restrict__ XY
 }
 
 // ------------------------------------------------------------------ exchange
-// Kp[s][k][m][n] (+)= 2^(eX + eY + 2) * sum_l S_l 2^(-7 l) over the inner
+// Kp[s][k][m][n] (+)= scale 2^(eX + eY + 2) * sum_l S_l 2^(-7 l) over the inner
 // blocks [s * kbl, (s + 1) * kbl) of split s.  X/Y planes: rows k * mp + m
 // from Xp / Yp (same strides); row exponents eX[k * mp + m], eY[k * mp + n].
 __global__ void __launch_bounds__(512) k_ex_mixed(const int8_t *__restrict__ Xp,
@@ -277,7 +277,8 @@ __global__ void __launch_bounds__(512) k_ex_mixed(const int8_t *__restrict__ Xp,
                                                   i64 kbstride, const int *__restrict__ eX,
                                                   const int *__restrict__ eY,
                                                   double *__restrict__ Kp, int nao, int nd, int mp,
-                                                  int nkb, int kbl, int accumulate, int sym)
+                                                  int nkb, int kbl, int accumulate, int sym,
+                                                  double scale)
 {
     extern __shared__ char lds[];
     typedef TileS TL;
@@ -317,8 +318,8 @@ __global__ void __launch_bounds__(512) k_ex_mixed(const int8_t *__restrict__ Xp,
             stile_coord_wide<TL>(tt, e, row, col);
             const int m = mb * kMT + row, n = nb * kNT + col;
             if (m < nao && n < nao) {
-                const double v = ldexp(combine_levels_wide<TL>(acc, tt, e),
-                                       eX[(i64)k * mp + m] + eY[(i64)k * mp + n] + 2);
+                const double v = scale * ldexp(combine_levels_wide<TL>(acc, tt, e),
+                                               eX[(i64)k * mp + m] + eY[(i64)k * mp + n] + 2);
                 const i64 o = (i64)m * nao + n;
                 Kk[o] = accumulate ? Kk[o] + v : v;
             }
@@ -434,7 +435,7 @@ int ex_mixed_nsplit(int mp, int nd, int nkb, int sym)
 
 hipError_t launch_ex_mixed(const int8_t *Xp, const int8_t *Yp, i64 pstride, i64 kbstride,
                            const int *eX, const int *eY, double *Kp, int nao, int nd, int mp, int nkb,
-                           int nsplit, int accumulate, hipStream_t s, int sym)
+                           int nsplit, int accumulate, hipStream_t s, int sym, double scale)
 {
     hipError_t e = set_lds((const void *)k_ex_mixed, g_lds_ex);
     if (e != hipSuccess)
@@ -445,7 +446,8 @@ hipError_t launch_ex_mixed(const int8_t *Xp, const int8_t *Yp, i64 pstride, i64 
     {
         ProfScope ps_("ex_mixed", s);
         hipLaunchKernelGGL(k_ex_mixed, dim3(nsplit * nd * pk), dim3(TileS::NTHR), TileS::LDS_BYTES, s, Xp,
-                           Yp, pstride, kbstride, eX, eY, Kp, nao, nd, mp, nkb, kbl, accumulate, sym);
+                           Yp, pstride, kbstride, eX, eY, Kp, nao, nd, mp, nkb, kbl, accumulate, sym,
+                           scale);
     }
     return hipGetLastError();
 }

@@ -208,8 +208,10 @@ __device__ inline void reduce_tile(const double *__restrict__ part, double *__re
 // per thread are in flight.  The inner loop has no branches: positions past
 // the end read a valid clamped address and densities past nd repeat the last
 // one; neither is stored.  HBM-bound stream over B.
+// J_k (+)= scale * sum_Q g[k][Q] B^Q (accumulate: add to what J holds).
 __device__ inline void coulomb_tile(const double *__restrict__ B, const double *__restrict__ g,
-                                    double *__restrict__ J, int naux, int nd, i64 npos, int tile)
+                                    double *__restrict__ J, int naux, int nd, i64 npos, int tile,
+                                    double scale = 1.0, int accumulate = 0)
 {
     const int npb = cdiv_i(npos, 512);
     const int kg = tile / npb, pb = tile % npb;
@@ -257,10 +259,11 @@ __device__ inline void coulomb_tile(const double *__restrict__ B, const double *
 #pragma unroll
     for (int k = 0; k < 8; k++)
         if (k < nk) {
+            double *Jk = J + (i64)(k0 + k) * npos;
             if (p0 < npos)
-                J[(i64)(k0 + k) * npos + p0] = a0[k];
+                Jk[p0] = accumulate ? Jk[p0] + scale * a0[k] : scale * a0[k];
             if (p1 < npos)
-                J[(i64)(k0 + k) * npos + p1] = a1[k];
+                Jk[p1] = accumulate ? Jk[p1] + scale * a1[k] : scale * a1[k];
         }
 }
 
@@ -299,9 +302,11 @@ __device__ inline void ht_tile(const double *__restrict__ B, const double *__res
 // inner range [0, nj) is cut into nsplit contiguous pieces of jlen.
 // With sym != 0 (Yw = Xw) only the tiles reaching n >= m are computed; the
 // rest of K is filled by mirroring afterwards.
+// Kp[split][k] (+)= scale * (the chunk's X Y^T over the split's inner range).
 __device__ inline void ex_tile(const double *__restrict__ Xw, const double *__restrict__ Yw,
                                double *__restrict__ Kp, int nao, int nd, int nj, int ldw, int jlen,
-                               int accumulate, int tile, double *lds, int sym = 0)
+                               int accumulate, int tile, double *lds, int sym = 0,
+                               double scale = 1.0)
 {
     typedef TileExch TL;
     const int nmt = cdiv_i(nao, kExM), nnt = cdiv_i(nao, kExN);
@@ -327,7 +332,7 @@ __device__ inline void ex_tile(const double *__restrict__ Xw, const double *__re
     tile_foreach(acc, mb * kExM, nb * kExN, [&](int m, int n, double v) {
         if (m < nao && n < nao) {
             const i64 o = (i64)m * nao + n;
-            Kk[o] = accumulate ? Kk[o] + v : v;
+            Kk[o] = accumulate ? Kk[o] + scale * v : scale * v;
         }
     });
 }

@@ -4,6 +4,7 @@ PyTorch supplies device memory and the current HIP stream; every step of the
 J/K path runs in the library's HIP kernels.
 
     J, K = jk_build(B, CL, CR)                  # Sec. 2.3, Eq. (4)
+    F = jk_fock(B, CL, CR, 2.0, -a_x, B_lr, -b)  # 2J - a_x K - b K_lr in one call
     dB, dCL, dCR = jk_vjp(B, CL, CR, Jbar, Kbar) # Sec. 2.1, Eq. (1)
     J, K = jk(B, CL, CR)                        # differentiable (autograd)
 
@@ -94,6 +95,33 @@ def jk_build(B, CL, CR, precision="fp64", want_j=True, want_k=True, nslice=0, ou
                              _ptr(ws), ws.numel(), _stream())
     _lib.check(st, "jk_build")
     return J, K
+
+
+def jk_fock(B, CL, CR, c_j=2.0, c_k=-1.0, B_lr=None, c_lr=0.0, precision="fp64", nslice=0,
+            out=None, ws=None):
+    """F_k = c_j J[D_k] + c_k K[D_k] + c_lr K_lr[D_k] in one call, K_lr from
+    the second factor set B_lr [naux_lr][nao][nao] (or none)."""
+    nao, naux, nd, r = _shapes(B, CL, CR)
+    naux_lr = 0
+    if B_lr is not None:
+        _check_tensor(B_lr, "B_lr")
+        if B_lr.dim() != 3 or tuple(B_lr.shape[1:]) != (nao, nao):
+            raise ValueError("B_lr must be [naux_lr][nao][nao]")
+        naux_lr = B_lr.shape[0]
+    prob = make_problem(nao, naux, nd, r, precision, True, True, nslice)
+    F = out if out is not None else torch.empty((nd, nao, nao), dtype=torch.float64,
+                                                device=B.device)
+    _check_tensor(F, "F", (nd, nao, nao))
+    nbytes = int(_lib.lib().jk_fock_workspace_bytes(ctypes.byref(prob), naux_lr))
+    if nbytes == 0:
+        raise _lib.JKError(_lib.JK_EINVAL, "jk_fock")
+    if ws is None:
+        ws = _workspace(nbytes, B.device)
+    coef = (ctypes.c_double * 3)(float(c_j), float(c_k), float(c_lr))
+    st = _lib.lib().jk_fock(ctypes.byref(prob), _ptr(B), _ptr(B_lr), naux_lr, _ptr(CL), _ptr(CR),
+                            coef, _ptr(F), _ptr(ws), ws.numel(), _stream())
+    _lib.check(st, "jk_fock")
+    return F
 
 
 def batched_workspace_bytes(probs) -> int:

@@ -111,3 +111,28 @@ def test_mixed_digit_count_unsupported(ns):
     need = L.jk_workspace_bytes(ctypes.byref(p))
     assert need > 0
     assert L.jk_build(ctypes.byref(p), 8, 8, 8, 8, 8, 256, need, None) == _lib.JK_EUNSUPPORTED
+
+
+def test_fock_validation():
+    L = _lib.lib()
+    p = _prob()
+    need = L.jk_fock_workspace_bytes(ctypes.byref(p), 0)
+    assert need > 0 and need % 256 == 0
+    assert L.jk_fock_workspace_bytes(ctypes.byref(p), 7) == need
+    assert L.jk_fock_workspace_bytes(ctypes.byref(p), -1) == 0
+    assert L.jk_fock_workspace_bytes(ctypes.byref(_prob(nao=0)), 0) == 0
+    c = (ctypes.c_double * 3)(2.0, -1.0, 0.0)
+    clr = (ctypes.c_double * 3)(2.0, -1.0, -0.5)
+    cnan = (ctypes.c_double * 3)(2.0, float("nan"), 0.0)
+    F = L.jk_fock
+    # B_lr and naux_lr must agree; c_lr needs B_lr
+    assert F(ctypes.byref(p), 8, None, 5, 8, 8, c, 8, 256, need, None) == _lib.JK_EINVAL
+    assert F(ctypes.byref(p), 8, 8, 0, 8, 8, c, 8, 256, need, None) == _lib.JK_EINVAL
+    assert F(ctypes.byref(p), 8, None, 0, 8, 8, clr, 8, 256, need, None) == _lib.JK_EINVAL
+    assert F(ctypes.byref(p), 8, None, 0, 8, 8, cnan, 8, 256, need, None) == _lib.JK_EINVAL
+    assert F(ctypes.byref(p), 8, None, 0, 8, 8, None, 8, 256, need, None) == _lib.JK_EINVAL
+    assert F(ctypes.byref(p), 8, None, 0, 8, 8, c, None, 256, need, None) == _lib.JK_EINVAL
+    assert F(ctypes.byref(p), 8, None, 0, 8, 8, c, 8, 264, need, None) == _lib.JK_EINVAL
+    assert F(ctypes.byref(p), 8, None, 0, 8, 8, c, 8, 256, need - 1, None) == _lib.JK_EWORKSPACE
+    assert F(ctypes.byref(_prob(flags=1)), 8, None, 0, 8, 8, c, 8, 256, need,
+             None) == _lib.JK_EINVAL

@@ -209,6 +209,29 @@ def main():
     except _lib.JKError as e:
         sym = {"symmetric": f"unavailable: {e}"}
 
+    # ---- packed-triangular B (half the bytes of B in HBM)
+    try:
+        iu = torch.triu_indices(nao, nao, device=dev)
+        Bpk = Bd[:, iu[0], iu[1]].contiguous()
+        del iu
+        Jp, Kp_ = torch.empty_like(J), torch.empty_like(K)
+        packed = {"B_bytes": Bpk.numel() * 8}
+        for prec in ("fp64",) + (() if args.no_mixed else ("mixed",)):
+            wsp = torch.empty(jk.workspace_bytes(jk.make_problem(nao, naux, nd, r, prec,
+                                                                 packed=True)),
+                              dtype=torch.uint8, device=dev)
+
+            def build_packed():
+                jk.jk_build(Bpk, Ld, Rd, precision=prec, out=(Jp, Kp_), ws=wsp)
+
+            t_p = rate(build_packed)
+            packed[f"build_ms_{prec}"] = round(1e3 * t_p, 3)
+            packed[f"builds_per_s_{prec}"] = round(nd / t_p, 2)
+            del wsp
+        del Bpk, Jp, Kp_
+    except _lib.JKError as e:
+        packed = {"packed": f"unavailable: {e}"}
+
     # ---- Fock combination 2J - a K - b K_lr in one call (second factor set:
     # a scaled copy of B in its own buffer, naux_lr = naux)
     try:
@@ -331,6 +354,7 @@ def main():
         "vjp_ms_fp64": round(1e3 * t_vjp, 3),
         "mixed": mixed,
         "symmetric_densities": sym,
+        "packed_b": packed,
         "fock": fock,
         "laplace": lap_res,
         "roofline": roof,

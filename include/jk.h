@@ -71,7 +71,15 @@ typedef enum {
                       magnitude lose the small entries (fixed point).       */
 } jk_precision;
 
-enum { JK_WANT_J = 1, JK_WANT_K = 2 };
+/* JK_B_PACKED: every B slab (and B_lr slab of jk_fock) is stored as its upper
+ * triangle, row by row: element (m, n), m <= n, of slab Q at
+ * Q * nao (nao + 1) / 2 + m nao - m (m - 1) / 2 + (n - m), so B takes
+ * naux nao (nao + 1) / 2 doubles, half the full square.  gamma and J stream
+ * the packed positions (half the bytes); the half-transforms read each
+ * element (m, n) at its packed place.  Accepted by jk_build, jk_fock and
+ * jk_laplace_build (FP64 and JK_MIXED; mixed needs nao <= 2048);
+ * jk_build_batched and jk_vjp return JK_EUNSUPPORTED. */
+enum { JK_WANT_J = 1, JK_WANT_K = 2, JK_B_PACKED = 4 };
 
 typedef struct {
     int64_t nao;       /* basis size, >= 1                                   */
@@ -79,7 +87,8 @@ typedef struct {
     int64_t ndens;     /* number of densities k, >= 1                        */
     int64_t rank;      /* columns of each CL_k / CR_k, 1 <= rank <= nao      */
     int32_t precision; /* jk_precision                                       */
-    int32_t flags;     /* JK_WANT_J | JK_WANT_K (0 means both)               */
+    int32_t flags;     /* JK_WANT_J | JK_WANT_K (neither means both),
+                          optionally | JK_B_PACKED                           */
     int32_t nslice;    /* JK_MIXED only: digits per operand; 0 or 5 (the
                           one implemented value; 1..4 give JK_EUNSUPPORTED) */
     int32_t reserved;  /* must be 0                                          */
@@ -120,7 +129,8 @@ size_t jk_fock_workspace_bytes(const jk_problem *p, int64_t naux_lr);
  *          (all zero: F = 0)
  *   B_lr   DEVICE pointer or NULL; NULL requires naux_lr == 0 and c_lr == 0
  *   F      DEVICE [ndens][nao][nao], overwritten
- * p->flags must be 0 or JK_WANT_J | JK_WANT_K.  FP64 and JK_MIXED (the
+ * p->flags must request both J and K (0, or JK_WANT_J | JK_WANT_K), with or
+ * without JK_B_PACKED.  FP64 and JK_MIXED (the
  * exchange products of both streams in INT8 slices, J in FP64).  CL == CR
  * takes the symmetric path as in jk_build.  Summation order differs from
  * adding separate jk_build results, so F agrees with them to rounding, not

@@ -1,0 +1,71 @@
+/*
+ * jk_tune.h -- plan autotuning of the J/K engine (jk.h).
+ *
+ * A build's plan has choices that do not change what is computed, only how
+ * fast: the tile shape of the FP64 half-transform and the Q-chunk budget
+ * (slabs per launch, hence launch count, workspace use and exchange
+ * splits).  jk_autotune times the candidate plans of one problem on the
+ * device and records the fastest for the problem's shape class; jk_build,
+ * jk_fock, jk_laplace_build and jk_build_batched then use the recorded plan
+ * for every problem of that class.  The table lives in the process and can
+ * be saved to and loaded from JSON.
+ *
+ * Shape class: (ceil(nao / 64), ceil(ndens * rank / 64), precision, packed).
+ *
+ * Results: every plan computes the same J and K to rounding; with a fixed
+ * table, results are bit-identical run to run.  A tile-shape choice alone
+ * leaves the results bit-identical; a chunk choice changes the summation
+ * order of K (and the half-transforms' inner products are unchanged).
+ * Workspace: every candidate fits the workspace jk_workspace_bytes reports.
+ */
+#ifndef JK_GFX950_TUNE_H
+#define JK_GFX950_TUNE_H
+
+#include "jk.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t ht_tile;    /* FP64 half-transform tile: 0 = 128 x 64 (three workgroups per CU),
+                           1 = 64 x 64 (four); packed B and JK_MIXED use 0             */
+    int32_t chunk_mb;   /* Q-chunk budget in MiB, 64 .. 1024 (jk_build_batched caps its
+                           members at 256)                                             */
+} jk_tuning;
+
+/* Times every candidate plan for problem *p (each: one untimed build, then
+ * `reps` timed builds bracketed by HIP events on the stream; reps 0 means 2),
+ * records the fastest for p's shape class and writes it to *chosen (may be
+ * NULL).  Arguments and workspace as jk_build; J and K end with the result of
+ * one more build under the chosen plan.  Synchronizes the stream.  Not for
+ * use under stream capture. */
+jk_status jk_autotune(const jk_problem *p, const double *B, const double *CL, const double *CR,
+                      double *J, double *K, void *ws, size_t ws_bytes, void *stream,
+                      int32_t reps, jk_tuning *chosen);
+
+/* The plan jk_build would use for *p: the recorded one, or the default
+ * {0, 1024}.  Returns JK_EINVAL for an invalid problem. */
+jk_status jk_tuning_get(const jk_problem *p, jk_tuning *t);
+
+/* Records *t for p's shape class (JK_EINVAL if a field is out of range). */
+jk_status jk_tuning_set(const jk_problem *p, const jk_tuning *t);
+
+/* Forgets every recorded plan. */
+void jk_tuning_clear(void);
+
+/* Writes the table as JSON into buf (NUL-terminated when cap allows) and
+ * returns the number of bytes the full text needs, NUL included; buf may be
+ * NULL with cap 0 to query the size. */
+size_t jk_tuning_save(char *buf, size_t cap);
+
+/* Merges the entries of a JSON text written by jk_tuning_save.  Returns
+ * JK_EINVAL (and records nothing) if the text does not parse or a value is
+ * out of range. */
+jk_status jk_tuning_load(const char *json);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libjk_gfx950.so")
 
 JK_OK, JK_EINVAL, JK_EWORKSPACE, JK_EUNSUPPORTED, JK_EHIP = 0, 1, 2, 3, 4
 JK_FP64, JK_MIXED = 0, 1
-JK_WANT_J, JK_WANT_K = 1, 2
+JK_WANT_J, JK_WANT_K, JK_B_PACKED = 1, 2, 4
 
 # Every symbol include/jk.h and include/jk_prof.h declare.
 EXPORTS = ("jk_workspace_bytes", "jk_build", "jk_fock_workspace_bytes", "jk_fock",
@@ -21,6 +21,8 @@ EXPORTS = ("jk_workspace_bytes", "jk_build", "jk_fock_workspace_bytes", "jk_fock
 LAPLACE_EXPORTS = ("jk_laplace_quadrature", "jk_laplace_factors", "jk_laplace_workspace_bytes",
                    "jk_laplace_build")
 LAPLACE_MAX_POINTS = 20
+TUNE_EXPORTS = ("jk_autotune", "jk_tuning_get", "jk_tuning_set", "jk_tuning_clear",
+                "jk_tuning_save", "jk_tuning_load")
 PROF_EXPORTS = ("jk_prof_enable", "jk_prof_reset", "jk_prof_collect", "jk_prof_entry",
                 "jk_prof_dropped")
 
@@ -35,6 +37,10 @@ class LaplaceProblem(ctypes.Structure):
     _fields_ = [("nao", ctypes.c_int64), ("naux", ctypes.c_int64), ("nocc", ctypes.c_int64),
                 ("nvir", ctypes.c_int64), ("nvec", ctypes.c_int64), ("npts", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("flags", ctypes.c_int32), ("nslice", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("ht_tile", ctypes.c_int32), ("chunk_mb", ctypes.c_int32)]
 
 
 class JKError(RuntimeError):
@@ -83,6 +89,19 @@ def lib():
         L.jk_laplace_workspace_bytes.argtypes = [lpp]
         L.jk_laplace_build.restype = ctypes.c_int
         L.jk_laplace_build.argtypes = [lpp, vp, vp, vp, vp, vp, vp, dp, dp, dbl, vp, vp, vp, sz, vp]
+        tp = ctypes.POINTER(Tuning)
+        L.jk_autotune.restype = ctypes.c_int
+        L.jk_autotune.argtypes = [pp, vp, vp, vp, vp, vp, vp, sz, vp, ctypes.c_int32, tp]
+        L.jk_tuning_get.restype = ctypes.c_int
+        L.jk_tuning_get.argtypes = [pp, tp]
+        L.jk_tuning_set.restype = ctypes.c_int
+        L.jk_tuning_set.argtypes = [pp, tp]
+        L.jk_tuning_clear.restype = None
+        L.jk_tuning_clear.argtypes = []
+        L.jk_tuning_save.restype = sz
+        L.jk_tuning_save.argtypes = [ctypes.c_char_p, sz]
+        L.jk_tuning_load.restype = ctypes.c_int
+        L.jk_tuning_load.argtypes = [ctypes.c_char_p]
         L.jk_prof_enable.restype = ctypes.c_int
         L.jk_prof_enable.argtypes = [ctypes.c_int32]
         L.jk_prof_reset.restype = None

@@ -15,6 +15,7 @@
 #include "jk_batched.hpp"
 #include "jk_kernels.hpp"
 #include "jk_tiles.hpp"
+#include "jk_tune.hpp"
 
 namespace {
 
@@ -30,6 +31,15 @@ constexpr size_t kChunkBudget = (size_t)1 << 30;
 constexpr size_t kChunkBudgetBatched = (size_t)256 << 20;
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// Chunk budgets a plan may use (jk_tune.h); workspace sizes cover all.
+constexpr int kChunkChoicesMb[] = {64, 128, 256, 512, 1024};
+
+// The plan choices of the current build: the recorded ones, or those being
+// timed by jk_autotune on this thread.
+thread_local const jk_tuning *t_forced = nullptr;
+jk_tuning plan_tuning(const jk_problem *p) { return t_forced ? *t_forced : jk::tuning_for(p); }
+inline size_t tuned_budget(const jk_problem *p) { return (size_t)plan_tuning(p).chunk_mb << 20; }
 
 struct Carve {
     size_t off = 0;
@@ -55,7 +65,7 @@ bool valid_problem(const jk_problem *p)
         return false;
     if (p->precision != JK_FP64 && p->precision != JK_MIXED)
         return false;
-    if (p->flags < 0 || p->flags > (JK_WANT_J | JK_WANT_K))
+    if (p->flags < 0 || (p->flags & ~(JK_WANT_J | JK_WANT_K | JK_B_PACKED)) != 0)
         return false;
     if (p->reserved != 0)
         return false;
@@ -64,7 +74,12 @@ bool valid_problem(const jk_problem *p)
     return true;
 }
 
-inline int want(const jk_problem *p) { return p->flags == 0 ? (JK_WANT_J | JK_WANT_K) : p->flags; }
+inline int want(const jk_problem *p)
+{
+    const int f = p->flags & (JK_WANT_J | JK_WANT_K);
+    return f == 0 ? (JK_WANT_J | JK_WANT_K) : f;
+}
+inline bool packed_b(const jk_problem *p) { return (p->flags & JK_B_PACKED) != 0; }
 
 // Slabs per chunk of the half-transform workspace.
 int chunk_slabs(const jk_problem *p, size_t budget)
@@ -81,7 +96,9 @@ int chunk_slabs(const jk_problem *p, size_t budget)
 struct FwdPlan {
     int qc, ldw, npb, plen, ndp, nsplit;
     int nsplit_sym;     // exchange splits when C_L = C_R (upper-triangle tiles)
-    size_t o_cc, o_d, o_part, o_g, o_x, o_y, o_kp, total;
+    bool packed;        // B slabs stored as packed upper triangles
+    i64 slab;           // doubles per slab of B
+    size_t o_cc, o_d, o_s, o_part, o_g, o_x, o_y, o_kp, total;
 };
 
 FwdPlan plan_forward(const jk_problem *p, size_t budget = kChunkBudget)
@@ -92,10 +109,14 @@ FwdPlan plan_forward(const jk_problem *p, size_t budget = kChunkBudget)
     f.qc = chunk_slabs(p, budget);
     f.ldw = (int)(f.qc * r);
     f.ndp = (int)(((nd + 7) / 8) * 8);
-    f.npb = jk::project_nblocks(npos, (int)p->naux, (int)nd, &f.plen);
+    f.packed = packed_b(p);
+    f.slab = f.packed ? jk::pk_size((int)nao) : npos;
+    // gamma runs over the stored positions of a slab
+    f.npb = jk::project_nblocks(f.slab, (int)p->naux, (int)nd, &f.plen);
     Carve c;
     f.o_cc = c.take(sizeof(double) * nao * 2 * R);
     f.o_d = c.take(sizeof(double) * nd * npos);
+    f.o_s = c.take(f.packed ? sizeof(double) * nd * f.slab : 0);
     f.o_part = c.take(sizeof(double) * (size_t)f.npb * p->naux * f.ndp);
     f.o_g = c.take(sizeof(double) * nd * p->naux);
     f.o_x = c.take(sizeof(double) * nd * nao * (size_t)f.ldw);
@@ -173,10 +194,10 @@ struct MixPlan {
 
 inline i64 pad_to(i64 x, i64 m) { return ((x + m - 1) / m) * m; }
 
-MixPlan plan_mixed(const jk_problem *p)
+MixPlan plan_mixed(const jk_problem *p, size_t budget = kChunkBudget)
 {
     MixPlan x;
-    x.f = plan_forward(p);
+    x.f = plan_forward(p, budget);
     const i64 nao = p->nao, nd = p->ndens, r = p->rank, R = nd * r;
     x.ns = jk::mixed_nslice();
     x.mp = (int)pad_to(nao, jk::mixed_row_pad());
@@ -272,18 +293,27 @@ struct BuildOut {
 };
 
 // The Coulomb part: gamma_kQ = <D_k, B^Q> in FP64, then
-// out (+)= scale sum_Q gamma_kQ B^Q.
+// out (+)= scale sum_Q gamma_kQ B^Q.  Packed slabs: gamma pairs B^Q with the
+// packed S_k = D_k + D_k^T (diagonal once), J runs over the packed positions
+// into the D buffer and is written out in full by the unpack pass.
 jk_status coulomb_part(const FwdPlan &f, int nao, int naux, int nd, int r, const double *B,
                        const double *CL, const double *CR, double *out, double scale,
                        int accumulate, char *ws, hipStream_t s)
 {
-    const i64 npos = (i64)nao * nao;
     double *D = (double *)(ws + f.o_d);
     double *part = (double *)(ws + f.o_part);
     double *g = (double *)(ws + f.o_g);
     JK_TRY(jk::launch_density(CL, CR, D, nao, nd, r, s));
-    JK_TRY(jk::launch_project(B, D, part, g, naux, nd, npos, s));
-    JK_TRY(jk::launch_coulomb(B, g, out, naux, nd, npos, s, scale, accumulate));
+    if (!f.packed) {
+        JK_TRY(jk::launch_project(B, D, part, g, naux, nd, f.slab, s));
+        JK_TRY(jk::launch_coulomb(B, g, out, naux, nd, f.slab, s, scale, accumulate));
+        return JK_OK;
+    }
+    double *S = (double *)(ws + f.o_s);
+    JK_TRY(jk::launch_sym_pack(D, S, nao, nd, s));
+    JK_TRY(jk::launch_project(B, S, part, g, naux, nd, f.slab, s));
+    JK_TRY(jk::launch_coulomb(B, g, D, naux, nd, f.slab, s));
+    JK_TRY(jk::launch_unpack_sym(D, out, nao, nd, scale, accumulate, s));
     return JK_OK;
 }
 
@@ -291,7 +321,8 @@ jk_status build_fp64(const jk_problem *p, const double *B, const KSeg *seg, int 
                      const double *CL, const double *CR, const BuildOut &o, char *ws,
                      hipStream_t s)
 {
-    const FwdPlan f = plan_forward(p);
+    const jk_tuning tu = plan_tuning(p);
+    const FwdPlan f = plan_forward(p, (size_t)tu.chunk_mb << 20);
     const int nao = (int)p->nao, naux = (int)p->naux, nd = (int)p->ndens, r = (int)p->rank;
     const i64 npos = (i64)nao * nao;
     const int w = want(p);
@@ -324,7 +355,8 @@ jk_status build_fp64(const jk_problem *p, const double *B, const KSeg *seg, int 
             for (int q0 = 0; q0 < sg.naux; q0 += f.qc) {
                 int nq = (sg.naux - q0) < f.qc ? (sg.naux - q0) : f.qc;
                 JK_TRY(jk::launch_half_transform(sg.B, Cc, Xw, Yw, nao, nd, r, q0, nq, f.ldw, s,
-                                                 sym ? nd * r : 2 * nd * r));
+                                                 sym ? nd * r : 2 * nd * r, f.packed ? 1 : 0,
+                                                 f.packed ? 0 : tu.ht_tile));
                 JK_TRY(jk::launch_exchange(Xw, Yx, Kp, nao, nd, nq * r, f.ldw, ns, !first, s, sym,
                                            sg.scale));
                 first = false;
@@ -404,11 +436,13 @@ jk_status build_mixed(const jk_problem *p, const double *B, const KSeg *seg, int
                       const double *CL, const double *CR, const BuildOut &o, char *ws,
                       hipStream_t s)
 {
-    const MixPlan x = plan_mixed(p);
+    const MixPlan x = plan_mixed(p, tuned_budget(p));
     const FwdPlan &f = x.f;
     const int nao = (int)p->nao, naux = (int)p->naux, nd = (int)p->ndens, r = (int)p->rank;
     const int R = nd * r, R2 = 2 * R;
     if (!jk::mixed_rowmax_ok(R2) || (p->nslice != 0 && p->nslice != jk::mixed_nslice()))
+        return JK_EUNSUPPORTED;
+    if (f.packed && !jk::mixed_packed_ok(nao, x.kp))
         return JK_EUNSUPPORTED;
     const i64 npos = (i64)nao * nao;
     const int w = want(p);
@@ -438,7 +472,7 @@ jk_status build_mixed(const jk_problem *p, const double *B, const KSeg *seg, int
     std::vector<Chunk> chunks;
     for (int sgi = 0; sgi < nseg; sgi++)
         for (int q0 = 0; q0 < seg[sgi].naux; q0 += f.qc)
-            chunks.push_back({seg[sgi].B + (i64)q0 * npos,
+            chunks.push_back({seg[sgi].B + (i64)q0 * f.slab,
                               (seg[sgi].naux - q0) < f.qc ? (seg[sgi].naux - q0) : f.qc,
                               seg[sgi].scale});
     double *Cc = (double *)(ws + f.o_cc);
@@ -478,8 +512,12 @@ jk_status build_mixed(const jk_problem *p, const double *B, const KSeg *seg, int
     hipEvent_t fork = E.ev[0], sb[2] = {E.ev[1], E.ev[2]}, ht[2] = {E.ev[3], E.ev[4]},
                sx[2] = {E.ev[5], E.ev[6]}, ex[2] = {E.ev[7], E.ev[8]};
     auto slice_b = [&](int c) -> jk_status {
-        JK_TRY(jk::launch_slice_b(chunks[c].B, npos, nao, nq_of(c), nao, nao, x.mp,
-                                  x.kp / KB, Bp(c), bps, bkb, eB(c), a));
+        if (f.packed)
+            JK_TRY(jk::launch_slice_b_packed(chunks[c].B, f.slab, nq_of(c), nao, x.mp, x.kp / KB,
+                                             Bp(c), bps, bkb, eB(c), a));
+        else
+            JK_TRY(jk::launch_slice_b(chunks[c].B, npos, nao, nq_of(c), nao, nao, x.mp,
+                                      x.kp / KB, Bp(c), bps, bkb, eB(c), a));
         JK_TRY(hipEventRecord(sb[c & 1], a));
         return JK_OK;
     };
@@ -549,6 +587,37 @@ jk_status build_mixed(const jk_problem *p, const double *B, const KSeg *seg, int
     return fock_j();
 }
 
+// Two events with timing enabled (for jk_autotune), destroyed on return.
+struct TimedEvents {
+    hipEvent_t ev[2] = {};
+    int n = 0;
+    hipError_t create()
+    {
+        for (n = 0; n < 2; n++) {
+            hipError_t e = hipEventCreate(&ev[n]);
+            if (e != hipSuccess)
+                return e;
+        }
+        return hipSuccess;
+    }
+    ~TimedEvents()
+    {
+        for (int i = 0; i < n; i++)
+            (void)hipEventDestroy(ev[i]);
+    }
+};
+
+// Largest forward (or mixed) plan over the chunk budgets a plan may use.
+size_t forward_bytes(const jk_problem *p)
+{
+    size_t a = 0;
+    for (int mb : kChunkChoicesMb) {
+        const size_t b = (size_t)mb << 20;
+        a = std::max(a, p->precision == JK_MIXED ? plan_mixed(p, b).total : plan_forward(p, b).total);
+    }
+    return a;
+}
+
 // The plain build: J and K of B as selected by flags.
 jk_status build_plain(const jk_problem *p, const double *B, const double *CL, const double *CR,
                       double *J, double *K, char *ws, hipStream_t s)
@@ -586,7 +655,8 @@ double tile_cost(int phase, const FwdPlan &f, const jk_problem &p)
     case jk::kPhaseProject: return (double)f.plen;
     case jk::kPhaseReduce: return (double)f.npb;
     case jk::kPhaseCoulomb: return (double)p.naux;
-    case jk::kPhaseHalf: return (double)p.nao;
+    case jk::kPhaseHalf:
+    case jk::kPhaseHalf64: return (double)p.nao;
     case jk::kPhaseExchange: return (double)f.qc * p.rank / f.nsplit;
     default: return (double)p.nao;
     }
@@ -597,9 +667,11 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p)
     BSchedule S;
     const int G = nprob;
     std::vector<FwdPlan> plans(G);
+    std::vector<int> tile_of(G);
     int maxsteps = 0;
     for (int g = 0; g < G; g++) {
-        plans[g] = plan_forward(&p[g], kChunkBudgetBatched);
+        tile_of[g] = plan_tuning(&p[g]).ht_tile;
+        plans[g] = plan_forward(&p[g], std::min(kChunkBudgetBatched, tuned_budget(&p[g])));
         const int st = (int)((p[g].naux + plans[g].qc - 1) / plans[g].qc);
         maxsteps = std::max(maxsteps, st);
     }
@@ -653,9 +725,13 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p)
                 const i64 q0 = (i64)c * plans[g].qc;
                 return (int)std::min<i64>(plans[g].qc, p[g].naux - q0);
             };
+            // members whose plan chose 64 x 64 half-transform tiles get a launch of their own
             add(jk::kPhaseHalf, c,
                 [&](int g) { return jk::ht_tiles((int)p[g].nao, (int)p[g].ndens, (int)p[g].rank, nq_of(g)); },
-                in_step);
+                [&](int g) { return in_step(g) && tile_of[g] == 0; });
+            add(jk::kPhaseHalf64, c,
+                [&](int g) { return jk::ht64_tiles((int)p[g].nao, (int)p[g].ndens, (int)p[g].rank, nq_of(g)); },
+                [&](int g) { return in_step(g) && tile_of[g] == 1; });
             add(jk::kPhaseExchange, c,
                 [&](int g) { return jk::ex_tiles((int)p[g].nao, (int)p[g].ndens, plans[g].nsplit); },
                 in_step);
@@ -710,9 +786,9 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p)
     S.key.reserve(64 + 48 * G);
     for (int g = 0; g < G; g++) {
         char buf[128];
-        snprintf(buf, sizeof buf, "%lld,%lld,%lld,%lld,%d,%d;", (long long)p[g].nao,
+        snprintf(buf, sizeof buf, "%lld,%lld,%lld,%lld,%d,%d,%d,%d;", (long long)p[g].nao,
                  (long long)p[g].naux, (long long)p[g].ndens, (long long)p[g].rank, p[g].precision,
-                 p[g].flags);
+                 p[g].flags, plans[g].qc, tile_of[g]);
         S.key += buf;
     }
     return S;
@@ -756,7 +832,7 @@ jk_status build_batched_fp64(int32_t nprob, const jk_problem *p, const double *c
     std::vector<char> host(S.header_bytes, 0);
     for (int g = 0; g < nprob; g++) {
         jk::BMember &m = S.mem[g];
-        const FwdPlan f = plan_forward(&p[g], kChunkBudgetBatched);
+        const FwdPlan f = plan_forward(&p[g], std::min(kChunkBudgetBatched, tuned_budget(&p[g])));
         char *base = ws + S.region[g];
         m.B = B[g];
         m.CL = CL[g];
@@ -824,13 +900,7 @@ size_t jk_workspace_bytes(const jk_problem *p)
 {
     if (!valid_problem(p))
         return 0;
-    size_t a = plan_forward(p).total, b = plan_vjp(p).total;
-    if (p->precision == JK_MIXED) {
-        size_t m = plan_mixed(p).total;
-        if (m > a)
-            a = m;
-    }
-    return a > b ? a : b;
+    return std::max(forward_bytes(p), plan_vjp(p).total);
 }
 
 jk_status jk_build(const jk_problem *p, const double *B, const double *CL, const double *CR,
@@ -856,14 +926,14 @@ size_t jk_fock_workspace_bytes(const jk_problem *p, int64_t naux_lr)
 {
     if (!valid_problem(p) || naux_lr < 0 || naux_lr > ((int64_t)1 << 28))
         return 0;
-    return p->precision == JK_MIXED ? plan_mixed(p).total : plan_forward(p).total;
+    return forward_bytes(p);
 }
 
 jk_status jk_fock(const jk_problem *p, const double *B, const double *B_lr, int64_t naux_lr,
                   const double *CL, const double *CR, const double *coef, double *F, void *ws,
                   size_t ws_bytes, void *stream)
 {
-    if (!valid_problem(p) || (p->flags != 0 && p->flags != (JK_WANT_J | JK_WANT_K)))
+    if (!valid_problem(p) || want(p) != (JK_WANT_J | JK_WANT_K))
         return JK_EINVAL;
     if (!B || !CL || !CR || !coef || !F || !ws || ((uintptr_t)ws) % kAlign)
         return JK_EINVAL;
@@ -929,6 +999,8 @@ jk_status jk_build_batched(int32_t nprob, const jk_problem *p, const double *con
         return JK_EINVAL;
     if (ws_bytes < jk_batched_workspace_bytes(nprob, p))
         return JK_EWORKSPACE;
+    if (packed_b(&p[0]))
+        return JK_EUNSUPPORTED;
     if (p[0].precision == JK_FP64)
         return build_batched_fp64(nprob, p, B, CL, CR, J, K, (char *)ws, (hipStream_t)stream);
     for (int32_t g = 0; g < nprob; g++) {
@@ -938,6 +1010,56 @@ jk_status jk_build_batched(int32_t nprob, const jk_problem *p, const double *con
             return st;
     }
     return JK_OK;
+}
+
+jk_status jk_autotune(const jk_problem *p, const double *B, const double *CL, const double *CR,
+                      double *J, double *K, void *ws, size_t ws_bytes, void *stream,
+                      int32_t reps, jk_tuning *chosen)
+{
+    if (!valid_problem(p) || reps < 0 || reps > 100)
+        return JK_EINVAL;
+    const int w = want(p);
+    if (!B || !CL || !CR || !ws || ((uintptr_t)ws) % kAlign)
+        return JK_EINVAL;
+    if (((w & JK_WANT_J) && !J) || ((w & JK_WANT_K) && !K))
+        return JK_EINVAL;
+    if (ws_bytes < jk_workspace_bytes(p))
+        return JK_EWORKSPACE;
+    if (reps == 0)
+        reps = 2;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<jk_tuning> cand;
+    const int ntile = (p->precision == JK_FP64 && !packed_b(p)) ? 2 : 1;
+    for (int tile = 0; tile < ntile; tile++)
+        for (int mb : {128, 256, 512, 1024})
+            cand.push_back(jk_tuning{tile, mb});
+    TimedEvents E;
+    JK_TRY(E.create());
+    float best = 0.0f;
+    jk_tuning pick = cand[0];
+    for (size_t c = 0; c < cand.size(); c++) {
+        t_forced = &cand[c];
+        jk_status st = build_plain(p, B, CL, CR, J, K, (char *)ws, s);
+        hipError_t he = hipEventRecord(E.ev[0], s);
+        for (int i = 0; i < reps && st == JK_OK && he == hipSuccess; i++)
+            st = build_plain(p, B, CL, CR, J, K, (char *)ws, s);
+        t_forced = nullptr;
+        if (st != JK_OK)
+            return st;
+        JK_TRY(he);
+        JK_TRY(hipEventRecord(E.ev[1], s));
+        JK_TRY(hipEventSynchronize(E.ev[1]));
+        float ms = 0.0f;
+        JK_TRY(hipEventElapsedTime(&ms, E.ev[0], E.ev[1]));
+        if (c == 0 || ms < best) {
+            best = ms;
+            pick = cand[c];
+        }
+    }
+    jk::tuning_record(p, pick);
+    if (chosen)
+        *chosen = pick;
+    return build_plain(p, B, CL, CR, J, K, (char *)ws, s);
 }
 
 jk_status jk_vjp(const jk_problem *p, const double *B, const double *CL, const double *CR,
@@ -952,7 +1074,7 @@ jk_status jk_vjp(const jk_problem *p, const double *B, const double *CL, const d
         return JK_EINVAL;
     if (ws_bytes < jk_workspace_bytes(p))
         return JK_EWORKSPACE;
-    if (p->precision != JK_FP64)
+    if (p->precision != JK_FP64 || packed_b(p))
         return JK_EUNSUPPORTED;
     if (!dB && !dCL)
         return JK_OK;

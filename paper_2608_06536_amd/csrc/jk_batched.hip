@@ -97,6 +97,17 @@ __global__ void __launch_bounds__(256, 3) k_b_half_transform(const BMember *__re
     ht_tile(m.B, m.Cc, m.Xw, m.Yw, m.nao, m.nd, m.r, q0, m.ldw, loc, lds);
 }
 
+__global__ void __launch_bounds__(256, 4) k_b_half_transform64(const BMember *__restrict__ M,
+                                                               const int *__restrict__ tab, int c)
+{
+    __shared__ double lds[TileHalf64::LDS_DOUBLES];
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    int q0, nq;
+    chunk_of(m, c, q0, nq);
+    ht_tile_tl<TileHalf64>(m.B, m.Cc, m.Xw, m.Yw, m.nao, m.nd, m.r, q0, m.ldw, loc, lds, -1);
+}
+
 __global__ void __launch_bounds__(512, 4) k_b_exchange(const BMember *__restrict__ M,
                                                        const int *__restrict__ tab, int c)
 {
@@ -155,6 +166,11 @@ hipError_t launch_batched_phase(int phase, const BMember *M, const int *tab, int
     case kPhaseHalf: {
         ProfScope ps_("b_half_transform", s);
         hipLaunchKernelGGL(k_b_half_transform, g, dim3(256), 0, s, M, tab, step);
+        break;
+    }
+    case kPhaseHalf64: {
+        ProfScope ps_("b_half_transform", s);
+        hipLaunchKernelGGL(k_b_half_transform64, g, dim3(256), 0, s, M, tab, step);
         break;
     }
     case kPhaseExchange: {

@@ -24,7 +24,8 @@ enum {
     kPhaseCoulomb = 4,
     kPhaseHalf = 5,
     kPhaseExchange = 6,
-    kPhaseSum = 7
+    kPhaseSum = 7,
+    kPhaseHalf64 = 8     // the half-transform with 64 x 64 tiles (members whose plan chose them)
 };
 
 // One launch of a phase over the members listed in tab (device pointer):

@@ -54,6 +54,60 @@ __global__ void __launch_bounds__(256, 3) k_half_transform(const double *__restr
     ht_tile(B, Cc, Xw, Yw, nao, nd, r, q0, ldw, xcd_swizzle(blockIdx.x, n), lds, ncol);
 }
 
+// The half-transform with 64 x 64 tiles (four workgroups per CU): a plan
+// choice (jk_tune.h) for shapes where the 128-row tiles waste rows.
+__global__ void __launch_bounds__(256, 4) k_half_transform64(const double *__restrict__ B,
+                                                             const double *__restrict__ Cc,
+                                                             double *__restrict__ Xw,
+                                                             double *__restrict__ Yw, int nao,
+                                                             int nd, int r, int q0, int nq, int ldw,
+                                                             int ncol)
+{
+    __shared__ double lds[TileHalf64::LDS_DOUBLES];
+    const int n = nq * cdiv_i(nao, 64) * cdiv_i(ncol, 64);
+    ht_tile_tl<TileHalf64>(B, Cc, Xw, Yw, nao, nd, r, q0, ldw, xcd_swizzle(blockIdx.x, n), lds,
+                           ncol);
+}
+
+// The same on packed slabs (jk.h JK_B_PACKED).
+__global__ void __launch_bounds__(256, 3) k_half_transform_packed(const double *__restrict__ B,
+                                                                  const double *__restrict__ Cc,
+                                                                  double *__restrict__ Xw,
+                                                                  double *__restrict__ Yw, int nao,
+                                                                  int nd, int r, int q0, int nq,
+                                                                  int ldw, int ncol)
+{
+    __shared__ double lds[TileHalf::LDS_DOUBLES];
+    const int n = ht_tiles_cols(nao, ncol, nq);
+    ht_tile<true>(B, Cc, Xw, Yw, nao, nd, r, q0, ldw, xcd_swizzle(blockIdx.x, n), lds, ncol);
+}
+
+// S_k packed from D_k: S[m <= n] = D[m][n] + D[n][m] (m < n), D[m][m], so
+// that <B^Q, D_k> = sum over the packed positions of B^Q S_k.  Block (k, m).
+__global__ void __launch_bounds__(256) k_sym_pack(const double *__restrict__ D,
+                                                  double *__restrict__ S, int nao)
+{
+    const int k = blockIdx.x, m = blockIdx.y;
+    const double *Dk = D + (i64)k * nao * nao;
+    double *Sk = S + (i64)k * pk_size(nao) + pk_row(m, nao) - m;
+    for (int n = m + threadIdx.x; n < nao; n += 256)
+        Sk[n] = n == m ? Dk[(i64)m * nao + m] : Dk[(i64)m * nao + n] + Dk[(i64)n * nao + m];
+}
+
+// out[k][m][n] (+)= scale * P[k][(m, n)] for packed symmetric P.  Block (k, m).
+__global__ void __launch_bounds__(256) k_unpack_sym(const double *__restrict__ P,
+                                                    double *__restrict__ out, int nao, double scale,
+                                                    int accumulate)
+{
+    const int k = blockIdx.x, m = blockIdx.y;
+    const double *Pk = P + (i64)k * pk_size(nao);
+    double *o = out + ((i64)k * nao + m) * nao;
+    for (int n = threadIdx.x; n < nao; n += 256) {
+        const double v = scale * Pk[pk_index(m, n, nao)];
+        o[n] = accumulate ? o[n] + v : v;
+    }
+}
+
 __global__ void __launch_bounds__(512, 4) k_exchange(const double *__restrict__ Xw,
                                                      const double *__restrict__ Yw,
                                                      double *__restrict__ Kp, int nao, int nd, int nj,
@@ -210,14 +264,42 @@ hipError_t launch_coulomb(const double *B, const double *g, double *J, int naux,
 
 hipError_t launch_half_transform(const double *B, const double *Cc, double *Xw, double *Yw,
                                  int nao, int nd, int r, int q0, int nq, int ldw, hipStream_t s,
-                                 int ncol)
+                                 int ncol, int packed, int tile)
 {
     if (ncol < 0)
         ncol = 2 * nd * r;
-    {
+    if (packed) {
+        ProfScope ps_("half_transform_packed", s);
+        hipLaunchKernelGGL(k_half_transform_packed, dim3(ht_tiles_cols(nao, ncol, nq)), dim3(256), 0,
+                           s, B, Cc, Xw, Yw, nao, nd, r, q0, nq, ldw, ncol);
+    } else if (tile == 1) {
+        ProfScope ps_("half_transform", s);
+        hipLaunchKernelGGL(k_half_transform64, dim3(nq * cdiv(nao, 64) * cdiv(ncol, 64)), dim3(256), 0,
+                           s, B, Cc, Xw, Yw, nao, nd, r, q0, nq, ldw, ncol);
+    } else {
         ProfScope ps_("half_transform", s);
         hipLaunchKernelGGL(k_half_transform, dim3(ht_tiles_cols(nao, ncol, nq)), dim3(256), 0, s, B, Cc,
                            Xw, Yw, nao, nd, r, q0, nq, ldw, ncol);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_pack(const double *D, double *S, int nao, int nd, hipStream_t s)
+{
+    {
+        ProfScope ps_("sym_pack", s);
+        hipLaunchKernelGGL(k_sym_pack, dim3(nd, nao), dim3(256), 0, s, D, S, nao);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_sym(const double *P, double *out, int nao, int nd, double scale,
+                             int accumulate, hipStream_t s)
+{
+    {
+        ProfScope ps_("unpack_sym", s);
+        hipLaunchKernelGGL(k_unpack_sym, dim3(nd, nao), dim3(256), 0, s, P, out, nao, scale,
+                           accumulate);
     }
     return hipGetLastError();
 }

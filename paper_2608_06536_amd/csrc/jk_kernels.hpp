@@ -42,9 +42,16 @@ hipError_t launch_project(const double *B, const double *A, double *part, double
 // J (+)= scale * sum_Q g B^Q; accumulate adds to what J holds.
 hipError_t launch_coulomb(const double *B, const double *g, double *J, int naux, int nd,
                           int64_t npos, hipStream_t s, double scale = 1.0, int accumulate = 0);
+// packed: B holds packed upper-triangle slabs (nao (nao + 1) / 2 doubles).
+// tile: 0 = 128 x 64 workgroup tiles, 1 = 64 x 64 (full slabs only).
 hipError_t launch_half_transform(const double *B, const double *Cc, double *Xw, double *Yw,
                                  int nao, int nd, int r, int q0, int nq, int ldw, hipStream_t s,
-                                 int ncol = -1);
+                                 int ncol = -1, int packed = 0, int tile = 0);
+// S_k = D_k + D_k^T off the diagonal, D_k on it, as packed upper triangles.
+hipError_t launch_sym_pack(const double *D, double *S, int nao, int nd, hipStream_t s);
+// out_k (+)= scale * P_k, P_k a packed symmetric matrix, written in full.
+hipError_t launch_unpack_sym(const double *P, double *out, int nao, int nd, double scale,
+                             int accumulate, hipStream_t s);
 // Lower triangle of every K_k from its upper triangle.
 hipError_t launch_mirror_upper(double *K, int nao, int nd, hipStream_t s);
 int exchange_nsplit(int nao, int nd, int nj, int sym = 0);
@@ -94,6 +101,12 @@ hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, i64 bkbstride, const 
                            const int8_t *Cp, i64 cpstride, i64 ckbstride, const int *eC, double *XY,
                            int nao, int R2, int nq, int mp, int cp, int nkb, hipStream_t s);
 int ex_mixed_nsplit(int mp, int nd, int nkb, int sym = 0);
+// B digit planes from packed slabs (slab stride bs = nao (nao + 1) / 2);
+// mixed_packed_ok tells whether the packed slicer covers rows of kp inner
+// elements (kp <= 2048).
+hipError_t launch_slice_b_packed(const double *src, i64 bs, int nb, int nao, int rp, int nkb,
+                                 int8_t *out, i64 pstride, i64 kbstride, int *exps, hipStream_t s);
+int mixed_packed_ok(int nao, int kp);
 hipError_t launch_ex_mixed(const int8_t *Xp, const int8_t *Yp, i64 pstride, i64 kbstride,
                            const int *eX, const int *eY, double *Kp, int nao, int nd, int mp, int nkb,
                            int nsplit, int accumulate, hipStream_t s, int sym = 0,

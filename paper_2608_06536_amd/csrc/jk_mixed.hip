@@ -9,6 +9,7 @@
 //   rowmax  exponent of every row (side, k, m) of X/Y over the chunk
 //   ex      K_k (+)= slices(X_k) x slices(Y_k) over the chunk, recombined in FP64
 #include "jk_kernels.hpp"
+#include "jk_tiles.hpp"
 #include "slice_core.hpp"
 
 namespace jk {
@@ -138,6 +139,83 @@ __global__ void __launch_bounds__(256) k_slice_rows_wave(const double *__restric
             for (int u = 0; u < 4; u++)
                 slice_value<kNS>(v[j][u], e, d[u]);
             write_digits(dst + (i64)kb * kbstride, pstride, d);
+        }
+    }
+}
+
+// The same for packed symmetric slabs (jk.h JK_B_PACKED).  A workgroup takes
+// a band of kBand rows [m0, m0 + kBand) of one slab and first gathers it into
+// LDS with coalesced reads: the part n >= m of row m is contiguous in packed
+// row m; the part n < m is column m of packed row n, and the band's kBand
+// columns of packed row n are contiguous.  Wave w then slices rows w, w + 4
+// of the band from LDS exactly as the one-pass slicer does.  nk = nr = nao.
+constexpr int kBand = 8;
+
+template <int NJ>
+__global__ void __launch_bounds__(256) k_slice_band_packed(const double *__restrict__ src, i64 bs,
+                                                           int nb, int nao, int rp, int nkb,
+                                                           int8_t *__restrict__ out, i64 pstride,
+                                                           i64 kbstride, int *__restrict__ exps)
+{
+    extern __shared__ double T[];              // [kBand][ld]
+    const int ld = nao;
+    const int nband = (rp + kBand - 1) / kBand;
+    const int b = blockIdx.x / nband, m0 = (blockIdx.x % nband) * kBand;
+    const double *P = src + (i64)b * bs;
+    const int tid = threadIdx.x;
+#pragma unroll 1
+    for (int r = 0; r < kBand; r++) {          // n >= m: packed row m
+        const int m = m0 + r;
+        if (m < nao) {
+            const double *row = P + pk_row(m, nao) - m;
+            for (int n = m + tid; n < nao; n += 256)
+                T[r * ld + n] = row[n];
+        }
+    }
+    const int nlow = (m0 + kBand < nao ? m0 + kBand : nao) * kBand;
+    for (int t = tid; t < nlow; t += 256) {    // n < m: column m of packed row n
+        const int n = t / kBand, r = t % kBand, m = m0 + r;
+        if (n < m && m < nao)
+            T[r * ld + n] = P[pk_row(n, nao) + (m - n)];
+    }
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll 1
+    for (int r = wave; r < kBand; r += 4) {
+        const int m = m0 + r;
+        if (m >= rp)
+            break;
+        const bool live = m < nao;
+        const i64 row = (i64)b * rp + m;
+        double v[NJ][4];
+        double mx = 0.0;
+#pragma unroll
+        for (int j = 0; j < NJ; j++) {
+            const int k0 = 256 * j + 4 * lane;
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int k = k0 + u;
+                v[j][u] = (live && k < nao) ? T[r * ld + k] : 0.0;
+                mx = fmax(mx, fabs(v[j][u]));
+            }
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1)
+            mx = fmax(mx, __shfl_xor(mx, o));
+        const int e = row_exponent(mx);
+        if (lane == 0)
+            exps[row] = live ? e : 0;
+        int8_t *dst = out + row * kSliceKB + 4 * (lane & 7);
+#pragma unroll
+        for (int j = 0; j < NJ; j++) {
+            const int kb = 8 * j + (lane >> 3);
+            if (kb < nkb) {
+                int8_t d[4][kNS];
+#pragma unroll
+                for (int u = 0; u < 4; u++)
+                    slice_value<kNS>(v[j][u], e, d[u]);
+                write_digits(dst + (i64)kb * kbstride, pstride, d);
+            }
         }
     }
 }
@@ -368,6 +446,49 @@ hipError_t launch_slice_b(const double *src, i64 bs, i64 rs, int nb, int nr, int
     }
     return hipGetLastError();
 }
+
+hipError_t launch_slice_b_packed(const double *src, i64 bs, int nb, int nao, int rp, int nkb,
+                                 int8_t *out, i64 pstride, i64 kbstride, int *exps, hipStream_t s)
+{
+    const int nj = cdiv(nkb, 8);
+    if (nj > 8 || nao > rp)
+        return hipErrorInvalidValue;        // rows beyond 2048 elements: not supported packed
+    const dim3 g((unsigned)((i64)nb * cdiv(rp, kBand)));
+    const size_t lds = sizeof(double) * kBand * nao;
+    if (lds > 65536) {        // above 64 KB of dynamic LDS: per-kernel attribute, once
+        static bool done[4] = {false, false, false, false};
+        const void *fn[4] = {(const void *)k_slice_band_packed<1>, (const void *)k_slice_band_packed<2>,
+                             (const void *)k_slice_band_packed<4>, (const void *)k_slice_band_packed<8>};
+        const int w = nj <= 1 ? 0 : nj <= 2 ? 1 : nj <= 4 ? 2 : 3;
+        if (!done[w]) {
+            hipError_t e = hipFuncSetAttribute(fn[w], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)(sizeof(double) * kBand * 2048));
+            if (e != hipSuccess)
+                return e;
+            done[w] = true;
+        }
+    }
+    {
+        ProfScope ps_("slice_b_packed", s);
+        if (nj <= 1)
+            hipLaunchKernelGGL(k_slice_band_packed<1>, g, dim3(256), lds, s, src, bs, nb, nao, rp,
+                               nkb, out, pstride, kbstride, exps);
+        else if (nj <= 2)
+            hipLaunchKernelGGL(k_slice_band_packed<2>, g, dim3(256), lds, s, src, bs, nb, nao, rp,
+                               nkb, out, pstride, kbstride, exps);
+        else if (nj <= 4)
+            hipLaunchKernelGGL(k_slice_band_packed<4>, g, dim3(256), lds, s, src, bs, nb, nao, rp,
+                               nkb, out, pstride, kbstride, exps);
+        else
+            hipLaunchKernelGGL(k_slice_band_packed<8>, g, dim3(256), lds, s, src, bs, nb, nao, rp,
+                               nkb, out, pstride, kbstride, exps);
+    }
+    return hipGetLastError();
+}
+
+// Packed slicer: rows of at most 2048 elements (and a band of 8 rows of
+// LDS, 128 KB at that size).
+int mixed_packed_ok(int nao, int kp) { return cdiv(kp / kSliceKB, 8) <= 8 && nao <= kp; }
 
 int mixed_rowmax_ok(int R2) { return R2 <= 8192; }
 

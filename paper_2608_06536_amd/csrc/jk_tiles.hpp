@@ -35,8 +35,45 @@ typedef Tile<kHtM, kHtN, 64, 32, 16> TileHalf;
 typedef Tile<kExM, kExN, 64, 16, 16> TileExch;
 typedef Tile<kProjRows, 8, 64, 8, 16> TileProject;
 typedef Tile<64, 64, 32, 32, 16> TileDensity;
+// The half-transform's second tile shape (a plan choice, jk_tune.h): 64 x 64,
+// four workgroups per CU; wins at small nao where 128-row tiles waste rows.
+typedef Tile<64, 64, 32, 32, 16> TileHalf64;
 
 __host__ __device__ inline int cdiv_i(i64 a, i64 b) { return (int)((a + b - 1) / b); }
+
+// ------------------------------------------------------------------ packed slabs
+// A symmetric slab stored as its upper triangle, row by row: element (m, n),
+// m <= n, at pk_row(m) + (n - m), pk_row(m) = m nao - m (m - 1) / 2;
+// nao (nao + 1) / 2 doubles per slab.
+__host__ __device__ inline i64 pk_size(int nao) { return (i64)nao * (nao + 1) / 2; }
+__host__ __device__ inline i64 pk_row(int m, int nao) { return (i64)m * (2 * (i64)nao - m + 1) / 2; }
+__host__ __device__ inline i64 pk_index(int m, int n, int nao)
+{
+    const int a = m < n ? m : n, b = m < n ? n : m;
+    return pk_row(a, nao) + (b - a);
+}
+
+// element (i, k) of a packed symmetric nao x nao slab, as an A operand of the
+// tile engine (both indices clamped for the load, zero outside).  Measured:
+// the row-major thread mapping already coalesces below the diagonal (sixteen
+// consecutive rows of one column are 128 contiguous bytes), and a per-stage
+// column mapping there was no faster.
+struct OpPackedSym {
+    static constexpr bool kContig = true;
+    static constexpr int NRAW = 1;
+    const double *p;
+    int nao;
+    __device__ __forceinline__ void fetch(int i, int k, double *raw) const
+    {
+        const int ic = i < nao ? i : nao - 1, kc = k < nao ? k : nao - 1;
+        raw[0] = p[pk_index(ic, kc, nao)];
+    }
+    __device__ __forceinline__ double finish(int i, int k, const double *raw) const
+    {
+        return (i < nao && k < nao) ? raw[0] : 0.0;
+    }
+};
+
 
 // ------------------------------------------------------------------ tile counts
 __host__ __device__ inline int pack_tiles(int nao, int nd, int r)
@@ -57,6 +94,10 @@ __host__ __device__ inline int coulomb_tiles(int nd, i64 npos) { return cdiv_i(n
 __host__ __device__ inline int ht_tiles(int nao, int nd, int r, int nq)
 {
     return nq * cdiv_i(nao, kHtM) * cdiv_i(2 * (i64)nd * r, kHtN);
+}
+__host__ __device__ inline int ht64_tiles(int nao, int nd, int r, int nq)
+{
+    return nq * cdiv_i(nao, 64) * cdiv_i(2 * (i64)nd * r, 64);
 }
 // ncol = 2R (X and Y) or R (X only, symmetric densities)
 __host__ __device__ inline int ht_tiles_cols(int nao, int ncol, int nq)
@@ -271,6 +312,8 @@ __device__ inline void coulomb_tile(const double *__restrict__ B, const double *
 // For slab Q = q0 + ql (ql < nq): XY[m][c] = sum_n B^Q[m][n] Cc[n][c], written
 // as X_ws[k][m][ql*r + i] (c = k*r + i < R) or Y_ws[k][m][ql*r + i] (c - R),
 // for the first ncol columns c (2R, or R when only X is needed).
+// PACKED: B holds packed slabs (pk_size(nao) doubles each).
+template <bool PACKED = false>
 __device__ inline void ht_tile(const double *__restrict__ B, const double *__restrict__ Cc,
                                double *__restrict__ Xw, double *__restrict__ Yw, int nao, int nd,
                                int r, int q0, int ldw, int tile, double *lds, int ncol = -1)
@@ -281,13 +324,46 @@ __device__ inline void ht_tile(const double *__restrict__ B, const double *__res
     const int nmt = cdiv_i(nao, kHtM), nct = cdiv_i(nc, kHtN);
     const int ql = tile / (nmt * nct), rem = tile % (nmt * nct);
     const int mb = rem / nct, cb = rem % nct;
+    const i64 n2 = PACKED ? pk_size(nao) : (i64)nao * nao;
+    OpIC b{Cc, R2, nc, nao};
+    Acc<TL> acc;
+    acc.zero();
+    if constexpr (PACKED) {
+        OpPackedSym a{B + (i64)(q0 + ql) * n2, nao};
+        tile_gemm<TL>(a, b, mb * kHtM, cb * kHtN, 0, nao, lds, acc);
+    } else {
+        OpKC a{B + (i64)(q0 + ql) * n2, nao, nao, nao};
+        tile_gemm<TL>(a, b, mb * kHtM, cb * kHtN, 0, nao, lds, acc);
+    }
+    tile_foreach(acc, mb * kHtM, cb * kHtN, [&](int m, int c, double v) {
+        if (m < nao && c < nc) {
+            double *dst = c < R ? Xw : Yw;
+            const int cc = c < R ? c : c - R;
+            const int k = cc / r, i = cc % r;
+            dst[((i64)k * nao + m) * ldw + (i64)ql * r + i] = v;
+        }
+    });
+}
+
+// The half-transform with an arbitrary tile shape TL (full slabs).
+template <class TL>
+__device__ inline void ht_tile_tl(const double *__restrict__ B, const double *__restrict__ Cc,
+                                  double *__restrict__ Xw, double *__restrict__ Yw, int nao, int nd,
+                                  int r, int q0, int ldw, int tile, double *lds, int ncol)
+{
+    constexpr int BM = TL::WROWS * TL::MA * 16, BN = TL::WCOLS * TL::NB * 4;
+    const int R = nd * r, R2 = 2 * R;
+    const int nc = ncol < 0 ? R2 : ncol;
+    const int nmt = cdiv_i(nao, BM), nct = cdiv_i(nc, BN);
+    const int ql = tile / (nmt * nct), rem = tile % (nmt * nct);
+    const int mb = rem / nct, cb = rem % nct;
     const i64 n2 = (i64)nao * nao;
     OpKC a{B + (i64)(q0 + ql) * n2, nao, nao, nao};
     OpIC b{Cc, R2, nc, nao};
     Acc<TL> acc;
     acc.zero();
-    tile_gemm<TL>(a, b, mb * kHtM, cb * kHtN, 0, nao, lds, acc);
-    tile_foreach(acc, mb * kHtM, cb * kHtN, [&](int m, int c, double v) {
+    tile_gemm<TL>(a, b, mb * BM, cb * BN, 0, nao, lds, acc);
+    tile_foreach(acc, mb * BM, cb * BN, [&](int m, int c, double v) {
         if (m < nao && c < nc) {
             double *dst = c < R ? Xw : Yw;
             const int cc = c < R ? c : c - R;

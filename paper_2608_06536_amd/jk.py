@@ -8,8 +8,10 @@ J/K path runs in the library's HIP kernels.
     dB, dCL, dCR = jk_vjp(B, CL, CR, Jbar, Kbar) # Sec. 2.1, Eq. (1)
     J, K = jk(B, CL, CR)                        # differentiable (autograd)
 
-Shapes: B [naux][nao][nao] (each slab symmetric), CL, CR [nd][nao][r],
-J, K, Jbar, Kbar [nd][nao][nao]; all float64, contiguous, on the GPU.
+Shapes: B [naux][nao][nao] (each slab symmetric), or packed upper triangles
+B [naux][nao (nao + 1) / 2] (row by row, the order of numpy's triu_indices),
+CL, CR [nd][nao][r], J, K, Jbar, Kbar [nd][nao][nao]; all float64,
+contiguous, on the GPU.
 """
 from __future__ import annotations
 
@@ -39,10 +41,13 @@ def _check_tensor(t, name, shape=None):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
 
 
-def make_problem(nao, naux, nd, r, precision="fp64", want_j=True, want_k=True, nslice=0):
+def make_problem(nao, naux, nd, r, precision="fp64", want_j=True, want_k=True, nslice=0,
+                 packed=False):
     flags = (_lib.JK_WANT_J if want_j else 0) | (_lib.JK_WANT_K if want_k else 0)
     if flags == 0:
         raise ValueError("nothing requested")
+    if packed:
+        flags |= _lib.JK_B_PACKED
     return _lib.Problem(int(nao), int(naux), int(nd), int(r), int(_PREC[precision]), flags,
                         int(nslice), 0)
 
@@ -60,15 +65,24 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def is_packed(B, nao):
+    """True for packed slabs [naux][nao (nao + 1) / 2], False for [naux][nao][nao]."""
+    if B.dim() == 2 and B.shape[1] == nao * (nao + 1) // 2:
+        return True
+    if B.dim() == 3 and tuple(B.shape[1:]) == (nao, nao):
+        return False
+    raise ValueError(f"B must be [naux][{nao}][{nao}] or packed [naux][{nao * (nao + 1) // 2}]")
+
+
 def _shapes(B, CL, CR):
     _check_tensor(B, "B")
     _check_tensor(CL, "CL")
     _check_tensor(CR, "CR")
-    if B.dim() != 3 or B.shape[1] != B.shape[2]:
-        raise ValueError("B must be [naux][nao][nao]")
-    naux, nao = B.shape[0], B.shape[1]
-    if CL.dim() != 3 or CL.shape[1] != nao:
+    if CL.dim() != 3:
         raise ValueError("CL must be [nd][nao][r]")
+    nao = CL.shape[1]
+    is_packed(B, nao)
+    naux = B.shape[0]
     if tuple(CR.shape) != tuple(CL.shape):
         raise ValueError("CR must have the shape of CL")
     return nao, naux, CL.shape[0], CL.shape[2]
@@ -77,7 +91,7 @@ def _shapes(B, CL, CR):
 def jk_build(B, CL, CR, precision="fp64", want_j=True, want_k=True, nslice=0, out=None, ws=None):
     """J_k = sum_Q <B^Q, D_k> B^Q and K_k = sum_Q B^Q D_k B^Q for D_k = CL_k CR_k^T."""
     nao, naux, nd, r = _shapes(B, CL, CR)
-    prob = make_problem(nao, naux, nd, r, precision, want_j, want_k, nslice)
+    prob = make_problem(nao, naux, nd, r, precision, want_j, want_k, nslice, is_packed(B, nao))
     if out is None:
         J = torch.empty((nd, nao, nao), dtype=torch.float64, device=B.device) if want_j else None
         K = torch.empty((nd, nao, nao), dtype=torch.float64, device=B.device) if want_k else None
@@ -102,13 +116,14 @@ def jk_fock(B, CL, CR, c_j=2.0, c_k=-1.0, B_lr=None, c_lr=0.0, precision="fp64",
     """F_k = c_j J[D_k] + c_k K[D_k] + c_lr K_lr[D_k] in one call, K_lr from
     the second factor set B_lr [naux_lr][nao][nao] (or none)."""
     nao, naux, nd, r = _shapes(B, CL, CR)
+    packed = is_packed(B, nao)
     naux_lr = 0
     if B_lr is not None:
         _check_tensor(B_lr, "B_lr")
-        if B_lr.dim() != 3 or tuple(B_lr.shape[1:]) != (nao, nao):
-            raise ValueError("B_lr must be [naux_lr][nao][nao]")
+        if is_packed(B_lr, nao) != packed:
+            raise ValueError("B_lr must have the layout of B")
         naux_lr = B_lr.shape[0]
-    prob = make_problem(nao, naux, nd, r, precision, True, True, nslice)
+    prob = make_problem(nao, naux, nd, r, precision, True, True, nslice, packed)
     F = out if out is not None else torch.empty((nd, nao, nao), dtype=torch.float64,
                                                 device=B.device)
     _check_tensor(F, "F", (nd, nao, nao))
@@ -122,6 +137,64 @@ def jk_fock(B, CL, CR, c_j=2.0, c_k=-1.0, B_lr=None, c_lr=0.0, precision="fp64",
                             coef, _ptr(F), _ptr(ws), ws.numel(), _stream())
     _lib.check(st, "jk_fock")
     return F
+
+
+def autotune(B, CL, CR, precision="fp64", reps=2, out=None, ws=None):
+    """Times the candidate plans of this problem, records the fastest for its
+    shape class (jk_tune.h) and returns (J, K, {"ht_tile", "chunk_mb"})."""
+    nao, naux, nd, r = _shapes(B, CL, CR)
+    prob = make_problem(nao, naux, nd, r, precision, packed=is_packed(B, nao))
+    if out is None:
+        J = torch.empty((nd, nao, nao), dtype=torch.float64, device=B.device)
+        K = torch.empty_like(J)
+    else:
+        J, K = out
+    if ws is None:
+        ws = _workspace(workspace_bytes(prob), B.device)
+    t = _lib.Tuning()
+    st = _lib.lib().jk_autotune(ctypes.byref(prob), _ptr(B), _ptr(CL), _ptr(CR), _ptr(J), _ptr(K),
+                                _ptr(ws), ws.numel(), _stream(), int(reps), ctypes.byref(t))
+    _lib.check(st, "jk_autotune")
+    return J, K, {"ht_tile": t.ht_tile, "chunk_mb": t.chunk_mb}
+
+
+def autotune_batched(items, precision="fp64", reps=2):
+    """Autotunes one member of each shape class present in a batch (the class
+    of jk_tune.h: nao and ndens * rank in steps of 64); returns {class: plan}.
+    jk_build_batched then builds every member with its class's plan."""
+    done = {}
+    for B, CL, CR in items:
+        nao, R = CL.shape[1], CL.shape[0] * CL.shape[2]
+        key = ((nao + 63) // 64, (R + 63) // 64)
+        if key not in done:
+            _, _, done[key] = autotune(B, CL, CR, precision, reps)
+    return done
+
+
+def tuning_get(prob):
+    t = _lib.Tuning()
+    _lib.check(_lib.lib().jk_tuning_get(ctypes.byref(prob), ctypes.byref(t)), "jk_tuning_get")
+    return {"ht_tile": t.ht_tile, "chunk_mb": t.chunk_mb}
+
+
+def tuning_set(prob, ht_tile, chunk_mb):
+    t = _lib.Tuning(int(ht_tile), int(chunk_mb))
+    _lib.check(_lib.lib().jk_tuning_set(ctypes.byref(prob), ctypes.byref(t)), "jk_tuning_set")
+
+
+def tuning_clear():
+    _lib.lib().jk_tuning_clear()
+
+
+def tuning_save() -> str:
+    n = int(_lib.lib().jk_tuning_save(None, 0))
+    buf = ctypes.create_string_buffer(n)
+    _lib.lib().jk_tuning_save(buf, n)
+    return buf.value.decode()
+
+
+def tuning_load(text: str):
+    _lib.check(_lib.lib().jk_tuning_load(text.encode()), "jk_tuning_load")
 
 
 def batched_workspace_bytes(probs) -> int:

@@ -19,7 +19,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from .jk import _PREC, _check_tensor, _ptr, _stream, _workspace
+from .jk import _PREC, _check_tensor, _ptr, _stream, _workspace, is_packed
 
 __all__ = ["laplace_quadrature", "denominator_range", "laplace_factors", "laplace_jk"]
 
@@ -82,10 +82,12 @@ def laplace_factors(C, e, alpha, coef, scale, X=None, nvec=1, out=None):
 
 
 def make_laplace_problem(nao, naux, nocc, nvir, nvec, npts, precision="fp64", want_j=True,
-                         want_k=True, nslice=0):
+                         want_k=True, nslice=0, packed=False):
     flags = (_lib.JK_WANT_J if want_j else 0) | (_lib.JK_WANT_K if want_k else 0)
     if flags == 0:
         raise ValueError("nothing requested")
+    if packed:
+        flags |= _lib.JK_B_PACKED
     return _lib.LaplaceProblem(int(nao), int(naux), int(nocc), int(nvir), int(nvec), int(npts),
                                int(_PREC[precision]), flags, int(nslice))
 
@@ -103,7 +105,8 @@ def laplace_jk(B, Cocc, e_occ, Cvir, e_vir, X, npts=8, shift=0.0, excitations=2,
     for t, name in ((B, "B"), (Cocc, "Cocc"), (e_occ, "e_occ"), (Cvir, "Cvir"), (e_vir, "e_vir"),
                     (X, "X")):
         _check_tensor(t, name)
-    naux, nao = B.shape[0], B.shape[1]
+    nao, naux = Cocc.shape[0], B.shape[0]
+    packed = is_packed(B, nao)
     nocc, nvir = Cocc.shape[1], Cvir.shape[1]
     if X.dim() != 3 or tuple(X.shape[1:]) != (nocc, nvir):
         raise ValueError("X must be [nvec][nocc][nvir]")
@@ -116,7 +119,7 @@ def laplace_jk(B, Cocc, e_occ, Cvir, e_vir, X, npts=8, shift=0.0, excitations=2,
         err = lev = None
     npts = w.size
     prob = make_laplace_problem(nao, naux, nocc, nvir, nvec, npts, precision, want_j, want_k,
-                                nslice)
+                                nslice, packed)
     nbytes = int(_lib.lib().jk_laplace_workspace_bytes(ctypes.byref(prob)))
     if nbytes == 0:
         raise _lib.JKError(_lib.JK_EINVAL, "jk_laplace_build")

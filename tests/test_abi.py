@@ -25,8 +25,11 @@ def test_header_symbols_exported():
     assert set(prof) == set(_lib.PROF_EXPORTS)
     lap = _declared("jk_laplace.h")
     assert set(lap) == set(_lib.LAPLACE_EXPORTS)
-    assert sorted(os.listdir(os.path.join(ROOT, "include"))) == ["jk.h", "jk_laplace.h", "jk_prof.h"]
-    for n in names + prof + lap:
+    tune = _declared("jk_tune.h")
+    assert set(tune) == set(_lib.TUNE_EXPORTS)
+    assert sorted(os.listdir(os.path.join(ROOT, "include"))) == ["jk.h", "jk_laplace.h", "jk_prof.h",
+                                                                "jk_tune.h"]
+    for n in names + prof + lap + tune:
         assert hasattr(L, n), n
 
 
@@ -38,7 +41,7 @@ def _prob(**kw):
 
 @pytest.mark.parametrize("bad", [
     dict(nao=0), dict(naux=0), dict(ndens=0), dict(rank=0), dict(rank=11), dict(precision=7),
-    dict(flags=4), dict(flags=-1), dict(reserved=1), dict(precision=1, nslice=-1),
+    dict(flags=8), dict(flags=-1), dict(reserved=1), dict(precision=1, nslice=-1),
     dict(precision=1, nslice=9), dict(nao=1 << 20),
 ])
 def test_invalid_problem(bad):
@@ -136,3 +139,89 @@ def test_fock_validation():
     assert F(ctypes.byref(p), 8, None, 0, 8, 8, c, 8, 256, need - 1, None) == _lib.JK_EWORKSPACE
     assert F(ctypes.byref(_prob(flags=1)), 8, None, 0, 8, 8, c, 8, 256, need,
              None) == _lib.JK_EINVAL
+
+
+def test_packed_b_unsupported_paths():
+    # packed slabs are valid for jk_build / jk_fock, but the derivative and the
+    # batched form refuse them before any launch
+    L = _lib.lib()
+    p = _prob(flags=_lib.JK_B_PACKED)
+    need = L.jk_workspace_bytes(ctypes.byref(p))
+    assert need > 0
+    assert L.jk_vjp(ctypes.byref(p), 8, 8, 8, 8, 8, 8, 8, 8, 256, need, None) == _lib.JK_EUNSUPPORTED
+    arr = (_lib.Problem * 2)(_prob(flags=_lib.JK_B_PACKED), _prob(nao=20, flags=_lib.JK_B_PACKED))
+    nb = L.jk_batched_workspace_bytes(2, arr)
+    assert nb > 0
+    VP = ctypes.c_void_p * 2
+    ptrs = VP(8, 8)
+    assert L.jk_build_batched(2, arr, ptrs, ptrs, ptrs, ptrs, ptrs, 256, nb,
+                              None) == _lib.JK_EUNSUPPORTED
+    # flags: both-or-neither of J and K for jk_fock, packed allowed
+    c = (ctypes.c_double * 3)(2.0, -1.0, 0.0)
+    pj = _prob(flags=_lib.JK_WANT_J | _lib.JK_B_PACKED)
+    assert L.jk_fock(ctypes.byref(pj), 8, None, 0, 8, 8, c, 8, 256, need, None) == _lib.JK_EINVAL
+
+
+def test_tuning_table_json_round_trip():
+    from paper_2608_06536_amd import jk
+    L = _lib.lib()
+    jk.tuning_clear()
+    p1 = _prob(nao=300, ndens=4, rank=30)
+    p2 = _prob(nao=100, ndens=6, rank=10, precision=1)
+    assert jk.tuning_get(p1) == {"ht_tile": 0, "chunk_mb": 1024}        # default
+    jk.tuning_set(p1, 1, 256)
+    jk.tuning_set(p2, 0, 128)
+    # same shape class (nao and R in steps of 64): same entry
+    assert jk.tuning_get(_prob(nao=290, ndens=2, rank=60)) == {"ht_tile": 1, "chunk_mb": 256}
+    text = jk.tuning_save()
+    jk.tuning_clear()
+    assert jk.tuning_get(p1)["chunk_mb"] == 1024
+    jk.tuning_load(text)
+    assert jk.tuning_get(p1) == {"ht_tile": 1, "chunk_mb": 256}
+    assert jk.tuning_get(p2) == {"ht_tile": 0, "chunk_mb": 128}
+    assert jk.tuning_save() == text
+    # a truncated buffer still reports the size it needs
+    n = L.jk_tuning_save(None, 0)
+    buf = ctypes.create_string_buffer(8)
+    assert L.jk_tuning_save(buf, 8) == n and len(buf.value) == 7
+    jk.tuning_clear()
+
+
+@pytest.mark.parametrize("bad", [
+    "", "{}", "[]", '{"version": 2, "entries": []}', '{"entries": [{"nao64": 1}]}',
+    '{"version": 1, "entries": [{"nao64": 1, "rank64": 1, "precision": 0, "packed": 0, '
+    '"ht_tile": 2, "chunk_mb": 256}]}',
+    '{"version": 1, "entries": [{"nao64": 1, "rank64": 1, "precision": 0, "packed": 0, '
+    '"ht_tile": 0, "chunk_mb": 32}]}',
+    '{"version": 1, "entries": [{"nao64": 1, "rank64": 1, "precision": 0, "packed": 0, '
+    '"ht_tile": 0, "chunk_mb": 256, "x": 1}]}',
+    '{"version": 1, "entries": [{"nao64": 1, "rank64": 1, "precision": 0, "packed": 0, '
+    '"ht_tile": 0, "chunk_mb": 256}] trailing',
+])
+def test_tuning_load_rejects(bad):
+    L = _lib.lib()
+    L.jk_tuning_clear()
+    assert L.jk_tuning_load(bad.encode()) == _lib.JK_EINVAL
+    n = L.jk_tuning_save(None, 0)
+    buf = ctypes.create_string_buffer(n)
+    L.jk_tuning_save(buf, n)
+    assert b"nao64" not in buf.value          # nothing recorded
+
+
+def test_tuning_validation():
+    L = _lib.lib()
+    p = _prob()
+    for t in [(2, 256), (0, 63), (0, 1025), (-1, 256)]:
+        tt = _lib.Tuning(*t)
+        assert L.jk_tuning_set(ctypes.byref(p), ctypes.byref(tt)) == _lib.JK_EINVAL
+    tt = _lib.Tuning(0, 256)
+    assert L.jk_tuning_set(ctypes.byref(_prob(nao=0)), ctypes.byref(tt)) == _lib.JK_EINVAL
+    assert L.jk_tuning_get(ctypes.byref(_prob(nao=0)), ctypes.byref(tt)) == _lib.JK_EINVAL
+    need = L.jk_workspace_bytes(ctypes.byref(p))
+    assert L.jk_autotune(ctypes.byref(p), 8, 8, 8, 8, 8, 256, need, None, -1,
+                         None) == _lib.JK_EINVAL
+    assert L.jk_autotune(ctypes.byref(p), 8, 8, 8, 8, 8, 256, need - 1, None, 2,
+                         None) == _lib.JK_EWORKSPACE
+    assert L.jk_autotune(ctypes.byref(p), None, 8, 8, 8, 8, 256, need, None, 2,
+                         None) == _lib.JK_EINVAL
+    L.jk_tuning_clear()

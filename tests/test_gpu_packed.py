@@ -1,0 +1,121 @@
+"""GPU parity with packed-triangular B (jk.h JK_B_PACKED): each slab stored
+as its upper triangle, row by row, nao (nao + 1) / 2 doubles.
+
+Against the oracle (FP64 1e-12, mixed 1e-8) and against the full-square
+build: the half-transforms read the same values, so K is bit-identical to the
+full-B build at either precision; J pairs B with D + D^T over the packed
+positions (a different summation, equal to rounding).  jk_fock and
+jk_laplace_build take the same layout.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import laplace as OL
+from paper_2608_06536_amd import synth
+from conftest import rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+TOL_MIXED = 1e-8
+
+
+def _pack(B):
+    iu = np.triu_indices(B.shape[1])
+    return np.ascontiguousarray(B[:, iu[0], iu[1]])
+
+
+def _dev(*arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a)).to("cuda") for a in arrs]
+
+
+@pytest.mark.parametrize("nao,naux,nd,r", [(1, 1, 1, 1), (2, 3, 1, 1), (23, 17, 2, 5),
+                                           (130, 37, 3, 13), (257, 20, 1, 64), (200, 50, 5, 17)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("sym", [False, True])
+def test_packed_build_vs_oracle(nao, naux, nd, r, precision, sym):
+    from paper_2608_06536_amd import jk
+    p = synth.Problem(nao=nao, naux=naux, nd=nd, r=r, ell=10.0, tau=naux / 4.0 + 1,
+                      n_ground=nd if sym else 0, seed=6000 + nao)
+    B, CL, CR = synth.make_problem(p)
+    if sym:
+        CR = CL
+    Bd, Bpd, Ld = _dev(B, _pack(B), CL)
+    Rd = Ld if sym else _dev(CR)[0]
+    J, K = jk.jk_build(Bpd, Ld, Rd, precision=precision)
+    Jf, Kf = jk.jk_build(Bd, Ld, Rd, precision=precision)
+    torch.cuda.synchronize()
+    Jr, Kr, _ = oracle.jk_factored(B, CL, CR)
+    Jh, Kh = J.cpu().numpy(), K.cpu().numpy()
+    tol = TOL if precision == "fp64" else TOL_MIXED
+    for k in range(nd):
+        assert rel_err(Jh[k], Jr[k]) <= TOL
+        assert rel_err(Kh[k], Kr[k]) <= tol
+        assert rel_err(Jh[k], Jf[k].cpu().numpy()) <= 1e-13
+    assert torch.equal(K, Kf)
+    assert np.array_equal(Jh, Jh.transpose(0, 2, 1))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_packed_fock_and_laplace(precision):
+    from paper_2608_06536_amd import jk
+    from paper_2608_06536_amd import laplace as lap
+    nao, naux = 90, 40
+    p = synth.Problem(nao=nao, naux=naux, nd=2, r=9, ell=10.0, tau=11.0, seed=6100)
+    B, CL, CR = synth.make_problem(p)
+    Blr = synth.make_B(synth.Problem(nao=nao, naux=25, nd=1, r=1, ell=4.0, tau=7.0, seed=6101))
+    Bd, Bpd, Blrd, Blrpd, Ld, Rd = _dev(B, _pack(B), Blr, _pack(Blr), CL, CR)
+    F = jk.jk_fock(Bpd, Ld, Rd, 2.0, -0.4, B_lr=Blrpd, c_lr=-0.6, precision=precision)
+    Ff = jk.jk_fock(Bd, Ld, Rd, 2.0, -0.4, B_lr=Blrd, c_lr=-0.6, precision=precision)
+    torch.cuda.synchronize()
+    J, K, _ = oracle.jk_factored(B, CL, CR)
+    _, Klr, _ = oracle.jk_factored(Blr, CL, CR)
+    Fr = 2.0 * J - 0.4 * K - 0.6 * Klr
+    tol = TOL if precision == "fp64" else TOL_MIXED
+    for k in range(2):
+        assert rel_err(F[k].cpu().numpy(), Fr[k]) <= tol
+        assert rel_err(F[k].cpu().numpy(), Ff[k].cpu().numpy()) <= tol
+    # Laplace pseudo-densities on packed B
+    o = synth.Orbitals(nao=nao, nocc=7, nvir=60, ncore=1, seed=6102)
+    Co, eo, Cv, ev = synth.make_orbitals(o)
+    X = synth.make_amplitudes(o, 2)
+    w, al = np.array([0.2, 0.9, 3.0]), np.array([0.05, 0.4, 2.0])
+    dev = _dev(Co, eo, Cv, ev, X)
+    Jl, Kl, _ = lap.laplace_jk(Bpd, *dev, rule=(w, al), precision=precision)
+    Jlf, Klf, _ = lap.laplace_jk(Bd, *dev, rule=(w, al), precision=precision)
+    torch.cuda.synchronize()
+    assert torch.equal(Kl, Klf)
+    FL = OL.scaled_factors(Co, eo, al, w, +1.0, nvec=2).reshape(6, nao, 7).copy()
+    FR = OL.scaled_factors(Cv, ev, al, np.ones(3), -1.0, X=X).reshape(6, nao, 7).copy()
+    Jr, Kr, _ = oracle.jk_factored(B, FL, FR)
+    Jh = Jl.cpu().numpy().reshape(6, nao, nao)
+    Kh = Kl.cpu().numpy().reshape(6, nao, nao)
+    for d in range(6):
+        assert rel_err(Jh[d], Jr[d]) <= TOL
+        assert rel_err(Kh[d], Kr[d]) <= tol
+
+
+def test_packed_headline_sampled():
+    # nao 500, naux 2000, 8 densities of rank 40, B packed (2 GB instead of 4)
+    from paper_2608_06536_amd import jk
+    p = synth.config(4)
+    B = synth.make_B(p)
+    CL, CR = synth.make_factors(p)
+    Bpd, Ld, Rd = _dev(_pack(B), CL, CR)
+    J, K = jk.jk_build(Bpd, Ld, Rd)
+    Jm, Km = jk.jk_build(Bpd, Ld, Rd, precision="mixed")
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(6200)
+    n = 24
+    ks, ms, ns = rng.integers(0, p.nd, n), rng.integers(0, p.nao, n), rng.integers(0, p.nao, n)
+    ms[:4] = p.nao - 1
+    ns[4:8] = p.nao - 1
+    Je, Ke = oracle.jk_entries(B, CL, CR, ks, ms, ns)
+    Jh, Kh, Kmh = J.cpu().numpy(), K.cpu().numpy(), Km.cpu().numpy()
+    assert np.max(np.abs(Jh[ks, ms, ns] - Je)) <= TOL * np.max(np.abs(Jh))
+    assert np.max(np.abs(Kh[ks, ms, ns] - Ke)) <= TOL * np.max(np.abs(Kh))
+    assert torch.equal(Jm, J)
+    for k in range(p.nd):
+        assert rel_err(Kmh[k], Kh[k]) <= TOL_MIXED

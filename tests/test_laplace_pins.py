@@ -140,7 +140,7 @@ def _lp(**kw):
 
 @pytest.mark.parametrize("bad", [dict(nao=0), dict(nocc=0), dict(nocc=11), dict(nvir=0),
                                  dict(nvec=0), dict(npts=0), dict(npts=21), dict(precision=5),
-                                 dict(flags=4), dict(naux=0)])
+                                 dict(flags=8), dict(naux=0)])
 def test_laplace_problem_invalid(bad):
     L = _lib.lib()
     p = _lp(**bad)

@@ -32,7 +32,8 @@
  *   - stream: a hipStream_t passed as void* (NULL = the default stream).  All
  *     work is enqueued on it; calls return without synchronising the host.
  *   - Errors: arguments are validated before anything is enqueued; on any
- *     error status nothing is written.  A failed launch returns JK_EHIP.
+ *     error status nothing is written.  A failed launch returns JK_EHIP;
+ *     a failed host allocation (plans, schedules, tables) returns JK_ENOMEM.
  *     Faults of already-enqueued kernels surface at the caller's next
  *     synchronisation.  No C++ exception crosses this interface.
  *   - Buffers of one call must not overlap, except that inputs may alias
@@ -55,7 +56,8 @@ typedef enum {
     JK_EINVAL = 1,        /* bad size, null required pointer, misaligned ws  */
     JK_EWORKSPACE = 2,    /* ws_bytes below the required size                */
     JK_EUNSUPPORTED = 3,  /* valid but not implemented combination           */
-    JK_EHIP = 4           /* a HIP launch or runtime call failed             */
+    JK_EHIP = 4,          /* a HIP launch or runtime call failed             */
+    JK_ENOMEM = 5         /* host-side bookkeeping could not be allocated     */
 } jk_status;
 
 typedef enum {

@@ -11,7 +11,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libjk_gfx950.so")
 
-JK_OK, JK_EINVAL, JK_EWORKSPACE, JK_EUNSUPPORTED, JK_EHIP = 0, 1, 2, 3, 4
+JK_OK, JK_EINVAL, JK_EWORKSPACE, JK_EUNSUPPORTED, JK_EHIP, JK_ENOMEM = 0, 1, 2, 3, 4, 5
 JK_FP64, JK_MIXED = 0, 1
 JK_WANT_J, JK_WANT_K, JK_B_PACKED = 1, 2, 4
 

@@ -903,7 +903,7 @@ size_t jk_workspace_bytes(const jk_problem *p)
     return std::max(forward_bytes(p), plan_vjp(p).total);
 }
 
-jk_status jk_build(const jk_problem *p, const double *B, const double *CL, const double *CR,
+static jk_status jk_build_impl(const jk_problem *p, const double *B, const double *CL, const double *CR,
                    double *J, double *K, void *ws, size_t ws_bytes, void *stream)
 {
     if (!valid_problem(p))
@@ -922,6 +922,16 @@ jk_status jk_build(const jk_problem *p, const double *B, const double *CL, const
     return build_plain(p, B, CL, CR, J, K, (char *)ws, (hipStream_t)stream);
 }
 
+jk_status jk_build(const jk_problem *p, const double *B, const double *CL, const double *CR,
+                   double *J, double *K, void *ws, size_t ws_bytes, void *stream)
+{
+    try {
+        return jk_build_impl(p, B, CL, CR, J, K, ws, ws_bytes, stream);
+    } catch (...) {
+        return JK_ENOMEM;
+    }
+}
+
 size_t jk_fock_workspace_bytes(const jk_problem *p, int64_t naux_lr)
 {
     if (!valid_problem(p) || naux_lr < 0 || naux_lr > ((int64_t)1 << 28))
@@ -929,7 +939,7 @@ size_t jk_fock_workspace_bytes(const jk_problem *p, int64_t naux_lr)
     return forward_bytes(p);
 }
 
-jk_status jk_fock(const jk_problem *p, const double *B, const double *B_lr, int64_t naux_lr,
+static jk_status jk_fock_impl(const jk_problem *p, const double *B, const double *B_lr, int64_t naux_lr,
                   const double *CL, const double *CR, const double *coef, double *F, void *ws,
                   size_t ws_bytes, void *stream)
 {
@@ -960,7 +970,18 @@ jk_status jk_fock(const jk_problem *p, const double *B, const double *B_lr, int6
                : build_fp64(p, B, seg, nseg, CL, CR, o, (char *)ws, (hipStream_t)stream);
 }
 
-size_t jk_batched_workspace_bytes(int32_t nprob, const jk_problem *p)
+jk_status jk_fock(const jk_problem *p, const double *B, const double *B_lr, int64_t naux_lr,
+                  const double *CL, const double *CR, const double *coef, double *F, void *ws,
+                  size_t ws_bytes, void *stream)
+{
+    try {
+        return jk_fock_impl(p, B, B_lr, naux_lr, CL, CR, coef, F, ws, ws_bytes, stream);
+    } catch (...) {
+        return JK_ENOMEM;
+    }
+}
+
+static size_t jk_batched_workspace_bytes_impl(int32_t nprob, const jk_problem *p)
 {
     if (nprob < 1 || !p)
         return 0;
@@ -980,7 +1001,16 @@ size_t jk_batched_workspace_bytes(int32_t nprob, const jk_problem *p)
     return mx;
 }
 
-jk_status jk_build_batched(int32_t nprob, const jk_problem *p, const double *const *B,
+size_t jk_batched_workspace_bytes(int32_t nprob, const jk_problem *p)
+{
+    try {
+        return jk_batched_workspace_bytes_impl(nprob, p);
+    } catch (...) {
+        return 0;
+    }
+}
+
+static jk_status jk_build_batched_impl(int32_t nprob, const jk_problem *p, const double *const *B,
                            const double *const *CL, const double *const *CR, double *const *J,
                            double *const *K, void *ws, size_t ws_bytes, void *stream)
 {
@@ -1012,7 +1042,18 @@ jk_status jk_build_batched(int32_t nprob, const jk_problem *p, const double *con
     return JK_OK;
 }
 
-jk_status jk_autotune(const jk_problem *p, const double *B, const double *CL, const double *CR,
+jk_status jk_build_batched(int32_t nprob, const jk_problem *p, const double *const *B,
+                           const double *const *CL, const double *const *CR, double *const *J,
+                           double *const *K, void *ws, size_t ws_bytes, void *stream)
+{
+    try {
+        return jk_build_batched_impl(nprob, p, B, CL, CR, J, K, ws, ws_bytes, stream);
+    } catch (...) {
+        return JK_ENOMEM;
+    }
+}
+
+static jk_status jk_autotune_impl(const jk_problem *p, const double *B, const double *CL, const double *CR,
                       double *J, double *K, void *ws, size_t ws_bytes, void *stream,
                       int32_t reps, jk_tuning *chosen)
 {
@@ -1062,7 +1103,18 @@ jk_status jk_autotune(const jk_problem *p, const double *B, const double *CL, co
     return build_plain(p, B, CL, CR, J, K, (char *)ws, s);
 }
 
-jk_status jk_vjp(const jk_problem *p, const double *B, const double *CL, const double *CR,
+jk_status jk_autotune(const jk_problem *p, const double *B, const double *CL, const double *CR,
+                      double *J, double *K, void *ws, size_t ws_bytes, void *stream,
+                      int32_t reps, jk_tuning *chosen)
+{
+    try {
+        return jk_autotune_impl(p, B, CL, CR, J, K, ws, ws_bytes, stream, reps, chosen);
+    } catch (...) {
+        return JK_ENOMEM;
+    }
+}
+
+static jk_status jk_vjp_impl(const jk_problem *p, const double *B, const double *CL, const double *CR,
                  const double *Jbar, const double *Kbar, double *dB, double *dCL, double *dCR,
                  void *ws, size_t ws_bytes, void *stream)
 {
@@ -1081,6 +1133,17 @@ jk_status jk_vjp(const jk_problem *p, const double *B, const double *CL, const d
     return vjp_fp64(p, B, CL, CR, Jbar, Kbar, dB, dCL, dCR, (char *)ws, (hipStream_t)stream);
 }
 
+jk_status jk_vjp(const jk_problem *p, const double *B, const double *CL, const double *CR,
+                 const double *Jbar, const double *Kbar, double *dB, double *dCL, double *dCR,
+                 void *ws, size_t ws_bytes, void *stream)
+{
+    try {
+        return jk_vjp_impl(p, B, CL, CR, Jbar, Kbar, dB, dCL, dCR, ws, ws_bytes, stream);
+    } catch (...) {
+        return JK_ENOMEM;
+    }
+}
+
 const char *jk_status_str(jk_status s)
 {
     switch (s) {
@@ -1089,6 +1152,7 @@ const char *jk_status_str(jk_status s)
     case JK_EWORKSPACE: return "workspace too small";
     case JK_EUNSUPPORTED: return "unsupported combination";
     case JK_EHIP: return "HIP launch or runtime failure";
+    case JK_ENOMEM: return "host allocation failed";
     }
     return "unknown status";
 }

@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(512, 4) k_exchange(const double *__restrict__ 
 
 // K[k][m][n] = K[k][n][m] for m > n: fills the lower triangle from the upper
 // one through a 32 x 32 LDS transpose (block (bi, bj), bi >= bj).
-__global__ void __launch_bounds__(256) k_mirror_upper(double *__restrict__ K, int nao)
+__global__ void __launch_bounds__(256) k_mirror_upper(double *__restrict__ K, int nao, int nd)
 {
     __shared__ double t[32][33];
     const int nb = cdiv_i(nao, 32);
@@ -132,18 +132,22 @@ __global__ void __launch_bounds__(256) k_mirror_upper(double *__restrict__ K, in
         bi++;
     }
     const int bj = b;
-    double *Kk = K + (i64)blockIdx.y * nao * nao;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    for (int y = ty; y < 32; y += 8) {
-        const int row = bj * 32 + y, col = bi * 32 + tx;       // upper source
-        if (row < nao && col < nao)
-            t[y][tx] = Kk[(i64)row * nao + col];
-    }
-    __syncthreads();
-    for (int y = ty; y < 32; y += 8) {
-        const int m = bi * 32 + y, n = bj * 32 + tx;           // lower target
-        if (m < nao && n < nao && m > n)
-            Kk[(i64)m * nao + n] = t[tx][y];
+    // densities k = blockIdx.y, + gridDim.y, ... (grid y is capped at 65535)
+    for (int k = blockIdx.y; k < nd; k += gridDim.y) {
+        double *Kk = K + (i64)k * nao * nao;
+        for (int y = ty; y < 32; y += 8) {
+            const int row = bj * 32 + y, col = bi * 32 + tx;       // upper source
+            if (row < nao && col < nao)
+                t[y][tx] = Kk[(i64)row * nao + col];
+        }
+        __syncthreads();
+        for (int y = ty; y < 32; y += 8) {
+            const int m = bi * 32 + y, n = bj * 32 + tx;           // lower target
+            if (m < nao && n < nao && m > n)
+                Kk[(i64)m * nao + n] = t[tx][y];
+        }
+        __syncthreads();
     }
     (void)nb;
 }
@@ -309,7 +313,8 @@ hipError_t launch_mirror_upper(double *K, int nao, int nd, hipStream_t s)
     const int nb = cdiv(nao, 32);
     {
         ProfScope ps_("mirror", s);
-        hipLaunchKernelGGL(k_mirror_upper, dim3(nb * (nb + 1) / 2, nd), dim3(256), 0, s, K, nao);
+        hipLaunchKernelGGL(k_mirror_upper, dim3(nb * (nb + 1) / 2, nd < 65535 ? nd : 65535), dim3(256),
+                           0, s, K, nao, nd);
     }
     return hipGetLastError();
 }

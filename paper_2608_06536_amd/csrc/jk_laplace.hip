@@ -179,7 +179,7 @@ size_t factor_bytes(const jk_problem &q) { return align_up((size_t)q.ndens * q.n
 
 extern "C" {
 
-jk_status jk_laplace_quadrature(int32_t npts, double x_min, double x_max, double *w, double *alpha,
+static jk_status jk_laplace_quadrature_impl(int32_t npts, double x_min, double x_max, double *w, double *alpha,
                                 double *max_rel_err, int32_t *is_minimax)
 {
     if (npts < 1 || npts > kMaxPts || !w || !alpha)
@@ -207,6 +207,16 @@ jk_status jk_laplace_quadrature(int32_t npts, double x_min, double x_max, double
     if (is_minimax)
         *is_minimax = ent.level ? 1 : 0;
     return JK_OK;
+}
+
+jk_status jk_laplace_quadrature(int32_t npts, double x_min, double x_max, double *w, double *alpha,
+                                double *max_rel_err, int32_t *is_minimax)
+{
+    try {
+        return jk_laplace_quadrature_impl(npts, x_min, x_max, w, alpha, max_rel_err, is_minimax);
+    } catch (...) {
+        return JK_ENOMEM;
+    }
 }
 
 jk_status jk_laplace_factors(int64_t nao, int64_t norb, int64_t rank, int64_t nvec, int32_t npts,
@@ -239,7 +249,7 @@ size_t jk_laplace_workspace_bytes(const jk_laplace_problem *p)
     return 2 * factor_bytes(q) + jk_workspace_bytes(&q);
 }
 
-jk_status jk_laplace_build(const jk_laplace_problem *p, const double *B, const double *Cocc,
+static jk_status jk_laplace_build_impl(const jk_laplace_problem *p, const double *B, const double *Cocc,
                            const double *e_occ, const double *Cvir, const double *e_vir,
                            const double *X, const double *w, const double *alpha, double shift,
                            double *J, double *K, void *ws, size_t ws_bytes, void *stream)
@@ -278,6 +288,18 @@ jk_status jk_laplace_build(const jk_laplace_problem *p, const double *B, const d
     if (st != JK_OK)
         return st;
     return jk_build(&q, B, CL, CR, J, K, rest, ws_bytes - 2 * fb, stream);
+}
+
+jk_status jk_laplace_build(const jk_laplace_problem *p, const double *B, const double *Cocc,
+                           const double *e_occ, const double *Cvir, const double *e_vir,
+                           const double *X, const double *w, const double *alpha, double shift,
+                           double *J, double *K, void *ws, size_t ws_bytes, void *stream)
+{
+    try {
+        return jk_laplace_build_impl(p, B, Cocc, e_occ, Cvir, e_vir, X, w, alpha, shift, J, K, ws, ws_bytes, stream);
+    } catch (...) {
+        return JK_ENOMEM;
+    }
 }
 
 } // extern "C"

@@ -8,6 +8,10 @@
 //   ht      [X^Q | Y^Q] = slices(B^Q) x slices([C_L | C_R]), recombined in FP64
 //   rowmax  exponent of every row (side, k, m) of X/Y over the chunk
 //   ex      K_k (+)= slices(X_k) x slices(Y_k) over the chunk, recombined in FP64
+#include <mutex>
+#include <set>
+#include <utility>
+
 #include "jk_kernels.hpp"
 #include "jk_tiles.hpp"
 #include "slice_core.hpp"
@@ -226,16 +230,12 @@ __global__ void __launch_bounds__(256) k_slice_band_packed(const double *__restr
 // exponents exps[plane row] known.  32 plane rows x one 32-byte inner block
 // per workgroup (grid: row groups x nkb); each plane write of a workgroup is
 // one contiguous kilobyte.
-__global__ void __launch_bounds__(256) k_slice_xy(const double *__restrict__ XY, int nao, int nkey,
-                                                  int r, int mp, int nj, int8_t *__restrict__ out,
-                                                  i64 pstride, i64 kbstride,
-                                                  const int *__restrict__ exps)
+__device__ __forceinline__ void slice_xy_block(const double *__restrict__ XY, int nao, int nkey,
+                                               int r, int mp, int nj, int8_t *__restrict__ out,
+                                               i64 pstride, i64 kbstride,
+                                               const int *__restrict__ exps, int row, int sub,
+                                               int kb)
 {
-    const int t = threadIdx.x, sub = t & 7;
-    const int row = blockIdx.x * 32 + (t >> 3);
-    const int kb = blockIdx.y;
-    if (row >= nkey * mp)
-        return;
     const int key = row / mp, m = row % mp;
     const bool live = m < nao;
     const int e = exps[row];
@@ -265,6 +265,20 @@ __global__ void __launch_bounds__(256) k_slice_xy(const double *__restrict__ XY,
     for (int u = 0; u < 4; u++)
         slice_value<kNS>((live && j0 + u < nj) ? x[u] : 0.0, e, d[u]);
     write_digits(out + (i64)kb * kbstride + (i64)row * kSliceKB + sub * 4, pstride, d);
+}
+
+__global__ void __launch_bounds__(256) k_slice_xy(const double *__restrict__ XY, int nao, int nkey,
+                                                  int r, int mp, int nj, int8_t *__restrict__ out,
+                                                  i64 pstride, i64 kbstride,
+                                                  const int *__restrict__ exps, int nkb)
+{
+    const int t = threadIdx.x, sub = t & 7;
+    const int row = blockIdx.x * 32 + (t >> 3);
+    if (row >= nkey * mp)
+        return;
+    // inner blocks kb = blockIdx.y, + gridDim.y, ... (grid y is capped at 65535)
+    for (int kb = blockIdx.y; kb < nkb; kb += gridDim.y)
+        slice_xy_block(XY, nao, nkey, r, mp, nj, out, pstride, kbstride, exps, row, sub, kb);
 }
 
 // ------------------------------------------------------------------ half-transform
@@ -447,6 +461,25 @@ hipError_t launch_slice_b(const double *src, i64 bs, i64 rs, int nb, int nr, int
     return hipGetLastError();
 }
 
+// Dynamic LDS above 64 KB needs a per-kernel attribute, set once per
+// (kernel, device).
+static hipError_t set_lds(const void *fn, int bytes)
+{
+    static std::mutex mu;
+    static std::set<std::pair<const void *, int>> done;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    std::lock_guard<std::mutex> lk(mu);
+    if (done.count({fn, dev}))
+        return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        done.insert({fn, dev});
+    return e;
+}
+
 hipError_t launch_slice_b_packed(const double *src, i64 bs, int nb, int nao, int rp, int nkb,
                                  int8_t *out, i64 pstride, i64 kbstride, int *exps, hipStream_t s)
 {
@@ -455,18 +488,14 @@ hipError_t launch_slice_b_packed(const double *src, i64 bs, int nb, int nao, int
         return hipErrorInvalidValue;        // rows beyond 2048 elements: not supported packed
     const dim3 g((unsigned)((i64)nb * cdiv(rp, kBand)));
     const size_t lds = sizeof(double) * kBand * nao;
-    if (lds > 65536) {        // above 64 KB of dynamic LDS: per-kernel attribute, once
-        static bool done[4] = {false, false, false, false};
-        const void *fn[4] = {(const void *)k_slice_band_packed<1>, (const void *)k_slice_band_packed<2>,
-                             (const void *)k_slice_band_packed<4>, (const void *)k_slice_band_packed<8>};
-        const int w = nj <= 1 ? 0 : nj <= 2 ? 1 : nj <= 4 ? 2 : 3;
-        if (!done[w]) {
-            hipError_t e = hipFuncSetAttribute(fn[w], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)(sizeof(double) * kBand * 2048));
-            if (e != hipSuccess)
-                return e;
-            done[w] = true;
-        }
+    if (lds > 65536) {        // above 64 KB of dynamic LDS: per-kernel attribute
+        const void *fn = nj <= 1   ? (const void *)k_slice_band_packed<1>
+                         : nj <= 2 ? (const void *)k_slice_band_packed<2>
+                         : nj <= 4 ? (const void *)k_slice_band_packed<4>
+                                   : (const void *)k_slice_band_packed<8>;
+        hipError_t e = set_lds(fn, (int)(sizeof(double) * kBand * 2048));
+        if (e != hipSuccess)
+            return e;
     }
     {
         ProfScope ps_("slice_b_packed", s);
@@ -508,30 +537,19 @@ hipError_t launch_slice_xy(const double *XY, int nao, int nkey, int r, int mp, i
 {
     {
         ProfScope ps_("slice_xy", s);
-        hipLaunchKernelGGL(k_slice_xy, dim3(cdiv((i64)nkey * mp, 32), nkb), dim3(256), 0, s, XY, nao,
-                           nkey, r, mp, nj, out, pstride, kbstride, exps);
+        hipLaunchKernelGGL(k_slice_xy, dim3(cdiv((i64)nkey * mp, 32), nkb < 65535 ? nkb : 65535),
+                           dim3(256), 0, s, XY, nao, nkey, r, mp, nj, out, pstride, kbstride, exps,
+                           nkb);
     }
     return hipGetLastError();
 }
 
-// Dynamic LDS above 64 KB needs a per-kernel attribute; set once per process.
-static hipError_t set_lds(const void *fn, bool &done)
-{
-    if (done)
-        return hipSuccess;
-    hipError_t e =
-        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, TileS::LDS_BYTES);
-    if (e == hipSuccess)
-        done = true;
-    return e;
-}
-static bool g_lds_ht = false, g_lds_ex = false;
 
 hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, i64 bkbstride, const int *eB,
                            const int8_t *Cp, i64 cpstride, i64 ckbstride, const int *eC, double *XY,
                            int nao, int R2, int nq, int mp, int cp, int nkb, hipStream_t s)
 {
-    hipError_t e = set_lds((const void *)k_ht_mixed, g_lds_ht);
+    hipError_t e = set_lds((const void *)k_ht_mixed, TileS::LDS_BYTES);
     if (e != hipSuccess)
         return e;
     {
@@ -558,7 +576,7 @@ hipError_t launch_ex_mixed(const int8_t *Xp, const int8_t *Yp, i64 pstride, i64 
                            const int *eX, const int *eY, double *Kp, int nao, int nd, int mp, int nkb,
                            int nsplit, int accumulate, hipStream_t s, int sym, double scale)
 {
-    hipError_t e = set_lds((const void *)k_ex_mixed, g_lds_ex);
+    hipError_t e = set_lds((const void *)k_ex_mixed, TileS::LDS_BYTES);
     if (e != hipSuccess)
         return e;
     const int kbl = cdiv(nkb, nsplit);

@@ -106,7 +106,7 @@ void tuning_record(const jk_problem *p, const jk_tuning &t)
 
 extern "C" {
 
-jk_status jk_tuning_get(const jk_problem *p, jk_tuning *t)
+static jk_status jk_tuning_get_impl(const jk_problem *p, jk_tuning *t)
 {
     if (!p || !t || jk_workspace_bytes(p) == 0)
         return JK_EINVAL;
@@ -114,7 +114,16 @@ jk_status jk_tuning_get(const jk_problem *p, jk_tuning *t)
     return JK_OK;
 }
 
-jk_status jk_tuning_set(const jk_problem *p, const jk_tuning *t)
+jk_status jk_tuning_get(const jk_problem *p, jk_tuning *t)
+{
+    try {
+        return jk_tuning_get_impl(p, t);
+    } catch (...) {
+        return JK_ENOMEM;
+    }
+}
+
+static jk_status jk_tuning_set_impl(const jk_problem *p, const jk_tuning *t)
 {
     if (!p || !t || !valid_tuning(*t) || jk_workspace_bytes(p) == 0)
         return JK_EINVAL;
@@ -122,13 +131,30 @@ jk_status jk_tuning_set(const jk_problem *p, const jk_tuning *t)
     return JK_OK;
 }
 
-void jk_tuning_clear(void)
+jk_status jk_tuning_set(const jk_problem *p, const jk_tuning *t)
+{
+    try {
+        return jk_tuning_set_impl(p, t);
+    } catch (...) {
+        return JK_ENOMEM;
+    }
+}
+
+static void jk_tuning_clear_impl(void)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     g_table.clear();
 }
 
-size_t jk_tuning_save(char *buf, size_t cap)
+void jk_tuning_clear(void)
+{
+    try {
+        jk_tuning_clear_impl();
+    } catch (...) {
+    }
+}
+
+static size_t jk_tuning_save_impl(char *buf, size_t cap)
 {
     std::string out = "{\"version\": 1, \"entries\": [";
     {
@@ -155,7 +181,16 @@ size_t jk_tuning_save(char *buf, size_t cap)
     return out.size() + 1;
 }
 
-jk_status jk_tuning_load(const char *json)
+size_t jk_tuning_save(char *buf, size_t cap)
+{
+    try {
+        return jk_tuning_save_impl(buf, cap);
+    } catch (...) {
+        return 0;
+    }
+}
+
+static jk_status jk_tuning_load_impl(const char *json)
 {
     if (!json)
         return JK_EINVAL;
@@ -230,6 +265,15 @@ jk_status jk_tuning_load(const char *json)
     for (const auto &e : got)
         g_table[e.first] = e.second;
     return JK_OK;
+}
+
+jk_status jk_tuning_load(const char *json)
+{
+    try {
+        return jk_tuning_load_impl(json);
+    } catch (...) {
+        return JK_ENOMEM;
+    }
 }
 
 } // extern "C"

@@ -91,8 +91,9 @@ def test_batched_validation():
 
 
 def test_status_strings():
-    for s in range(5):
+    for s in range(6):
         assert len(_lib.status_str(s)) > 0
+        assert "unknown" not in _lib.status_str(s)
     assert "unknown" in _lib.status_str(99)
 
 

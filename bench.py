@@ -113,6 +113,10 @@ def main():
     nbytes = jk.workspace_bytes(jk.make_problem(nao, naux, nd, r))
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
+    # plan of this shape from the autotuner (untimed; jk_tune.h)
+    t_tune = time.perf_counter()
+    _, _, plan_fp64 = jk.autotune(Bd, Ld, Rd, out=(J, K), ws=ws)
+    t_tune = time.perf_counter() - t_tune
 
     def build():
         jk.jk_build(Bd, Ld, Rd, out=(J, K), ws=ws)
@@ -352,6 +356,7 @@ def main():
         "vjps_per_s_fp64": round(nd / t_vjp, 2),
         "build_ms_fp64": round(1e3 * t_build, 3),
         "vjp_ms_fp64": round(1e3 * t_vjp, 3),
+        "plan": {"fp64": plan_fp64, "autotune_s": round(t_tune, 2)},
         "mixed": mixed,
         "symmetric_densities": sym,
         "packed_b": packed,

@@ -28,8 +28,10 @@ extern "C" {
 #endif
 
 typedef struct {
-    int32_t ht_tile;    /* FP64 half-transform tile: 0 = 128 x 64 (three workgroups per CU),
-                           1 = 64 x 64 (four); packed B and JK_MIXED use 0             */
+    int32_t ht_tile;    /* FP64 half-transform tile: 0 = 128 x 64 of four 64 x 32 wave
+                           tiles (three waves per SIMD), 1 = 64 x 64 (four), 2 = 128 x 64 of
+                           eight 64 x 16 wave tiles (four waves per SIMD); packed B and
+                           JK_MIXED use their own kernels; jk_build_batched runs 2 as 0 */
     int32_t chunk_mb;   /* Q-chunk budget in MiB, 64 .. 1024 (jk_build_batched caps its
                            members at 256)                                             */
 } jk_tuning;
@@ -45,7 +47,8 @@ jk_status jk_autotune(const jk_problem *p, const double *B, const double *CL, co
                       int32_t reps, jk_tuning *chosen);
 
 /* The plan jk_build would use for *p: the recorded one, or the default
- * {0, 1024}.  Returns JK_EINVAL for an invalid problem. */
+ * {nao <= 384 ? 1 : 2, 1024} (the measured best tile by size).  Returns
+ * JK_EINVAL for an invalid problem. */
 jk_status jk_tuning_get(const jk_problem *p, jk_tuning *t);
 
 /* Records *t for p's shape class (JK_EINVAL if a field is out of range). */

@@ -670,7 +670,7 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p)
     std::vector<int> tile_of(G);
     int maxsteps = 0;
     for (int g = 0; g < G; g++) {
-        tile_of[g] = plan_tuning(&p[g]).ht_tile;
+        tile_of[g] = plan_tuning(&p[g]).ht_tile == 1 ? 1 : 0;   // the batch runs 2 as 0
         plans[g] = plan_forward(&p[g], std::min(kChunkBudgetBatched, tuned_budget(&p[g])));
         const int st = (int)((p[g].naux + plans[g].qc - 1) / plans[g].qc);
         maxsteps = std::max(maxsteps, st);
@@ -1070,7 +1070,7 @@ static jk_status jk_autotune_impl(const jk_problem *p, const double *B, const do
         reps = 2;
     hipStream_t s = (hipStream_t)stream;
     std::vector<jk_tuning> cand;
-    const int ntile = (p->precision == JK_FP64 && !packed_b(p)) ? 2 : 1;
+    const int ntile = (p->precision == JK_FP64 && !packed_b(p)) ? 3 : 1;
     for (int tile = 0; tile < ntile; tile++)
         for (int mb : {128, 256, 512, 1024})
             cand.push_back(jk_tuning{tile, mb});

@@ -69,6 +69,23 @@ __global__ void __launch_bounds__(256, 4) k_half_transform64(const double *__res
                            ncol);
 }
 
+// The half-transform with the 128 x 64 tile split over eight 64 x 16 wave
+// tiles (110 VGPRs, four waves per SIMD): more waves to hide the fragment
+// reads and barriers of each stage (measured 49.7 against 47.3 TF at nao 500).
+typedef Tile<128, 64, 64, 16, 16> TileHalfW8;
+__global__ void __launch_bounds__(512, 2) k_half_transform_w8(const double *__restrict__ B,
+                                                              const double *__restrict__ Cc,
+                                                              double *__restrict__ Xw,
+                                                              double *__restrict__ Yw, int nao,
+                                                              int nd, int r, int q0, int nq,
+                                                              int ldw, int ncol)
+{
+    __shared__ double lds[TileHalfW8::LDS_DOUBLES];
+    const int n = ht_tiles_cols(nao, ncol, nq);
+    ht_tile_tl<TileHalfW8>(B, Cc, Xw, Yw, nao, nd, r, q0, ldw, xcd_swizzle(blockIdx.x, n), lds,
+                           ncol);
+}
+
 // The same on packed slabs (jk.h JK_B_PACKED).
 __global__ void __launch_bounds__(256, 3) k_half_transform_packed(const double *__restrict__ B,
                                                                   const double *__restrict__ Cc,
@@ -276,6 +293,10 @@ hipError_t launch_half_transform(const double *B, const double *Cc, double *Xw, 
         ProfScope ps_("half_transform_packed", s);
         hipLaunchKernelGGL(k_half_transform_packed, dim3(ht_tiles_cols(nao, ncol, nq)), dim3(256), 0,
                            s, B, Cc, Xw, Yw, nao, nd, r, q0, nq, ldw, ncol);
+    } else if (tile == 2) {
+        ProfScope ps_("half_transform", s);
+        hipLaunchKernelGGL(k_half_transform_w8, dim3(ht_tiles_cols(nao, ncol, nq)), dim3(512), 0, s, B,
+                           Cc, Xw, Yw, nao, nd, r, q0, nq, ldw, ncol);
     } else if (tile == 1) {
         ProfScope ps_("half_transform", s);
         hipLaunchKernelGGL(k_half_transform64, dim3(nq * cdiv(nao, 64) * cdiv(ncol, 64)), dim3(256), 0,

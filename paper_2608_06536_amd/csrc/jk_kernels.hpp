@@ -43,7 +43,8 @@ hipError_t launch_project(const double *B, const double *A, double *part, double
 hipError_t launch_coulomb(const double *B, const double *g, double *J, int naux, int nd,
                           int64_t npos, hipStream_t s, double scale = 1.0, int accumulate = 0);
 // packed: B holds packed upper-triangle slabs (nao (nao + 1) / 2 doubles).
-// tile: 0 = 128 x 64 workgroup tiles, 1 = 64 x 64 (full slabs only).
+// tile: 0 = 128 x 64 workgroup tiles of four waves, 1 = 64 x 64, 2 = 128 x 64
+// of eight waves (full slabs only).
 hipError_t launch_half_transform(const double *B, const double *Cc, double *Xw, double *Yw,
                                  int nao, int nd, int r, int q0, int nq, int ldw, hipStream_t s,
                                  int ncol = -1, int packed = 0, int tile = 0);

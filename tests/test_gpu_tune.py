@@ -39,14 +39,17 @@ def test_tile_choice_is_bit_identical(nao, naux, nd, r):
     from paper_2608_06536_amd import jk
     B, CL, CR = _case(nao, naux, nd, r, 7100 + nao)
     Bd, Ld, Rd = _dev(B, CL, CR)
+    prob = jk.make_problem(nao, naux, nd, r)
+    jk.tuning_set(prob, 0, 1024)
     J0, K0 = jk.jk_build(Bd, Ld, Rd)
-    jk.tuning_set(jk.make_problem(nao, naux, nd, r), 1, 1024)
-    J1, K1 = jk.jk_build(Bd, Ld, Rd)
-    torch.cuda.synchronize()
-    assert torch.equal(J0, J1) and torch.equal(K0, K1)
     Jr, Kr, _ = oracle.jk_factored(B, CL, CR)
-    for k in range(nd):
-        assert rel_err(K1[k].cpu().numpy(), Kr[k]) <= TOL
+    for tile in (1, 2):
+        jk.tuning_set(prob, tile, 1024)
+        J1, K1 = jk.jk_build(Bd, Ld, Rd)
+        torch.cuda.synchronize()
+        assert torch.equal(J0, J1) and torch.equal(K0, K1)
+        for k in range(nd):
+            assert rel_err(K1[k].cpu().numpy(), Kr[k]) <= TOL
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -75,7 +78,7 @@ def test_autotune_records_and_reproduces(precision):
     prob = jk.make_problem(200, 300, 3, 20, precision)
     assert jk.tuning_get(prob) == choice
     assert choice["chunk_mb"] in (128, 256, 512, 1024)
-    assert choice["ht_tile"] in ((0, 1) if precision == "fp64" else (0,))
+    assert choice["ht_tile"] in ((0, 1, 2) if precision == "fp64" else (0,))
     J2, K2 = jk.jk_build(Bd, Ld, Rd, precision=precision)
     torch.cuda.synchronize()
     assert torch.equal(J, J2) and torch.equal(K, K2)
@@ -86,7 +89,7 @@ def test_autotune_records_and_reproduces(precision):
         assert rel_err(K[k].cpu().numpy(), Kr[k]) <= tol
 
 
-@pytest.mark.parametrize("tiles", [(0, 0, 0), (1, 0, 1), (1, 1, 1)])
+@pytest.mark.parametrize("tiles", [(0, 0, 0), (1, 0, 1), (1, 1, 1), (2, 1, 2)])
 def test_batched_follows_class_plans(tiles):
     # members of one batch with different half-transform tiles and chunk budgets
     from paper_2608_06536_amd import jk

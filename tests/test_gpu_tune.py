@@ -128,3 +128,25 @@ def test_autotune_batched_classes():
         Jr, Kr, _ = oracle.jk_factored(B, CL, CR)
         for k in range(q.nd):
             assert rel_err(K[k].cpu().numpy(), Kr[k]) <= TOL
+
+
+def test_q_blocking_independence():
+    # The Q-chunk is a memory knob: 64 MB and 1 GB chunks (different launch
+    # counts and exchange splits) agree to rounding, and each is bit-identical
+    # on a rerun.
+    from paper_2608_06536_amd import jk
+    p = synth.config(2)
+    B, CL, CR = synth.make_problem(p)
+    Bd, Ld, Rd = _dev(B, CL, CR)
+    prob = jk.make_problem(p.nao, p.naux, p.nd, p.r)
+    out = {}
+    for mb in (64, 1024):
+        jk.tuning_set(prob, 0, mb)
+        a = jk.jk_build(Bd, Ld, Rd)
+        b = jk.jk_build(Bd, Ld, Rd)
+        torch.cuda.synchronize()
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+        out[mb] = a
+    for t in (0, 1):
+        for k in range(p.nd):
+            assert rel_err(out[64][t][k].cpu().numpy(), out[1024][t][k].cpu().numpy()) <= 1e-14

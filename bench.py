@@ -37,9 +37,10 @@ PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
 TRAFFIC_SOURCES = {"half_transform": ["f64_core.hpp", "jk_fp64.hip", "jk_tiles.hpp"]}
 
 
-def measured_traffic(kernel):
-    """Bytes per launch (fetched + written) from the committed counter record,
-    or None when there is none for this kernel or its sources changed since."""
+def measured_traffic(kernel, plan):
+    """Bytes per launch (fetched + written) from the committed counter record
+    taken under the same plan, or None when there is none for this kernel and
+    plan or its sources changed since."""
     import glob
     import hashlib
     if kernel not in TRAFFIC_SOURCES:
@@ -52,7 +53,8 @@ def measured_traffic(kernel):
         for line in open(path):
             if line.startswith("traffic-record:"):
                 rec = json.loads(line.split(":", 1)[1])
-                if rec.get("kernel") == kernel and rec.get("sources_sha256") == h.hexdigest():
+                if (rec.get("kernel") == kernel and rec.get("sources_sha256") == h.hexdigest()
+                        and rec.get("plan") == [plan["ht_tile"], plan["chunk_mb"]]):
                     return rec["fetch_bytes"] + rec["write_bytes"]
     return None
 
@@ -83,6 +85,8 @@ def main():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision build")
+    ap.add_argument("--plan", default="",
+                    help="TILE,CHUNK_MB: use this plan instead of autotuning (profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="after the JSON line, run a plain copy kernel of known size "
                          "(read and write 1 GiB each) for HBM counter calibration")
@@ -113,9 +117,14 @@ def main():
     nbytes = jk.workspace_bytes(jk.make_problem(nao, naux, nd, r))
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
-    # plan of this shape from the autotuner (untimed; jk_tune.h)
+    # plan of this shape: from the autotuner (untimed; jk_tune.h), or given
     t_tune = time.perf_counter()
-    _, _, plan_fp64 = jk.autotune(Bd, Ld, Rd, out=(J, K), ws=ws)
+    if args.plan:
+        tile, mb = (int(v) for v in args.plan.split(","))
+        jk.tuning_set(jk.make_problem(nao, naux, nd, r), tile, mb)
+        plan_fp64 = {"ht_tile": tile, "chunk_mb": mb}
+    else:
+        _, _, plan_fp64 = jk.autotune(Bd, Ld, Rd, reps=5, out=(J, K), ws=ws)
     t_tune = time.perf_counter() - t_tune
 
     def build():
@@ -325,14 +334,14 @@ def main():
         achieved = amount * args.steps / (dom_ms * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 3),
-                "traffic": measured_traffic(dom), "traffic_unit": "HBM bytes per launch (counters)",
+                "traffic": measured_traffic(dom, plan_fp64), "traffic_unit": "HBM bytes per launch (counters)",
                 "flop_per_launch": amount * args.steps / dom_cnt,
                 "avg_launch_us": round(1e3 * dom_ms / dom_cnt, 1)}
     else:
         achieved = amount * args.steps / (dom_ms * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 3),
-                "traffic": measured_traffic(dom), "traffic_unit": "HBM bytes per launch (counters)",
+                "traffic": measured_traffic(dom, plan_fp64), "traffic_unit": "HBM bytes per launch (counters)",
                 "byte_per_launch": amount * args.steps / dom_cnt,
                 "avg_launch_us": round(1e3 * dom_ms / dom_cnt, 1)}
 

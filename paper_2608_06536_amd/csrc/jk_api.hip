@@ -416,7 +416,8 @@ jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const
     for (int q0 = 0; q0 < naux; q0 += f.qc) {
         const int nq = (naux - q0) < f.qc ? (naux - q0) : f.qc;
         if (has_v)
-            JK_TRY(jk::launch_half_transform(B, Cc, Xw, Yw, nao, nd, r, q0, nq, f.ldw, s));
+            JK_TRY(jk::launch_half_transform(B, Cc, Xw, Yw, nao, nd, r, q0, nq, f.ldw, s, -1, 0,
+                                             plan_tuning(p).ht_tile));
         JK_TRY(jk::launch_vjp_stage_b(V, Xw, Yw, Cc, omx, L, nao, nd, r, q0, nq * r, f.ldw, has_v,
                                       has_w, s));
         if (want_dc)

@@ -34,7 +34,7 @@ PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
 
 # Kernel sources whose HBM traffic was measured with counters (the record in
 # profiles/ names their sha256; a changed source voids the record).
-TRAFFIC_SOURCES = {"half_transform": ["f64_core.hpp", "jk_fp64.hip", "jk_tiles.hpp"]}
+TRAFFIC_SOURCES = {"half_transform": ["f64_core.hpp", "f64_mfma16.hpp", "jk_fp64.hip", "jk_tiles.hpp"]}
 
 
 def measured_traffic(kernel, plan):

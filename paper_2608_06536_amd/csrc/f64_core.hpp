@@ -173,8 +173,10 @@ struct TileLoader {
 // ---------------------------------------------------------------- tile GEMM
 // One workgroup computes a BM x BN output tile with inner stages of BK;
 // waves are laid out (BM/WM) x (BN/WN), each owning a WM x WN sub-tile.
-template <int BM, int BN, int WM, int WN, int BK>
+template <int BM_, int BN_, int WM, int WN, int BK>
 struct Tile {
+    static constexpr bool kMfma16 = false;
+    static constexpr int BM = BM_, BN = BN_;
     static constexpr int WROWS = BM / WM, WCOLS = BN / WN;
     static constexpr int NWAVE = WROWS * WCOLS;
     static constexpr int NTHR = NWAVE * 64;

@@ -1,0 +1,341 @@
+// f64_mfma16.hpp -- the second FP64 matrix-core tile engine, on
+// V_MFMA_F64_16X16X4_F64.
+//
+// One instruction is a 16 x 16 x 4 product (2048 flop, four times the work
+// of the 4x4x4 form for the same two operand registers), so a wave tile
+// needs a quarter of the fragment reads per flop.  Lane mapping (measured on
+// the device with one-hot operands):
+//   A fragment (16 rows x 4 inner):  lane l holds A[row l & 15][k l >> 4]
+//   B fragment (4 inner x 16 cols):  lane l holds B[k l >> 4][col l & 15]
+//   output (16 x 16), 4 per lane:    value v of lane l is C[(l >> 4) + 4v][l & 15]
+// The instruction reaches its full rate only with the accumulators in
+// VGPRs; the compiler picks that form when the launch bounds cap a wave at
+// 256 VGPRs or fewer (every kernel using this engine declares a minimum of
+// two workgroups of four waves per CU, or more).
+//
+// Both fragments have the same shape (16 indices x 4 inner), so both operand
+// tiles sit in LDS in fragment order: blocks of 64 doubles, [k & 3][i & 15],
+// one block per (group of 16 indices, inner step of 4), blocks 68 doubles
+// apart.  A fragment read is one contiguous 512-byte read per wave.  The
+// 4-double pad keeps the loader's writes free of bank conflicts.
+//
+// Operands are read with buffer loads: a 128-bit resource (base, size in
+// bytes) in scalar registers, a per-lane byte offset computed once per tile,
+// and the stage's advance along the inner index as a scalar offset, so a
+// stage's loads cost no vector address arithmetic.  Each lane loads four
+// consecutive doubles along the operand's contiguous index (two 16-byte
+// loads).  Indices are clamped to the operand once per tile; inner indices
+// past the end are zeroed in the last stage only.  A read past the
+// resource's size returns zero (the hardware's range check).
+#pragma once
+#include "f64_core.hpp"
+
+namespace jk {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4v mfma16(double a, double b, d4v c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Operand element (i, k), i the row of A or the column of B, k the inner
+// index, valid for i < ni, k < nk:
+//   BufKC: at p[i ld + k]  (k contiguous)
+//   BufIC: at p[k ld + i]  (i contiguous)
+// Host code must keep the operand's extent below 4 GiB (buf_extent_ok).
+// In a segmented product every segment gets a resource of its own.
+struct BufKC {
+    static constexpr bool kContig = true;
+    const double *p;
+    i64 ld;
+    int ni, nk;
+    __device__ __forceinline__ i64 extent() const { return ((i64)(ni - 1) * ld + nk) * 8; }
+};
+struct BufIC {
+    static constexpr bool kContig = false;
+    const double *p;
+    i64 ld;
+    int ni, nk;
+    __device__ __forceinline__ i64 extent() const { return ((i64)(nk - 1) * ld + ni) * 8; }
+};
+__host__ __device__ inline bool buf_extent_ok(i64 elements) { return elements * 8 < (1LL << 32); }
+
+template <int BM_, int BN_, int WM_, int WN_, int BK_>
+struct Tile16 {
+    static constexpr bool kMfma16 = true;
+    static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, BK = BK_;
+    static constexpr int WROWS = BM / WM, WCOLS = BN / WN;
+    static constexpr int NWAVE = WROWS * WCOLS;
+    static constexpr int NTHR = NWAVE * 64;
+    static constexpr int MA = WM / 16, NB = WN / 16, NSUB = BK / 4;
+    static constexpr int BLK = 68;                          // doubles per fragment block
+    static constexpr int A_DOUBLES = (BM / 16) * NSUB * BLK, B_DOUBLES = (BN / 16) * NSUB * BLK;
+    static constexpr int STAGE = A_DOUBLES + B_DOUBLES;
+    static constexpr int LDS_DOUBLES = 2 * STAGE;
+    static_assert(BM % WM == 0 && BN % WN == 0 && WM % 16 == 0 && WN % 16 == 0, "tile16");
+    static_assert(BK % 4 == 0 && (BM * BK / 4) % NTHR == 0 && (BN * BK / 4) % NTHR == 0, "tile16");
+};
+
+template <class TL>
+struct Acc16 {
+    d4v c[TL::MA][TL::NB];
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int i = 0; i < TL::MA; i++)
+#pragma unroll
+            for (int j = 0; j < TL::NB; j++)
+                c[i][j] = (d4v){0.0, 0.0, 0.0, 0.0};
+    }
+};
+
+// fragment-order slot of element (i, k) within a stage's operand tile
+template <int NSUB>
+__device__ __forceinline__ int frag_slot(int i, int k)
+{
+    return ((i >> 4) * NSUB + (k >> 2)) * 68 + 16 * (k & 3) + (i & 15);
+}
+
+// Moves a T x BK operand tile: groups of four consecutive elements along the
+// contiguous index, group g = tid + s NTHR.
+template <int T, int BK, int NTHR, class Op>
+struct BufLoader {
+    static constexpr int NGRP = T * BK / 4, NS = NGRP / NTHR, NSUB = BK / 4;
+    const char *base;      // segment 0
+    int nbytes;            // extent of one segment (bit pattern of an unsigned)
+    unsigned voff[NS];     // byte offset of the group at inner index 0 of the tile
+    double raw[NS][4];
+
+    // local (i, k) of the first element of group s
+    __device__ __forceinline__ static void local(int g, int &li, int &lk)
+    {
+        if (Op::kContig) {
+            li = g / (BK / 4);
+            lk = (g % (BK / 4)) * 4;
+        } else {
+            lk = g / (T / 4);
+            li = (g % (T / 4)) * 4;
+        }
+    }
+
+    // Per tile: i0 = first index of the tile, kb = first inner index.
+    __device__ __forceinline__ void init(const Op &op, int i0, int kb, int tid)
+    {
+        base = (const char *)op.p;
+        nbytes = (int)op.extent();
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            int li, lk;
+            local(tid + s * NTHR, li, lk);
+            int i = i0 + li;
+            if (Op::kContig)
+                i = i < op.ni ? i : op.ni - 1;       // rows past the end: clamped
+            voff[s] = Op::kContig ? (unsigned)(((i64)i * op.ld + kb + lk) * 8)
+                                  : (unsigned)(((i64)(kb + lk) * op.ld + i) * 8);
+        }
+    }
+
+    // Loads the stage at inner index kk (from the tile's first) of segment
+    // seg, segments seg_bytes apart.
+    __device__ __forceinline__ void load(const Op &op, int seg, int kk, i64 seg_bytes)
+    {
+        const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(base + seg * seg_bytes), (short)0, nbytes, 0x00020000);
+        const unsigned soff = (unsigned)(Op::kContig ? (i64)kk * 8 : (i64)kk * op.ld * 8);
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            const u4v lo = __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[s], soff, 0);
+            const u4v hi = __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[s] + 16, soff, 0);
+            const double2 a = __builtin_bit_cast(double2, lo), b = __builtin_bit_cast(double2, hi);
+            raw[s][0] = a.x;
+            raw[s][1] = a.y;
+            raw[s][2] = b.x;
+            raw[s][3] = b.y;
+        }
+    }
+
+    // Writes the stage into LDS; with MASK, elements at local inner index
+    // kleft or beyond (possible in a tile's last stage only) are zeroed.
+    template <bool MASK>
+    __device__ __forceinline__ void store(double *lds, int tid, int kleft) const
+    {
+        const bool tail = MASK && kleft < BK;
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            int li, lk;
+            local(tid + s * NTHR, li, lk);
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int i = Op::kContig ? li : li + e, k = Op::kContig ? lk + e : lk;
+                double v = raw[s][e];
+                if (tail && k >= kleft)
+                    v = 0.0;
+                lds[frag_slot<NSUB>(i, k)] = v;
+            }
+        }
+    }
+};
+
+// acc += sum over segments g < nseg of sum over k in [k_begin, k_begin +
+// kdepth) of A_g(m0 + i, k) * B_g(n0 + j, k), where A_g is A with its base
+// moved by g segA elements (B_g likewise).  The stages of all segments form
+// one pipeline.
+//
+// Pipeline: two LDS stages and two register sets of global loads.  While
+// stage kt is multiplied out of LDS, the loads of stage kt + 2 are in flight
+// into one register set and stage kt + 1, loaded one stage earlier, is
+// written from the other set into the second LDS stage; one barrier per
+// stage.  A load therefore has a full stage of products to arrive before
+// its data are written to LDS.
+template <class TL, class OA, class OB, bool MASK>
+struct Gemm16 {
+    static constexpr int BK = TL::BK, NSUB = TL::NSUB;
+    typedef BufLoader<TL::BM, BK, TL::NTHR, OA> LA;
+    typedef BufLoader<TL::BN, BK, TL::NTHR, OB> LB;
+
+    struct Seq {             // stage kt -> (segment, inner offset)
+        int nks, kdepth;
+        i64 sega, segb;      // bytes
+        __device__ __forceinline__ void at(int kt, int &g, int &kk) const
+        {
+            g = kt / nks;
+            kk = (kt - g * nks) * BK;
+        }
+    };
+
+    __device__ static __forceinline__ void products(const double *lds, int cur, int fa, int fb,
+                                                    Acc16<TL> &acc)
+    {
+        const double *pa = lds + cur * TL::STAGE + fa;
+        const double *pb = lds + cur * TL::STAGE + fb;
+#pragma unroll
+        for (int s = 0; s < NSUB; s++) {
+            double a[TL::MA], b[TL::NB];
+#pragma unroll
+            for (int i = 0; i < TL::MA; i++)
+                a[i] = pa[(i * NSUB + s) * 68];
+#pragma unroll
+            for (int j = 0; j < TL::NB; j++)
+                b[j] = pb[(j * NSUB + s) * 68];
+#pragma unroll
+            for (int i = 0; i < TL::MA; i++)
+#pragma unroll
+                for (int j = 0; j < TL::NB; j++)
+                    acc.c[i][j] = mfma16(a[i], b[j], acc.c[i][j]);
+        }
+    }
+
+    // One stage: loads of stage kt + 2 into (la_n, lb_n); stage kt + 1,
+    // loaded one stage earlier, from (la_s, lb_s) into the LDS buffer the
+    // previous stage read (free since that stage's barrier); products of
+    // stage kt; barrier.
+    __device__ static __forceinline__ void stage(const OA &A, const OB &B, const Seq &q, int kt,
+                                                 int nk, double *lds, int fa, int fb, int tid,
+                                                 LA &la_n, LB &lb_n, const LA &la_s,
+                                                 const LB &lb_s, Acc16<TL> &acc)
+    {
+        if (kt + 2 < nk) {
+            int g, kk;
+            q.at(kt + 2, g, kk);
+            la_n.load(A, g, kk, q.sega);
+            lb_n.load(B, g, kk, q.segb);
+        }
+        if (kt + 1 < nk) {
+            int g, kk;
+            q.at(kt + 1, g, kk);
+            const int kleft = q.kdepth - kk;
+            la_s.template store<MASK>(lds + ((kt + 1) & 1) * TL::STAGE, tid, kleft);
+            lb_s.template store<MASK>(lds + ((kt + 1) & 1) * TL::STAGE + TL::A_DOUBLES, tid, kleft);
+        }
+        products(lds, kt & 1, fa, fb, acc);
+        __syncthreads();
+    }
+
+    __device__ static __forceinline__ void run(const OA &A, const OB &B, int m0, int n0,
+                                               int k_begin, int kdepth, int nseg, i64 segA,
+                                               i64 segB, double *lds, Acc16<TL> &acc)
+    {
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = tid >> 6;
+        const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
+        Seq q;
+        q.nks = (kdepth + BK - 1) / BK;
+        q.kdepth = kdepth;
+        q.sega = segA * 8;
+        q.segb = segB * 8;
+        const int nk = q.nks * nseg;
+        if (nk <= 0)
+            return;
+        LA la0, la1;
+        LB lb0, lb1;
+        la0.init(A, m0, k_begin, tid);
+        lb0.init(B, n0, k_begin, tid);
+        la1 = la0;
+        lb1 = lb0;
+        la0.load(A, 0, 0, q.sega);
+        lb0.load(B, 0, 0, q.segb);
+        if (nk > 1) {
+            int g, kk;
+            q.at(1, g, kk);
+            la1.load(A, g, kk, q.sega);
+            lb1.load(B, g, kk, q.segb);
+        }
+        la0.template store<MASK>(lds, tid, kdepth);
+        lb0.template store<MASK>(lds + TL::A_DOUBLES, tid, kdepth);
+        __syncthreads();
+        const int fa = wr * TL::MA * NSUB * 68 + lane;
+        const int fb = TL::A_DOUBLES + wc * TL::NB * NSUB * 68 + lane;
+        // register set of stage s: s & 1 (set 0 holds stages 0, 2, 4, ...)
+        int kt = 0;
+        for (; kt + 1 < nk; kt += 2) {
+            stage(A, B, q, kt, nk, lds, fa, fb, tid, la0, lb0, la1, lb1, acc);
+            stage(A, B, q, kt + 1, nk, lds, fa, fb, tid, la1, lb1, la0, lb0, acc);
+        }
+        if (kt < nk)
+            products(lds, kt & 1, fa, fb, acc);
+    }
+};
+
+// acc += sum over k in [k_begin, k_end) of A(m0 + i, k) * B(n0 + j, k).
+// MASK false: inner indices past k_end are not zeroed.  Exact only when
+// the other operand reads zero there (for instance through the range check
+// at the end of its resource) and these elements are finite.
+template <class TL, bool MASK = true, class OA, class OB>
+__device__ __forceinline__ void tile_gemm16(const OA &A, const OB &B, int m0, int n0, int k_begin,
+                                            int k_end, double *lds, Acc16<TL> &acc)
+{
+    Gemm16<TL, OA, OB, MASK>::run(A, B, m0, n0, k_begin, k_end - k_begin, 1, 0, 0, lds, acc);
+}
+
+// acc += sum over g < nseg of the product over k in [0, kdepth) of A_g and
+// B_g (bases moved by g segA and g segB elements).
+template <class TL, class OA, class OB>
+__device__ __forceinline__ void tile_gemm16_seg(const OA &A, const OB &B, i64 segA, i64 segB,
+                                                int nseg, int m0, int n0, int kdepth, double *lds,
+                                                Acc16<TL> &acc)
+{
+    Gemm16<TL, OA, OB, true>::run(A, B, m0, n0, 0, kdepth, nseg, segA, segB, lds, acc);
+}
+
+// Calls f(row, col, value) for every output element this lane holds: value v
+// of accumulator (i, j) is element (m0 + wr WM + 16 i + (lane >> 4) + 4 v,
+// n0 + wc WN + 16 j + (lane & 15)).
+template <class TL, class F>
+__device__ __forceinline__ void tile_foreach16(const Acc16<TL> &acc, int m0, int n0, F &&f)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
+    const int rb = m0 + wr * TL::WM + (lane >> 4);
+    const int cb = n0 + wc * TL::WN + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < TL::MA; i++)
+#pragma unroll
+        for (int j = 0; j < TL::NB; j++)
+#pragma unroll
+            for (int v = 0; v < 4; v++)
+                f(rb + 16 * i + 4 * v, cb + 16 * j, acc.c[i][j][v]);
+}
+
+} // namespace jk

@@ -1071,8 +1071,13 @@ static jk_status jk_autotune_impl(const jk_problem *p, const double *B, const do
         reps = 2;
     hipStream_t s = (hipStream_t)stream;
     std::vector<jk_tuning> cand;
-    const int ntile = (p->precision == JK_FP64 && !packed_b(p)) ? 3 : 1;
-    for (int tile = 0; tile < ntile; tile++)
+    // FP64 half-transform tiles: the 16 x 16 x 4 engine's two (4, 3) and the
+    // eight-wave tile of the 4x4x4 engine (2); other precisions and layouts
+    // have one kernel
+    std::vector<int> tiles = {4};
+    if (p->precision == JK_FP64 && !packed_b(p))
+        tiles = {4, 3, 2};
+    for (int tile : tiles)
         for (int mb : {128, 256, 512, 1024})
             cand.push_back(jk_tuning{tile, mb});
     TimedEvents E;

@@ -3,6 +3,10 @@
 #include "jk_kernels.hpp"
 #include "jk_tiles.hpp"
 
+#include <mutex>
+#include <set>
+#include <utility>
+
 namespace jk {
 
 __global__ void __launch_bounds__(256) k_pack_c(const double *__restrict__ CL,
@@ -86,6 +90,37 @@ __global__ void __launch_bounds__(512, 2) k_half_transform_w8(const double *__re
                            ncol);
 }
 
+// The half-transform on the 16 x 16 x 4 engine, over the chunk's stacked
+// slabs: 128 x 128 tiles of four 64 x 64 wave tiles in stages of 8 inner
+// indices (two workgroups per CU), or 128 x 64 tiles of four 64 x 32 wave
+// tiles in stages of 16 (three workgroups per CU).  Dynamic LDS: 35 and 52 KB.
+typedef Tile16<128, 128, 64, 64, 8> TileH16a;
+typedef Tile16<128, 64, 64, 32, 16> TileH16c;
+__global__ void __launch_bounds__(256, 2) k_half_transform16a(const double *__restrict__ B,
+                                                              const double *__restrict__ Cc,
+                                                              double *__restrict__ Xw,
+                                                              double *__restrict__ Yw, int nao,
+                                                              int nd, int r, int q0, int nq,
+                                                              int ldw, int ncol)
+{
+    extern __shared__ double lds_dyn[];
+    const int n = ht_flat_tiles<TileH16a>(nao, ncol, nq);
+    ht_tile_flat<TileH16a>(B, Cc, Xw, Yw, nao, nd, r, q0, nq, ldw, xcd_swizzle(blockIdx.x, n),
+                           lds_dyn, ncol);
+}
+__global__ void __launch_bounds__(256, 3) k_half_transform16(const double *__restrict__ B,
+                                                             const double *__restrict__ Cc,
+                                                             double *__restrict__ Xw,
+                                                             double *__restrict__ Yw, int nao,
+                                                             int nd, int r, int q0, int nq, int ldw,
+                                                             int ncol)
+{
+    extern __shared__ double lds_dyn[];
+    const int n = ht_flat_tiles<TileH16c>(nao, ncol, nq);
+    ht_tile_flat<TileH16c>(B, Cc, Xw, Yw, nao, nd, r, q0, nq, ldw, xcd_swizzle(blockIdx.x, n),
+                           lds_dyn, ncol);
+}
+
 // The same on packed slabs (jk.h JK_B_PACKED).
 __global__ void __launch_bounds__(256, 3) k_half_transform_packed(const double *__restrict__ B,
                                                                   const double *__restrict__ Cc,
@@ -123,6 +158,21 @@ __global__ void __launch_bounds__(256) k_unpack_sym(const double *__restrict__ P
         const double v = scale * Pk[pk_index(m, n, nao)];
         o[n] = accumulate ? o[n] + v : v;
     }
+}
+
+// The exchange product on the 16 x 16 x 4 engine: the same 128 x 64 tiles,
+// four 64 x 32 wave tiles, three workgroups per CU (52 KB of dynamic LDS).
+typedef TileH16c TileEx16;
+__global__ void __launch_bounds__(256, 3) k_exchange16(const double *__restrict__ Xw,
+                                                       const double *__restrict__ Yw,
+                                                       double *__restrict__ Kp, int nao, int nd,
+                                                       int nj, int ldw, int nsplit, int jlen,
+                                                       int accumulate, int sym, double scale)
+{
+    extern __shared__ double lds_dyn[];
+    const int n = nsplit * nd * (sym ? ex_tri_tiles(nao) : cdiv_i(nao, kExM) * cdiv_i(nao, kExN));
+    ex_tile<TileEx16>(Xw, Yw, Kp, nao, nd, nj, ldw, jlen, accumulate, xcd_swizzle(blockIdx.x, n),
+                      lds_dyn, sym, scale);
 }
 
 __global__ void __launch_bounds__(512, 4) k_exchange(const double *__restrict__ Xw,
@@ -283,16 +333,50 @@ hipError_t launch_coulomb(const double *B, const double *g, double *J, int naux,
     return hipGetLastError();
 }
 
+// Dynamic LDS above 64 KB needs a per-kernel attribute, set once per
+// (kernel, device).
+hipError_t set_dynamic_lds(const void *fn, int bytes)
+{
+    static std::mutex mu;
+    static std::set<std::pair<const void *, int>> done;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    std::lock_guard<std::mutex> lk(mu);
+    if (done.count({fn, dev}))
+        return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        done.insert({fn, dev});
+    return e;
+}
+
 hipError_t launch_half_transform(const double *B, const double *Cc, double *Xw, double *Yw,
                                  int nao, int nd, int r, int q0, int nq, int ldw, hipStream_t s,
                                  int ncol, int packed, int tile)
 {
     if (ncol < 0)
         ncol = 2 * nd * r;
+    if (tile >= 3 && !buf_extent_ok((i64)nq * nao * nao))
+        tile = 2;                                 // chunk beyond the buffer loads' 4 GiB reach
     if (packed) {
         ProfScope ps_("half_transform_packed", s);
         hipLaunchKernelGGL(k_half_transform_packed, dim3(ht_tiles_cols(nao, ncol, nq)), dim3(256), 0,
                            s, B, Cc, Xw, Yw, nao, nd, r, q0, nq, ldw, ncol);
+    } else if (tile == 3 || tile == 4) {
+        const void *fn = tile == 3 ? (const void *)k_half_transform16a : (const void *)k_half_transform16;
+        const int lds = (int)sizeof(double) * (tile == 3 ? TileH16a::LDS_DOUBLES : TileH16c::LDS_DOUBLES);
+        hipError_t e = set_dynamic_lds(fn, lds);
+        if (e != hipSuccess)
+            return e;
+        ProfScope ps_("half_transform", s);
+        if (tile == 3)
+            hipLaunchKernelGGL(k_half_transform16a, dim3(ht_flat_tiles<TileH16a>(nao, ncol, nq)),
+                               dim3(256), lds, s, B, Cc, Xw, Yw, nao, nd, r, q0, nq, ldw, ncol);
+        else
+            hipLaunchKernelGGL(k_half_transform16, dim3(ht_flat_tiles<TileH16c>(nao, ncol, nq)),
+                               dim3(256), lds, s, B, Cc, Xw, Yw, nao, nd, r, q0, nq, ldw, ncol);
     } else if (tile == 2) {
         ProfScope ps_("half_transform", s);
         hipLaunchKernelGGL(k_half_transform_w8, dim3(ht_tiles_cols(nao, ncol, nq)), dim3(512), 0, s, B,
@@ -347,7 +431,8 @@ int exchange_nsplit(int nao, int nd, int nj, int sym)
     int maxs = nj / 256 > 1 ? nj / 256 : 1;
     if (maxs > 16)
         maxs = 16;
-    return pick_split(tiles, maxs);
+    // k_exchange16 holds three workgroups per CU
+    return pick_split_slots(tiles, maxs, device_slots() / 2 * 3);
 }
 
 hipError_t launch_exchange(const double *Xw, const double *Yw, double *Kp, int nao, int nd, int nj,
@@ -356,7 +441,15 @@ hipError_t launch_exchange(const double *Xw, const double *Yw, double *Kp, int n
     int jlen = cdiv(nj, nsplit);
     jlen = ((jlen + 15) / 16) * 16;
     const int per = sym ? ex_tri_tiles(nao) : cdiv(nao, kExM) * cdiv(nao, kExN);
-    {
+    if (buf_extent_ok((i64)nao * ldw)) {
+        const int lds = (int)sizeof(double) * TileEx16::LDS_DOUBLES;
+        hipError_t e = set_dynamic_lds((const void *)k_exchange16, lds);
+        if (e != hipSuccess)
+            return e;
+        ProfScope ps_("exchange", s);
+        hipLaunchKernelGGL(k_exchange16, dim3(nsplit * nd * per), dim3(TileEx16::NTHR), lds, s, Xw,
+                           Yw, Kp, nao, nd, nj, ldw, nsplit, jlen, accumulate, sym, scale);
+    } else {
         ProfScope ps_("exchange", s);
         hipLaunchKernelGGL(k_exchange, dim3(nsplit * nd * per), dim3(TileExch::NTHR), 0, s, Xw, Yw, Kp,
                            nao, nd, nj, ldw, nsplit, jlen, accumulate, sym, scale);

@@ -29,6 +29,9 @@ int device_slots();
 // whose last round of workgroups is at least 90% full with at least one full
 // round, else the s with the fullest rounds.
 int pick_split(int tiles, int smax);
+// Allows `bytes` of dynamic LDS for kernel fn on the current device (once per
+// kernel and device).
+hipError_t set_dynamic_lds(const void *fn, int bytes);
 // Same with an explicit number of concurrent workgroup slots.
 int pick_split_slots(int tiles, int smax, int slots);
 

@@ -19,6 +19,7 @@
 // operand row is contiguous over the chunk's inner index (Q, i).
 #pragma once
 #include "f64_core.hpp"
+#include "f64_mfma16.hpp"
 
 namespace jk {
 
@@ -345,13 +346,14 @@ __device__ inline void ht_tile(const double *__restrict__ B, const double *__res
     });
 }
 
-// The half-transform with an arbitrary tile shape TL (full slabs).
+// The half-transform with an arbitrary tile shape TL of the 4x4x4 engine
+// (full slabs).
 template <class TL>
 __device__ inline void ht_tile_tl(const double *__restrict__ B, const double *__restrict__ Cc,
                                   double *__restrict__ Xw, double *__restrict__ Yw, int nao, int nd,
                                   int r, int q0, int ldw, int tile, double *lds, int ncol)
 {
-    constexpr int BM = TL::WROWS * TL::MA * 16, BN = TL::WCOLS * TL::NB * 4;
+    constexpr int BM = TL::BM, BN = TL::BN;
     const int R = nd * r, R2 = 2 * R;
     const int nc = ncol < 0 ? R2 : ncol;
     const int nmt = cdiv_i(nao, BM), nct = cdiv_i(nc, BN);
@@ -360,11 +362,52 @@ __device__ inline void ht_tile_tl(const double *__restrict__ B, const double *__
     const i64 n2 = (i64)nao * nao;
     OpKC a{B + (i64)(q0 + ql) * n2, nao, nao, nao};
     OpIC b{Cc, R2, nc, nao};
+    auto out = [&](int m, int c, double v) {
+        if (m < nao && c < nc) {
+            double *dst = c < R ? Xw : Yw;
+            const int cc = c < R ? c : c - R;
+            const int k = cc / r, i = cc % r;
+            dst[((i64)k * nao + m) * ldw + (i64)ql * r + i] = v;
+        }
+    };
     Acc<TL> acc;
     acc.zero();
     tile_gemm<TL>(a, b, mb * BM, cb * BN, 0, nao, lds, acc);
-    tile_foreach(acc, mb * BM, cb * BN, [&](int m, int c, double v) {
-        if (m < nao && c < nc) {
+    tile_foreach(acc, mb * BM, cb * BN, out);
+}
+
+// The half-transform of the chunk's nq slabs as one product: the slabs,
+// stacked, are an (nq nao) x nao matrix, so tile rows run across slab
+// boundaries and no rows are padded per slab.  Row t of the stack is row
+// t % nao of slab q0 + t / nao.  TL is a tile of the 16 x 16 x 4 engine; the
+// chunk's slabs must span less than 4 GiB (buf_extent_ok).
+template <class TL>
+__host__ __device__ inline int ht_flat_tiles(int nao, int ncol, int nq)
+{
+    return cdiv_i((i64)nq * nao, TL::BM) * cdiv_i(ncol, TL::BN);
+}
+template <class TL>
+__device__ inline void ht_tile_flat(const double *__restrict__ B, const double *__restrict__ Cc,
+                                    double *__restrict__ Xw, double *__restrict__ Yw, int nao,
+                                    int nd, int r, int q0, int nq, int ldw, int tile, double *lds,
+                                    int ncol)
+{
+    constexpr int BM = TL::BM, BN = TL::BN;
+    const int R = nd * r, R2 = 2 * R;
+    const int nc = ncol < 0 ? R2 : ncol;
+    const int rows = nq * nao;
+    const int nct = cdiv_i(nc, BN);
+    const int mb = tile / nct, cb = tile % nct;
+    BufKC a{B + (i64)q0 * nao * nao, nao, rows, nao};
+    BufIC b{Cc, R2, nc, nao};
+    Acc16<TL> acc;
+    acc.zero();
+    // No inner-index masking: past row nao - 1, Cc reads zero (the end of its
+    // resource), and the slab rows read there are finite data of the next row.
+    tile_gemm16<TL, false>(a, b, mb * BM, cb * BN, 0, nao, lds, acc);
+    tile_foreach16(acc, mb * BM, cb * BN, [&](int t, int c, double v) {
+        if (t < rows && c < nc) {
+            const int ql = t / nao, m = t - ql * nao;
             double *dst = c < R ? Xw : Yw;
             const int cc = c < R ? c : c - R;
             const int k = cc / r, i = cc % r;
@@ -379,12 +422,13 @@ __device__ inline void ht_tile_tl(const double *__restrict__ B, const double *__
 // With sym != 0 (Yw = Xw) only the tiles reaching n >= m are computed; the
 // rest of K is filled by mirroring afterwards.
 // Kp[split][k] (+)= scale * (the chunk's X Y^T over the split's inner range).
+template <class TL = TileExch>
 __device__ inline void ex_tile(const double *__restrict__ Xw, const double *__restrict__ Yw,
                                double *__restrict__ Kp, int nao, int nd, int nj, int ldw, int jlen,
                                int accumulate, int tile, double *lds, int sym = 0,
                                double scale = 1.0)
 {
-    typedef TileExch TL;
+    static_assert(TL::BM == kExM && TL::BN == kExN, "exchange tile shape");
     const int nmt = cdiv_i(nao, kExM), nnt = cdiv_i(nao, kExN);
     const int pk = sym ? ex_tri_tiles(nao) : nmt * nnt;
     const int per = nd * pk;
@@ -399,18 +443,30 @@ __device__ inline void ex_tile(const double *__restrict__ Xw, const double *__re
         nb = rem % nnt;
     }
     const int j0 = sp * jlen, j1 = (j0 + jlen) < nj ? (j0 + jlen) : nj;
-    OpKC a{Xw + (i64)k * nao * ldw, ldw, nao, j1};
-    OpKC b{Yw + (i64)k * nao * ldw, ldw, nao, j1};
-    Acc<TL> acc;
-    acc.zero();
-    tile_gemm<TL>(a, b, mb * kExM, nb * kExN, j0, j1, lds, acc);
     double *Kk = Kp + ((i64)sp * nd + k) * nao * nao;
-    tile_foreach(acc, mb * kExM, nb * kExN, [&](int m, int n, double v) {
+    auto out = [&](int m, int n, double v) {
         if (m < nao && n < nao) {
             const i64 o = (i64)m * nao + n;
             Kk[o] = accumulate ? Kk[o] + scale * v : scale * v;
         }
-    });
+    };
+    if constexpr (TL::kMfma16) {
+        // resources end at column j1 of the last row; inner indices past j1
+        // are masked in the last stage
+        BufKC a{Xw + (i64)k * nao * ldw, ldw, nao, j1};
+        BufKC b{Yw + (i64)k * nao * ldw, ldw, nao, j1};
+        Acc16<TL> acc;
+        acc.zero();
+        tile_gemm16<TL>(a, b, mb * kExM, nb * kExN, j0, j1, lds, acc);
+        tile_foreach16(acc, mb * kExM, nb * kExN, out);
+    } else {
+        OpKC a{Xw + (i64)k * nao * ldw, ldw, nao, j1};
+        OpKC b{Yw + (i64)k * nao * ldw, ldw, nao, j1};
+        Acc<TL> acc;
+        acc.zero();
+        tile_gemm<TL>(a, b, mb * kExM, nb * kExN, j0, j1, lds, acc);
+        tile_foreach(acc, mb * kExM, nb * kExN, out);
+    }
 }
 
 // out[e] = sum_{s < nsplit} part[s * n + e] (fixed order).

@@ -31,7 +31,7 @@ Key key_of(const jk_problem *p)
 
 bool valid_tuning(const jk_tuning &t)
 {
-    return t.ht_tile >= 0 && t.ht_tile <= 2 && t.chunk_mb >= 64 && t.chunk_mb <= 1024;
+    return t.ht_tile >= 0 && t.ht_tile <= 4 && t.chunk_mb >= 64 && t.chunk_mb <= 1024;
 }
 
 // Minimal reader for the flat JSON this file writes: objects of integer
@@ -93,7 +93,7 @@ jk_tuning tuning_for(const jk_problem *p)
     auto it = g_table.find(key_of(p));
     if (it != g_table.end())
         return it->second;
-    return jk_tuning{p->nao <= 384 ? 1 : 2, 1024};
+    return jk_tuning{4, 1024};
 }
 
 void tuning_record(const jk_problem *p, const jk_tuning &t)

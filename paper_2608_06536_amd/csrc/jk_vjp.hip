@@ -23,18 +23,16 @@
 //     sum_{j<2R} L[a][j] L[b][2R + j] = C_R R'^T + P' C_L^T.
 // Cc[n][c] is [C_L | C_R] with c < 2R; omx[Q][c] = omega_{c / r, Q}, c < R.
 #include "f64_core.hpp"
+#include "f64_mfma16.hpp"
 #include "jk_kernels.hpp"
 
 namespace jk {
 
 namespace {
-// 128 x 64 workgroup tiles.  Stage D: four 64 x 32 wave tiles (two
-// workgroups per CU).  Stages B and C: eight 64 x 16 wave tiles (four waves
-// per SIMD; measured 12% faster for stage B of R', 3% for stage C and stage B
-// of P', 1% slower for stage D).
+// 128 x 64 workgroup tiles of four 64 x 32 wave tiles on the 16 x 16 x 4
+// engine, three workgroups per CU (52 KB of dynamic LDS each).
 constexpr int kTM = 128, kTN = 64;
-typedef Tile<kTM, kTN, 64, 32, 16> TileV;
-typedef Tile<kTM, kTN, 64, 16, 16> TileV8;
+typedef Tile16<kTM, kTN, 64, 32, 16> TileV;
 } // namespace
 
 // omx[Q][c] = om[c / r][Q], c < R.
@@ -74,7 +72,7 @@ __global__ void __launch_bounds__(256) k_vjp_fill_blocks(const double *__restric
 // (om = omega_{k, q0+ql}; products skipped when has_v == 0, omega terms when
 // has_w == 0).  grid.x = nd * nmt * njt (XCD-swizzled).
 template <int WHICH>
-__global__ void __launch_bounds__(512, 2) k_vjp_stage_b(const double *__restrict__ V,
+__global__ void __launch_bounds__(256, 3) k_vjp_stage_b(const double *__restrict__ V,
                                                         const double *__restrict__ Zw,
                                                         const double *__restrict__ Cc,
                                                         const double *__restrict__ omx,
@@ -82,27 +80,27 @@ __global__ void __launch_bounds__(512, 2) k_vjp_stage_b(const double *__restrict
                                                         int r, int q0, int nj, int ldw, int has_v,
                                                         int has_w)
 {
-    typedef TileV8 TL;
-    __shared__ double lds[TL::LDS_DOUBLES];
+    typedef TileV TL;
+    extern __shared__ double lds[];
     const int R = nd * r, R2 = 2 * R, R4 = 4 * R;
     const int nmt = (nao + kTM - 1) / kTM, njt = (nj + kTN - 1) / kTN;
     const int t = xcd_swizzle(blockIdx.x, nd * nmt * njt);
     const int k = t / (nmt * njt), rem = t % (nmt * njt);
     const int mb = rem / njt, jb = rem % njt;
-    Acc<TL> acc;
+    Acc16<TL> acc;
     acc.zero();
     if (has_v) {
         const double *Vk = V + (i64)k * nao * nao;
-        OpIC b{Zw + (i64)k * nao * ldw, ldw, nj, nao};
+        BufIC b{Zw + (i64)k * nao * ldw, ldw, nj, nao};
         if (WHICH == 0) {
-            OpKC a{Vk, nao, nao, nao};
-            tile_gemm<TL>(a, b, mb * kTM, jb * kTN, 0, nao, lds, acc);
+            BufKC a{Vk, nao, nao, nao};
+            tile_gemm16<TL>(a, b, mb * kTM, jb * kTN, 0, nao, lds, acc);
         } else {
-            OpIC a{Vk, nao, nao, nao};
-            tile_gemm<TL>(a, b, mb * kTM, jb * kTN, 0, nao, lds, acc);
+            BufIC a{Vk, nao, nao, nao};
+            tile_gemm16<TL>(a, b, mb * kTM, jb * kTN, 0, nao, lds, acc);
         }
     }
-    tile_foreach(acc, mb * kTM, jb * kTN, [&](int m, int j, double v) {
+    tile_foreach16(acc, mb * kTM, jb * kTN, [&](int m, int j, double v) {
         if (m < nao && j < nj) {
             const int ql = j / r, i = j - ql * r;
             const int c = k * r + i;
@@ -116,31 +114,31 @@ __global__ void __launch_bounds__(512, 2) k_vjp_stage_b(const double *__restrict
 // ------------------------------------------------------------------ stage C
 // dCp[sp][m][c] (+)= sum_{ql in split sp} sum_n B^{q0+ql}[m][n] L[ql][n][R + c], c < 2R.
 // grid.x = nsplit * nmt * nct.
-__global__ void __launch_bounds__(512, 2) k_vjp_stage_c(const double *__restrict__ B,
+__global__ void __launch_bounds__(256, 3) k_vjp_stage_c(const double *__restrict__ B,
                                                         const double *__restrict__ L,
                                                         double *__restrict__ dCp, int nao, int R,
                                                         int q0, int nq, int nsplit, int qlen,
                                                         int accumulate)
 {
-    typedef TileV8 TL;
-    __shared__ double lds[TL::LDS_DOUBLES];
+    typedef TileV TL;
+    extern __shared__ double lds[];
     const int R2 = 2 * R, R4 = 4 * R;
     const int nmt = (nao + kTM - 1) / kTM, nct = (R2 + kTN - 1) / kTN;
     const int t = xcd_swizzle(blockIdx.x, nsplit * nmt * nct);
     const int sp = t / (nmt * nct), rem = t % (nmt * nct);
     const int mb = rem / nct, cb = rem % nct;
     const i64 n2 = (i64)nao * nao;
-    Acc<TL> acc;
+    Acc16<TL> acc;
     acc.zero();
     const int qa = sp * qlen, qb = (qa + qlen) < nq ? (qa + qlen) : nq;
     if (qb > qa) {
-        // slabs qa..qb-1 as one pipelined sum
-        OpKC a{B + (i64)(q0 + qa) * n2, nao, nao, nao};
-        OpIC b{L + (i64)qa * nao * R4 + R, R4, R2, nao};
-        tile_gemm_seg<TL>(a, b, n2, (i64)nao * R4, qb - qa, mb * kTM, cb * kTN, nao, lds, acc);
+        // slabs qa..qb-1 as one pipelined sum, one resource per slab
+        BufKC a{B + (i64)(q0 + qa) * n2, nao, nao, nao};
+        BufIC b{L + (i64)qa * nao * R4 + R, R4, R2, nao};
+        tile_gemm16_seg<TL>(a, b, n2, (i64)nao * R4, qb - qa, mb * kTM, cb * kTN, nao, lds, acc);
     }
     double *out = dCp + (i64)sp * nao * R2;
-    tile_foreach(acc, mb * kTM, cb * kTN, [&](int m, int c, double v) {
+    tile_foreach16(acc, mb * kTM, cb * kTN, [&](int m, int c, double v) {
         if (m < nao && c < R2) {
             i64 o = (i64)m * R2 + c;
             out[o] = accumulate ? out[o] + v : v;
@@ -183,26 +181,26 @@ __global__ void __launch_bounds__(256) k_vjp_e_matrix(const double *__restrict__
 // ------------------------------------------------------------------ stage D
 // dB[q0+ql][a][b] = sum_{j<2R} L[ql][a][j] L[ql][b][2R + j].
 // grid.x = nq * nmt * nnt (XCD-swizzled).
-__global__ void __launch_bounds__(256, 2) k_vjp_stage_d(const double *__restrict__ L,
+__global__ void __launch_bounds__(256, 3) k_vjp_stage_d(const double *__restrict__ L,
                                                         double *__restrict__ dB, int nao, int R,
                                                         int q0, int nq)
 {
     typedef TileV TL;
-    __shared__ double lds[TL::LDS_DOUBLES];
+    extern __shared__ double lds[];
     const int R2 = 2 * R, R4 = 4 * R;
     const int nmt = (nao + kTM - 1) / kTM, nnt = (nao + kTN - 1) / kTN;
     const int t = xcd_swizzle(blockIdx.x, nq * nmt * nnt);
     const int ql = t / (nmt * nnt), rem = t % (nmt * nnt);
     const int ab = rem / nnt, bb = rem % nnt;
     const double *Lq = L + (i64)ql * nao * R4;
-    OpKC a{Lq, R4, nao, R2};
-    OpKC b{Lq + R2, R4, nao, R2};
-    Acc<TL> acc;
+    BufKC a{Lq, R4, nao, R2};
+    BufKC b{Lq + R2, R4, nao, R2};
+    Acc16<TL> acc;
     acc.zero();
-    tile_gemm<TL>(a, b, ab * kTM, bb * kTN, 0, R2, lds, acc);
+    tile_gemm16<TL>(a, b, ab * kTM, bb * kTN, 0, R2, lds, acc);
     const i64 n2 = (i64)nao * nao;
     double *out = dB + (i64)(q0 + ql) * n2;
-    tile_foreach(acc, ab * kTM, bb * kTN, [&](int ia, int ib, double v) {
+    tile_foreach16(acc, ab * kTM, bb * kTN, [&](int ia, int ib, double v) {
         if (ia < nao && ib < nao)
             out[(i64)ia * nao + ib] = v;
     });
@@ -327,18 +325,24 @@ hipError_t launch_vjp_stage_b(const double *V, const double *Xw, const double *Y
 {
     const int nmt = cdiv(nao, kTM), njt = cdiv(nj, kTN);
     dim3 grid(nd * nmt * njt);
+    const int lds = (int)sizeof(double) * TileV::LDS_DOUBLES;
+    hipError_t e = set_dynamic_lds((const void *)k_vjp_stage_b<0>, lds);
+    if (e == hipSuccess)
+        e = set_dynamic_lds((const void *)k_vjp_stage_b<1>, lds);
+    if (e != hipSuccess)
+        return e;
     {
         ProfScope ps_("vjp_stage_b_p", s);
-        hipLaunchKernelGGL(k_vjp_stage_b<0>, grid, dim3(TileV8::NTHR), 0, s, V, Yw, Cc, omx, L, nao, nd, r,
-                           q0, nj, ldw, has_v, has_w);
+        hipLaunchKernelGGL(k_vjp_stage_b<0>, grid, dim3(TileV::NTHR), lds, s, V, Yw, Cc, omx, L, nao, nd,
+                           r, q0, nj, ldw, has_v, has_w);
     }
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess)
         return e;
     {
         ProfScope ps_("vjp_stage_b_r", s);
-        hipLaunchKernelGGL(k_vjp_stage_b<1>, grid, dim3(TileV8::NTHR), 0, s, V, Xw, Cc, omx, L, nao, nd, r,
-                           q0, nj, ldw, has_v, has_w);
+        hipLaunchKernelGGL(k_vjp_stage_b<1>, grid, dim3(TileV::NTHR), lds, s, V, Xw, Cc, omx, L, nao, nd,
+                           r, q0, nj, ldw, has_v, has_w);
     }
     return hipGetLastError();
 }
@@ -346,7 +350,8 @@ hipError_t launch_vjp_stage_b(const double *V, const double *Xw, const double *Y
 int vjp_stage_c_nsplit(int nao, int R, int qc)
 {
     const int tiles = cdiv(nao, kTM) * cdiv(2 * (i64)R, kTN);
-    return pick_split(tiles, qc < 64 ? qc : 64);
+    // three workgroups per CU
+    return pick_split_slots(tiles, qc < 64 ? qc : 64, device_slots() / 2 * 3);
 }
 
 hipError_t launch_vjp_stage_c(const double *B, const double *L, double *dCp, int nao, int R,
@@ -354,10 +359,14 @@ hipError_t launch_vjp_stage_c(const double *B, const double *L, double *dCp, int
 {
     const int nmt = cdiv(nao, kTM), nct = cdiv(2 * (i64)R, kTN);
     const int qlen = cdiv(nq, nsplit);
+    const int lds = (int)sizeof(double) * TileV::LDS_DOUBLES;
+    hipError_t e = set_dynamic_lds((const void *)k_vjp_stage_c, lds);
+    if (e != hipSuccess)
+        return e;
     {
         ProfScope ps_("vjp_stage_c", s);
-        hipLaunchKernelGGL(k_vjp_stage_c, dim3(nsplit * nmt * nct), dim3(TileV8::NTHR), 0, s, B, L, dCp, nao,
-                           R, q0, nq, nsplit, qlen, accumulate);
+        hipLaunchKernelGGL(k_vjp_stage_c, dim3(nsplit * nmt * nct), dim3(TileV::NTHR), lds, s, B, L, dCp,
+                           nao, R, q0, nq, nsplit, qlen, accumulate);
     }
     return hipGetLastError();
 }
@@ -386,10 +395,14 @@ hipError_t launch_vjp_e_matrix(const double *D, double *E, int nao, int nd, hipS
 hipError_t launch_vjp_stage_d(const double *L, double *dB, int nao, int R, int q0, int nq,
                               hipStream_t s)
 {
+    const int lds = (int)sizeof(double) * TileV::LDS_DOUBLES;
+    hipError_t e = set_dynamic_lds((const void *)k_vjp_stage_d, lds);
+    if (e != hipSuccess)
+        return e;
     {
         ProfScope ps_("vjp_stage_d", s);
-        hipLaunchKernelGGL(k_vjp_stage_d, dim3(nq * cdiv(nao, kTM) * cdiv(nao, kTN)), dim3(256), 0, s,
-                           L, dB, nao, R, q0, nq);
+        hipLaunchKernelGGL(k_vjp_stage_d, dim3(nq * cdiv(nao, kTM) * cdiv(nao, kTN)), dim3(TileV::NTHR),
+                           lds, s, L, dB, nao, R, q0, nq);
     }
     return hipGetLastError();
 }

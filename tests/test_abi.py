@@ -169,8 +169,8 @@ def test_tuning_table_json_round_trip():
     jk.tuning_clear()
     p1 = _prob(nao=300, ndens=4, rank=30)
     p2 = _prob(nao=100, ndens=6, rank=10, precision=1)
-    assert jk.tuning_get(p1) == {"ht_tile": 1, "chunk_mb": 1024}        # default, nao <= 384
-    assert jk.tuning_get(_prob(nao=500, ndens=8, rank=40))["ht_tile"] == 2
+    assert jk.tuning_get(p1) == {"ht_tile": 4, "chunk_mb": 1024}        # default
+    assert jk.tuning_get(_prob(nao=500, ndens=8, rank=40))["ht_tile"] == 4
     jk.tuning_set(p1, 1, 256)
     jk.tuning_set(p2, 0, 128)
     # same shape class (nao and R in steps of 64): same entry
@@ -192,7 +192,7 @@ def test_tuning_table_json_round_trip():
 @pytest.mark.parametrize("bad", [
     "", "{}", "[]", '{"version": 2, "entries": []}', '{"entries": [{"nao64": 1}]}',
     '{"version": 1, "entries": [{"nao64": 1, "rank64": 1, "precision": 0, "packed": 0, '
-    '"ht_tile": 3, "chunk_mb": 256}]}',
+    '"ht_tile": 5, "chunk_mb": 256}]}',
     '{"version": 1, "entries": [{"nao64": 1, "rank64": 1, "precision": 0, "packed": 0, '
     '"ht_tile": 0, "chunk_mb": 32}]}',
     '{"version": 1, "entries": [{"nao64": 1, "rank64": 1, "precision": 0, "packed": 0, '
@@ -213,7 +213,7 @@ def test_tuning_load_rejects(bad):
 def test_tuning_validation():
     L = _lib.lib()
     p = _prob()
-    for t in [(3, 256), (0, 63), (0, 1025), (-1, 256)]:
+    for t in [(5, 256), (0, 63), (0, 1025), (-1, 256)]:
         tt = _lib.Tuning(*t)
         assert L.jk_tuning_set(ctypes.byref(p), ctypes.byref(tt)) == _lib.JK_EINVAL
     tt = _lib.Tuning(0, 256)

@@ -43,7 +43,7 @@ def test_tile_choice_is_bit_identical(nao, naux, nd, r):
     jk.tuning_set(prob, 0, 1024)
     J0, K0 = jk.jk_build(Bd, Ld, Rd)
     Jr, Kr, _ = oracle.jk_factored(B, CL, CR)
-    for tile in (1, 2):
+    for tile in (1, 2, 3, 4):
         jk.tuning_set(prob, tile, 1024)
         J1, K1 = jk.jk_build(Bd, Ld, Rd)
         torch.cuda.synchronize()
@@ -78,7 +78,7 @@ def test_autotune_records_and_reproduces(precision):
     prob = jk.make_problem(200, 300, 3, 20, precision)
     assert jk.tuning_get(prob) == choice
     assert choice["chunk_mb"] in (128, 256, 512, 1024)
-    assert choice["ht_tile"] in ((0, 1, 2) if precision == "fp64" else (0,))
+    assert choice["ht_tile"] in ((2, 3, 4) if precision == "fp64" else (4,))
     J2, K2 = jk.jk_build(Bd, Ld, Rd, precision=precision)
     torch.cuda.synchronize()
     assert torch.equal(J, J2) and torch.equal(K, K2)
@@ -89,7 +89,7 @@ def test_autotune_records_and_reproduces(precision):
         assert rel_err(K[k].cpu().numpy(), Kr[k]) <= tol
 
 
-@pytest.mark.parametrize("tiles", [(0, 0, 0), (1, 0, 1), (1, 1, 1), (2, 1, 2)])
+@pytest.mark.parametrize("tiles", [(0, 0, 0), (1, 0, 1), (1, 1, 1), (2, 1, 2), (4, 3, 1)])
 def test_batched_follows_class_plans(tiles):
     # members of one batch with different half-transform tiles and chunk budgets
     from paper_2608_06536_amd import jk

@@ -657,7 +657,8 @@ double tile_cost(int phase, const FwdPlan &f, const jk_problem &p)
     case jk::kPhaseReduce: return (double)f.npb;
     case jk::kPhaseCoulomb: return (double)p.naux;
     case jk::kPhaseHalf:
-    case jk::kPhaseHalf64: return (double)p.nao;
+    case jk::kPhaseHalf64:
+    case jk::kPhaseHalf16: return (double)p.nao;
     case jk::kPhaseExchange: return (double)f.qc * p.rank / f.nsplit;
     default: return (double)p.nao;
     }
@@ -671,8 +672,12 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p)
     std::vector<int> tile_of(G);
     int maxsteps = 0;
     for (int g = 0; g < G; g++) {
-        tile_of[g] = plan_tuning(&p[g]).ht_tile == 1 ? 1 : 0;   // the batch runs 2 as 0
         plans[g] = plan_forward(&p[g], std::min(kChunkBudgetBatched, tuned_budget(&p[g])));
+        // the batch runs tile 2 as 0 and tile 3 as 4; tiles 3 and 4 need the chunk's
+        // slabs within a buffer resource's reach
+        const int t = plan_tuning(&p[g]).ht_tile;
+        const bool fits = jk::buf_extent_ok((i64)plans[g].qc * p[g].nao * p[g].nao);
+        tile_of[g] = t == 1 ? 1 : (t >= 3 && fits) ? 4 : 0;
         const int st = (int)((p[g].naux + plans[g].qc - 1) / plans[g].qc);
         maxsteps = std::max(maxsteps, st);
     }
@@ -733,6 +738,12 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p)
             add(jk::kPhaseHalf64, c,
                 [&](int g) { return jk::ht64_tiles((int)p[g].nao, (int)p[g].ndens, (int)p[g].rank, nq_of(g)); },
                 [&](int g) { return in_step(g) && tile_of[g] == 1; });
+            add(jk::kPhaseHalf16, c,
+                [&](int g) {
+                    return jk::ht_flat_tiles<jk::TileHalf16>((int)p[g].nao, 2 * (int)(p[g].ndens * p[g].rank),
+                                                           nq_of(g));
+                },
+                [&](int g) { return in_step(g) && tile_of[g] == 4; });
             add(jk::kPhaseExchange, c,
                 [&](int g) { return jk::ex_tiles((int)p[g].nao, (int)p[g].ndens, plans[g].nsplit); },
                 in_step);
@@ -854,6 +865,8 @@ jk_status build_batched_fp64(int32_t nprob, const jk_problem *p, const double *c
     if (hipMemcpyAsync(ws, host.data(), S.header_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
         return JK_EHIP;
 
+    if (jk::prepare_batched_kernels() != hipSuccess)
+        return JK_EHIP;
     if (s == nullptr || !graphs_enabled())
         return enqueue_batched(S, ws, s);
 

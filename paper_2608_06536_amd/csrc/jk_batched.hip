@@ -108,10 +108,27 @@ __global__ void __launch_bounds__(256, 4) k_b_half_transform64(const BMember *__
     ht_tile_tl<TileHalf64>(m.B, m.Cc, m.Xw, m.Yw, m.nao, m.nd, m.r, q0, m.ldw, loc, lds, -1);
 }
 
-__global__ void __launch_bounds__(512, 4) k_b_exchange(const BMember *__restrict__ M,
+// Stacked-slab half-transform on the 16 x 16 x 4 engine (the plan's tile 3
+// or 4; the schedule keeps members whose chunk of slabs spans 4 GiB or more
+// on the 4x4x4 tile).
+typedef TileHalf16 TileB16;
+__global__ void __launch_bounds__(256, 3) k_b_half_transform16(const BMember *__restrict__ M,
+                                                               const int *__restrict__ tab, int c)
+{
+    extern __shared__ double lds[];
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    int q0, nq;
+    chunk_of(m, c, q0, nq);
+    ht_tile_flat<TileB16>(m.B, m.Cc, m.Xw, m.Yw, m.nao, m.nd, m.r, q0, nq, m.ldw, loc, lds, -1);
+}
+
+// The exchange on the 16 x 16 x 4 engine (member chunk workspaces are capped
+// at 256 MB, so X and Y of a density stay within a buffer resource's reach).
+__global__ void __launch_bounds__(256, 3) k_b_exchange(const BMember *__restrict__ M,
                                                        const int *__restrict__ tab, int c)
 {
-    __shared__ double lds[TileExch::LDS_DOUBLES];
+    extern __shared__ double lds[];
     int loc;
     const BMember &m = M[find_member(tab, blockIdx.x, loc)];
     int q0, nq;
@@ -119,7 +136,8 @@ __global__ void __launch_bounds__(512, 4) k_b_exchange(const BMember *__restrict
     const int nj = nq * m.r;
     int jlen = cdiv_i(nj, m.nsplit);
     jlen = ((jlen + 15) / 16) * 16;
-    ex_tile(m.Xw, m.Yw, m.nsplit > 1 ? m.Kp : m.K, m.nao, m.nd, nj, m.ldw, jlen, c > 0, loc, lds);
+    ex_tile<TileB16>(m.Xw, m.Yw, m.nsplit > 1 ? m.Kp : m.K, m.nao, m.nd, nj, m.ldw, jlen, c > 0, loc,
+                     lds);
 }
 
 __global__ void __launch_bounds__(256) k_b_sum_splits(const BMember *__restrict__ M,
@@ -131,6 +149,16 @@ __global__ void __launch_bounds__(256) k_b_sum_splits(const BMember *__restrict_
 }
 
 // ------------------------------------------------------------------ launch
+static constexpr int kLds16 = (int)sizeof(double) * TileB16::LDS_DOUBLES;
+
+hipError_t prepare_batched_kernels()
+{
+    hipError_t e = set_dynamic_lds((const void *)k_b_half_transform16, kLds16);
+    if (e == hipSuccess)
+        e = set_dynamic_lds((const void *)k_b_exchange, kLds16);
+    return e;
+}
+
 hipError_t launch_batched_phase(int phase, const BMember *M, const int *tab, int ntiles, int step,
                                 hipStream_t s)
 {
@@ -173,9 +201,14 @@ hipError_t launch_batched_phase(int phase, const BMember *M, const int *tab, int
         hipLaunchKernelGGL(k_b_half_transform64, g, dim3(256), 0, s, M, tab, step);
         break;
     }
+    case kPhaseHalf16: {
+        ProfScope ps_("b_half_transform", s);
+        hipLaunchKernelGGL(k_b_half_transform16, g, dim3(TileB16::NTHR), kLds16, s, M, tab, step);
+        break;
+    }
     case kPhaseExchange: {
         ProfScope ps_("b_exchange", s);
-        hipLaunchKernelGGL(k_b_exchange, g, dim3(TileExch::NTHR), 0, s, M, tab, step);
+        hipLaunchKernelGGL(k_b_exchange, g, dim3(TileB16::NTHR), kLds16, s, M, tab, step);
         break;
     }
     case kPhaseSum: {

@@ -25,8 +25,13 @@ enum {
     kPhaseHalf = 5,
     kPhaseExchange = 6,
     kPhaseSum = 7,
-    kPhaseHalf64 = 8     // the half-transform with 64 x 64 tiles (members whose plan chose them)
+    kPhaseHalf64 = 8,    // the half-transform with 64 x 64 tiles (members whose plan chose them)
+    kPhaseHalf16 = 9     // the half-transform on the 16 x 16 x 4 engine over stacked slabs
 };
+
+// Sets the dynamic LDS size of the batched kernels that need it on the
+// current device (before a launch sequence is captured).
+hipError_t prepare_batched_kernels();
 
 // One launch of a phase over the members listed in tab (device pointer):
 // ntiles workgroups, step = chunk index for the chunked phases.

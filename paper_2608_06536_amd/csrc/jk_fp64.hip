@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(512, 2) k_half_transform_w8(const double *__re
 // indices (two workgroups per CU), or 128 x 64 tiles of four 64 x 32 wave
 // tiles in stages of 16 (three workgroups per CU).  Dynamic LDS: 35 and 52 KB.
 typedef Tile16<128, 128, 64, 64, 8> TileH16a;
-typedef Tile16<128, 64, 64, 32, 16> TileH16c;
+typedef TileHalf16 TileH16c;
 __global__ void __launch_bounds__(256, 2) k_half_transform16a(const double *__restrict__ B,
                                                               const double *__restrict__ Cc,
                                                               double *__restrict__ Xw,

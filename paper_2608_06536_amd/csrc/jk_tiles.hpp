@@ -39,6 +39,9 @@ typedef Tile<64, 64, 32, 32, 16> TileDensity;
 // The half-transform's second tile shape (a plan choice, jk_tune.h): 64 x 64,
 // four workgroups per CU; wins at small nao where 128-row tiles waste rows.
 typedef Tile<64, 64, 32, 32, 16> TileHalf64;
+// The default half-transform tile (jk_tune.h tile 4): 128 x 64 on the 16 x 16 x 4
+// engine, four 64 x 32 wave tiles, over stacked slabs.
+typedef Tile16<128, 64, 64, 32, 16> TileHalf16;
 
 __host__ __device__ inline int cdiv_i(i64 a, i64 b) { return (int)((a + b - 1) / b); }
 

@@ -408,15 +408,43 @@ __device__ inline void ht_tile_flat(const double *__restrict__ B, const double *
     // No inner-index masking: past row nao - 1, Cc reads zero (the end of its
     // resource), and the slab rows read there are finite data of the next row.
     tile_gemm16<TL, false>(a, b, mb * BM, cb * BN, 0, nao, lds, acc);
-    tile_foreach16(acc, mb * BM, cb * BN, [&](int t, int c, double v) {
-        if (t < rows && c < nc) {
-            const int ql = t / nao, m = t - ql * nao;
-            double *dst = c < R ? Xw : Yw;
-            const int cc = c < R ? c : c - R;
-            const int k = cc / r, i = cc % r;
-            dst[((i64)k * nao + m) * ldw + (i64)ql * r + i] = v;
+    // Output (t, c) goes to col(c)[row(t)]: col(c) = X_ws or Y_ws at density
+    // k = c' / r, column i = c' % r (c' = c or c - R), and row(t) = m ldw +
+    // ql r for t = ql nao + m.  A lane holds NB columns and 4 MA rows
+    // (16 apart within 4 apart), decoded once each.
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
+    const int rb = mb * BM + wr * TL::WM + (lane >> 4);
+    const int cb0 = cb * BN + wc * TL::WN + (lane & 15);
+    double *col[TL::NB];
+    bool col_ok[TL::NB];
+#pragma unroll
+    for (int j = 0; j < TL::NB; j++) {
+        const int c = cb0 + 16 * j;
+        col_ok[j] = c < nc;
+        const int cc = c < R ? c : c - R;
+        const int k = cc / r, i = cc - k * r;
+        col[j] = (c < R ? Xw : Yw) + (i64)k * nao * ldw + i;
+    }
+    const int ql0 = rb / nao, m0 = rb - ql0 * nao;
+#pragma unroll
+    for (int i = 0; i < TL::MA; i++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int d = 16 * i + 4 * v;
+            if (rb + d < rows) {
+                int m = m0 + d, ql = ql0;
+                while (m >= nao) {
+                    m -= nao;
+                    ql++;
+                }
+                const i64 off = (i64)m * ldw + (i64)ql * r;
+#pragma unroll
+                for (int j = 0; j < TL::NB; j++)
+                    if (col_ok[j])
+                        col[j][off] = acc.c[i][j][v];
+            }
         }
-    });
 }
 
 // ------------------------------------------------------------------ exchange

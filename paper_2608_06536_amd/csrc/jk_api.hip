@@ -413,21 +413,47 @@ jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const
     }
     if (want_db)
         JK_TRY(jk::launch_vjp_fill_blocks(Cc, L, nao, R, f.qc, s));
+    // Two streams, so that one launch's last partial round of workgroups
+    // overlaps another launch:
+    //   main: HT(c), B[P'](c), D(c), affine(c)
+    //   aux:  B[R'](c), C(c)
+    // Order: aux's B[R'](c) after HT(c) (reads X) and after D(c - 1) (R' of
+    // the slab blocks); main's B[P'](c) after C(c - 1) (reads the blocks);
+    // C(c) and D(c) after both B's; main ends after aux's last work.
+    hipStream_t a = nullptr;
+    JK_TRY(aux_stream(&a));
+    EventSet ev;
+    JK_TRY(ev.create(4));
+    hipEvent_t ev_x = ev.ev[0], ev_br = ev.ev[1], ev_b = ev.ev[2], ev_aux = ev.ev[3];
+    JK_TRY(hipEventRecord(ev_aux, s));           // aux starts after the prologue
+    const int tile = plan_tuning(p).ht_tile;
     for (int q0 = 0; q0 < naux; q0 += f.qc) {
         const int nq = (naux - q0) < f.qc ? (naux - q0) : f.qc;
         if (has_v)
             JK_TRY(jk::launch_half_transform(B, Cc, Xw, Yw, nao, nd, r, q0, nq, f.ldw, s, -1, 0,
-                                             plan_tuning(p).ht_tile));
-        JK_TRY(jk::launch_vjp_stage_b(V, Xw, Yw, Cc, omx, L, nao, nd, r, q0, nq * r, f.ldw, has_v,
-                                      has_w, s));
-        if (want_dc)
-            JK_TRY(jk::launch_vjp_stage_c(B, L, dCp, nao, R, q0, nq, f.nsplit_c, q0 > 0, s));
+                                             tile));
+        JK_TRY(hipEventRecord(ev_x, s));         // X, Y of this chunk; D of the last done
+        JK_TRY(hipStreamWaitEvent(a, ev_x, 0));
+        JK_TRY(jk::launch_vjp_stage_b_one(1, V, Xw, Cc, omx, L, nao, nd, r, q0, nq * r, f.ldw, has_v,
+                                          has_w, a));
+        JK_TRY(hipEventRecord(ev_br, a));
+        JK_TRY(hipStreamWaitEvent(s, ev_aux, 0)); // C of the last chunk done with the blocks
+        JK_TRY(jk::launch_vjp_stage_b_one(0, V, Yw, Cc, omx, L, nao, nd, r, q0, nq * r, f.ldw, has_v,
+                                          has_w, s));
+        JK_TRY(hipStreamWaitEvent(s, ev_br, 0));
+        JK_TRY(hipEventRecord(ev_b, s));
+        if (want_dc) {
+            JK_TRY(hipStreamWaitEvent(a, ev_b, 0));
+            JK_TRY(jk::launch_vjp_stage_c(B, L, dCp, nao, R, q0, nq, f.nsplit_c, q0 > 0, a));
+        }
+        JK_TRY(hipEventRecord(ev_aux, a));
         if (want_db) {
             JK_TRY(jk::launch_vjp_stage_d(L, dB, nao, R, q0, nq, s));
             if (has_w)
                 JK_TRY(jk::launch_vjp_db_affine(g, om, W, E, dB, nd, naux, npos, q0, nq, s));
         }
     }
+    JK_TRY(hipStreamWaitEvent(s, ev_aux, 0));
     if (want_dc)
         JK_TRY(jk::launch_vjp_dc_finish(dCp, dCL, dCR, nao, nd, r, f.nsplit_c, s));
     return JK_OK;

@@ -71,6 +71,10 @@ hipError_t launch_omega_expand(const double *om, double *omx, int naux, int nd, 
                                hipStream_t s);
 hipError_t launch_vjp_fill_blocks(const double *Cc, double *L, int nao, int R, int nslot,
                                   hipStream_t s);
+// One of the two stage-B products: which = 0 gives P' (Zw = Y_ws), 1 gives R' (Zw = X_ws).
+hipError_t launch_vjp_stage_b_one(int which, const double *V, const double *Zw, const double *Cc,
+                                  const double *omx, double *L, int nao, int nd, int r, int q0,
+                                  int nj, int ldw, int has_v, int has_w, hipStream_t s);
 hipError_t launch_vjp_stage_b(const double *V, const double *Xw, const double *Yw,
                               const double *Cc, const double *omx, double *L, int nao, int nd,
                               int r, int q0, int nj, int ldw, int has_v, int has_w, hipStream_t s);

@@ -319,6 +319,29 @@ hipError_t launch_vjp_fill_blocks(const double *Cc, double *L, int nao, int R, i
     return hipGetLastError();
 }
 
+hipError_t launch_vjp_stage_b_one(int which, const double *V, const double *Zw, const double *Cc,
+                                  const double *omx, double *L, int nao, int nd, int r, int q0,
+                                  int nj, int ldw, int has_v, int has_w, hipStream_t s)
+{
+    const int nmt = cdiv(nao, kTM), njt = cdiv(nj, kTN);
+    dim3 grid(nd * nmt * njt);
+    const int lds = (int)sizeof(double) * TileV::LDS_DOUBLES;
+    const void *fn = which ? (const void *)k_vjp_stage_b<1> : (const void *)k_vjp_stage_b<0>;
+    hipError_t e = set_dynamic_lds(fn, lds);
+    if (e != hipSuccess)
+        return e;
+    if (which) {
+        ProfScope ps_("vjp_stage_b_r", s);
+        hipLaunchKernelGGL(k_vjp_stage_b<1>, grid, dim3(TileV::NTHR), lds, s, V, Zw, Cc, omx, L, nao, nd,
+                           r, q0, nj, ldw, has_v, has_w);
+    } else {
+        ProfScope ps_("vjp_stage_b_p", s);
+        hipLaunchKernelGGL(k_vjp_stage_b<0>, grid, dim3(TileV::NTHR), lds, s, V, Zw, Cc, omx, L, nao, nd,
+                           r, q0, nj, ldw, has_v, has_w);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_vjp_stage_b(const double *V, const double *Xw, const double *Yw,
                               const double *Cc, const double *omx, double *L, int nao, int nd,
                               int r, int q0, int nj, int ldw, int has_v, int has_w, hipStream_t s)

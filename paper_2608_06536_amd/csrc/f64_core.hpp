@@ -356,12 +356,14 @@ __device__ __forceinline__ void tile_foreach(const Acc<TL> &acc, int m0, int n0,
 
 // Workgroup index remapped so that consecutive logical tiles land on the same
 // XCD (the hardware deals workgroups round-robin over the 8 XCDs, each with
-// its own L2): logical = xcd * (n/8) + hw/8 when n is a multiple of 8.
+// its own L2): over the first 8 (n / 8) indices, logical = xcd * (n / 8) +
+// hw / 8; the last n % 8 keep their index.
 __device__ __forceinline__ int xcd_swizzle(int hw, int n)
 {
-    if (n % 8 != 0)
+    const int q = n >> 3;
+    if (hw >= 8 * q)
         return hw;
-    return (hw & 7) * (n >> 3) + (hw >> 3);
+    return (hw & 7) * q + (hw >> 3);
 }
 
 } // namespace jk

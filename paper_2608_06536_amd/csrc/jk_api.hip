@@ -431,7 +431,7 @@ jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const
         const int nq = (naux - q0) < f.qc ? (naux - q0) : f.qc;
         if (has_v)
             JK_TRY(jk::launch_half_transform(B, Cc, Xw, Yw, nao, nd, r, q0, nq, f.ldw, s, -1, 0,
-                                             tile));
+                                             tile, "vjp_half_transform"));
         JK_TRY(hipEventRecord(ev_x, s));         // X, Y of this chunk; D of the last done
         JK_TRY(hipStreamWaitEvent(a, ev_x, 0));
         JK_TRY(jk::launch_vjp_stage_b_one(1, V, Xw, Cc, omx, L, nao, nd, r, q0, nq * r, f.ldw, has_v,

@@ -354,7 +354,7 @@ hipError_t set_dynamic_lds(const void *fn, int bytes)
 
 hipError_t launch_half_transform(const double *B, const double *Cc, double *Xw, double *Yw,
                                  int nao, int nd, int r, int q0, int nq, int ldw, hipStream_t s,
-                                 int ncol, int packed, int tile)
+                                 int ncol, int packed, int tile, const char *prof)
 {
     if (ncol < 0)
         ncol = 2 * nd * r;
@@ -370,7 +370,7 @@ hipError_t launch_half_transform(const double *B, const double *Cc, double *Xw, 
         hipError_t e = set_dynamic_lds(fn, lds);
         if (e != hipSuccess)
             return e;
-        ProfScope ps_("half_transform", s);
+        ProfScope ps_(prof, s);
         if (tile == 3)
             hipLaunchKernelGGL(k_half_transform16a, dim3(ht_flat_tiles<TileH16a>(nao, ncol, nq)),
                                dim3(256), lds, s, B, Cc, Xw, Yw, nao, nd, r, q0, nq, ldw, ncol);
@@ -378,15 +378,15 @@ hipError_t launch_half_transform(const double *B, const double *Cc, double *Xw, 
             hipLaunchKernelGGL(k_half_transform16, dim3(ht_flat_tiles<TileH16c>(nao, ncol, nq)),
                                dim3(256), lds, s, B, Cc, Xw, Yw, nao, nd, r, q0, nq, ldw, ncol);
     } else if (tile == 2) {
-        ProfScope ps_("half_transform", s);
+        ProfScope ps_(prof, s);
         hipLaunchKernelGGL(k_half_transform_w8, dim3(ht_tiles_cols(nao, ncol, nq)), dim3(512), 0, s, B,
                            Cc, Xw, Yw, nao, nd, r, q0, nq, ldw, ncol);
     } else if (tile == 1) {
-        ProfScope ps_("half_transform", s);
+        ProfScope ps_(prof, s);
         hipLaunchKernelGGL(k_half_transform64, dim3(nq * cdiv(nao, 64) * cdiv(ncol, 64)), dim3(256), 0,
                            s, B, Cc, Xw, Yw, nao, nd, r, q0, nq, ldw, ncol);
     } else {
-        ProfScope ps_("half_transform", s);
+        ProfScope ps_(prof, s);
         hipLaunchKernelGGL(k_half_transform, dim3(ht_tiles_cols(nao, ncol, nq)), dim3(256), 0, s, B, Cc,
                            Xw, Yw, nao, nd, r, q0, nq, ldw, ncol);
     }

@@ -46,11 +46,14 @@ hipError_t launch_project(const double *B, const double *A, double *part, double
 hipError_t launch_coulomb(const double *B, const double *g, double *J, int naux, int nd,
                           int64_t npos, hipStream_t s, double scale = 1.0, int accumulate = 0);
 // packed: B holds packed upper-triangle slabs (nao (nao + 1) / 2 doubles).
-// tile: 0 = 128 x 64 workgroup tiles of four waves, 1 = 64 x 64, 2 = 128 x 64
-// of eight waves (full slabs only).
+// tile (full slabs only; jk_tune.h): 0 = 128 x 64 workgroup tiles of four
+// waves, 1 = 64 x 64, 2 = 128 x 64 of eight waves (4x4x4 engine); 3 = 128 x 128,
+// 4 = 128 x 64 over stacked slabs (16x16x4 engine).  prof: the name the
+// launch is timed under.
 hipError_t launch_half_transform(const double *B, const double *Cc, double *Xw, double *Yw,
                                  int nao, int nd, int r, int q0, int nq, int ldw, hipStream_t s,
-                                 int ncol = -1, int packed = 0, int tile = 0);
+                                 int ncol = -1, int packed = 0, int tile = 0,
+                                 const char *prof = "half_transform");
 // S_k = D_k + D_k^T off the diagonal, D_k on it, as packed upper triangles.
 hipError_t launch_sym_pack(const double *D, double *S, int nao, int nd, hipStream_t s);
 // out_k (+)= scale * P_k, P_k a packed symmetric matrix, written in full.

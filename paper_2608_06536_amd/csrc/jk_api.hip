@@ -86,6 +86,13 @@ int chunk_slabs(const jk_problem *p, size_t budget)
 {
     size_t per = 2 * (size_t)p->nao * (size_t)(p->ndens * p->rank) * sizeof(double);
     i64 qc = (i64)(budget / (per ? per : 1));
+    // a multiple of 16 / gcd(rank, 16) slabs, so that a full chunk's exchange
+    // depth qc * rank is a whole number of 16-deep stages (no masked stage)
+    i64 m = 16;
+    for (i64 g = p->rank; g % 2 == 0 && m > 1; g /= 2)
+        m /= 2;
+    if (qc >= m)
+        qc -= qc % m;
     if (qc < 1)
         qc = 1;
     if (qc > p->naux)

@@ -163,6 +163,7 @@ __global__ void __launch_bounds__(256) k_unpack_sym(const double *__restrict__ P
 // The exchange product on the 16 x 16 x 4 engine: the same 128 x 64 tiles,
 // four 64 x 32 wave tiles, three workgroups per CU (52 KB of dynamic LDS).
 typedef TileH16c TileEx16;
+template <bool MASK>
 __global__ void __launch_bounds__(256, 3) k_exchange16(const double *__restrict__ Xw,
                                                        const double *__restrict__ Yw,
                                                        double *__restrict__ Kp, int nao, int nd,
@@ -171,8 +172,8 @@ __global__ void __launch_bounds__(256, 3) k_exchange16(const double *__restrict_
 {
     extern __shared__ double lds_dyn[];
     const int n = nsplit * nd * (sym ? ex_tri_tiles(nao) : cdiv_i(nao, kExM) * cdiv_i(nao, kExN));
-    ex_tile<TileEx16>(Xw, Yw, Kp, nao, nd, nj, ldw, jlen, accumulate, xcd_swizzle(blockIdx.x, n),
-                      lds_dyn, sym, scale);
+    ex_tile<TileEx16, MASK>(Xw, Yw, Kp, nao, nd, nj, ldw, jlen, accumulate,
+                            xcd_swizzle(blockIdx.x, n), lds_dyn, sym, scale);
 }
 
 __global__ void __launch_bounds__(512, 4) k_exchange(const double *__restrict__ Xw,
@@ -442,13 +443,21 @@ hipError_t launch_exchange(const double *Xw, const double *Yw, double *Kp, int n
     jlen = ((jlen + 15) / 16) * 16;
     const int per = sym ? ex_tri_tiles(nao) : cdiv(nao, kExM) * cdiv(nao, kExN);
     if (buf_extent_ok((i64)nao * ldw)) {
+        // splits end on 16-deep stage boundaries (jlen is a multiple of 16), so
+        // only a depth nj off that grid leaves a stage to mask
+        const bool mask = nj % 16 != 0;
         const int lds = (int)sizeof(double) * TileEx16::LDS_DOUBLES;
-        hipError_t e = set_dynamic_lds((const void *)k_exchange16, lds);
+        hipError_t e = set_dynamic_lds(mask ? (const void *)k_exchange16<true>
+                                            : (const void *)k_exchange16<false>, lds);
         if (e != hipSuccess)
             return e;
         ProfScope ps_("exchange", s);
-        hipLaunchKernelGGL(k_exchange16, dim3(nsplit * nd * per), dim3(TileEx16::NTHR), lds, s, Xw,
-                           Yw, Kp, nao, nd, nj, ldw, nsplit, jlen, accumulate, sym, scale);
+        if (mask)
+            hipLaunchKernelGGL(k_exchange16<true>, dim3(nsplit * nd * per), dim3(TileEx16::NTHR), lds,
+                               s, Xw, Yw, Kp, nao, nd, nj, ldw, nsplit, jlen, accumulate, sym, scale);
+        else
+            hipLaunchKernelGGL(k_exchange16<false>, dim3(nsplit * nd * per), dim3(TileEx16::NTHR), lds,
+                               s, Xw, Yw, Kp, nao, nd, nj, ldw, nsplit, jlen, accumulate, sym, scale);
     } else {
         ProfScope ps_("exchange", s);
         hipLaunchKernelGGL(k_exchange, dim3(nsplit * nd * per), dim3(TileExch::NTHR), 0, s, Xw, Yw, Kp,

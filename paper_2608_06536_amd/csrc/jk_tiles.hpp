@@ -453,7 +453,7 @@ __device__ inline void ht_tile_flat(const double *__restrict__ B, const double *
 // With sym != 0 (Yw = Xw) only the tiles reaching n >= m are computed; the
 // rest of K is filled by mirroring afterwards.
 // Kp[split][k] (+)= scale * (the chunk's X Y^T over the split's inner range).
-template <class TL = TileExch>
+template <class TL = TileExch, bool MASK = true>
 __device__ inline void ex_tile(const double *__restrict__ Xw, const double *__restrict__ Yw,
                                double *__restrict__ Kp, int nao, int nd, int nj, int ldw, int jlen,
                                int accumulate, int tile, double *lds, int sym = 0,
@@ -482,13 +482,14 @@ __device__ inline void ex_tile(const double *__restrict__ Xw, const double *__re
         }
     };
     if constexpr (TL::kMfma16) {
-        // resources end at column j1 of the last row; inner indices past j1
-        // are masked in the last stage
+        // Resources end at column j1 of the last row.  MASK: inner indices
+        // past j1 are zeroed in the last stage (needed unless every split
+        // ends on a 16-deep stage boundary).
         BufKC a{Xw + (i64)k * nao * ldw, ldw, nao, j1};
         BufKC b{Yw + (i64)k * nao * ldw, ldw, nao, j1};
         Acc16<TL> acc;
         acc.zero();
-        tile_gemm16<TL>(a, b, mb * kExM, nb * kExN, j0, j1, lds, acc);
+        tile_gemm16<TL, MASK>(a, b, mb * kExM, nb * kExN, j0, j1, lds, acc);
         tile_foreach16(acc, mb * kExM, nb * kExN, out);
     } else {
         OpKC a{Xw + (i64)k * nao * ldw, ldw, nao, j1};

@@ -181,6 +181,7 @@ __global__ void __launch_bounds__(256) k_vjp_e_matrix(const double *__restrict__
 // ------------------------------------------------------------------ stage D
 // dB[q0+ql][a][b] = sum_{j<2R} L[ql][a][j] L[ql][b][2R + j].
 // grid.x = nq * nmt * nnt (XCD-swizzled).
+template <bool MASK>
 __global__ void __launch_bounds__(256, 3) k_vjp_stage_d(const double *__restrict__ L,
                                                         double *__restrict__ dB, int nao, int R,
                                                         int q0, int nq)
@@ -197,7 +198,7 @@ __global__ void __launch_bounds__(256, 3) k_vjp_stage_d(const double *__restrict
     BufKC b{Lq + R2, R4, nao, R2};
     Acc16<TL> acc;
     acc.zero();
-    tile_gemm16<TL>(a, b, ab * kTM, bb * kTN, 0, R2, lds, acc);
+    tile_gemm16<TL, MASK>(a, b, ab * kTM, bb * kTN, 0, R2, lds, acc);
     const i64 n2 = (i64)nao * nao;
     double *out = dB + (i64)(q0 + ql) * n2;
     tile_foreach16(acc, ab * kTM, bb * kTN, [&](int ia, int ib, double v) {
@@ -419,13 +420,18 @@ hipError_t launch_vjp_stage_d(const double *L, double *dB, int nao, int R, int q
                               hipStream_t s)
 {
     const int lds = (int)sizeof(double) * TileV::LDS_DOUBLES;
-    hipError_t e = set_dynamic_lds((const void *)k_vjp_stage_d, lds);
+    const bool mask = (2 * R) % TileV::BK != 0;      // a depth of whole stages needs no mask
+    hipError_t e = set_dynamic_lds(mask ? (const void *)k_vjp_stage_d<true>
+                                        : (const void *)k_vjp_stage_d<false>, lds);
     if (e != hipSuccess)
         return e;
     {
         ProfScope ps_("vjp_stage_d", s);
-        hipLaunchKernelGGL(k_vjp_stage_d, dim3(nq * cdiv(nao, kTM) * cdiv(nao, kTN)), dim3(TileV::NTHR),
-                           lds, s, L, dB, nao, R, q0, nq);
+        const dim3 g(nq * cdiv(nao, kTM) * cdiv(nao, kTN));
+        if (mask)
+            hipLaunchKernelGGL(k_vjp_stage_d<true>, g, dim3(TileV::NTHR), lds, s, L, dB, nao, R, q0, nq);
+        else
+            hipLaunchKernelGGL(k_vjp_stage_d<false>, g, dim3(TileV::NTHR), lds, s, L, dB, nao, R, q0, nq);
     }
     return hipGetLastError();
 }

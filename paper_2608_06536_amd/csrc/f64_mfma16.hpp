@@ -156,12 +156,13 @@ struct BufLoader {
         }
     }
 
-    // Writes the stage into LDS; with MASK, elements at local inner index
-    // kleft or beyond (possible in a tile's last stage only) are zeroed.
+    // Writes the stage into LDS.  With MASK, elements at local inner index
+    // kleft or beyond (possible in a tile's last stage only) are then
+    // overwritten with zero by the thread that wrote them, in a branch taken
+    // only by such a stage, so the other stages carry no selects.
     template <bool MASK>
     __device__ __forceinline__ void store(double *lds, int tid, int kleft) const
     {
-        const bool tail = MASK && kleft < BK;
 #pragma unroll
         for (int s = 0; s < NS; s++) {
             int li, lk;
@@ -169,10 +170,20 @@ struct BufLoader {
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 const int i = Op::kContig ? li : li + e, k = Op::kContig ? lk + e : lk;
-                double v = raw[s][e];
-                if (tail && k >= kleft)
-                    v = 0.0;
-                lds[frag_slot<NSUB>(i, k)] = v;
+                lds[frag_slot<NSUB>(i, k)] = raw[s][e];
+            }
+        }
+        if (MASK && kleft < BK) {
+#pragma unroll
+            for (int s = 0; s < NS; s++) {
+                int li, lk;
+                local(tid + s * NTHR, li, lk);
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int i = Op::kContig ? li : li + e, k = Op::kContig ? lk + e : lk;
+                    if (k >= kleft)
+                        lds[frag_slot<NSUB>(i, k)] = 0.0;
+                }
             }
         }
     }

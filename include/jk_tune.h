@@ -16,7 +16,8 @@
  * table, results are bit-identical run to run.  A tile-shape choice alone
  * leaves the results bit-identical; a chunk choice changes the summation
  * order of K (and the half-transforms' inner products are unchanged).
- * Workspace: every candidate fits the workspace jk_workspace_bytes reports.
+ * Workspace: every candidate fits the workspace jk_workspace_bytes reports
+ * (chunks up to 4 GiB; the derivative's chunks take 4 GiB as well).
  */
 #ifndef JK_GFX950_TUNE_H
 #define JK_GFX950_TUNE_H
@@ -28,11 +29,13 @@ extern "C" {
 #endif
 
 typedef struct {
-    int32_t ht_tile;    /* FP64 half-transform tile: 0 = 128 x 64 of four 64 x 32 wave
-                           tiles (three waves per SIMD), 1 = 64 x 64 (four), 2 = 128 x 64 of
-                           eight 64 x 16 wave tiles (four waves per SIMD); packed B and
-                           JK_MIXED use their own kernels; jk_build_batched runs 2 as 0 */
-    int32_t chunk_mb;   /* Q-chunk budget in MiB, 64 .. 1024 (jk_build_batched caps its
+    int32_t ht_tile;    /* FP64 half-transform tile.  On the 4x4x4 matrix instruction:
+                           0 = 128 x 64 of four 64 x 32 wave tiles, 1 = 64 x 64, 2 = 128 x 64
+                           of eight 64 x 16 wave tiles.  On the 16x16x4 instruction, over
+                           the chunk's slabs stacked as one matrix: 3 = 128 x 128, 4 =
+                           128 x 64.  Packed B and JK_MIXED use their own kernels;
+                           jk_build_batched runs 2 as 0 and 3 as 4 */
+    int32_t chunk_mb;   /* Q-chunk budget in MiB, 64 .. 4096 (jk_build_batched caps its
                            members at 256)                                             */
 } jk_tuning;
 
@@ -47,8 +50,7 @@ jk_status jk_autotune(const jk_problem *p, const double *B, const double *CL, co
                       int32_t reps, jk_tuning *chosen);
 
 /* The plan jk_build would use for *p: the recorded one, or the default
- * {nao <= 384 ? 1 : 2, 1024} (the measured best tile by size).  Returns
- * JK_EINVAL for an invalid problem. */
+ * {4, 1024}.  Returns JK_EINVAL for an invalid problem. */
 jk_status jk_tuning_get(const jk_problem *p, jk_tuning *t);
 
 /* Records *t for p's shape class (JK_EINVAL if a field is out of range). */

@@ -33,7 +33,7 @@ constexpr size_t kChunkBudgetBatched = (size_t)256 << 20;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 // Chunk budgets a plan may use (jk_tune.h); workspace sizes cover all.
-constexpr int kChunkChoicesMb[] = {64, 128, 256, 512, 1024};
+constexpr int kChunkChoicesMb[] = {64, 128, 256, 512, 1024, 2048, 4096};
 
 // The plan choices of the current build: the recorded ones, or those being
 // timed by jk_autotune on this thread.
@@ -137,11 +137,13 @@ FwdPlan plan_forward(const jk_problem *p, size_t budget = kChunkBudget)
 }
 
 // Slabs per chunk of the derivative: X, Y and the slab blocks [C_R|P'|R'|C_L]
-// of one chunk in the budget.
+// of one chunk in the budget (4 GB: fewer, larger launches, so that each
+// launch's last partial round of workgroups is a smaller share of it).
+constexpr size_t kChunkBudgetVjp = (size_t)4 << 30;
 int chunk_slabs_vjp(const jk_problem *p)
 {
     size_t per = 6 * (size_t)p->nao * (size_t)(p->ndens * p->rank) * sizeof(double);
-    i64 qc = (i64)(kChunkBudget / (per ? per : 1));
+    i64 qc = (i64)(kChunkBudgetVjp / (per ? per : 1));
     if (qc < 1)
         qc = 1;
     if (qc > p->naux)
@@ -1124,7 +1126,7 @@ static jk_status jk_autotune_impl(const jk_problem *p, const double *B, const do
     if (p->precision == JK_FP64 && !packed_b(p))
         tiles = {4, 3, 2};
     for (int tile : tiles)
-        for (int mb : {128, 256, 512, 1024})
+        for (int mb : {128, 256, 512, 1024, 2048, 4096})
             cand.push_back(jk_tuning{tile, mb});
     TimedEvents E;
     JK_TRY(E.create());

@@ -31,7 +31,7 @@ Key key_of(const jk_problem *p)
 
 bool valid_tuning(const jk_tuning &t)
 {
-    return t.ht_tile >= 0 && t.ht_tile <= 4 && t.chunk_mb >= 64 && t.chunk_mb <= 1024;
+    return t.ht_tile >= 0 && t.ht_tile <= 4 && t.chunk_mb >= 64 && t.chunk_mb <= 4096;
 }
 
 // Minimal reader for the flat JSON this file writes: objects of integer

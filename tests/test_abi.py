@@ -213,7 +213,7 @@ def test_tuning_load_rejects(bad):
 def test_tuning_validation():
     L = _lib.lib()
     p = _prob()
-    for t in [(5, 256), (0, 63), (0, 1025), (-1, 256)]:
+    for t in [(5, 256), (0, 63), (0, 4097), (-1, 256)]:
         tt = _lib.Tuning(*t)
         assert L.jk_tuning_set(ctypes.byref(p), ctypes.byref(tt)) == _lib.JK_EINVAL
     tt = _lib.Tuning(0, 256)

@@ -139,7 +139,7 @@ struct BufLoader {
 
     // Loads the stage at inner index kk (from the tile's first) of segment
     // seg, segments seg_bytes apart.
-    __device__ __forceinline__ void load(const Op &op, int seg, int kk, i64 seg_bytes)
+    __device__ __forceinline__ void load(const Op &op, int seg, int kk, i64 seg_bytes, int = 0)
     {
         const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
             (void *)(base + seg * seg_bytes), (short)0, nbytes, 0x00020000);
@@ -189,6 +189,151 @@ struct BufLoader {
     }
 };
 
+// A symmetric nao x nao slab stored as its upper triangle, row by row:
+// element (a, b), a <= b, at p[a (2 nao - a + 1) / 2 + b - a].  As an
+// operand: element (i, k), i the row of A, k the inner index.
+struct BufPackedSym {
+    const double *p;
+    int nao;
+    __device__ __forceinline__ i64 extent() const { return (i64)nao * (nao + 1) / 2 * 8; }
+};
+__device__ __forceinline__ int pk_row16(int a, int nao) { return (int)((i64)a * (2 * nao - a + 1) / 2); }
+
+// Loader of a packed symmetric operand.  Each stage takes one of three
+// forms, the same for every thread (it depends on the tile's rows and the
+// stage's inner range only):
+//   above the diagonal (k >= i throughout): row i of the packed storage is
+//     contiguous in k; groups of 4 consecutive k, offsets fixed per tile plus
+//     a scalar advance;
+//   below it (k <= i throughout): element (i, k) = (k, i) is packed row k,
+//     contiguous in i; groups of 4 consecutive i, one row offset per group;
+//   on the diagonal: each element's own offset.
+// Indices are clamped to the slab.  Inner indices past nao read data of the
+// next packed row (finite) or zero past the slab; the caller's other operand
+// must read zero there (no mask).
+template <int T, int BK, int NTHR>
+struct PackedLoader16 {
+    static constexpr int NGRP = T * BK / 4, NS = NGRP / NTHR, NSUB = BK / 4;
+    static_assert(NGRP % NTHR == 0, "packed loader");
+    const char *base;
+    int nbytes, nao, i0, kb;
+    int mode, k0;          // of the stage held in raw: 0 above, 1 below, 2 diagonal
+    unsigned rowoff[NS];   // above: byte offset of (row, inner 0) for group s, kContig mapping
+    double raw[NS][4];
+
+    __device__ __forceinline__ static void local_k(int g, int &li, int &lk)
+    {
+        li = g / (BK / 4);
+        lk = (g % (BK / 4)) * 4;
+    }
+    __device__ __forceinline__ static void local_i(int g, int &li, int &lk)
+    {
+        lk = g / (T / 4);
+        li = (g % (T / 4)) * 4;
+    }
+
+    __device__ __forceinline__ void init(const BufPackedSym &op, int i0_, int kb_, int tid)
+    {
+        base = (const char *)op.p;
+        nbytes = (int)op.extent();
+        nao = op.nao;
+        i0 = i0_;
+        kb = kb_;
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            int li, lk;
+            local_k(tid + s * NTHR, li, lk);
+            int i = i0 + li;
+            i = i < nao ? i : nao - 1;
+            rowoff[s] = (unsigned)(((i64)pk_row16(i, nao) - i + kb + lk) * 8);
+        }
+    }
+
+    __device__ __forceinline__ void load(const BufPackedSym &, int, int kk, i64, int tid)
+    {
+        const __amdgpu_buffer_rsrc_t rsrc =
+            __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, nbytes, 0x00020000);
+        k0 = kb + kk;
+        mode = (k0 >= i0 + T - 1) ? 0 : (k0 + BK - 1 <= i0) ? 1 : 2;
+        if (mode == 0) {
+            const unsigned soff = (unsigned)kk * 8;
+#pragma unroll
+            for (int s = 0; s < NS; s++) {
+                const u4v lo = __builtin_amdgcn_raw_buffer_load_b128(rsrc, rowoff[s], soff, 0);
+                const u4v hi = __builtin_amdgcn_raw_buffer_load_b128(rsrc, rowoff[s] + 16, soff, 0);
+                const double2 a = __builtin_bit_cast(double2, lo), b = __builtin_bit_cast(double2, hi);
+                raw[s][0] = a.x;
+                raw[s][1] = a.y;
+                raw[s][2] = b.x;
+                raw[s][3] = b.y;
+            }
+        } else if (mode == 1) {
+#pragma unroll
+            for (int s = 0; s < NS; s++) {
+                int li, lk;
+                local_i(tid + s * NTHR, li, lk);
+                const int k = k0 + lk;                       // < nao below the diagonal
+                const unsigned off = (unsigned)(((i64)pk_row16(k, nao) - k + i0 + li) * 8);
+                const u4v lo = __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, 0);
+                const u4v hi = __builtin_amdgcn_raw_buffer_load_b128(rsrc, off + 16, 0, 0);
+                const double2 a = __builtin_bit_cast(double2, lo), b = __builtin_bit_cast(double2, hi);
+                raw[s][0] = a.x;
+                raw[s][1] = a.y;
+                raw[s][2] = b.x;
+                raw[s][3] = b.y;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < NS; s++) {
+                int li, lk;
+                local_k(tid + s * NTHR, li, lk);
+                int i = i0 + li;
+                i = i < nao ? i : nao - 1;
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    int k = k0 + lk + e;
+                    k = k < nao ? k : nao - 1;
+                    const int a = i < k ? i : k, b = i < k ? k : i;
+                    const unsigned off = (unsigned)(((i64)pk_row16(a, nao) + b - a) * 8);
+                    raw[s][e] = __builtin_bit_cast(
+                        double, __builtin_amdgcn_raw_buffer_load_b64(rsrc, off, 0, 0));
+                }
+            }
+        }
+    }
+
+    template <bool MASK>
+    __device__ __forceinline__ void store(double *lds, int tid, int) const
+    {
+        static_assert(!MASK, "a packed operand is used unmasked");
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            int li, lk;
+            if (mode == 1) {
+                local_i(tid + s * NTHR, li, lk);
+#pragma unroll
+                for (int e = 0; e < 4; e++)
+                    lds[frag_slot<NSUB>(li + e, lk)] = raw[s][e];
+            } else {
+                local_k(tid + s * NTHR, li, lk);
+#pragma unroll
+                for (int e = 0; e < 4; e++)
+                    lds[frag_slot<NSUB>(li, lk + e)] = raw[s][e];
+            }
+        }
+    }
+};
+
+// The loader of each operand type.
+template <int T, int BK, int NTHR, class Op>
+struct LoaderOf {
+    typedef BufLoader<T, BK, NTHR, Op> type;
+};
+template <int T, int BK, int NTHR>
+struct LoaderOf<T, BK, NTHR, BufPackedSym> {
+    typedef PackedLoader16<T, BK, NTHR> type;
+};
+
 // acc += sum over segments g < nseg of sum over k in [k_begin, k_begin +
 // kdepth) of A_g(m0 + i, k) * B_g(n0 + j, k), where A_g is A with its base
 // moved by g segA elements (B_g likewise).  The stages of all segments form
@@ -203,8 +348,8 @@ struct BufLoader {
 template <class TL, class OA, class OB, bool MASK>
 struct Gemm16 {
     static constexpr int BK = TL::BK, NSUB = TL::NSUB;
-    typedef BufLoader<TL::BM, BK, TL::NTHR, OA> LA;
-    typedef BufLoader<TL::BN, BK, TL::NTHR, OB> LB;
+    typedef typename LoaderOf<TL::BM, BK, TL::NTHR, OA>::type LA;
+    typedef typename LoaderOf<TL::BN, BK, TL::NTHR, OB>::type LB;
 
     struct Seq {             // stage kt -> (segment, inner offset)
         int nks, kdepth;
@@ -250,8 +395,8 @@ struct Gemm16 {
         if (kt + 2 < nk) {
             int g, kk;
             q.at(kt + 2, g, kk);
-            la_n.load(A, g, kk, q.sega);
-            lb_n.load(B, g, kk, q.segb);
+            la_n.load(A, g, kk, q.sega, tid);
+            lb_n.load(B, g, kk, q.segb, tid);
         }
         if (kt + 1 < nk) {
             int g, kk;
@@ -285,13 +430,13 @@ struct Gemm16 {
         lb0.init(B, n0, k_begin, tid);
         la1 = la0;
         lb1 = lb0;
-        la0.load(A, 0, 0, q.sega);
-        lb0.load(B, 0, 0, q.segb);
+        la0.load(A, 0, 0, q.sega, tid);
+        lb0.load(B, 0, 0, q.segb, tid);
         if (nk > 1) {
             int g, kk;
             q.at(1, g, kk);
-            la1.load(A, g, kk, q.sega);
-            lb1.load(B, g, kk, q.segb);
+            la1.load(A, g, kk, q.sega, tid);
+            lb1.load(B, g, kk, q.segb, tid);
         }
         la0.template store<MASK>(lds, tid, kdepth);
         lb0.template store<MASK>(lds + TL::A_DOUBLES, tid, kdepth);

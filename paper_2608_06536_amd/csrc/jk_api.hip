@@ -365,7 +365,7 @@ jk_status build_fp64(const jk_problem *p, const double *B, const KSeg *seg, int 
                 int nq = (sg.naux - q0) < f.qc ? (sg.naux - q0) : f.qc;
                 JK_TRY(jk::launch_half_transform(sg.B, Cc, Xw, Yw, nao, nd, r, q0, nq, f.ldw, s,
                                                  sym ? nd * r : 2 * nd * r, f.packed ? 1 : 0,
-                                                 f.packed ? 0 : tu.ht_tile));
+                                                 tu.ht_tile));
                 JK_TRY(jk::launch_exchange(Xw, Yx, Kp, nao, nd, nq * r, f.ldw, ns, !first, s, sym,
                                            sg.scale));
                 first = false;

@@ -121,6 +121,21 @@ __global__ void __launch_bounds__(256, 3) k_half_transform16(const double *__res
                            lds_dyn, ncol);
 }
 
+// Packed slabs on the 16 x 16 x 4 engine (plan tiles 3 and 4): 128 x 64 tiles
+// per slab, three workgroups per CU.
+__global__ void __launch_bounds__(256, 3) k_half_transform16_packed(const double *__restrict__ B,
+                                                                    const double *__restrict__ Cc,
+                                                                    double *__restrict__ Xw,
+                                                                    double *__restrict__ Yw,
+                                                                    int nao, int nd, int r, int q0,
+                                                                    int nq, int ldw, int ncol)
+{
+    extern __shared__ double lds_dyn[];
+    const int n = nq * cdiv_i(nao, TileHalf16::BM) * cdiv_i(ncol, TileHalf16::BN);
+    ht_tile16_packed<TileHalf16>(B, Cc, Xw, Yw, nao, nd, r, q0, ldw, xcd_swizzle(blockIdx.x, n),
+                                 lds_dyn, ncol);
+}
+
 // The same on packed slabs (jk.h JK_B_PACKED).
 __global__ void __launch_bounds__(256, 3) k_half_transform_packed(const double *__restrict__ B,
                                                                   const double *__restrict__ Cc,
@@ -359,9 +374,20 @@ hipError_t launch_half_transform(const double *B, const double *Cc, double *Xw, 
 {
     if (ncol < 0)
         ncol = 2 * nd * r;
-    if (tile >= 3 && !buf_extent_ok((i64)nq * nao * nao))
+    // packed slabs: one buffer resource per slab
+    if (!packed && tile >= 3 && !buf_extent_ok((i64)nq * nao * nao))
         tile = 2;                                 // chunk beyond the buffer loads' 4 GiB reach
-    if (packed) {
+    if (packed && tile >= 3) {
+        const int lds = (int)sizeof(double) * TileHalf16::LDS_DOUBLES;
+        hipError_t e = set_dynamic_lds((const void *)k_half_transform16_packed, lds);
+        if (e != hipSuccess)
+            return e;
+        ProfScope ps_("half_transform_packed", s);
+        hipLaunchKernelGGL(k_half_transform16_packed,
+                           dim3(nq * cdiv(nao, TileHalf16::BM) * cdiv(ncol, TileHalf16::BN)),
+                           dim3(TileHalf16::NTHR), lds, s, B, Cc, Xw, Yw, nao, nd, r, q0, nq, ldw,
+                           ncol);
+    } else if (packed) {
         ProfScope ps_("half_transform_packed", s);
         hipLaunchKernelGGL(k_half_transform_packed, dim3(ht_tiles_cols(nao, ncol, nq)), dim3(256), 0,
                            s, B, Cc, Xw, Yw, nao, nd, r, q0, nq, ldw, ncol);

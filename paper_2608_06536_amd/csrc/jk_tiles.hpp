@@ -447,6 +447,37 @@ __device__ inline void ht_tile_flat(const double *__restrict__ B, const double *
         }
 }
 
+// The half-transform of packed slabs (jk.h JK_B_PACKED) on the 16 x 16 x 4
+// engine: tiles per slab, the packed operand read in the form each stage
+// allows (above, below or on the diagonal).  No inner-index mask: past row
+// nao - 1, Cc reads zero and the packed reads are finite data or zero.
+template <class TL>
+__device__ inline void ht_tile16_packed(const double *__restrict__ B, const double *__restrict__ Cc,
+                                        double *__restrict__ Xw, double *__restrict__ Yw, int nao,
+                                        int nd, int r, int q0, int ldw, int tile, double *lds,
+                                        int ncol)
+{
+    constexpr int BM = TL::BM, BN = TL::BN;
+    const int R = nd * r, R2 = 2 * R;
+    const int nc = ncol < 0 ? R2 : ncol;
+    const int nmt = cdiv_i(nao, BM), nct = cdiv_i(nc, BN);
+    const int ql = tile / (nmt * nct), rem = tile % (nmt * nct);
+    const int mb = rem / nct, cb = rem % nct;
+    BufPackedSym a{B + (i64)(q0 + ql) * pk_size(nao), nao};
+    BufIC b{Cc, R2, nc, nao};
+    Acc16<TL> acc;
+    acc.zero();
+    tile_gemm16<TL, false>(a, b, mb * BM, cb * BN, 0, nao, lds, acc);
+    tile_foreach16(acc, mb * BM, cb * BN, [&](int m, int c, double v) {
+        if (m < nao && c < nc) {
+            double *dst = c < R ? Xw : Yw;
+            const int cc = c < R ? c : c - R;
+            const int k = cc / r, i = cc - k * r;
+            dst[((i64)k * nao + m) * ldw + (i64)ql * r + i] = v;
+        }
+    });
+}
+
 // ------------------------------------------------------------------ exchange
 // Kp[s][k][m][n] (+)= sum_{j in split s} X_ws[k][m][j] Y_ws[k][n][j]; the
 // inner range [0, nj) is cut into nsplit contiguous pieces of jlen.

@@ -1182,6 +1182,10 @@ static jk_status jk_vjp_impl(const jk_problem *p, const double *B, const double 
         return JK_EWORKSPACE;
     if (p->precision != JK_FP64 || packed_b(p))
         return JK_EUNSUPPORTED;
+    // stages C and D read a slab's block [C_R | P' | R' | C_L] (nao x 4R) through one
+    // buffer resource, whose offsets stop at 4 GiB
+    if (!jk::buf_extent_ok(p->nao * 4 * p->ndens * p->rank))
+        return JK_EUNSUPPORTED;
     if (!dB && !dCL)
         return JK_OK;
     return vjp_fp64(p, B, CL, CR, Jbar, Kbar, dB, dCL, dCR, (char *)ws, (hipStream_t)stream);

@@ -101,7 +101,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(the sharded multi-GPU path is a design note, not part of this build)",
+              "(the library runs one process on one GPU; sharding over GPUs is not implemented)",
               file=sys.stderr)
         sys.exit(2)
 

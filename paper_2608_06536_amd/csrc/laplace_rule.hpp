@@ -14,7 +14,7 @@
 //      the error curve towards equal ripples;
 //   3. Remez exchange: Newton's method on eta(y_i) = (-1)^i E at the 2n + 1
 //      extrema, the extrema moved to those of the new curve, until level.
-// Every candidate is judged by its measured maximum error (a dense
+// Every candidate is ranked by its measured maximum error (a dense
 // logarithmic scan refined at each local extremum); the best one is kept.
 #pragma once
 

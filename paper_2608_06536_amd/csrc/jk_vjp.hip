@@ -85,8 +85,10 @@ __global__ void __launch_bounds__(256, 3) k_vjp_stage_b(const double *__restrict
     const int R = nd * r, R2 = 2 * R, R4 = 4 * R;
     const int nmt = (nao + kTM - 1) / kTM, njt = (nj + kTN - 1) / kTN;
     const int t = xcd_swizzle(blockIdx.x, nd * nmt * njt);
+    // row tiles fastest: the nmt tiles of a column block share its X/Y block,
+    // read once from HBM while V_k's row panels stay in L2
     const int k = t / (nmt * njt), rem = t % (nmt * njt);
-    const int mb = rem / njt, jb = rem % njt;
+    const int jb = rem / nmt, mb = rem % nmt;
     Acc16<TL> acc;
     acc.zero();
     if (has_v) {
@@ -100,15 +102,44 @@ __global__ void __launch_bounds__(256, 3) k_vjp_stage_b(const double *__restrict
             tile_gemm16<TL>(a, b, mb * kTM, jb * kTN, 0, nao, lds, acc);
         }
     }
-    tile_foreach16(acc, mb * kTM, jb * kTN, [&](int m, int j, double v) {
-        if (m < nao && j < nj) {
-            const int ql = j / r, i = j - ql * r;
-            const int c = k * r + i;
-            if (has_w)
-                v = fma(omx[(i64)(q0 + ql) * R + c], Cc[(i64)m * R2 + (WHICH == 0 ? R + c : c)], v);
-            L[((i64)ql * nao + m) * R4 + (WHICH == 0 ? R : R2) + c] = v;
+    // Output (m, j) goes to L at column block j: slot ql = j / r, column
+    // c = k r + j % r, element ((ql nao + m) 4R + part + c); the omega term
+    // adds omx[q0 + ql][c] * Cc[m][c or R + c].  A lane holds TL::NB columns
+    // and 4 TL::MA rows, decoded once each.
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
+    const int rb = mb * kTM + wr * TL::WM + (lane >> 4);
+    const int cb0 = jb * kTN + wc * TL::WN + (lane & 15);
+    i64 col_l[TL::NB];
+    int col_cc[TL::NB];
+    double col_om[TL::NB];
+    bool col_ok[TL::NB];
+#pragma unroll
+    for (int jj = 0; jj < TL::NB; jj++) {
+        const int j = cb0 + 16 * jj;
+        col_ok[jj] = j < nj;
+        const int ql = j / r, i = j - ql * r;
+        const int c = k * r + i;
+        col_l[jj] = (i64)ql * nao * R4 + (WHICH == 0 ? R : R2) + c;
+        col_cc[jj] = WHICH == 0 ? R + c : c;
+        col_om[jj] = (has_w && col_ok[jj]) ? omx[(i64)(q0 + ql) * R + c] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < TL::MA; i++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int m = rb + 16 * i + 4 * v;
+            if (m < nao) {
+#pragma unroll
+                for (int jj = 0; jj < TL::NB; jj++)
+                    if (col_ok[jj]) {
+                        double x = acc.c[i][jj][v];
+                        if (has_w)
+                            x = fma(col_om[jj], Cc[(i64)m * R2 + col_cc[jj]], x);
+                        L[col_l[jj] + (i64)m * R4] = x;
+                    }
+            }
         }
-    });
 }
 
 // ------------------------------------------------------------------ stage C

@@ -168,7 +168,7 @@ jk_status jk_build_batched(int32_t nprob, const jk_problem *p,
  * half-transforms are recomputed, not stored.  dB may be NULL (not computed);
  * dCL and dCR are both NULL (not computed) or both non-NULL (else
  * JK_EINVAL).  Only JK_FP64 with full slabs is supported, and one slab's
- * block of factor columns must stay below 4 GiB: 32 nao ndens rank < 2^32
+ * block of factor columns must stay below 4 GiB: 16 nao ndens rank < 2^32
  * bytes (else JK_EUNSUPPORTED). */
 jk_status jk_vjp(const jk_problem *p, const double *B, const double *CL,
                  const double *CR, const double *Jbar, const double *Kbar,

@@ -136,13 +136,13 @@ FwdPlan plan_forward(const jk_problem *p, size_t budget = kChunkBudget)
     return f;
 }
 
-// Slabs per chunk of the derivative: X, Y and the slab blocks [C_R|P'|R'|C_L]
-// of one chunk in the budget (4 GB: fewer, larger launches, so that each
+// Slabs per chunk of the derivative: X, Y and the slab blocks [P' | R'] of one
+// chunk in the budget (4 GB: fewer, larger launches, so that each
 // launch's last partial round of workgroups is a smaller share of it).
 constexpr size_t kChunkBudgetVjp = (size_t)4 << 30;
 int chunk_slabs_vjp(const jk_problem *p)
 {
-    size_t per = 6 * (size_t)p->nao * (size_t)(p->ndens * p->rank) * sizeof(double);
+    size_t per = 4 * (size_t)p->nao * (size_t)(p->ndens * p->rank) * sizeof(double);
     i64 qc = (i64)(kChunkBudgetVjp / (per ? per : 1));
     if (qc < 1)
         qc = 1;
@@ -176,7 +176,7 @@ VjpPlan plan_vjp(const jk_problem *p)
     f.o_omx = c.take(sizeof(double) * naux * R);
     f.o_x = c.take(sizeof(double) * nd * nao * (size_t)f.ldw);
     f.o_y = c.take(sizeof(double) * nd * nao * (size_t)f.ldw);
-    f.o_pr = c.take(sizeof(double) * (size_t)f.qc * nao * 4 * R);
+    f.o_pr = c.take(sizeof(double) * (size_t)f.qc * nao * 2 * R);
     f.o_dcp = c.take(sizeof(double) * (size_t)f.nsplit_c * nao * 2 * R);
     f.total = c.off;
     return f;
@@ -420,8 +420,6 @@ jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const
             JK_TRY(jk::launch_vjp_e_matrix(D, E, nao, nd, s));
         }
     }
-    if (want_db)
-        JK_TRY(jk::launch_vjp_fill_blocks(Cc, L, nao, R, f.qc, s));
     // Two streams, so that one launch's last partial round of workgroups
     // overlaps another launch:
     //   main: HT(c), B[P'](c), D(c), affine(c)
@@ -457,7 +455,7 @@ jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const
         }
         JK_TRY(hipEventRecord(ev_aux, a));
         if (want_db) {
-            JK_TRY(jk::launch_vjp_stage_d(L, dB, nao, R, q0, nq, s));
+            JK_TRY(jk::launch_vjp_stage_d(L, Cc, dB, nao, R, q0, nq, s));
             if (has_w)
                 JK_TRY(jk::launch_vjp_db_affine(g, om, W, E, dB, nd, naux, npos, q0, nq, s));
         }
@@ -1182,9 +1180,9 @@ static jk_status jk_vjp_impl(const jk_problem *p, const double *B, const double 
         return JK_EWORKSPACE;
     if (p->precision != JK_FP64 || packed_b(p))
         return JK_EUNSUPPORTED;
-    // stages C and D read a slab's block [C_R | P' | R' | C_L] (nao x 4R) through one
-    // buffer resource, whose offsets stop at 4 GiB
-    if (!jk::buf_extent_ok(p->nao * 4 * p->ndens * p->rank))
+    // stages C and D read a slab's block [P' | R'] (nao x 2R) through one buffer
+    // resource, whose offsets stop at 4 GiB
+    if (!jk::buf_extent_ok(p->nao * 2 * p->ndens * p->rank))
         return JK_EUNSUPPORTED;
     if (!dB && !dCL)
         return JK_OK;

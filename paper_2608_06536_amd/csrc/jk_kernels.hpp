@@ -72,8 +72,6 @@ hipError_t launch_sum_splits(const double *part, double *out, i64 n, int nsplit,
 // derivative (jk_vjp.hip)
 hipError_t launch_omega_expand(const double *om, double *omx, int naux, int nd, int r,
                                hipStream_t s);
-hipError_t launch_vjp_fill_blocks(const double *Cc, double *L, int nao, int R, int nslot,
-                                  hipStream_t s);
 // One of the two stage-B products: which = 0 gives P' (Zw = Y_ws), 1 gives R' (Zw = X_ws).
 hipError_t launch_vjp_stage_b_one(int which, const double *V, const double *Zw, const double *Cc,
                                   const double *omx, double *L, int nao, int nd, int r, int q0,
@@ -87,8 +85,8 @@ hipError_t launch_vjp_stage_c(const double *B, const double *L, double *dCp, int
 hipError_t launch_vjp_dc_finish(const double *dCp, double *dCL, double *dCR, int nao, int nd,
                                 int r, int nsplit, hipStream_t s);
 hipError_t launch_vjp_e_matrix(const double *D, double *E, int nao, int nd, hipStream_t s);
-hipError_t launch_vjp_stage_d(const double *L, double *dB, int nao, int R, int q0, int nq,
-                              hipStream_t s);
+hipError_t launch_vjp_stage_d(const double *L, const double *Cc, double *dB, int nao, int R,
+                              int q0, int nq, hipStream_t s);
 hipError_t launch_vjp_db_affine(const double *gam, const double *om, const double *W,
                                 const double *E, double *dB, int nd, int naux, i64 npos, int q0,
                                 int nq, hipStream_t s);

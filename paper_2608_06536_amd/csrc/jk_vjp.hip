@@ -17,11 +17,10 @@
 //
 // Layouts: X/Y come from the half-transform kernel as X_ws[k][m][ql*r + i].
 // Each slab slot ql of the chunk owns one row-major block
-//     L[ql][m][0:4R] = [ C_R | P' | R' | C_L ]      (column c = k*r + i per part)
-// whose constant parts are written once per call.  Stage C reads the middle
-// half [P' | R'] and stage D is one product of the first half with the last:
-//     sum_{j<2R} L[a][j] L[b][2R + j] = C_R R'^T + P' C_L^T.
-// Cc[n][c] is [C_L | C_R] with c < 2R; omx[Q][c] = omega_{c / r, Q}, c < R.
+//     L[ql][m][0:2R] = [ P' | R' ]      (column c = k*r + i per part)
+// Stage C reads it whole; stage D is two products, C_R R'^T then P' C_L^T,
+// with C_L and C_R read from Cc.  Cc[n][c] is [C_L | C_R] with c < 2R;
+// omx[Q][c] = omega_{c / r, Q}, c < R.
 #include "f64_core.hpp"
 #include "f64_mfma16.hpp"
 #include "jk_kernels.hpp"
@@ -48,27 +47,9 @@ __global__ void __launch_bounds__(256) k_omega_expand(const double *__restrict__
     }
 }
 
-// ------------------------------------------------------------------ slab blocks
-// L[ql][n][0:R] = C_R[n], L[ql][n][3R:4R] = C_L[n] for every slot ql < nslot.
-__global__ void __launch_bounds__(256) k_vjp_fill_blocks(const double *__restrict__ Cc,
-                                                         double *__restrict__ L, int nao, int R,
-                                                         int nslot)
-{
-    const int R2 = 2 * R, R4 = 4 * R;
-    const i64 total = (i64)nslot * nao * R2;
-    for (i64 e = (i64)blockIdx.x * 256 + threadIdx.x; e < total; e += (i64)gridDim.x * 256) {
-        const i64 row = e / R2;          // ql * nao + n
-        const int c = (int)(e % R2);
-        const int n = (int)(row % nao);
-        const bool right = c < R;        // c < R: C_R part, else C_L part
-        const int cc = right ? c : c - R;
-        L[row * R4 + (right ? cc : 3 * R + cc)] = Cc[(i64)n * R2 + (right ? R + cc : cc)];
-    }
-}
-
 // ------------------------------------------------------------------ stage B
-// WHICH = 0: L[ql][m][R  + k*r+i] = sum_n V_k[m][n] Y_ws[k][n][ql*r+i] + om * C_R
-// WHICH = 1: L[ql][m][2R + k*r+i] = sum_n V_k[n][m] X_ws[k][n][ql*r+i] + om * C_L
+// WHICH = 0: L[ql][m][     k*r+i] = sum_n V_k[m][n] Y_ws[k][n][ql*r+i] + om * C_R
+// WHICH = 1: L[ql][m][R  + k*r+i] = sum_n V_k[n][m] X_ws[k][n][ql*r+i] + om * C_L
 // (om = omega_{k, q0+ql}; products skipped when has_v == 0, omega terms when
 // has_w == 0).  grid.x = nd * nmt * njt (XCD-swizzled).
 template <int WHICH>
@@ -82,7 +63,7 @@ __global__ void __launch_bounds__(256, 3) k_vjp_stage_b(const double *__restrict
 {
     typedef TileV TL;
     extern __shared__ double lds[];
-    const int R = nd * r, R2 = 2 * R, R4 = 4 * R;
+    const int R = nd * r, R2 = 2 * R;
     const int nmt = (nao + kTM - 1) / kTM, njt = (nj + kTN - 1) / kTN;
     const int t = xcd_swizzle(blockIdx.x, nd * nmt * njt);
     // row tiles fastest: the nmt tiles of a column block share its X/Y block,
@@ -103,7 +84,7 @@ __global__ void __launch_bounds__(256, 3) k_vjp_stage_b(const double *__restrict
         }
     }
     // Output (m, j) goes to L at column block j: slot ql = j / r, column
-    // c = k r + j % r, element ((ql nao + m) 4R + part + c); the omega term
+    // c = k r + j % r, element ((ql nao + m) 2R + part + c); the omega term
     // adds omx[q0 + ql][c] * Cc[m][c or R + c].  A lane holds TL::NB columns
     // and 4 TL::MA rows, decoded once each.
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -120,7 +101,7 @@ __global__ void __launch_bounds__(256, 3) k_vjp_stage_b(const double *__restrict
         col_ok[jj] = j < nj;
         const int ql = j / r, i = j - ql * r;
         const int c = k * r + i;
-        col_l[jj] = (i64)ql * nao * R4 + (WHICH == 0 ? R : R2) + c;
+        col_l[jj] = (i64)ql * nao * R2 + (WHICH == 0 ? 0 : R) + c;
         col_cc[jj] = WHICH == 0 ? R + c : c;
         col_om[jj] = (has_w && col_ok[jj]) ? omx[(i64)(q0 + ql) * R + c] : 0.0;
     }
@@ -136,14 +117,14 @@ __global__ void __launch_bounds__(256, 3) k_vjp_stage_b(const double *__restrict
                         double x = acc.c[i][jj][v];
                         if (has_w)
                             x = fma(col_om[jj], Cc[(i64)m * R2 + col_cc[jj]], x);
-                        L[col_l[jj] + (i64)m * R4] = x;
+                        L[col_l[jj] + (i64)m * R2] = x;
                     }
             }
         }
 }
 
 // ------------------------------------------------------------------ stage C
-// dCp[sp][m][c] (+)= sum_{ql in split sp} sum_n B^{q0+ql}[m][n] L[ql][n][R + c], c < 2R.
+// dCp[sp][m][c] (+)= sum_{ql in split sp} sum_n B^{q0+ql}[m][n] L[ql][n][c], c < 2R.
 // grid.x = nsplit * nmt * nct.
 __global__ void __launch_bounds__(256, 3) k_vjp_stage_c(const double *__restrict__ B,
                                                         const double *__restrict__ L,
@@ -153,7 +134,7 @@ __global__ void __launch_bounds__(256, 3) k_vjp_stage_c(const double *__restrict
 {
     typedef TileV TL;
     extern __shared__ double lds[];
-    const int R2 = 2 * R, R4 = 4 * R;
+    const int R2 = 2 * R;
     const int nmt = (nao + kTM - 1) / kTM, nct = (R2 + kTN - 1) / kTN;
     const int t = xcd_swizzle(blockIdx.x, nsplit * nmt * nct);
     const int sp = t / (nmt * nct), rem = t % (nmt * nct);
@@ -165,8 +146,8 @@ __global__ void __launch_bounds__(256, 3) k_vjp_stage_c(const double *__restrict
     if (qb > qa) {
         // slabs qa..qb-1 as one pipelined sum, one resource per slab
         BufKC a{B + (i64)(q0 + qa) * n2, nao, nao, nao};
-        BufIC b{L + (i64)qa * nao * R4 + R, R4, R2, nao};
-        tile_gemm16_seg<TL>(a, b, n2, (i64)nao * R4, qb - qa, mb * kTM, cb * kTN, nao, lds, acc);
+        BufIC b{L + (i64)qa * nao * R2, R2, R2, nao};
+        tile_gemm16_seg<TL>(a, b, n2, (i64)nao * R2, qb - qa, mb * kTM, cb * kTN, nao, lds, acc);
     }
     double *out = dCp + (i64)sp * nao * R2;
     tile_foreach16(acc, mb * kTM, cb * kTN, [&](int m, int c, double v) {
@@ -210,26 +191,33 @@ __global__ void __launch_bounds__(256) k_vjp_e_matrix(const double *__restrict__
 }
 
 // ------------------------------------------------------------------ stage D
-// dB[q0+ql][a][b] = sum_{j<2R} L[ql][a][j] L[ql][b][2R + j].
+// dB[q0+ql][a][b] = sum_{c<R} C_R[a][c] R'[ql][b][c] + sum_{c<R} P'[ql][a][c] C_L[b][c]
+// (C_R[a][c] = Cc[a][R + c], C_L[b][c] = Cc[b][c]), the two sums in this order.
 // grid.x = nq * nmt * nnt (XCD-swizzled).
-template <bool MASK>
 __global__ void __launch_bounds__(256, 3) k_vjp_stage_d(const double *__restrict__ L,
+                                                        const double *__restrict__ Cc,
                                                         double *__restrict__ dB, int nao, int R,
                                                         int q0, int nq)
 {
     typedef TileV TL;
     extern __shared__ double lds[];
-    const int R2 = 2 * R, R4 = 4 * R;
+    const int R2 = 2 * R;
     const int nmt = (nao + kTM - 1) / kTM, nnt = (nao + kTN - 1) / kTN;
     const int t = xcd_swizzle(blockIdx.x, nq * nmt * nnt);
     const int ql = t / (nmt * nnt), rem = t % (nmt * nnt);
     const int ab = rem / nnt, bb = rem % nnt;
-    const double *Lq = L + (i64)ql * nao * R4;
-    BufKC a{Lq, R4, nao, R2};
-    BufKC b{Lq + R2, R4, nao, R2};
+    const double *Lq = L + (i64)ql * nao * R2;
     Acc16<TL> acc;
     acc.zero();
-    tile_gemm16<TL, MASK>(a, b, ab * kTM, bb * kTN, 0, R2, lds, acc);
+    // The two products as two segments of one pipeline: segment g reads its
+    // operands at the first segment's plus g times the distance between them
+    // (both matrices have row length 2R, so their per-lane offsets agree).
+    const double *a0 = Cc + R, *a1 = Lq, *b0 = Lq + R, *b1 = Cc;
+    BufKC a{a0, R2, nao, R};
+    BufKC b{b0, R2, nao, R};
+    const i64 sa = ((i64)(intptr_t)a1 - (i64)(intptr_t)a0) / 8;
+    const i64 sb = ((i64)(intptr_t)b1 - (i64)(intptr_t)b0) / 8;
+    tile_gemm16_seg<TL>(a, b, sa, sb, 2, ab * kTM, bb * kTN, R, lds, acc);
     const i64 n2 = (i64)nao * nao;
     double *out = dB + (i64)(q0 + ql) * n2;
     tile_foreach16(acc, ab * kTM, bb * kTN, [&](int ia, int ib, double v) {
@@ -340,17 +328,6 @@ hipError_t launch_omega_expand(const double *om, double *omx, int naux, int nd, 
     return hipGetLastError();
 }
 
-hipError_t launch_vjp_fill_blocks(const double *Cc, double *L, int nao, int R, int nslot,
-                                  hipStream_t s)
-{
-    {
-        ProfScope ps_("vjp_fill_blocks", s);
-        hipLaunchKernelGGL(k_vjp_fill_blocks, dim3(grid_1d((i64)nslot * nao * 2 * R)), dim3(256), 0, s,
-                           Cc, L, nao, R, nslot);
-    }
-    return hipGetLastError();
-}
-
 hipError_t launch_vjp_stage_b_one(int which, const double *V, const double *Zw, const double *Cc,
                                   const double *omx, double *L, int nao, int nd, int r, int q0,
                                   int nj, int ldw, int has_v, int has_w, hipStream_t s)
@@ -447,22 +424,17 @@ hipError_t launch_vjp_e_matrix(const double *D, double *E, int nao, int nd, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_vjp_stage_d(const double *L, double *dB, int nao, int R, int q0, int nq,
-                              hipStream_t s)
+hipError_t launch_vjp_stage_d(const double *L, const double *Cc, double *dB, int nao, int R,
+                              int q0, int nq, hipStream_t s)
 {
     const int lds = (int)sizeof(double) * TileV::LDS_DOUBLES;
-    const bool mask = (2 * R) % TileV::BK != 0;      // a depth of whole stages needs no mask
-    hipError_t e = set_dynamic_lds(mask ? (const void *)k_vjp_stage_d<true>
-                                        : (const void *)k_vjp_stage_d<false>, lds);
+    hipError_t e = set_dynamic_lds((const void *)k_vjp_stage_d, lds);
     if (e != hipSuccess)
         return e;
     {
         ProfScope ps_("vjp_stage_d", s);
         const dim3 g(nq * cdiv(nao, kTM) * cdiv(nao, kTN));
-        if (mask)
-            hipLaunchKernelGGL(k_vjp_stage_d<true>, g, dim3(TileV::NTHR), lds, s, L, dB, nao, R, q0, nq);
-        else
-            hipLaunchKernelGGL(k_vjp_stage_d<false>, g, dim3(TileV::NTHR), lds, s, L, dB, nao, R, q0, nq);
+        hipLaunchKernelGGL(k_vjp_stage_d, g, dim3(TileV::NTHR), lds, s, L, Cc, dB, nao, R, q0, nq);
     }
     return hipGetLastError();
 }

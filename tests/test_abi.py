@@ -143,11 +143,11 @@ def test_fock_validation():
 
 
 def test_vjp_block_beyond_buffer_reach_unsupported():
-    # one slab's [C_R | P' | R' | C_L] block of nao x 4R doubles must stay
-    # below 4 GiB (stages C and D read it through one buffer resource): the
-    # derivative refuses such a problem before any launch
+    # one slab's [P' | R'] block of nao x 2R doubles must stay below 4 GiB
+    # (stages C and D read it through one buffer resource): the derivative
+    # refuses such a problem before any launch
     L = _lib.lib()
-    p = _prob(nao=16384, naux=1, ndens=1, rank=8192)        # 16384 * 4 * 8192 * 8 B = 4 GiB
+    p = _prob(nao=16384, naux=1, ndens=1, rank=16384)       # 16384 * 2 * 16384 * 8 B = 4 GiB
     need = L.jk_workspace_bytes(ctypes.byref(p))
     assert need > 0
     assert L.jk_vjp(ctypes.byref(p), 8, 8, 8, 8, 8, 8, 8, 8, 256, need, None) == _lib.JK_EUNSUPPORTED

@@ -295,7 +295,8 @@ __global__ void __launch_bounds__(512) k_ht_mixed(const int8_t *__restrict__ Bp,
     extern __shared__ char lds[];
     typedef TileS TL;
     const int nmt = mp / kMT, nct = cp / kNT;
-    const int t = blockIdx.x;
+    // consecutive tiles (the column tiles of a row panel) on one XCD, sharing its L2
+    const int t = xcd_swizzle(blockIdx.x, gridDim.x);
     const int ql = t / (nmt * nct), rem = t % (nmt * nct);
     const int mb = rem / nct, cb = rem % nct;
     SPlanes a{Bp + (i64)ql * mp * kSliceKB, bpstride, bkbstride};
@@ -378,7 +379,7 @@ __global__ void __launch_bounds__(512) k_ex_mixed(const int8_t *__restrict__ Xp,
     // sym: Y = X, only the square tiles with nb >= mb (upper triangle)
     const int pk = sym ? nmt * (nmt + 1) / 2 : nmt * nnt;
     const int per = nd * pk;
-    const int t = blockIdx.x;
+    const int t = xcd_swizzle(blockIdx.x, gridDim.x);
     const int sp = t / per, rem0 = t % per;
     const int k = rem0 / pk, rem = rem0 % pk;
     int mb, nb;

@@ -40,6 +40,19 @@ __device__ __forceinline__ d4v mfma16(double a, double b, d4v c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// A value that is the same in every lane of the wave (it depends on the
+// workgroup index and kernel arguments only), moved to scalar registers.  A
+// buffer resource must be built from scalar values: where the compiler cannot
+// prove a base or size uniform, it wraps every load in a per-lane loop.
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ const char *wave_uniform(const char *p)
+{
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (const char *)(((unsigned long long)hi << 32) | lo);
+}
+
 // Operand element (i, k), i the row of A or the column of B, k the inner
 // index, valid for i < ni, k < nk:
 //   BufKC: at p[i ld + k]  (k contiguous)
@@ -98,15 +111,24 @@ __device__ __forceinline__ int frag_slot(int i, int k)
     return ((i >> 4) * NSUB + (k >> 2)) * 68 + 16 * (k & 3) + (i & 15);
 }
 
-// Moves a T x BK operand tile: groups of four consecutive elements along the
-// contiguous index, group g = tid + s NTHR.
+// Moves a T x BK operand tile in groups of consecutive elements along the
+// contiguous index, group g = tid + s NTHR:
+//   BufKC: four consecutive k of one row i (two 16-byte loads).  A lane's
+//     four values go to four rows of a fragment block, 128 bytes apart.
+//   BufIC: two consecutive i of one inner index k (one 16-byte load).  The
+//     16 lanes that one LDS write cycle serves then cover 256 consecutive
+//     bytes of two fragment blocks, one bank each; groups of four i put
+//     lanes 8 apart on the same banks (the blocks of one k are 272 doubles
+//     apart).
 template <int T, int BK, int NTHR, class Op>
 struct BufLoader {
-    static constexpr int NGRP = T * BK / 4, NS = NGRP / NTHR, NSUB = BK / 4;
+    static constexpr int G = Op::kContig ? 4 : 2;
+    static constexpr int NGRP = T * BK / G, NS = NGRP / NTHR, NSUB = BK / 4;
+    static_assert(NGRP % NTHR == 0, "operand tile and thread count");
     const char *base;      // segment 0
     int nbytes;            // extent of one segment (bit pattern of an unsigned)
     unsigned voff[NS];     // byte offset of the group at inner index 0 of the tile
-    double raw[NS][4];
+    double raw[NS][G];
 
     // local (i, k) of the first element of group s
     __device__ __forceinline__ static void local(int g, int &li, int &lk)
@@ -115,16 +137,16 @@ struct BufLoader {
             li = g / (BK / 4);
             lk = (g % (BK / 4)) * 4;
         } else {
-            lk = g / (T / 4);
-            li = (g % (T / 4)) * 4;
+            lk = g / (T / 2);
+            li = (g % (T / 2)) * 2;
         }
     }
 
     // Per tile: i0 = first index of the tile, kb = first inner index.
     __device__ __forceinline__ void init(const Op &op, int i0, int kb, int tid)
     {
-        base = (const char *)op.p;
-        nbytes = (int)op.extent();
+        base = wave_uniform((const char *)op.p);
+        nbytes = wave_uniform((int)op.extent());
 #pragma unroll
         for (int s = 0; s < NS; s++) {
             int li, lk;
@@ -147,12 +169,15 @@ struct BufLoader {
 #pragma unroll
         for (int s = 0; s < NS; s++) {
             const u4v lo = __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[s], soff, 0);
-            const u4v hi = __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[s] + 16, soff, 0);
-            const double2 a = __builtin_bit_cast(double2, lo), b = __builtin_bit_cast(double2, hi);
+            const double2 a = __builtin_bit_cast(double2, lo);
             raw[s][0] = a.x;
             raw[s][1] = a.y;
-            raw[s][2] = b.x;
-            raw[s][3] = b.y;
+            if constexpr (G == 4) {
+                const u4v hi = __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[s] + 16, soff, 0);
+                const double2 b = __builtin_bit_cast(double2, hi);
+                raw[s][2] = b.x;
+                raw[s][3] = b.y;
+            }
         }
     }
 
@@ -168,7 +193,7 @@ struct BufLoader {
             int li, lk;
             local(tid + s * NTHR, li, lk);
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
+            for (int e = 0; e < G; e++) {
                 const int i = Op::kContig ? li : li + e, k = Op::kContig ? lk + e : lk;
                 lds[frag_slot<NSUB>(i, k)] = raw[s][e];
             }
@@ -179,7 +204,7 @@ struct BufLoader {
                 int li, lk;
                 local(tid + s * NTHR, li, lk);
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
+                for (int e = 0; e < G; e++) {
                     const int i = Op::kContig ? li : li + e, k = Op::kContig ? lk + e : lk;
                     if (k >= kleft)
                         lds[frag_slot<NSUB>(i, k)] = 0.0;
@@ -234,8 +259,8 @@ struct PackedLoader16 {
 
     __device__ __forceinline__ void init(const BufPackedSym &op, int i0_, int kb_, int tid)
     {
-        base = (const char *)op.p;
-        nbytes = (int)op.extent();
+        base = wave_uniform((const char *)op.p);
+        nbytes = wave_uniform((int)op.extent());
         nao = op.nao;
         i0 = i0_;
         kb = kb_;

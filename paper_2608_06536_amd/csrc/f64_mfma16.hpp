@@ -22,9 +22,9 @@
 // Operands are read with buffer loads: a 128-bit resource (base, size in
 // bytes) in scalar registers, a per-lane byte offset computed once per tile,
 // and the stage's advance along the inner index as a scalar offset, so a
-// stage's loads cost no vector address arithmetic.  Each lane loads four
-// consecutive doubles along the operand's contiguous index (two 16-byte
-// loads).  Indices are clamped to the operand once per tile; inner indices
+// stage's loads cost no vector address arithmetic.  Each lane loads a run of
+// consecutive doubles along the operand's contiguous index (four k, or two
+// i; see BufLoader).  Indices are clamped to the operand once per tile; inner indices
 // past the end are zeroed in the last stage only.  A read past the
 // resource's size returns zero (the hardware's range check).
 #pragma once

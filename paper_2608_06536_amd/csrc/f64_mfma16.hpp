@@ -231,7 +231,8 @@ __device__ __forceinline__ int pk_row16(int a, int nao) { return (int)((i64)a * 
 //     contiguous in k; groups of 4 consecutive k, offsets fixed per tile plus
 //     a scalar advance;
 //   below it (k <= i throughout): element (i, k) = (k, i) is packed row k,
-//     contiguous in i; groups of 4 consecutive i, one row offset per group;
+//     contiguous in i; groups of 2 consecutive i, one row offset per group
+//     (pairs keep the LDS writes' bank conflicts low, as for BufIC);
 //   on the diagonal: each element's own offset.
 // Indices are clamped to the slab.  Inner indices past nao read data of the
 // next packed row (finite) or zero past the slab; the caller's other operand
@@ -253,8 +254,8 @@ struct PackedLoader16 {
     }
     __device__ __forceinline__ static void local_i(int g, int &li, int &lk)
     {
-        lk = g / (T / 4);
-        li = (g % (T / 4)) * 4;
+        lk = g / (T / 2);
+        li = (g % (T / 2)) * 2;
     }
 
     __device__ __forceinline__ void init(const BufPackedSym &op, int i0_, int kb_, int tid)
@@ -293,19 +294,17 @@ struct PackedLoader16 {
                 raw[s][3] = b.y;
             }
         } else if (mode == 1) {
+            // 2 NS pairs: pair u in raw[u / 2][2 (u % 2) ..]
 #pragma unroll
-            for (int s = 0; s < NS; s++) {
+            for (int u = 0; u < 2 * NS; u++) {
                 int li, lk;
-                local_i(tid + s * NTHR, li, lk);
+                local_i(tid + u * NTHR, li, lk);
                 const int k = k0 + lk;                       // < nao below the diagonal
                 const unsigned off = (unsigned)(((i64)pk_row16(k, nao) - k + i0 + li) * 8);
                 const u4v lo = __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, 0);
-                const u4v hi = __builtin_amdgcn_raw_buffer_load_b128(rsrc, off + 16, 0, 0);
-                const double2 a = __builtin_bit_cast(double2, lo), b = __builtin_bit_cast(double2, hi);
-                raw[s][0] = a.x;
-                raw[s][1] = a.y;
-                raw[s][2] = b.x;
-                raw[s][3] = b.y;
+                const double2 a = __builtin_bit_cast(double2, lo);
+                raw[u / 2][2 * (u % 2)] = a.x;
+                raw[u / 2][2 * (u % 2) + 1] = a.y;
             }
         } else {
 #pragma unroll
@@ -331,15 +330,18 @@ struct PackedLoader16 {
     __device__ __forceinline__ void store(double *lds, int tid, int) const
     {
         static_assert(!MASK, "a packed operand is used unmasked");
+        if (mode == 1) {
 #pragma unroll
-        for (int s = 0; s < NS; s++) {
-            int li, lk;
-            if (mode == 1) {
-                local_i(tid + s * NTHR, li, lk);
+            for (int u = 0; u < 2 * NS; u++) {
+                int li, lk;
+                local_i(tid + u * NTHR, li, lk);
+                lds[frag_slot<NSUB>(li, lk)] = raw[u / 2][2 * (u % 2)];
+                lds[frag_slot<NSUB>(li + 1, lk)] = raw[u / 2][2 * (u % 2) + 1];
+            }
+        } else {
 #pragma unroll
-                for (int e = 0; e < 4; e++)
-                    lds[frag_slot<NSUB>(li + e, lk)] = raw[s][e];
-            } else {
+            for (int s = 0; s < NS; s++) {
+                int li, lk;
                 local_k(tid + s * NTHR, li, lk);
 #pragma unroll
                 for (int e = 0; e < 4; e++)

@@ -70,7 +70,13 @@ typedef enum {
                       sum and the final accumulation.  Normwise error of K
                       about 1e-10..1e-9 on smoothly scaled inputs; rows
                       whose inner-index magnitudes span many orders of
-                      magnitude lose the small entries (fixed point).       */
+                      magnitude lose the small entries (fixed point).
+                      Exactness of the int32 sums: |digit| <= 64, and a
+                      level adds at most 5 digit pairs per inner index, so
+                      a sum over n indices stays below 2^31 for
+                      n <= 104857; the planner splits every contraction to
+                      at most that depth (jk_plan_describe in jk_tune.h
+                      reports it).                                           */
 } jk_precision;
 
 /* JK_B_PACKED: every B slab (and B_lr slab of jk_fock) is stored as its upper
@@ -148,8 +154,14 @@ size_t jk_batched_workspace_bytes(int32_t nprob, const jk_problem *p);
  * nao, naux, ndens and rank) in one call.  p, B, CL, CR, J, K are HOST arrays
  * of length nprob; B[g], CL[g], ... are DEVICE pointers with the layouts
  * above.  Every problem must share one precision and one flags value.  Each
- * member's outputs are bit-identical to a jk_build call of that member alone
- * with the same precision. */
+ * member's outputs agree with a jk_build call of that member alone to
+ * rounding, and are bit-identical to it when that build's plan (jk_tune.h)
+ * has a chunk budget of at most 256 MiB: each member's Q-chunks are capped
+ * at 256 MiB, and K sums its chunks in order.  With a non-default stream the
+ * launch sequence is captured once per shape signature, workspace and device
+ * and replayed (at most 32 such graphs are kept; the oldest is destroyed,
+ * after a device synchronisation, when a new one is made).  The member
+ * table is copied from a pinned host buffer that the library owns. */
 jk_status jk_build_batched(int32_t nprob, const jk_problem *p,
                            const double *const *B, const double *const *CL,
                            const double *const *CR, double *const *J,

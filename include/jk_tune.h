@@ -56,6 +56,27 @@ jk_status jk_tuning_get(const jk_problem *p, jk_tuning *t);
 /* Records *t for p's shape class (JK_EINVAL if a field is out of range). */
 jk_status jk_tuning_set(const jk_problem *p, const jk_tuning *t);
 
+/* What a plan does with problem *p (host only, enqueues nothing).  With
+ * t == NULL the plan jk_build would use (jk_tuning_get), else the plan *t. */
+typedef struct {
+    int32_t chunk_slabs;    /* slabs per Q-chunk                                         */
+    int32_t nsplit;         /* exchange splits of a chunk, general densities             */
+    int32_t nsplit_sym;     /* exchange splits of a chunk, C_L = C_R                     */
+    int32_t int_depth;      /* JK_MIXED: the most inner indices any int32 slice-level
+                               sum of the build takes (half-transform: the padded nao;
+                               exchange: one split of a chunk's slab-rank index); 0 for
+                               JK_FP64                                                    */
+    int32_t int_depth_cap;  /* JK_MIXED: the depth up to which those sums are exact,
+                               104857 (5 digit pairs of at most 2^12 per index stay
+                               below 2^31); 0 for JK_FP64.  Every plan keeps
+                               int_depth <= int_depth_cap by splitting the exchange.   */
+    int32_t reserved;
+} jk_plan_info;
+
+/* Fills *out for problem *p under plan t (or the current plan).  Returns
+ * JK_EINVAL for an invalid problem, plan or NULL out. */
+jk_status jk_plan_describe(const jk_problem *p, const jk_tuning *t, jk_plan_info *out);
+
 /* Forgets every recorded plan. */
 void jk_tuning_clear(void);
 

@@ -204,9 +204,10 @@ def jvp(B, CL, CR, dB=None, dCL=None, dCR=None):
     return dJ, dK
 
 
-def vjp_factored(B, CL, CR, W=None, V=None, q0=0, q1=None, want_dB=True):
+def vjp_factored(B, CL, CR, W=None, V=None, q0=0, q1=None, want_dB=True, want_dCL=True,
+                 want_dCR=True):
     """Factored derivative (symmetric B) over slabs [q0, q1).  Returns
-    (dB or None, dCL, dCR); dB rows outside [q0, q1) are zero."""
+    (dB or None, dCL or None, dCR or None); dB rows outside [q0, q1) are zero."""
     B, CL, CR = _c(B), _c(CL), _c(CR)
     W = None if W is None else _c(W)
     V = None if V is None else _c(V)
@@ -214,8 +215,8 @@ def vjp_factored(B, CL, CR, W=None, V=None, q0=0, q1=None, want_dB=True):
     nd, _, r = CL.shape
     q1 = naux if q1 is None else q1
     dB = np.zeros_like(B) if want_dB else None
-    dCL = np.empty_like(CL)
-    dCR = np.empty_like(CR)
+    dCL = np.empty_like(CL) if want_dCL else None
+    dCR = np.empty_like(CR) if want_dCR else None
     _load().jko_vjp_factored(_I(nd), _I(nao), _I(naux), _I(r), _d(B), _d(CL), _d(CR), _d(W),
                              _d(V), _I(q0), _I(q1), _d(dB), _d(dCL), _d(dCR))
     return dB, dCL, dCR

@@ -479,7 +479,7 @@ void jko_vjp_factored(i64 nd, i64 nao, i64 naux, i64 r, const double *B,
                     pp[m * r + i] = sp;
                     rr[m * r + i] = sr;
                 }
-            if (dCL)
+            if (dCL || dCR)
 #pragma omp parallel for schedule(static)
                 for (i64 m = 0; m < nao; m++)
                     for (i64 i = 0; i < r; i++) {
@@ -488,8 +488,10 @@ void jko_vjp_factored(i64 nd, i64 nao, i64 naux, i64 r, const double *B,
                             sl += Bq[m * nao + n] * pp[n * r + i];
                             sr += Bq[m * nao + n] * rr[n * r + i];
                         }
-                        dCL[(k * nao + m) * r + i] += sl;
-                        dCR[(k * nao + m) * r + i] += sr;
+                        if (dCL)
+                            dCL[(k * nao + m) * r + i] += sl;
+                        if (dCR)
+                            dCR[(k * nao + m) * r + i] += sr;
                     }
             if (dB)
 #pragma omp parallel for schedule(static)

@@ -22,7 +22,7 @@ LAPLACE_EXPORTS = ("jk_laplace_quadrature", "jk_laplace_factors", "jk_laplace_wo
                    "jk_laplace_build")
 LAPLACE_MAX_POINTS = 20
 TUNE_EXPORTS = ("jk_autotune", "jk_tuning_get", "jk_tuning_set", "jk_tuning_clear",
-                "jk_tuning_save", "jk_tuning_load")
+                "jk_tuning_save", "jk_tuning_load", "jk_plan_describe")
 PROF_EXPORTS = ("jk_prof_enable", "jk_prof_reset", "jk_prof_collect", "jk_prof_entry",
                 "jk_prof_dropped")
 
@@ -41,6 +41,12 @@ class LaplaceProblem(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("ht_tile", ctypes.c_int32), ("chunk_mb", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("chunk_slabs", ctypes.c_int32), ("nsplit", ctypes.c_int32),
+                ("nsplit_sym", ctypes.c_int32), ("int_depth", ctypes.c_int32),
+                ("int_depth_cap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class JKError(RuntimeError):
@@ -102,6 +108,8 @@ def lib():
         L.jk_tuning_save.argtypes = [ctypes.c_char_p, sz]
         L.jk_tuning_load.restype = ctypes.c_int
         L.jk_tuning_load.argtypes = [ctypes.c_char_p]
+        L.jk_plan_describe.restype = ctypes.c_int
+        L.jk_plan_describe.argtypes = [pp, tp, ctypes.POINTER(PlanInfo)]
         L.jk_prof_enable.restype = ctypes.c_int
         L.jk_prof_enable.argtypes = [ctypes.c_int32]
         L.jk_prof_reset.restype = None

@@ -840,14 +840,98 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p)
 }
 
 // Captured launch sequences, keyed by shape signature, workspace and device.
+// At most kMaxGraphs are kept; inserting one more first destroys the oldest,
+// after a synchronisation of the device it was made on (a replay of it may
+// still be running).
+constexpr size_t kMaxGraphs = 32;
 struct GraphCache {
     std::mutex mu;
-    std::map<std::string, hipGraphExec_t> execs;
+    struct Entry {
+        hipGraphExec_t exec;
+        int dev;
+    };
+    std::map<std::string, Entry> execs;
+    std::vector<std::string> order;    // insertion order, oldest first
 };
 GraphCache &graph_cache()
 {
     static GraphCache c;
     return c;
+}
+
+// Inserts exec under key (the cache mutex held); false if an eviction failed.
+bool graph_cache_insert(GraphCache &gc, const std::string &key, hipGraphExec_t exec, int dev)
+{
+    while (gc.execs.size() >= kMaxGraphs && !gc.order.empty()) {
+        const std::string old = gc.order.front();
+        auto it = gc.execs.find(old);
+        if (it != gc.execs.end()) {
+            int cur = 0;
+            if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(it->second.dev) != hipSuccess)
+                return false;
+            const hipError_t e = hipDeviceSynchronize();
+            (void)hipSetDevice(cur);
+            if (e != hipSuccess)
+                return false;
+            (void)hipGraphExecDestroy(it->second.exec);
+            gc.execs.erase(it);
+        }
+        gc.order.erase(gc.order.begin());
+    }
+    gc.execs[key] = GraphCache::Entry{exec, dev};
+    gc.order.push_back(key);
+    return true;
+}
+
+// Pinned host staging of the batched header, one buffer per device.  A call
+// rewrites it only after the previous call's copy out of it has completed
+// (an event recorded after that copy), so an asynchronous copy never reads a
+// buffer that is being overwritten or freed.
+struct HeaderStage {
+    char *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+};
+
+hipError_t copy_header(const jk::BMember *mem, int nprob, const std::vector<int> &tabs,
+                       size_t header_bytes, void *dst, hipStream_t s)
+{
+    static std::mutex mu;
+    static std::map<int, HeaderStage> stages;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    std::lock_guard<std::mutex> lk(mu);
+    HeaderStage &st = stages[dev];
+    if (!st.done) {
+        e = hipEventCreateWithFlags(&st.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            st.done = nullptr;
+            return e;
+        }
+    } else if ((e = hipEventSynchronize(st.done)) != hipSuccess) {
+        return e;
+    }
+    if (st.cap < header_bytes) {
+        if (st.host)
+            (void)hipHostFree(st.host);
+        st.host = nullptr;
+        st.cap = 0;
+        e = hipHostMalloc((void **)&st.host, header_bytes, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            st.host = nullptr;
+            return e;
+        }
+        st.cap = header_bytes;
+    }
+    memset(st.host, 0, header_bytes);
+    memcpy(st.host, mem, sizeof(jk::BMember) * nprob);
+    memcpy(st.host + align_up(sizeof(jk::BMember) * nprob), tabs.data(), sizeof(int) * tabs.size());
+    e = hipMemcpyAsync(dst, st.host, header_bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess)
+        return e;
+    return hipEventRecord(st.done, s);
 }
 
 bool graphs_enabled()
@@ -873,8 +957,7 @@ jk_status build_batched_fp64(int32_t nprob, const jk_problem *p, const double *c
                              double *const *K, char *ws, hipStream_t s)
 {
     BSchedule S = make_schedule(nprob, p);
-    // host image of the header: descriptors with this call's pointers, tables
-    std::vector<char> host(S.header_bytes, 0);
+    // the header: descriptors with this call's pointers, then the tables
     for (int g = 0; g < nprob; g++) {
         jk::BMember &m = S.mem[g];
         const FwdPlan f = plan_forward(&p[g], std::min(kChunkBudgetBatched, tuned_budget(&p[g])));
@@ -892,10 +975,7 @@ jk_status build_batched_fp64(int32_t nprob, const jk_problem *p, const double *c
         m.Yw = (double *)(base + f.o_y);
         m.Kp = (double *)(base + f.o_kp);
     }
-    memcpy(host.data(), S.mem.data(), sizeof(jk::BMember) * nprob);
-    const size_t tab0 = align_up(sizeof(jk::BMember) * nprob);
-    memcpy(host.data() + tab0, S.tabs.data(), sizeof(int) * S.tabs.size());
-    if (hipMemcpyAsync(ws, host.data(), S.header_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+    if (copy_header(S.mem.data(), nprob, S.tabs, S.header_bytes, ws, s) != hipSuccess)
         return JK_EHIP;
 
     if (jk::prepare_batched_kernels() != hipSuccess)
@@ -915,7 +995,7 @@ jk_status build_batched_fp64(int32_t nprob, const jk_problem *p, const double *c
         std::lock_guard<std::mutex> lk(gc.mu);
         auto it = gc.execs.find(key);
         if (it != gc.execs.end())
-            exec = it->second;
+            exec = it->second.exec;
     }
     if (!exec) {
         hipGraph_t graph = nullptr;
@@ -934,7 +1014,10 @@ jk_status build_batched_fp64(int32_t nprob, const jk_problem *p, const double *c
         if (e != hipSuccess)
             return JK_EHIP;
         std::lock_guard<std::mutex> lk(gc.mu);
-        gc.execs[key] = exec;
+        if (!graph_cache_insert(gc, key, exec, dev)) {
+            (void)hipGraphExecDestroy(exec);
+            return JK_EHIP;
+        }
     }
     return hipGraphLaunch(exec, s) == hipSuccess ? JK_OK : JK_EHIP;
 }
@@ -1195,6 +1278,44 @@ jk_status jk_vjp(const jk_problem *p, const double *B, const double *CL, const d
 {
     try {
         return jk_vjp_impl(p, B, CL, CR, Jbar, Kbar, dB, dCL, dCR, ws, ws_bytes, stream);
+    } catch (...) {
+        return JK_ENOMEM;
+    }
+}
+
+static jk_status jk_plan_describe_impl(const jk_problem *p, const jk_tuning *t, jk_plan_info *out)
+{
+    if (!valid_problem(p) || !out)
+        return JK_EINVAL;
+    const jk_tuning tu = t ? *t : plan_tuning(p);
+    if (tu.ht_tile < 0 || tu.ht_tile > 4 || tu.chunk_mb < 64 || tu.chunk_mb > 4096)
+        return JK_EINVAL;
+    const size_t budget = (size_t)tu.chunk_mb << 20;
+    memset(out, 0, sizeof(*out));
+    if (p->precision == JK_MIXED) {
+        const MixPlan x = plan_mixed(p, budget);
+        const int KB = jk::mixed_k_block();
+        const int nkb = x.jp / KB;
+        out->chunk_slabs = x.f.qc;
+        out->nsplit = x.nsplit;
+        out->nsplit_sym = x.nsplit_sym;
+        const int ns = std::min(x.nsplit, x.nsplit_sym);
+        const int ex_depth = (nkb + ns - 1) / ns * KB;
+        out->int_depth = std::max(x.kp, ex_depth);
+        out->int_depth_cap = jk::mixed_max_depth();
+    } else {
+        const FwdPlan f = plan_forward(p, budget);
+        out->chunk_slabs = f.qc;
+        out->nsplit = f.nsplit;
+        out->nsplit_sym = f.nsplit_sym;
+    }
+    return JK_OK;
+}
+
+jk_status jk_plan_describe(const jk_problem *p, const jk_tuning *t, jk_plan_info *out)
+{
+    try {
+        return jk_plan_describe_impl(p, t, out);
     } catch (...) {
         return JK_ENOMEM;
     }

@@ -109,7 +109,11 @@ hipError_t launch_slice_xy(const double *XY, int nao, int nkey, int r, int mp, i
 hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, i64 bkbstride, const int *eB,
                            const int8_t *Cp, i64 cpstride, i64 ckbstride, const int *eC, double *XY,
                            int nao, int R2, int nq, int mp, int cp, int nkb, hipStream_t s);
+// Exchange splits of a chunk of nkb inner blocks: chosen for occupancy, and
+// never fewer than keep each split's int32 sums exact (mixed_max_depth()
+// inner indices at most).
 int ex_mixed_nsplit(int mp, int nd, int nkb, int sym = 0);
+int mixed_max_depth();
 // B digit planes from packed slabs (slab stride bs = nao (nao + 1) / 2);
 // mixed_packed_ok tells whether the packed slicer covers rows of kp inner
 // elements (kp <= 2048).

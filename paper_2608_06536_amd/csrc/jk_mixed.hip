@@ -562,6 +562,8 @@ hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, i64 bkbstride, const 
     return hipGetLastError();
 }
 
+int mixed_max_depth() { return kSliceMaxDepth; }
+
 int ex_mixed_nsplit(int mp, int nd, int nkb, int sym)
 {
     // one 512-thread workgroup per CU (registers), so half the usual slots
@@ -570,7 +572,11 @@ int ex_mixed_nsplit(int mp, int nd, int nkb, int sym)
     int maxs = nkb / 16 > 1 ? nkb / 16 : 1;
     if (maxs > 16)
         maxs = 16;
-    return pick_split_slots(tiles, maxs, device_slots() / 2);
+    const int s = pick_split_slots(tiles, maxs, device_slots() / 2);
+    // exact int32 level sums: a split of cdiv(nkb, s) inner blocks may hold at
+    // most kSliceMaxDepth inner indices
+    const int need = cdiv(nkb, kSliceMaxDepth / kSliceKB);
+    return s > need ? s : need;
 }
 
 hipError_t launch_ex_mixed(const int8_t *Xp, const int8_t *Yp, i64 pstride, i64 kbstride,

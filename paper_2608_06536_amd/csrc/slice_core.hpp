@@ -9,7 +9,8 @@
 //     S_l = sum_{i+j=l} sum_k d_i(a_k) d_j(b_k),
 // keeping the pairs with i + j <= NS + 1.  Each S_l is an exact integer: the
 // matrix cores multiply int8 digits and accumulate in int32, and
-// |S_l| <= 5 * n * 2^12 < 2^31 for n <= 100000 inner indices.  The levels are
+// |S_l| <= 5 * n * 2^12 < 2^31 for n <= kSliceMaxDepth = 104857 inner indices
+// per accumulation (enforced by the planner).  The levels are
 // combined in FP64 at the end (exact conversions, power-of-two weights), so
 // the only approximations are the dropped low digits (relative ~2^-34 for
 // NS = 5) and FP64 rounding.
@@ -35,6 +36,11 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kSliceBits = 7;          // bits per digit
 constexpr int kSliceKB = 32;           // inner block: bytes per row per block
+// Most inner indices one int32 level sum may take: a level holds at most 5
+// digit pairs of |d_i d_j| <= 2^12 per index, so n indices give
+// |S_l| <= 5 n 2^12, below 2^31 for n <= 104857.  Every plan splits its
+// contractions so that no accumulation exceeds this depth.
+constexpr int kSliceMaxDepth = 104857;
 
 __device__ __forceinline__ v16i mfma_i8(v4i a, v4i b, v16i c)
 {

@@ -182,6 +182,21 @@ def tuning_set(prob, ht_tile, chunk_mb):
     _lib.check(_lib.lib().jk_tuning_set(ctypes.byref(prob), ctypes.byref(t)), "jk_tuning_set")
 
 
+def plan_describe(prob, ht_tile=None, chunk_mb=None):
+    """What the plan (the current one, or {ht_tile, chunk_mb}) does with the
+    problem: slabs per chunk, exchange splits and, for the mixed precision,
+    the deepest int32 slice sum against its exactness cap (host only)."""
+    t = None
+    if ht_tile is not None or chunk_mb is not None:
+        cur = tuning_get(prob)
+        t = _lib.Tuning(int(cur["ht_tile"] if ht_tile is None else ht_tile),
+                        int(cur["chunk_mb"] if chunk_mb is None else chunk_mb))
+    info = _lib.PlanInfo()
+    _lib.check(_lib.lib().jk_plan_describe(ctypes.byref(prob), None if t is None else ctypes.byref(t),
+                                           ctypes.byref(info)), "jk_plan_describe")
+    return {f: getattr(info, f) for f, _ in _lib.PlanInfo._fields_ if f != "reserved"}
+
+
 def tuning_clear():
     _lib.lib().jk_tuning_clear()
 
@@ -209,7 +224,8 @@ def jk_build_batched(items, precision="fp64", want_j=True, want_k=True, nslice=0
     probs, res = [], []
     for g, (B, CL, CR) in enumerate(items):
         nao, naux, nd, r = _shapes(B, CL, CR)
-        probs.append(make_problem(nao, naux, nd, r, precision, want_j, want_k, nslice))
+        probs.append(make_problem(nao, naux, nd, r, precision, want_j, want_k, nslice,
+                                  is_packed(B, nao)))
         if outs is None:
             J = torch.empty((nd, nao, nao), dtype=torch.float64, device=B.device) if want_j else None
             K = torch.empty((nd, nao, nao), dtype=torch.float64, device=B.device) if want_k else None
@@ -239,7 +255,8 @@ def jk_vjp(B, CL, CR, Jbar=None, Kbar=None, want_dB=True, want_dC=True, out=None
     for t, name in ((Jbar, "Jbar"), (Kbar, "Kbar")):
         if t is not None:
             _check_tensor(t, name, (nd, nao, nao))
-    prob = make_problem(nao, naux, nd, r, "fp64")
+    # packed slabs travel as a flag, so the library refuses them before any launch
+    prob = make_problem(nao, naux, nd, r, "fp64", packed=is_packed(B, nao))
     if out is None:
         dB = torch.empty_like(B) if want_dB else None
         dCL = torch.empty_like(CL) if want_dC else None

@@ -28,10 +28,13 @@ to 1000 AO):
 from __future__ import annotations
 
 import dataclasses
+import functools
+import os
+
 import numpy as np
 
 __all__ = [
-    "Problem", "CONFIGS", "config", "make_B", "make_B_slabs", "make_factors",
+    "Problem", "CONFIGS", "config", "make_B", "make_B_slabs", "make_B_parallel", "make_factors",
     "make_cotangents", "make_problem", "batched_problems", "Orbitals", "make_orbitals",
     "make_amplitudes", "LAPLACE_BENCH",
 ]
@@ -76,14 +79,24 @@ def config(i: int) -> Problem:
     return CONFIGS[i]
 
 
+@functools.lru_cache(maxsize=8)
+def _slab_consts(nao: int, ell: float):
+    """Upper-triangle indices and the decay matrix exp(-|m-n|/ell) (shared by
+    every slab of a problem; read-only)."""
+    iu = np.triu_indices(nao)
+    idx = np.arange(nao)
+    decay = np.exp(-np.abs(idx[:, None] - idx[None, :]) / ell)
+    for a in (*iu, decay):
+        a.setflags(write=False)
+    return iu, decay
+
+
 def _slab(nao: int, q: int, ell: float, tau: float, seed: int) -> np.ndarray:
     rng = np.random.default_rng(np.random.SeedSequence(seed, spawn_key=(0, q)))
-    iu = np.triu_indices(nao)
+    iu, decay = _slab_consts(nao, ell)
     g = np.empty((nao, nao))
     g[iu] = rng.standard_normal(iu[0].size)
     g.T[iu] = g[iu]
-    idx = np.arange(nao)
-    decay = np.exp(-np.abs(idx[:, None] - idx[None, :]) / ell)
     return g * decay * np.exp(-q / tau)
 
 
@@ -100,6 +113,19 @@ def make_B_slabs(p: Problem, qs, out: np.ndarray | None = None) -> np.ndarray:
 def make_B(p: Problem) -> np.ndarray:
     """Full factor ``B[naux][nao][nao]`` (FP64, each slab symmetric)."""
     return make_B_slabs(p, range(p.naux))
+
+
+def make_B_parallel(p: Problem, workers: int = 16, step: int = 32) -> np.ndarray:
+    """``make_B(p)`` drawn by a pool of threads over blocks of slabs (each slab
+    has its own stream, so the result is the same array)."""
+    from concurrent.futures import ThreadPoolExecutor
+    B = np.empty((p.naux, p.nao, p.nao))
+    workers = max(1, min(workers, os.cpu_count() or 1))
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(lambda a: make_B_slabs(p, range(a, min(a + step, p.naux)),
+                                           out=B[a:min(a + step, p.naux)]),
+                    range(0, p.naux, step)))
+    return B
 
 
 def _orth(rng: np.random.Generator, nao: int, r: int) -> np.ndarray:

@@ -102,3 +102,52 @@ def test_batched_mixed():
         assert rel_err(J.cpu().numpy(), Jr) <= TOL
         for k in range(K.shape[0]):
             assert rel_err(K[k].cpu().numpy(), Kr[k]) <= 1e-8
+
+
+def test_batched_member_over_several_chunks():
+    # nao = 300, naux = 1200, 6 densities of rank 30: 4 chunks of 256 MiB in
+    # the batch.  Bit-identical to a single build under a 256 MiB plan, and
+    # equal to rounding under the default 1024 MiB plan (one chunk).
+    from paper_2608_06536_amd import jk
+    probs = [synth.Problem(nao=300, naux=1200, nd=6, r=30, ell=20.0, tau=300.0, n_ground=1,
+                           seed=8801),
+             synth.Problem(nao=90, naux=360, nd=6, r=9, ell=20.0, tau=90.0, n_ground=1, seed=8802)]
+    items, host = _make(probs)
+    res = jk.jk_build_batched(items)
+    p0 = probs[0]
+    prob = jk.make_problem(p0.nao, p0.naux, p0.nd, p0.r)
+    Jd, Kd = jk.jk_build(*items[0])
+    try:
+        jk.tuning_set(prob, 4, 256)
+        assert jk.plan_describe(prob)["chunk_slabs"] < p0.naux
+        Js, Ks = jk.jk_build(*items[0])
+    finally:
+        jk.tuning_clear()
+    torch.cuda.synchronize()
+    assert torch.equal(res[0][0], Js) and torch.equal(res[0][1], Ks)
+    assert torch.equal(res[0][0], Jd)
+    assert rel_err(res[0][1].cpu().numpy(), Kd.cpu().numpy()) <= TOL
+    B, CL, CR = host[0]
+    Jr, Kr, _ = oracle.jk_factored(B, CL, CR)
+    assert rel_err(res[0][0].cpu().numpy(), Jr) <= TOL
+    assert rel_err(res[0][1].cpu().numpy(), Kr) <= TOL
+
+
+def test_batched_graph_cache_eviction():
+    # 34 shape signatures on one non-default stream, more than the 32 graphs
+    # the library keeps: the oldest are destroyed on the way (after a device
+    # synchronisation).  Every call, and a later replay of the first shape
+    # (captured anew), matches the single builds.
+    from paper_2608_06536_amd import jk
+    stream = torch.cuda.Stream()
+    shapes = [[5 + g, 3 + (g % 7)] for g in range(34)] + [[5, 3]]
+    for g, naos in enumerate(shapes):
+        probs = _problems(naos, seed=300 + g % 34)
+        items, _ = _make(probs)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            res = jk.jk_build_batched(items)
+            singles = [jk.jk_build(*it) for it in items]
+        stream.synchronize()
+        for (J, K), (Js, Ks) in zip(res, singles):
+            assert torch.equal(J, Js) and torch.equal(K, Ks), g

@@ -435,6 +435,17 @@ def test_vjp_factored_equals_literal(dprob):
         assert rel_err(fB, rB) < 1e-13 and rel_err(fL, rL) < 1e-13 and rel_err(fR, rR) < 1e-13
 
 
+def test_vjp_factored_one_sided_outputs(dprob):
+    # either factor adjoint alone (the other output NULL) equals its part of
+    # the two-sided call, and no output is touched through a NULL pointer
+    B, CL, CR, W, V = dprob
+    _, fL, fR = oracle.vjp_factored(B, CL, CR, W, V, want_dB=False)
+    _, oL, nR = oracle.vjp_factored(B, CL, CR, W, V, want_dB=False, want_dCR=False)
+    _, nL, oR = oracle.vjp_factored(B, CL, CR, W, V, want_dB=False, want_dCL=False)
+    assert nR is None and nL is None
+    assert np.array_equal(oL, fL) and np.array_equal(oR, fR)
+
+
 def test_vjp_zero_cotangents(dprob):
     B, CL, CR, W, V = dprob
     dB, dCL, dCR = oracle.vjp(B, CL, CR, None, None)

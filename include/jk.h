@@ -118,6 +118,25 @@ jk_status jk_build(const jk_problem *p, const double *B, const double *CL,
                    const double *CR, double *J, double *K, void *ws,
                    size_t ws_bytes, void *stream);
 
+/* jk_build without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same operation, arguments, outputs and symmetric-density
+ * rule as jk_build; the caller still passes B, CL, CR, J and K.  Every kernel
+ * buffer lives in a 256 MiB array of device memory inside the library, one
+ * per GPU, held until the process ends; the call allocates nothing.
+ *   - JK_FP64 only (full or packed slabs); JK_MIXED gives JK_EUNSUPPORTED.
+ *   - Problems whose smallest plan needs more than 256 MiB return
+ *     JK_EWORKSPACE before anything is enqueued (for example nao = 1000 with
+ *     16 densities of rank 80 fits, in chunks of a few slabs; nao = 2000 with
+ *     16 densities, whose densities alone take 512 MB, does not).
+ *   - The plan is the recorded tile (jk_tune.h) with the largest chunk budget
+ *     up to 256 MiB that fits, so K agrees with jk_build to rounding.
+ *   - All calls on one GPU share that GPU's array: calls that overlap in time
+ *     on one GPU (different streams, or threads) race and give wrong
+ *     results; serialise them.  No buffer needs to start at zero. */
+jk_status jk_build_noalloc(const jk_problem *p, const double *B, const double *CL,
+                           const double *CR, double *J, double *K, void *stream);
+
 /* Workspace bytes needed by jk_fock for problem *p (0 if invalid). */
 size_t jk_fock_workspace_bytes(const jk_problem *p, int64_t naux_lr);
 

@@ -17,6 +17,13 @@
 #include "jk_tiles.hpp"
 #include "jk_tune.hpp"
 
+// Device memory of jk_build_noalloc (jk.h): every kernel buffer of that entry
+// point lives here instead of in a caller's workspace.  One copy per device,
+// held until the process ends.  Host code never passes this name to a kernel
+// or a copy: it uses the device address that scratch_address() looks up.
+constexpr size_t kNoAllocScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
 
 typedef int64_t i64;
@@ -1058,6 +1065,89 @@ jk_status jk_build(const jk_problem *p, const double *B, const double *CL, const
     try {
         return jk_build_impl(p, B, CL, CR, J, K, ws, ws_bytes, stream);
     } catch (...) {
+        return JK_ENOMEM;
+    }
+}
+
+} // extern "C"
+
+namespace {
+
+// Device address of the scratch array on the current device, looked up once
+// per device (with that device current) and kept.
+hipError_t scratch_address(char **out)
+{
+    static std::mutex mu;
+    static std::map<int, char *> addr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        if (ptr == nullptr || ((uintptr_t)ptr) % kAlign)
+            return hipErrorInvalidSymbol;
+        it = addr.emplace(dev, (char *)ptr).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
+
+// Largest chunk budget (MiB, a power of two up to 256) whose FP64 plan fits
+// the scratch array; 0 if none does.
+int noalloc_chunk_mb(const jk_problem *p)
+{
+    for (int mb = 256; mb >= 1; mb /= 2)
+        if (plan_forward(p, (size_t)mb << 20).total <= kNoAllocScratchBytes)
+            return mb;
+    return 0;
+}
+
+jk_status jk_build_noalloc_impl(const jk_problem *p, const double *B, const double *CL,
+                                const double *CR, double *J, double *K, void *stream)
+{
+    if (!valid_problem(p))
+        return JK_EINVAL;
+    const int w = want(p);
+    if (!B || !CL || !CR)
+        return JK_EINVAL;
+    if ((w & JK_WANT_J) && !J)
+        return JK_EINVAL;
+    if ((w & JK_WANT_K) && !K)
+        return JK_EINVAL;
+    if (p->precision != JK_FP64)
+        return JK_EUNSUPPORTED;
+    const int mb = noalloc_chunk_mb(p);
+    if (mb == 0)
+        return JK_EWORKSPACE;
+    char *ws = nullptr;
+    if (scratch_address(&ws) != hipSuccess)
+        return JK_EHIP;
+    // the recorded tile, with the chunk budget the scratch array allows
+    jk_tuning plan = plan_tuning(p);
+    plan.chunk_mb = mb;
+    t_forced = &plan;
+    const jk_status st = build_plain(p, B, CL, CR, J, K, ws, (hipStream_t)stream);
+    t_forced = nullptr;
+    return st;
+}
+
+} // namespace
+
+extern "C" {
+
+jk_status jk_build_noalloc(const jk_problem *p, const double *B, const double *CL, const double *CR,
+                           double *J, double *K, void *stream)
+{
+    try {
+        return jk_build_noalloc_impl(p, B, CL, CR, J, K, stream);
+    } catch (...) {
+        t_forced = nullptr;
         return JK_ENOMEM;
     }
 }

@@ -63,18 +63,22 @@ typedef enum {
 typedef enum {
     JK_FP64 = 0,   /* every product and sum in FP64                          */
     JK_MIXED = 1   /* half-transforms and K products on the INT8 matrix
-                      cores as exact fixed-point slice products (5 signed
-                      7-bit digits per value, one power-of-two scale per
-                      row, int32 accumulation); FP64 for gamma, J, the
-                      recombination of the slice levels, every cross-chunk
-                      sum and the final accumulation.  Normwise error of K
-                      about 1e-10..1e-9 on smoothly scaled inputs; rows
-                      whose inner-index magnitudes span many orders of
-                      magnitude lose the small entries (fixed point).
-                      Exactness of the int32 sums: |digit| <= 64, and a
-                      level adds at most 5 digit pairs per inner index, so
+                      cores as exact fixed-point slice products: each row
+                      gets one power-of-two scale 2^e (max|row| <=
+                      2^e 127/128) and each value the 31-bit integer
+                      rint(a 2^(31-e)), written as 4 balanced base-256
+                      digits; the 13 digit pairs with i + j <= 6 are
+                      multiplied with int32 accumulation.  FP64 for gamma,
+                      J, the recombination of the digit levels (power-of-
+                      two weights), every cross-chunk sum and the final
+                      accumulation.  Normwise error of K about 1e-9 on
+                      smoothly scaled inputs; rows whose inner-index
+                      magnitudes span many orders of magnitude lose the
+                      small entries (fixed point).
+                      Exactness of the int32 sums: |digit| <= 128, and a
+                      level adds at most 4 digit pairs per inner index, so
                       a sum over n indices stays below 2^31 for
-                      n <= 104857; the planner splits every contraction to
+                      n <= 32767; the planner splits every contraction to
                       at most that depth (jk_plan_describe in jk_tune.h
                       reports it).                                           */
 } jk_precision;
@@ -97,8 +101,9 @@ typedef struct {
     int32_t precision; /* jk_precision                                       */
     int32_t flags;     /* JK_WANT_J | JK_WANT_K (neither means both),
                           optionally | JK_B_PACKED                           */
-    int32_t nslice;    /* JK_MIXED only: digits per operand; 0 or 5 (the
-                          one implemented value; 1..4 give JK_EUNSUPPORTED) */
+    int32_t nslice;    /* JK_MIXED only: digits per operand; 0 or 4 (the
+                          one implemented value; 1..3 and 5 give
+                          JK_EUNSUPPORTED)                                   */
     int32_t reserved;  /* must be 0                                          */
 } jk_problem;
 

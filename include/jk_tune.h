@@ -67,7 +67,7 @@ typedef struct {
                                exchange: one split of a chunk's slab-rank index); 0 for
                                JK_FP64                                                    */
     int32_t int_depth_cap;  /* JK_MIXED: the depth up to which those sums are exact,
-                               104857 (5 digit pairs of at most 2^12 per index stay
+                               32767 (4 digit pairs of at most 2^14 per index stay
                                below 2^31); 0 for JK_FP64.  Every plan keeps
                                int_depth <= int_depth_cap by splitting the exchange.   */
     int32_t reserved;

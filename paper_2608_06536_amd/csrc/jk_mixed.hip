@@ -19,7 +19,7 @@
 namespace jk {
 
 namespace {
-constexpr int kNS = 5;                  // digits per operand (35 bits)
+constexpr int kNS = kSliceDigits;       // digits per operand (31 bits)
 constexpr int kMT = 128, kNT = 128;     // workgroup tile: eight waves of 32 x 64
 constexpr int kWTN = 2;                 // MFMA tiles per wave, side by side
 constexpr int kRowPad = 128;            // plane rows are padded to this
@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(256) k_slice_rows(const double *__restrict__ s
         for (int u = 0; u < 4; u++) {
             const int k = kb * kSliceKB + sub * 4 + u;
             const double v = (live && k < nk) ? s[(i64)k * ks] : 0.0;
-            slice_value<kNS>(v, e, d[u]);
+            slice_value(v, e, d[u]);
         }
         write_digits(dst + (i64)kb * kbstride, pstride, d);
     }
@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(256) k_slice_rows_wave(const double *__restric
             int8_t d[4][kNS];
 #pragma unroll
             for (int u = 0; u < 4; u++)
-                slice_value<kNS>(v[j][u], e, d[u]);
+                slice_value(v[j][u], e, d[u]);
             write_digits(dst + (i64)kb * kbstride, pstride, d);
         }
     }
@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(256) k_slice_band_packed(const double *__restr
                 int8_t d[4][kNS];
 #pragma unroll
                 for (int u = 0; u < 4; u++)
-                    slice_value<kNS>(v[j][u], e, d[u]);
+                    slice_value(v[j][u], e, d[u]);
                 write_digits(dst + (i64)kb * kbstride, pstride, d);
             }
         }
@@ -263,7 +263,7 @@ __device__ __forceinline__ void slice_xy_block(const double *__restrict__ XY, in
     int8_t d[4][kNS];
 #pragma unroll
     for (int u = 0; u < 4; u++)
-        slice_value<kNS>((live && j0 + u < nj) ? x[u] : 0.0, e, d[u]);
+        slice_value((live && j0 + u < nj) ? x[u] : 0.0, e, d[u]);
     write_digits(out + (i64)kb * kbstride + (i64)row * kSliceKB + sub * 4, pstride, d);
 }
 
@@ -282,7 +282,7 @@ __global__ void __launch_bounds__(256) k_slice_xy(const double *__restrict__ XY,
 }
 
 // ------------------------------------------------------------------ half-transform
-// For slab ql of the chunk: XY[ql][m][c] = 2^(eB + eC + 2) * sum_l S_l 2^(-7 l)
+// For slab ql of the chunk: XY[ql][m][c] = 2^(eB + eC - 14) * sum_l S_l 2^(-8 (l - 2))
 // (c < R: X = B^Q C_L, c >= R: Y = B^Q C_R).  A planes: rows ql * mp + m;
 // B planes: rows c.  Each workgroup writes whole 512-byte row segments.
 __global__ void __launch_bounds__(512) k_ht_mixed(const int8_t *__restrict__ Bp, i64 bpstride,
@@ -303,7 +303,7 @@ __global__ void __launch_bounds__(512) k_ht_mixed(const int8_t *__restrict__ Bp,
     SPlanes b{Cp, cpstride, ckbstride};
     SAccW<TL> acc;
     acc.zero();
-    stile_gemm_wide<TL, kNS>(a, b, mb * kMT, cb * kNT, 0, nkb, lds, acc);
+    stile_gemm_pp<TL, kNS>(a, b, mb * kMT, cb * kNT, 0, nkb, lds, acc);
     double *out = XY + (i64)ql * nao * R2;
 #pragma unroll
     for (int tt = 0; tt < kWTN; tt++)
@@ -314,7 +314,7 @@ __global__ void __launch_bounds__(512) k_ht_mixed(const int8_t *__restrict__ Bp,
             const int m = mb * kMT + row, c = cb * kNT + col;
             if (m < nao && c < R2)
                 out[(i64)m * R2 + c] =
-                    ldexp(combine_levels_wide<TL>(acc, tt, e), eB[(i64)ql * mp + m] + eC[c] + 2);
+                    ldexp(combine_levels_wide<TL>(acc, tt, e), eB[(i64)ql * mp + m] + eC[c] + kSliceProdShift);
         }
 }
 
@@ -362,7 +362,7 @@ __global__ void __launch_bounds__(256) k_xy_rowmax(const double *__restrict__ XY
 }
 
 // ------------------------------------------------------------------ exchange
-// Kp[s][k][m][n] (+)= scale 2^(eX + eY + 2) * sum_l S_l 2^(-7 l) over the inner
+// Kp[s][k][m][n] (+)= scale 2^(eX + eY - 14) * sum_l S_l 2^(-8 (l - 2)) over the inner
 // blocks [s * kbl, (s + 1) * kbl) of split s.  X/Y planes: rows k * mp + m
 // from Xp / Yp (same strides); row exponents eX[k * mp + m], eY[k * mp + n].
 __global__ void __launch_bounds__(512) k_ex_mixed(const int8_t *__restrict__ Xp,
@@ -401,7 +401,7 @@ __global__ void __launch_bounds__(512) k_ex_mixed(const int8_t *__restrict__ Xp,
     SPlanes b{Yp + (i64)k * mp * kSliceKB, pstride, kbstride};
     SAccW<TL> acc;
     acc.zero();
-    stile_gemm_wide<TL, kNS>(a, b, mb * kMT, nb * kNT, kb0, kb1, lds, acc);
+    stile_gemm_pp<TL, kNS>(a, b, mb * kMT, nb * kNT, kb0, kb1, lds, acc);
     double *Kk = Kp + ((i64)sp * nd + k) * nao * nao;
 #pragma unroll
     for (int tt = 0; tt < kWTN; tt++)
@@ -412,7 +412,7 @@ __global__ void __launch_bounds__(512) k_ex_mixed(const int8_t *__restrict__ Xp,
             const int m = mb * kMT + row, n = nb * kNT + col;
             if (m < nao && n < nao) {
                 const double v = scale * ldexp(combine_levels_wide<TL>(acc, tt, e),
-                                               eX[(i64)k * mp + m] + eY[(i64)k * mp + n] + 2);
+                                               eX[(i64)k * mp + m] + eY[(i64)k * mp + n] + kSliceProdShift);
                 const i64 o = (i64)m * nao + n;
                 Kk[o] = accumulate ? Kk[o] + v : v;
             }
@@ -550,13 +550,13 @@ hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, i64 bkbstride, const 
                            const int8_t *Cp, i64 cpstride, i64 ckbstride, const int *eC, double *XY,
                            int nao, int R2, int nq, int mp, int cp, int nkb, hipStream_t s)
 {
-    hipError_t e = set_lds((const void *)k_ht_mixed, TileS::LDS_BYTES);
+    hipError_t e = set_lds((const void *)k_ht_mixed, SPingPong<TileS>::LDS_BYTES);
     if (e != hipSuccess)
         return e;
     {
         ProfScope ps_("ht_mixed", s);
         hipLaunchKernelGGL(k_ht_mixed, dim3(nq * (mp / kMT) * (cp / kNT)), dim3(TileS::NTHR),
-                           TileS::LDS_BYTES, s, Bp, bpstride, bkbstride, eB, Cp, cpstride, ckbstride,
+                           SPingPong<TileS>::LDS_BYTES, s, Bp, bpstride, bkbstride, eB, Cp, cpstride, ckbstride,
                            eC, XY, nao, R2, mp, cp, nkb);
     }
     return hipGetLastError();
@@ -583,7 +583,7 @@ hipError_t launch_ex_mixed(const int8_t *Xp, const int8_t *Yp, i64 pstride, i64 
                            const int *eX, const int *eY, double *Kp, int nao, int nd, int mp, int nkb,
                            int nsplit, int accumulate, hipStream_t s, int sym, double scale)
 {
-    hipError_t e = set_lds((const void *)k_ex_mixed, TileS::LDS_BYTES);
+    hipError_t e = set_lds((const void *)k_ex_mixed, SPingPong<TileS>::LDS_BYTES);
     if (e != hipSuccess)
         return e;
     const int kbl = cdiv(nkb, nsplit);
@@ -591,7 +591,7 @@ hipError_t launch_ex_mixed(const int8_t *Xp, const int8_t *Yp, i64 pstride, i64 
     const int pk = sym ? nmt * (nmt + 1) / 2 : nmt * (mp / kNT);
     {
         ProfScope ps_("ex_mixed", s);
-        hipLaunchKernelGGL(k_ex_mixed, dim3(nsplit * nd * pk), dim3(TileS::NTHR), TileS::LDS_BYTES, s, Xp,
+        hipLaunchKernelGGL(k_ex_mixed, dim3(nsplit * nd * pk), dim3(TileS::NTHR), SPingPong<TileS>::LDS_BYTES, s, Xp,
                            Yp, pstride, kbstride, eX, eY, Kp, nao, nd, mp, nkb, kbl, accumulate, sym,
                            scale);
     }

@@ -1,23 +1,27 @@
 // slice_core.hpp -- fixed-point slice products on gfx950 INT8 matrix cores.
 //
 // Split-precision scheme of the mixed J/K path.  Every FP64 row a[0..n) of an
-// operand gets one power-of-two scale 2^e with max|a| < 2^e, and is cut into
-// NS signed 7-bit digits (base 2^7, round to nearest, |digit| <= 64):
-//     a = 2^(e+1) * sum_{i=1..NS} d_i 2^(-7 i) + rest,  |rest| <= 2^(e - 7 NS)
-// so each digit plane holds int8 values.  A product of two rows is
-//     sum_k a_k b_k = 2^(ea+eb+2) * sum_{l} 2^(-7 l) * S_l,
+// operand gets one power-of-two scale 2^e with max|a| <= 2^e * 127/128, and
+// each element is rounded to the 31-bit integer N = rint(a 2^(31 - e)),
+// |N| <= 127 * 2^24, written as NS = 4 balanced base-256 digits
+//     N = d1 2^24 + d2 2^16 + d3 2^8 + d4,   d2..d4 in [-128, 127],
+// taken from the bottom (d4 = ((N + 128) mod 256) - 128, then N -> (N - d4)/256,
+// ...); the leading digit is what remains, |d1| <= 127.  So
+//     a = 2^(e - 7) * sum_{i=1..4} d_i 2^(-8 (i - 1)) + rest,  |rest| <= 2^(e - 32).
+// A product of two rows is
+//     sum_k a_k b_k = 2^(ea + eb - 14) * sum_{l=2..L} 2^(-8 (l - 2)) * S_l,
 //     S_l = sum_{i+j=l} sum_k d_i(a_k) d_j(b_k),
-// keeping the pairs with i + j <= NS + 1.  Each S_l is an exact integer: the
-// matrix cores multiply int8 digits and accumulate in int32, and
-// |S_l| <= 5 * n * 2^12 < 2^31 for n <= kSliceMaxDepth = 104857 inner indices
-// per accumulation (enforced by the planner).  The levels are
-// combined in FP64 at the end (exact conversions, power-of-two weights), so
-// the only approximations are the dropped low digits (relative ~2^-34 for
-// NS = 5) and FP64 rounding.
+// keeping the 13 digit pairs with i + j <= L = 6.  Each S_l is an exact
+// integer: the matrix cores multiply int8 digits and accumulate in int32; a
+// level holds at most 4 pairs of |d_i d_j| <= 2^14 per inner index, so
+// |S_l| <= 2^16 n < 2^31 for n <= kSliceMaxDepth = 32767 inner indices per
+// accumulation (enforced by the planner).  The levels are combined in FP64
+// with power-of-two weights, so the only approximations are the rounding of
+// N (relative 2^-32 of the row scale), the three dropped pairs, and FP64
+// rounding of the combination.
 //
-// Instruction: V_MFMA_I32_32X32X32_I8 (measured 4.6 POP/s on MI355X, about
-// twice the BF16 32x32x16 rate).  Lane layout (measured on the device): lane
-// l holds A[row l % 32][k 16*(l/32) .. +15] and B[k 16*(l/32) .. +15][col
+// Instruction: V_MFMA_I32_32X32X32_I8.  Lane layout (measured on the device):
+// lane l holds A[row l % 32][k 16*(l/32) .. +15] and B[k 16*(l/32) .. +15][col
 // l % 32] as 16 bytes each, and output element j (0..15) is
 // C[8*(j/4) + 4*(l/32) + j%4][l % 32].
 //
@@ -34,37 +38,45 @@ typedef int64_t i64;
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kSliceBits = 7;          // bits per digit
+constexpr int kSliceDigits = 4;        // digits per value (planes per operand)
+constexpr int kSliceLevel = 6;         // products d_i d_j with i + j <= 6 are kept
 constexpr int kSliceKB = 32;           // inner block: bytes per row per block
-// Most inner indices one int32 level sum may take: a level holds at most 5
-// digit pairs of |d_i d_j| <= 2^12 per index, so n indices give
-// |S_l| <= 5 n 2^12, below 2^31 for n <= 104857.  Every plan splits its
+constexpr int kSliceProdShift = -14;   // a row product is 2^(ea + eb - 14) * sum_l ...
+// Most inner indices one int32 level sum may take (see above): at most 4
+// digit pairs of |d_i d_j| <= 2^14 per index, so n indices give
+// |S_l| <= 2^16 n, below 2^31 for n <= 32767.  Every plan splits its
 // contractions so that no accumulation exceeds this depth.
-constexpr int kSliceMaxDepth = 104857;
+constexpr int kSliceMaxDepth = 32767;
 
 __device__ __forceinline__ v16i mfma_i8(v4i a, v4i b, v16i c)
 {
     return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
 }
 
-// Digits of one value given the row exponent e (max|row| < 2^e):
-// d[i] = digit i+1 of a * 2^-e, i < NS.
-template <int NS>
-__device__ __forceinline__ void slice_value(double a, int e, int8_t *d)
-{
-    double x = ldexp(a, -e) * 64.0;            // |x| < 64
-#pragma unroll
-    for (int i = 0; i < NS; i++) {
-        const double t = rint(x);
-        d[i] = (int8_t)(int)t;
-        x = (x - t) * 128.0;                   // |x| <= 64, exact
-    }
-}
-
-// Exponent with max|row| < 2^e (0 for an all-zero row).
+// Scale exponent of a row: the smallest e with maxabs <= 2^e * 127/128 (0 for
+// an all-zero row).  Both comparisons are exact in FP64.
 __device__ __forceinline__ int row_exponent(double maxabs)
 {
-    return maxabs > 0.0 ? ilogb(maxabs) + 1 : 0;
+    if (!(maxabs > 0.0))
+        return 0;
+    int e = ilogb(maxabs) + 1;                       // 2^(e-1) <= maxabs < 2^e
+    if (maxabs * 128.0 > ldexp(127.0, e))
+        e++;
+    return e;
+}
+
+// The four digits of a, given the row exponent e (|a| <= 2^e * 127/128):
+// d[0] is the leading digit.
+__device__ __forceinline__ void slice_value(double a, int e, int8_t *d)
+{
+    int n = (int)rint(ldexp(a, 31 - e));             // |n| <= 127 * 2^24
+#pragma unroll
+    for (int i = kSliceDigits - 1; i > 0; i--) {
+        const int t = ((n + 128) & 255) - 128;
+        d[i] = (int8_t)t;
+        n = (n - t) >> 8;                            // exact: n - t is a multiple of 256
+    }
+    d[0] = (int8_t)n;
 }
 
 // ---------------------------------------------------------------- planes
@@ -79,150 +91,13 @@ struct SPlanes {
     i64 kbstride;         // bytes between inner blocks
 };
 
-// ---------------------------------------------------------------- tile GEMM
-// One workgroup: BM x BN output tile, waves (BM/32) x (BN/32), one 32x32
-// MFMA tile per wave, NS digit planes per operand, one 32-byte inner block
-// per pipeline stage.  LDS stage layout: [plane][row][32 bytes] for A, then
-// the same for B.  The two 16-byte halves of a row swap places on every
-// other group of 8 rows, so the 64 lanes of a fragment read (rows r..r+31,
-// half l/32) spread evenly over the LDS banks.
-template <int BM, int BN, int NS>
-struct STile {
-    static constexpr int WROWS = BM / 32, WCOLS = BN / 32;
-    static constexpr int NWAVE = WROWS * WCOLS;
-    static constexpr int NTHR = NWAVE * 64;
-    static constexpr int NLEV = NS;            // levels 2..NS+1
-    static constexpr int A_BYTES = NS * BM * kSliceKB, B_BYTES = NS * BN * kSliceKB;
-    static constexpr int STAGE_BYTES = A_BYTES + B_BYTES;
-    static constexpr int LDS_BYTES = 2 * STAGE_BYTES;
-};
-
-// Byte offset of (row, 16-byte half) inside a plane of an LDS stage.
+// Byte offset of (row, 16-byte half) inside a plane of an LDS stage.  The two
+// 16-byte halves of a row swap places on every other group of 8 rows, so the
+// 64 lanes of a fragment read (rows r..r+31, half l/32) spread evenly over
+// the LDS banks.
 __device__ __forceinline__ int slds_off(int row, int half)
 {
     return row * kSliceKB + ((half ^ ((row >> 3) & 1)) << 4);
-}
-
-template <int T, int NS, int NTHR>
-struct SLoader {
-    // 16-byte chunks per stage: NS planes x T rows x 2 halves
-    static constexpr int NCH = NS * T * 2;
-    static constexpr int NSTEP = (NCH + NTHR - 1) / NTHR;
-    v4i v[NSTEP];
-
-    __device__ __forceinline__ void load(const SPlanes &op, int i0, int kb, int tid)
-    {
-#pragma unroll
-        for (int s = 0; s < NSTEP; s++) {
-            const int c = tid + s * NTHR;
-            if (NCH % NTHR == 0 || c < NCH) {
-                const int p = c / (T * 2), rr = c % (T * 2);
-                v[s] = *(const v4i *)(op.base + p * op.pstride + (i64)kb * op.kbstride +
-                                      (i64)i0 * kSliceKB + rr * 16);
-            }
-        }
-    }
-
-    __device__ __forceinline__ void store(char *lds, int tid) const
-    {
-#pragma unroll
-        for (int s = 0; s < NSTEP; s++) {
-            const int c = tid + s * NTHR;
-            if (NCH % NTHR == 0 || c < NCH) {
-                const int p = c / (T * 2), rr = c % (T * 2);
-                *(v4i *)(lds + p * T * kSliceKB + slds_off(rr >> 1, rr & 1)) = v[s];
-            }
-        }
-    }
-};
-
-template <class TL>
-struct SAcc {
-    v16i c[TL::NLEV];
-    __device__ __forceinline__ void zero()
-    {
-#pragma unroll
-        for (int l = 0; l < TL::NLEV; l++)
-#pragma unroll
-            for (int e = 0; e < 16; e++)
-                c[l][e] = 0;
-    }
-};
-
-// acc_l += sum over inner blocks [kb_begin, kb_end) of the digit pair
-// products with i + j = l + 2 (i, j = 1..NS, i + j <= NS + 1).
-//
-// Pipeline: the block of stage s is copied global -> registers -> LDS buffer
-// s % 2 during stage s - 2, its fragments are read from LDS into registers
-// during stage s - 1 (while the MFMAs of stage s - 1 run), and it is
-// multiplied in stage s.  One barrier per stage (plus one after the first
-// fragment reads); a buffer is refilled only after a barrier that follows
-// every read of its previous contents.
-template <class TL, int NS>
-__device__ __forceinline__ void stile_gemm(const SPlanes &A, const SPlanes &B, int m0, int n0,
-                                           int kb_begin, int kb_end, char *lds, SAcc<TL> &acc)
-{
-    constexpr int BM = TL::WROWS * 32, BN = TL::WCOLS * 32;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
-    SLoader<BM, NS, TL::NTHR> la;
-    SLoader<BN, NS, TL::NTHR> lb;
-    const int nst = kb_end - kb_begin;
-    if (nst <= 0)
-        return;
-    la.load(A, m0, kb_begin, tid);
-    lb.load(B, n0, kb_begin, tid);
-    la.store(lds, tid);
-    lb.store(lds + TL::A_BYTES, tid);
-    if (nst > 1) {
-        la.load(A, m0, kb_begin + 1, tid);
-        lb.load(B, n0, kb_begin + 1, tid);
-        la.store(lds + TL::STAGE_BYTES, tid);
-        lb.store(lds + TL::STAGE_BYTES + TL::A_BYTES, tid);
-    }
-    __syncthreads();
-    const int aoff = slds_off(wr * 32 + (lane & 31), lane >> 5);
-    const int boff = slds_off(wc * 32 + (lane & 31), lane >> 5);
-    v4i fa[NS], fb[NS];
-#pragma unroll
-    for (int p = 0; p < NS; p++) {
-        fa[p] = *(const v4i *)(lds + p * BM * kSliceKB + aoff);
-        fb[p] = *(const v4i *)(lds + TL::A_BYTES + p * BN * kSliceKB + boff);
-    }
-    // buffer 0 is refilled in the first stage: every wave must have read its
-    // stage-0 fragments first
-    __syncthreads();
-    for (int st = 0; st < nst; st++) {
-        const bool more2 = st + 2 < nst;
-        if (more2) {
-            la.load(A, m0, kb_begin + st + 2, tid);
-            lb.load(B, n0, kb_begin + st + 2, tid);
-        }
-        // fragments of stage st + 1 (on the last stage: a harmless re-read)
-        const char *sa = lds + ((st + 1) & 1) * TL::STAGE_BYTES;
-        const char *sb = sa + TL::A_BYTES;
-        v4i ga[NS], gb[NS];
-#pragma unroll
-        for (int p = 0; p < NS; p++) {
-            ga[p] = *(const v4i *)(sa + p * BM * kSliceKB + aoff);
-            gb[p] = *(const v4i *)(sb + p * BN * kSliceKB + boff);
-        }
-#pragma unroll
-        for (int i = 0; i < NS; i++)
-#pragma unroll
-            for (int j = 0; j < NS - i; j++)          // (i+1) + (j+1) <= NS + 1
-                acc.c[i + j] = mfma_i8(fa[i], fb[j], acc.c[i + j]);
-#pragma unroll
-        for (int p = 0; p < NS; p++) {
-            fa[p] = ga[p];
-            fb[p] = gb[p];
-        }
-        if (more2) {
-            la.store(lds + (st & 1) * TL::STAGE_BYTES, tid);
-            lb.store(lds + (st & 1) * TL::STAGE_BYTES + TL::A_BYTES, tid);
-        }
-        __syncthreads();
-    }
 }
 
 // 16 bytes per lane from global memory straight into LDS at dst + 16 * lane
@@ -235,118 +110,20 @@ __device__ __forceinline__ void global_to_lds16(const int8_t *src, char *dst)
 #endif
 }
 
-// Same product with direct global -> LDS copies (global_load_lds_dwordx4):
-// no staging registers.  A wave instruction fills one kilobyte of LDS, lane l
-// at byte 16 l (measured), so each lane picks the global 16-byte chunk that
-// belongs at its LDS slot of the swizzled layout: the slot (row, half') holds
-// the chunk (row, half' ^ swizzle(row)).  A stage is NS planes x (BM + BN) / 32
-// such blocks, spread over the waves.  Stage s is copied into buffer s % 2
-// at the start of stage s - 2 and waited for at the end of that stage.
-template <class TL, int NS, int SCHED = 0>
-__device__ __forceinline__ void stile_gemm_direct(const SPlanes &A, const SPlanes &B, int m0, int n0,
-                                                  int kb_begin, int kb_end, char *lds,
-                                                  SAcc<TL> &acc)
-{
-    constexpr int BM = TL::WROWS * 32, BN = TL::WCOLS * 32;
-    constexpr int NBA = NS * (BM / 32), NB = NBA + NS * (BN / 32);
-    constexpr int NW = TL::NWAVE, PER = (NB + NW - 1) / NW;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
-    const int nst = kb_end - kb_begin;
-    if (nst <= 0)
-        return;
-    const int8_t *gp[PER];
-    i64 kbs[PER];
-    int loff[PER];
-#pragma unroll
-    for (int u = 0; u < PER; u++) {
-        const int b = wave + u * NW;
-        const int bb = b < NB ? b : 0;
-        const bool isA = bb < NBA;
-        const int bl = isA ? bb : bb - NBA;
-        const int T = isA ? BM : BN;
-        const int p = bl / (T / 32), rh = bl % (T / 32);
-        const int row = rh * 32 + (lane >> 1);
-        const int half = (lane & 1) ^ ((row >> 3) & 1);
-        const SPlanes &op = isA ? A : B;
-        gp[u] = op.base + p * op.pstride + (i64)((isA ? m0 : n0) + row) * kSliceKB + half * 16;
-        kbs[u] = op.kbstride;
-        loff[u] = (isA ? 0 : TL::A_BYTES) + p * T * kSliceKB + rh * 32 * kSliceKB;
-    }
-    auto issue = [&](int kb, int buf) {
-#pragma unroll
-        for (int u = 0; u < PER; u++)
-            if (NB % NW == 0 || wave + u * NW < NB)
-                global_to_lds16(gp[u] + (i64)kb * kbs[u], lds + buf * TL::STAGE_BYTES + loff[u]);
-    };
-    issue(kb_begin, 0);
-    if (nst > 1)
-        issue(kb_begin + 1, 1);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    const int aoff = slds_off(wr * 32 + (lane & 31), lane >> 5);
-    const int boff = slds_off(wc * 32 + (lane & 31), lane >> 5);
-    v4i fa[NS], fb[NS];
-#pragma unroll
-    for (int p = 0; p < NS; p++) {
-        fa[p] = *(const v4i *)(lds + p * BM * kSliceKB + aoff);
-        fb[p] = *(const v4i *)(lds + TL::A_BYTES + p * BN * kSliceKB + boff);
-    }
-    __syncthreads();     // buffer 0 is refilled in the first stage
-    for (int st = 0; st < nst; st++) {
-        if (st + 2 < nst)
-            issue(kb_begin + st + 2, st & 1);
-        const char *sa = lds + ((st + 1) & 1) * TL::STAGE_BYTES;
-        const char *sb = sa + TL::A_BYTES;
-        v4i ga[NS], gb[NS];
-#pragma unroll
-        for (int p = 0; p < NS; p++) {
-            ga[p] = *(const v4i *)(sa + p * BM * kSliceKB + aoff);
-            gb[p] = *(const v4i *)(sb + p * BN * kSliceKB + boff);
-        }
-#pragma unroll
-        for (int i = 0; i < NS; i++)
-#pragma unroll
-            for (int j = 0; j < NS - i; j++)
-                acc.c[i + j] = mfma_i8(fa[i], fb[j], acc.c[i + j]);
-        if (SCHED == 1) {
-            // next-stage fragment reads first, then the products
-            __builtin_amdgcn_sched_group_barrier(0x100, 2 * NS, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, NS * (NS + 1) / 2, 0);
-        } else if (SCHED == 2) {
-            // one fragment read between consecutive products
-#pragma unroll
-            for (int q = 0; q < 2 * NS; q++) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            }
-            __builtin_amdgcn_sched_group_barrier(0x008, NS * (NS + 1) / 2 - 2 * NS, 0);
-        }
-#pragma unroll
-        for (int p = 0; p < NS; p++) {
-            fa[p] = ga[p];
-            fb[p] = gb[p];
-        }
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------- wide tiles
-// Each wave owns 32 x (32 WTN) outputs (WTN MFMA tiles side by side), so one
-// A fragment feeds WTN tiles: fewer LDS bytes per product.  Waves (BM/32) x
-// (BN/(32 WTN)).  Direct global -> LDS copies, double-buffered LDS stages,
-// fragments read at the start of each stage.
+// ---------------------------------------------------------------- tiles
+// Workgroup tile BM x BN; each wave owns 32 x (32 WTN) outputs (WTN MFMA
+// tiles side by side), so one A fragment feeds WTN tiles.  Waves (BM/32) x
+// (BN/(32 WTN)).  One pipeline stage is one 32-byte inner block of NS planes
+// of both operands.
 template <int BM, int BN, int NS, int WTN>
 struct STileW {
     static constexpr int WROWS = BM / 32, WCOLS = BN / (32 * WTN);
     static constexpr int NWAVE = WROWS * WCOLS;
     static constexpr int NTHR = NWAVE * 64;
-    static constexpr int NLEV = NS;
+    static constexpr int NLEV = kSliceLevel - 1;       // levels 2..kSliceLevel
     static constexpr int TN = WTN;
     static constexpr int A_BYTES = NS * BM * kSliceKB, B_BYTES = NS * BN * kSliceKB;
     static constexpr int STAGE_BYTES = A_BYTES + B_BYTES;
-    static constexpr int LDS_BYTES = 2 * STAGE_BYTES;
 };
 
 template <class TL>
@@ -364,20 +141,81 @@ struct SAccW {
     }
 };
 
+// ---------------------------------------------------------------- ping-pong GEMM
+// acc_l += sum over inner blocks [kb_begin, kb_end) of the kept digit pairs of
+// level l, for the 128 x 128 tile of eight waves of 32 x 64 outputs.  The
+// waves work in two groups half a stage apart.  Group 0 (waves 0-3, rows
+// 0..63) reads a stage's fragments from LDS while group 1 (waves 4-7, rows
+// 64..127) multiplies the previous stage's, then the roles swap; every SIMD
+// holds one wave of each group, so its matrix core is fed by one group while
+// the other waits on LDS.  A workgroup barrier separates the phases.
+//
+// Three LDS stage buffers: the blocks of stage s are copied global -> LDS
+// (direct, 16 bytes per lane) in phase 2s - 4 and must have landed by the end
+// of phase 2s - 1, before group 0 reads them in phase 2s.  Stage s's buffer
+// is refilled with stage s + 3 in phase 2s + 2, after the barrier that ends
+// group 1's read of stage s (phase 2s + 1).
+template <class TL>
+struct SPingPong {
+    static_assert(TL::NWAVE == 8 && TL::WROWS == 4 && TL::WCOLS == 2, "two groups of four waves");
+    static constexpr int NBUF = 3;
+    static constexpr int LDS_BYTES = NBUF * TL::STAGE_BYTES;
+};
+
+// s_waitcnt with vmcnt <= n and the other counters unconstrained (gfx9
+// encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt()
+{
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// A pointer that is the same for every lane of the wave, kept in scalar
+// registers.
+__device__ __forceinline__ const int8_t *uniform_ptr(const int8_t *p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const int8_t *)(((uint64_t)hi << 32) | lo);
+}
+
+// Workgroup barrier without the memory fence of __syncthreads(): that fence
+// waits for every outstanding global load (vmcnt 0), which would drain the
+// copies of later stages.  The waits each phase needs are explicit.  The
+// empty asm statements keep memory accesses on their side of it, and the
+// scheduling barriers keep every other instruction there too (the compiler
+// would otherwise hoist matrix products into the other group's phase).
+__device__ __forceinline__ void wg_barrier()
+{
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 template <class TL, int NS>
-__device__ __forceinline__ void stile_gemm_wide(const SPlanes &A, const SPlanes &B, int m0, int n0,
-                                                int kb_begin, int kb_end, char *lds, SAccW<TL> &acc)
+__device__ __forceinline__ void stile_gemm_pp(const SPlanes &A, const SPlanes &B, int m0, int n0,
+                                              int kb_begin, int kb_end, char *lds, SAccW<TL> &acc)
 {
     constexpr int BM = TL::WROWS * 32, BN = TL::WCOLS * 32 * TL::TN, WTN = TL::TN;
     constexpr int NBA = NS * (BM / 32), NB = NBA + NS * (BN / 32);
     constexpr int NW = TL::NWAVE, PER = (NB + NW - 1) / NW;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NBUF = SPingPong<TL>::NBUF;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
+    const int grp = wave >> 2;
     const int nst = kb_end - kb_begin;
     if (nst <= 0)
         return;
-    const int8_t *gp[PER];
-    i64 kbs[PER];
+    // Block copies: a block is 32 rows x 32 bytes of one plane (1 KB, one
+    // wave instruction).  The block's global start and LDS slot are the same
+    // for the whole wave; lane l copies row l / 2, half (l & 1) swizzled to
+    // the LDS layout of slds_off.
+    const uint32_t lane_off = (lane >> 1) * kSliceKB + (((lane & 1) ^ ((lane >> 4) & 1)) << 4);
+    const int8_t *ub[PER];
     int loff[PER];
 #pragma unroll
     for (int u = 0; u < PER; u++) {
@@ -387,33 +225,29 @@ __device__ __forceinline__ void stile_gemm_wide(const SPlanes &A, const SPlanes 
         const int bl = isA ? bb : bb - NBA;
         const int T = isA ? BM : BN;
         const int p = bl / (T / 32), rh = bl % (T / 32);
-        const int row = rh * 32 + (lane >> 1);
-        const int half = (lane & 1) ^ ((row >> 3) & 1);
         const SPlanes &op = isA ? A : B;
-        gp[u] = op.base + p * op.pstride + (i64)((isA ? m0 : n0) + row) * kSliceKB + half * 16;
-        kbs[u] = op.kbstride;
+        ub[u] = uniform_ptr(op.base + p * op.pstride + (i64)((isA ? m0 : n0) + rh * 32) * kSliceKB);
         loff[u] = (isA ? 0 : TL::A_BYTES) + p * T * kSliceKB + rh * 32 * kSliceKB;
     }
+    const i64 akbs = A.kbstride, bkbs = B.kbstride;
     auto issue = [&](int kb, int buf) {
 #pragma unroll
-        for (int u = 0; u < PER; u++)
-            if (NB % NW == 0 || wave + u * NW < NB)
-                global_to_lds16(gp[u] + (i64)kb * kbs[u], lds + buf * TL::STAGE_BYTES + loff[u]);
+        for (int u = 0; u < PER; u++) {
+            const int b = wave + u * NW;
+            if (NB % NW == 0 || b < NB)
+                global_to_lds16(ub[u] + (i64)kb * (b < NBA ? akbs : bkbs) + lane_off,
+                                lds + buf * TL::STAGE_BYTES + loff[u]);
+        }
     };
     const int aoff = slds_off(wr * 32 + (lane & 31), lane >> 5);
     int boff[WTN];
 #pragma unroll
     for (int t = 0; t < WTN; t++)
         boff[t] = slds_off((wc * WTN + t) * 32 + (lane & 31), lane >> 5);
-    issue(kb_begin, 0);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    for (int st = 0; st < nst; st++) {
-        if (st + 1 < nst)
-            issue(kb_begin + st + 1, (st + 1) & 1);
-        const char *sa = lds + (st & 1) * TL::STAGE_BYTES;
+    v4i fa[NS], fb[WTN][NS];
+    auto read = [&](int st) {
+        const char *sa = lds + (st % NBUF) * TL::STAGE_BYTES;
         const char *sb = sa + TL::A_BYTES;
-        v4i fa[NS], fb[WTN][NS];
 #pragma unroll
         for (int p = 0; p < NS; p++) {
             fa[p] = *(const v4i *)(sa + p * BM * kSliceKB + aoff);
@@ -421,19 +255,70 @@ __device__ __forceinline__ void stile_gemm_wide(const SPlanes &A, const SPlanes 
             for (int t = 0; t < WTN; t++)
                 fb[t][p] = *(const v4i *)(sb + p * BN * kSliceKB + boff[t]);
         }
+    };
+    // digit pairs (i + 1, j + 1) with i + j + 2 <= kSliceLevel, into level i + j
+    auto mult = [&]() {
 #pragma unroll
         for (int i = 0; i < NS; i++)
 #pragma unroll
             for (int t = 0; t < WTN; t++)
 #pragma unroll
-                for (int j = 0; j < NS - i; j++)
-                    acc.c[t][i + j] = mfma_i8(fa[i], fb[t][j], acc.c[t][i + j]);
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
+                for (int j = 0; j < NS; j++)
+                    if (i + j + 2 <= kSliceLevel)
+                        acc.c[t][i + j] = mfma_i8(fa[i], fb[t][j], acc.c[t][i + j]);
+    };
+    // Each group runs its own loop (straight-line bodies, one fragment set
+    // each); the workgroup barriers pair up phase by phase:
+    //   phase 2s      group 0 reads stage s,       group 1 multiplies stage s - 1
+    //   phase 2s + 1  group 0 multiplies stage s,  group 1 reads stage s
+    // Both groups issue their copies of stage s in phase 2s - 4 and wait for
+    // them at the end of phase 2s - 1.
+    issue(kb_begin, 0);
+    if (nst > 1) {
+        issue(kb_begin + 1, 1);
+        wait_vmcnt<PER>();
+    } else {
+        wait_vmcnt<0>();
+    }
+    wg_barrier();
+    if (grp == 0) {
+#pragma clang loop unroll(disable)
+        for (int st = 0; st < nst; st++) {
+            if (st + 2 < nst)
+                issue(kb_begin + st + 2, (st + 2) % NBUF);
+            read(st);
+            __builtin_amdgcn_s_waitcnt(0xC07F);     // lgkmcnt(0): fragments in registers
+            wg_barrier();
+            mult();
+            if (st + 2 < nst)
+                wait_vmcnt<PER>();                  // stage st + 1 landed
+            else
+                wait_vmcnt<0>();
+            wg_barrier();
+        }
+    } else {
+        if (nst > 2)
+            issue(kb_begin + 2, 2);
+        wg_barrier();
+#pragma clang loop unroll(disable)
+        for (int st = 0; st < nst; st++) {
+            read(st);
+            __builtin_amdgcn_s_waitcnt(0xC07F);
+            if (st + 2 < nst)
+                wait_vmcnt<PER>();
+            else
+                wait_vmcnt<0>();
+            wg_barrier();
+            if (st + 3 < nst)
+                issue(kb_begin + st + 3, (st + 3) % NBUF);
+            mult();
+            if (st + 1 < nst)
+                wg_barrier();
+        }
     }
 }
 
-// Output coordinates of element e of tile t of this lane (wide tiles).
+// Output coordinates of element e of tile t of this lane.
 template <class TL>
 __device__ __forceinline__ void stile_coord_wide(int t, int e, int &row, int &col)
 {
@@ -443,36 +328,18 @@ __device__ __forceinline__ void stile_coord_wide(int t, int e, int &row, int &co
     col = (wc * TL::TN + t) * 32 + (lane & 31);
 }
 
+// FP64 value of output element e of tile t of this lane:
+// sum_l S_l 2^(-8 (l - 2)), before the 2^(ea + eb + kSliceProdShift) row and
+// column scale.  Every step is exact (power-of-two weights) unless the sum
+// needs more than 53 bits.
 template <class TL>
 __device__ __forceinline__ double combine_levels_wide(const SAccW<TL> &acc, int t, int e)
 {
-    double v = 0.0;
+    double v = (double)acc.c[t][TL::NLEV - 1][e];
 #pragma unroll
-    for (int l = TL::NLEV - 1; l >= 0; l--)
-        v += ldexp((double)acc.c[t][l][e], -kSliceBits * (l + 2));
+    for (int l = TL::NLEV - 2; l >= 0; l--)
+        v = fma(v, 0x1p-8, (double)acc.c[t][l][e]);
     return v;
-}
-
-// FP64 value of output element e (0..15) of this lane: sum_l S_l 2^(-7(l+2)),
-// before the 2^(ea+eb+2) row/column scale.
-template <class TL>
-__device__ __forceinline__ double combine_levels(const SAcc<TL> &acc, int e)
-{
-    double v = 0.0;
-#pragma unroll
-    for (int l = TL::NLEV - 1; l >= 0; l--)
-        v += ldexp((double)acc.c[l][e], -kSliceBits * (l + 2));
-    return v;
-}
-
-// Output coordinates of element e of this lane inside the workgroup tile.
-template <class TL>
-__device__ __forceinline__ void stile_coord(int e, int &row, int &col)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
-    row = wr * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-    col = wc * 32 + (lane & 31);
 }
 
 } // namespace jk

@@ -8,11 +8,11 @@ path's int32 slice sums at the deepest exchange split a plan allows.
   normwise), J identical across plans (it does not depend on chunks), K equal
   across plans to rounding, and the mixed build's K within 1e-8.
 * The int32 cap: a sum over n inner indices of digit-pair products stays
-  exact for n <= 104857.  Identity slabs and factors whose every entry is
-  v = 2 (64/128 - 64/128^2 + 64/128^3 - 64/128^4 + 64/128^5) give X and Y rows
-  of constant magnitude whose digits are (64, -64, 64, -64, 64): every level
-  sum is then as large as the digits allow (level 6 adds 5 * 4096 per index,
-  2,146,304,000 at depth 104800).  K and J have closed forms.
+  exact for n <= 32767.  Identity slabs and factors whose every entry is
+  v = (127 2^24 - 128 2^16 + 127 2^8 - 128) / 2^31 give X and Y rows of
+  constant magnitude whose digits are (127, -128, 127, -128): level 5 then
+  adds 4 * (-16256) per index, -2,119,782,400 at depth 32600, the most
+  negative sum these digits allow.  K and J have closed forms.
 """
 import numpy as np
 import pytest
@@ -88,25 +88,25 @@ def test_tile4_large_chunks(config4):
 
 
 def _digit_edge_value():
-    d = (64, -64, 64, -64, 64)
-    return 2.0 * sum(di * 128.0 ** -(i + 1) for i, di in enumerate(d))
+    n = 127 * 2 ** 24 - 128 * 2 ** 16 + 127 * 2 ** 8 - 128
+    return n / 2.0 ** 31
 
 
 @pytest.mark.parametrize("sym", [False, True])
 def test_mixed_int32_sums_at_the_cap(sym):
     from paper_2608_06536_amd import jk
     # one split per chunk needs a full round of exchange tiles: nao = 2048
-    # (16 x 16 tiles of 128); naux * r = 524 * 200 = 104800 inner indices
-    nao, naux, nd, r = 2048, 524, 1, 200
+    # (16 x 16 tiles of 128); naux * r = 163 * 200 = 32600 inner indices
+    nao, naux, nd, r = 2048, 163, 1, 200
     v = _digit_edge_value()
-    assert 0.99 < v < 1.0
+    assert 0.98 < v * 128 / 127 < 1.0           # row exponent 0, leading digit 127
     prob = jk.make_problem(nao, naux, nd, r, "mixed")
     try:
         jk.tuning_set(prob, 4, 4096)
         info = jk.plan_describe(prob)
         print(f"near-cap plan: {info}", flush=True)
         assert info["chunk_slabs"] == naux
-        assert 104000 <= info["int_depth"] <= info["int_depth_cap"]
+        assert 32000 <= info["int_depth"] <= info["int_depth_cap"]
         if not sym:
             assert info["nsplit"] == 1
         dev = torch.device("cuda")

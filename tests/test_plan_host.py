@@ -1,10 +1,10 @@
 """Host-side planning (no GPU): the mixed path's int32 slice sums stay exact
 under every plan the autotuner can pick.
 
-The mixed precision multiplies signed 7-bit digits (|d| <= 64) on the INT8
-matrix cores and sums each slice level in int32.  A level holds at most 5
-digit pairs of |d_i d_j| <= 2^12 per inner index, so a sum over n indices is
-exact while 5 n 2^12 < 2^31, i.e. n <= 104857.  jk_plan_describe reports the
+The mixed precision multiplies balanced base-256 digits (|d| <= 128) on the
+INT8 matrix cores and sums each slice level in int32.  A level holds at most 4
+digit pairs of |d_i d_j| <= 2^14 per inner index, so a sum over n indices is
+exact while 4 n 2^14 < 2^31, i.e. n <= 32767.  jk_plan_describe reports the
 deepest such sum of a plan (the half-transform's padded nao, or one exchange
 split of a chunk's slab-rank index) and the cap; the planner must split the
 exchange so that every plan stays within it.
@@ -16,7 +16,7 @@ import pytest
 from paper_2608_06536_amd import _lib, jk
 
 CHUNKS_MB = (64, 128, 256, 512, 1024, 2048, 4096)
-CAP = 104857
+CAP = 32767
 
 
 def _mixed(nao, naux, nd, r):
@@ -26,7 +26,7 @@ def _mixed(nao, naux, nd, r):
 def test_cap_value():
     info = jk.plan_describe(_mixed(48, 192, 1, 8), 4, 1024)
     assert info["int_depth_cap"] == CAP
-    assert 5 * CAP * 4096 < 2 ** 31 <= 5 * (CAP + 1) * 4096
+    assert 4 * CAP * 2 ** 14 < 2 ** 31 <= 4 * (CAP + 1) * 2 ** 14
 
 
 def test_deep_single_density_splits():
@@ -35,7 +35,7 @@ def test_deep_single_density_splits():
     p = _mixed(2000, 8000, 1, 200)
     info = jk.plan_describe(p, 4, 4096)
     assert info["chunk_slabs"] * 200 > CAP           # the chunk alone would overflow
-    assert info["nsplit"] >= 2 and info["nsplit_sym"] >= 2
+    assert info["nsplit"] >= 5 and info["nsplit_sym"] >= 5
     assert info["int_depth"] <= CAP
 
 

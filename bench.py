@@ -164,15 +164,20 @@ def main():
     ms_per_step = 1e3 * t_total / args.steps
     value = nd * args.steps / t_total
 
-    # ---- separate rates of the build and the derivative
-    def rate(fn, n=3):
+    # ---- separate rates of the build and the derivative: median over n calls,
+    # each bracketed by events on the calling stream (the library joins any
+    # second stream back into it before returning)
+    def rate(fn, n=20):
         fn()
         torch.cuda.synchronize()
-        a = time.perf_counter()
-        for _ in range(n):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(n)]
+        for a, b in ev:
+            a.record()
             fn()
+            b.record()
         torch.cuda.synchronize()
-        return (time.perf_counter() - a) / n
+        return float(np.median([a.elapsed_time(b) for a, b in ev])) * 1e-3
 
     t_build = rate(build)
     t_vjp = rate(vjp)
@@ -198,7 +203,24 @@ def main():
                  "speedup_mixed_vs_fp64_build": round(t_build / t_mixed, 3),
                  "max_err_K_mixed_vs_fp64": max(errs),
                  "J_mixed_equals_fp64": bool(torch.equal(Jm, J))}
-        del wsm
+        # B's digit planes made once (jk_slice_b, timed on its own) and reused
+        # by every build over the same B, as the paper's repeated builds on
+        # fixed Cholesky vectors would (Sec. 2.1, 2.2)
+        S = jk.slice_b(Bd, nao)
+        t_slice = rate(lambda: jk.slice_b(Bd, nao, out=S), n=5)
+        Kp = torch.empty_like(K)
+
+        def build_mixed_pre():
+            jk.jk_build(Bd, Ld, Rd, precision="mixed", out=(Jm, Kp), ws=wsm, slices=S)
+
+        t_pre = rate(build_mixed_pre)
+        torch.cuda.synchronize()
+        mixed.update({"build_ms_mixed_presliced": round(1e3 * t_pre, 3),
+                      "builds_per_s_mixed_presliced": round(nd / t_pre, 2),
+                      "speedup_mixed_presliced_vs_fp64_build": round(t_build / t_pre, 3),
+                      "slice_b_ms": round(1e3 * t_slice, 3), "slices_bytes": int(S.numel()),
+                      "presliced_K_equals_mixed": bool(torch.equal(Kp, Km))})
+        del wsm, S
     except StopIteration:
         pass
     except _lib.JKError as e:

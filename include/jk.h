@@ -123,6 +123,34 @@ jk_status jk_build(const jk_problem *p, const double *B, const double *CL,
                    const double *CR, double *J, double *K, void *ws,
                    size_t ws_bytes, void *stream);
 
+/* Digit planes of B for JK_MIXED, made once and reused by every build over
+ * the same B.  The consumers of the paper rebuild J and K many times on one
+ * set of Cholesky vectors (Sec. 2.1: the Z-vector iterations; Sec. 2.2: one
+ * build per Laplace point), so slicing B (reading its FP64 values and
+ * writing the integer planes) need not be repeated.
+ *   jk_slices_bytes   size of the buffer for problem *p (0 if *p is invalid
+ *                     or not JK_MIXED).  It depends on nao and naux only:
+ *                     about 4 bytes per element of B plus padding to 128
+ *                     rows and 32 columns per slab.
+ *   jk_slice_b        writes the planes of B (full or packed slabs, as
+ *                     p->flags says) into `slices` (DEVICE, 256-byte aligned,
+ *                     caller-owned), on the stream.
+ *   jk_build_sliced   jk_build with JK_MIXED that reads the half-transforms'
+ *                     B operand from `slices` instead of slicing B again; B
+ *                     itself is still read for gamma and J (FP64).  Same
+ *                     workspace as jk_build (jk_workspace_bytes).  The
+ *                     results are bit-identical to jk_build's.  `slices`
+ *                     must have been made by jk_slice_b from this B with the
+ *                     same nao, naux and layout flag (not checked); a B that
+ *                     changes needs new slices.
+ * Errors as jk_build; JK_EINVAL for a precision other than JK_MIXED. */
+size_t jk_slices_bytes(const jk_problem *p);
+jk_status jk_slice_b(const jk_problem *p, const double *B, void *slices, size_t slices_bytes,
+                     void *stream);
+jk_status jk_build_sliced(const jk_problem *p, const double *B, const void *slices,
+                          size_t slices_bytes, const double *CL, const double *CR, double *J,
+                          double *K, void *ws, size_t ws_bytes, void *stream);
+
 /* jk_build without a workspace, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Same operation, arguments, outputs and symmetric-density

@@ -16,8 +16,8 @@ JK_FP64, JK_MIXED = 0, 1
 JK_WANT_J, JK_WANT_K, JK_B_PACKED = 1, 2, 4
 
 # Every symbol include/jk.h and include/jk_prof.h declare.
-EXPORTS = ("jk_workspace_bytes", "jk_build", "jk_build_noalloc", "jk_fock_workspace_bytes",
-           "jk_fock",
+EXPORTS = ("jk_workspace_bytes", "jk_build", "jk_build_noalloc", "jk_slices_bytes", "jk_slice_b",
+           "jk_build_sliced", "jk_fock_workspace_bytes", "jk_fock",
            "jk_batched_workspace_bytes", "jk_build_batched", "jk_vjp", "jk_status_str")
 LAPLACE_EXPORTS = ("jk_laplace_quadrature", "jk_laplace_factors", "jk_laplace_workspace_bytes",
                    "jk_laplace_build")
@@ -74,6 +74,12 @@ def lib():
         L.jk_build.argtypes = [pp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.jk_build_noalloc.restype = ctypes.c_int
         L.jk_build_noalloc.argtypes = [pp, vp, vp, vp, vp, vp, vp]
+        L.jk_slices_bytes.restype = sz
+        L.jk_slices_bytes.argtypes = [pp]
+        L.jk_slice_b.restype = ctypes.c_int
+        L.jk_slice_b.argtypes = [pp, vp, vp, sz, vp]
+        L.jk_build_sliced.restype = ctypes.c_int
+        L.jk_build_sliced.argtypes = [pp, vp, vp, sz, vp, vp, vp, vp, vp, sz, vp]
         L.jk_fock_workspace_bytes.restype = sz
         L.jk_fock_workspace_bytes.argtypes = [pp, ctypes.c_int64]
         L.jk_fock.restype = ctypes.c_int

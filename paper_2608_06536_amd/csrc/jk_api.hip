@@ -473,9 +473,32 @@ jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const
     return JK_OK;
 }
 
+// Digit planes of a whole B made once by jk_slice_b (jk.h): row exponents of
+// the naux * mp plane rows, then the planes, K-blocked over all slabs.
+struct SliceLayout {
+    int mp, kp;
+    size_t o_exp, o_planes, total;
+    i64 kbstride, pstride;
+};
+
+SliceLayout slice_layout(const jk_problem *p)
+{
+    SliceLayout L;
+    L.mp = (int)pad_to(p->nao, jk::mixed_row_pad());
+    L.kp = (int)pad_to(p->nao, jk::mixed_k_pad());
+    const int KB = jk::mixed_k_block();
+    L.kbstride = (i64)p->naux * L.mp * KB;
+    L.pstride = L.kbstride * (L.kp / KB);
+    Carve c;
+    L.o_exp = c.take(sizeof(int) * (size_t)p->naux * L.mp);
+    L.o_planes = c.take((size_t)jk::mixed_nslice() * L.pstride);
+    L.total = c.off;
+    return L;
+}
+
 jk_status build_mixed(const jk_problem *p, const double *B, const KSeg *seg, int nseg,
                       const double *CL, const double *CR, const BuildOut &o, char *ws,
-                      hipStream_t s)
+                      hipStream_t s, const char *pre = nullptr)
 {
     const MixPlan x = plan_mixed(p, tuned_budget(p));
     const FwdPlan &f = x.f;
@@ -507,15 +530,20 @@ jk_status build_mixed(const jk_problem *p, const double *B, const KSeg *seg, int
     // exchange scale.
     struct Chunk {
         const double *B;
-        int nq;
+        int q0, nq;
         double scale;
     };
     std::vector<Chunk> chunks;
     for (int sgi = 0; sgi < nseg; sgi++)
         for (int q0 = 0; q0 < seg[sgi].naux; q0 += f.qc)
-            chunks.push_back({seg[sgi].B + (i64)q0 * f.slab,
+            chunks.push_back({seg[sgi].B + (i64)q0 * f.slab, q0,
                               (seg[sgi].naux - q0) < f.qc ? (seg[sgi].naux - q0) : f.qc,
                               seg[sgi].scale});
+    // B's digit planes: made here chunk by chunk, or read from the caller's
+    // prepared planes of the whole B (one segment only)
+    if (pre && nseg != 1)
+        return JK_EINVAL;
+    const SliceLayout SL = slice_layout(p);
     double *Cc = (double *)(ws + f.o_cc);
     int8_t *Cp = (int8_t *)(ws + x.o_cp);
     int *eC = (int *)(ws + x.o_ec);
@@ -527,14 +555,20 @@ jk_status build_mixed(const jk_problem *p, const double *B, const KSeg *seg, int
     double *Kp = nsplit > 1 ? (double *)(ws + x.o_kp) : K;
     const int KB = jk::mixed_k_block();
     // K-blocked plane strides (slice_core.hpp): kbstride = rows * 32 bytes
-    const i64 bkb = (i64)f.qc * x.mp * KB, bps = bkb * (x.kp / KB);
+    const i64 bkb = pre ? SL.kbstride : (i64)f.qc * x.mp * KB;
+    const i64 bps = pre ? SL.pstride : bkb * (x.kp / KB);
     const i64 ckb = (i64)x.cp * KB, cps = ckb * (x.kp / KB);
     const i64 xkb = (i64)2 * nd * x.mp * KB, xps = xkb * (x.jp / KB);
     const int nchunk = (int)chunks.size();
     auto nq_of = [&](int c) { return chunks[c].nq; };
     auto nkb_of = [&](int c) { return (int)(pad_to((i64)nq_of(c) * r, jk::mixed_k_pad()) / KB); };
-    auto Bp = [&](int c) { return (int8_t *)(ws + x.o_bp[c & 1]); };
-    auto eB = [&](int c) { return (int *)(ws + x.o_eb[c & 1]); };
+    auto Bp = [&](int c) {
+        return pre ? (int8_t *)(pre + SL.o_planes) + (i64)chunks[c].q0 * x.mp * KB
+                   : (int8_t *)(ws + x.o_bp[c & 1]);
+    };
+    auto eB = [&](int c) {
+        return pre ? (int *)(pre + SL.o_exp) + (i64)chunks[c].q0 * x.mp : (int *)(ws + x.o_eb[c & 1]);
+    };
     auto XY = [&](int c) { return (double *)(ws + x.o_xy[c & 1]); };
     auto XYp = [&](int c) { return (int8_t *)(ws + x.o_xyp[c & 1]); };
     auto eXY = [&](int c) { return (int *)(ws + x.o_exy[c & 1]); };
@@ -553,6 +587,10 @@ jk_status build_mixed(const jk_problem *p, const double *B, const KSeg *seg, int
     hipEvent_t fork = E.ev[0], sb[2] = {E.ev[1], E.ev[2]}, ht[2] = {E.ev[3], E.ev[4]},
                sx[2] = {E.ev[5], E.ev[6]}, ex[2] = {E.ev[7], E.ev[8]};
     auto slice_b = [&](int c) -> jk_status {
+        if (pre) {              // prepared planes: nothing to make
+            JK_TRY(hipEventRecord(sb[c & 1], a));
+            return JK_OK;
+        }
         if (f.packed)
             JK_TRY(jk::launch_slice_b_packed(chunks[c].B, f.slab, nq_of(c), nao, x.mp, x.kp / KB,
                                              Bp(c), bps, bkb, eB(c), a));
@@ -1064,6 +1102,89 @@ jk_status jk_build(const jk_problem *p, const double *B, const double *CL, const
 {
     try {
         return jk_build_impl(p, B, CL, CR, J, K, ws, ws_bytes, stream);
+    } catch (...) {
+        return JK_ENOMEM;
+    }
+}
+
+size_t jk_slices_bytes(const jk_problem *p)
+{
+    if (!valid_problem(p) || p->precision != JK_MIXED)
+        return 0;
+    return slice_layout(p).total;
+}
+
+static jk_status jk_slice_b_impl(const jk_problem *p, const double *B, void *slices,
+                                 size_t slices_bytes, void *stream)
+{
+    if (!valid_problem(p) || p->precision != JK_MIXED || !B || !slices ||
+        ((uintptr_t)slices) % kAlign)
+        return JK_EINVAL;
+    if (slices_bytes < jk_slices_bytes(p))
+        return JK_EWORKSPACE;
+    if (p->nslice != 0 && p->nslice != jk::mixed_nslice())
+        return JK_EUNSUPPORTED;
+    const SliceLayout L = slice_layout(p);
+    const int KB = jk::mixed_k_block();
+    const int nao = (int)p->nao, naux = (int)p->naux;
+    if (packed_b(p) && !jk::mixed_packed_ok(nao, L.kp))
+        return JK_EUNSUPPORTED;
+    char *base = (char *)slices;
+    int8_t *planes = (int8_t *)(base + L.o_planes);
+    int *exps = (int *)(base + L.o_exp);
+    hipStream_t s = (hipStream_t)stream;
+    if (packed_b(p))
+        JK_TRY(jk::launch_slice_b_packed(B, jk::pk_size(nao), naux, nao, L.mp, L.kp / KB, planes,
+                                         L.pstride, L.kbstride, exps, s));
+    else
+        JK_TRY(jk::launch_slice_b(B, (i64)nao * nao, nao, naux, nao, nao, L.mp, L.kp / KB, planes,
+                                  L.pstride, L.kbstride, exps, s));
+    return JK_OK;
+}
+
+jk_status jk_slice_b(const jk_problem *p, const double *B, void *slices, size_t slices_bytes,
+                     void *stream)
+{
+    try {
+        return jk_slice_b_impl(p, B, slices, slices_bytes, stream);
+    } catch (...) {
+        return JK_ENOMEM;
+    }
+}
+
+static jk_status jk_build_sliced_impl(const jk_problem *p, const double *B, const void *slices,
+                                      size_t slices_bytes, const double *CL, const double *CR,
+                                      double *J, double *K, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!valid_problem(p) || p->precision != JK_MIXED)
+        return JK_EINVAL;
+    const int w = want(p);
+    if (!B || !CL || !CR || !ws || !slices || ((uintptr_t)slices) % kAlign)
+        return JK_EINVAL;
+    if ((w & JK_WANT_J) && !J)
+        return JK_EINVAL;
+    if ((w & JK_WANT_K) && !K)
+        return JK_EINVAL;
+    if (((uintptr_t)ws) % kAlign)
+        return JK_EINVAL;
+    if (slices_bytes < jk_slices_bytes(p))
+        return JK_EWORKSPACE;
+    if (ws_bytes < jk_workspace_bytes(p))
+        return JK_EWORKSPACE;
+    const KSeg seg{B, (int)p->naux, 1.0};
+    BuildOut o;
+    o.J = J;
+    o.K = K;
+    return build_mixed(p, B, &seg, 1, CL, CR, o, (char *)ws, (hipStream_t)stream,
+                       (const char *)slices);
+}
+
+jk_status jk_build_sliced(const jk_problem *p, const double *B, const void *slices,
+                          size_t slices_bytes, const double *CL, const double *CR, double *J,
+                          double *K, void *ws, size_t ws_bytes, void *stream)
+{
+    try {
+        return jk_build_sliced_impl(p, B, slices, slices_bytes, CL, CR, J, K, ws, ws_bytes, stream);
     } catch (...) {
         return JK_ENOMEM;
     }

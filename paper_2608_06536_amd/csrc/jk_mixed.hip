@@ -24,7 +24,12 @@ constexpr int kMT = 128, kNT = 128;     // workgroup tile: eight waves of 32 x 6
 constexpr int kWTN = 2;                 // MFMA tiles per wave, side by side
 constexpr int kRowPad = 128;            // plane rows are padded to this
 constexpr int kKPad = kSliceKB;         // plane inner bytes are padded to this
-typedef STileW<kMT, kNT, kNS, kWTN> TileS;
+typedef STileW<kMT, kNT, kNS, kWTN> TileS;   // exchange: eight waves, one workgroup per CU
+constexpr int kHtMT = 64;                     // half-transform: 64 x 128, four waves,
+typedef STileW<kHtMT, kNT, kNS, kWTN> TileH;  // two workgroups per CU
+constexpr int kNbHt = 3, kNbEx = 3;           // LDS stage buffers
+typedef SPipe<TileH, kNbHt> PipeHt;
+typedef SPipe<TileS, kNbEx> PipeEx;
 
 inline int cdiv(i64 a, i64 b) { return (int)((a + b - 1) / b); }
 
@@ -284,8 +289,8 @@ __global__ void __launch_bounds__(256) k_slice_xy(const double *__restrict__ XY,
 // ------------------------------------------------------------------ half-transform
 // For slab ql of the chunk: XY[ql][m][c] = 2^(eB + eC - 14) * sum_l S_l 2^(-8 (l - 2))
 // (c < R: X = B^Q C_L, c >= R: Y = B^Q C_R).  A planes: rows ql * mp + m;
-// B planes: rows c.  Each workgroup writes whole 512-byte row segments.
-__global__ void __launch_bounds__(512) k_ht_mixed(const int8_t *__restrict__ Bp, i64 bpstride,
+// B planes: rows c.  Each workgroup writes whole 1 KB row segments.
+__global__ void __launch_bounds__(256, 2) k_ht_mixed(const int8_t *__restrict__ Bp, i64 bpstride,
                                                   i64 bkbstride, const int *__restrict__ eB,
                                                   const int8_t *__restrict__ Cp, i64 cpstride,
                                                   i64 ckbstride, const int *__restrict__ eC,
@@ -293,8 +298,8 @@ __global__ void __launch_bounds__(512) k_ht_mixed(const int8_t *__restrict__ Bp,
                                                   int cp, int nkb)
 {
     extern __shared__ char lds[];
-    typedef TileS TL;
-    const int nmt = mp / kMT, nct = cp / kNT;
+    typedef TileH TL;
+    const int nmt = mp / kHtMT, nct = cp / kNT;
     // consecutive tiles (the column tiles of a row panel) on one XCD, sharing its L2
     const int t = xcd_swizzle(blockIdx.x, gridDim.x);
     const int ql = t / (nmt * nct), rem = t % (nmt * nct);
@@ -303,7 +308,7 @@ __global__ void __launch_bounds__(512) k_ht_mixed(const int8_t *__restrict__ Bp,
     SPlanes b{Cp, cpstride, ckbstride};
     SAccW<TL> acc;
     acc.zero();
-    stile_gemm_pp<TL, kNS>(a, b, mb * kMT, cb * kNT, 0, nkb, lds, acc);
+    stile_gemm_w4<TL, kNS, kNbHt>(a, b, mb * kHtMT, cb * kNT, 0, nkb, lds, acc);
     double *out = XY + (i64)ql * nao * R2;
 #pragma unroll
     for (int tt = 0; tt < kWTN; tt++)
@@ -311,7 +316,7 @@ __global__ void __launch_bounds__(512) k_ht_mixed(const int8_t *__restrict__ Bp,
         for (int e = 0; e < 16; e++) {
             int row, col;
             stile_coord_wide<TL>(tt, e, row, col);
-            const int m = mb * kMT + row, c = cb * kNT + col;
+            const int m = mb * kHtMT + row, c = cb * kNT + col;
             if (m < nao && c < R2)
                 out[(i64)m * R2 + c] =
                     ldexp(combine_levels_wide<TL>(acc, tt, e), eB[(i64)ql * mp + m] + eC[c] + kSliceProdShift);
@@ -401,7 +406,7 @@ __global__ void __launch_bounds__(512) k_ex_mixed(const int8_t *__restrict__ Xp,
     SPlanes b{Yp + (i64)k * mp * kSliceKB, pstride, kbstride};
     SAccW<TL> acc;
     acc.zero();
-    stile_gemm_pp<TL, kNS>(a, b, mb * kMT, nb * kNT, kb0, kb1, lds, acc);
+    stile_gemm_pp<TL, kNS, kNbEx>(a, b, mb * kMT, nb * kNT, kb0, kb1, lds, acc);
     double *Kk = Kp + ((i64)sp * nd + k) * nao * nao;
 #pragma unroll
     for (int tt = 0; tt < kWTN; tt++)
@@ -550,13 +555,13 @@ hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, i64 bkbstride, const 
                            const int8_t *Cp, i64 cpstride, i64 ckbstride, const int *eC, double *XY,
                            int nao, int R2, int nq, int mp, int cp, int nkb, hipStream_t s)
 {
-    hipError_t e = set_lds((const void *)k_ht_mixed, SPingPong<TileS>::LDS_BYTES);
+    hipError_t e = set_lds((const void *)k_ht_mixed, PipeHt::LDS_BYTES);
     if (e != hipSuccess)
         return e;
     {
         ProfScope ps_("ht_mixed", s);
-        hipLaunchKernelGGL(k_ht_mixed, dim3(nq * (mp / kMT) * (cp / kNT)), dim3(TileS::NTHR),
-                           SPingPong<TileS>::LDS_BYTES, s, Bp, bpstride, bkbstride, eB, Cp, cpstride, ckbstride,
+        hipLaunchKernelGGL(k_ht_mixed, dim3(nq * (mp / kHtMT) * (cp / kNT)), dim3(TileH::NTHR),
+                           PipeHt::LDS_BYTES, s, Bp, bpstride, bkbstride, eB, Cp, cpstride, ckbstride,
                            eC, XY, nao, R2, mp, cp, nkb);
     }
     return hipGetLastError();
@@ -583,7 +588,7 @@ hipError_t launch_ex_mixed(const int8_t *Xp, const int8_t *Yp, i64 pstride, i64 
                            const int *eX, const int *eY, double *Kp, int nao, int nd, int mp, int nkb,
                            int nsplit, int accumulate, hipStream_t s, int sym, double scale)
 {
-    hipError_t e = set_lds((const void *)k_ex_mixed, SPingPong<TileS>::LDS_BYTES);
+    hipError_t e = set_lds((const void *)k_ex_mixed, PipeEx::LDS_BYTES);
     if (e != hipSuccess)
         return e;
     const int kbl = cdiv(nkb, nsplit);
@@ -591,7 +596,7 @@ hipError_t launch_ex_mixed(const int8_t *Xp, const int8_t *Yp, i64 pstride, i64 
     const int pk = sym ? nmt * (nmt + 1) / 2 : nmt * (mp / kNT);
     {
         ProfScope ps_("ex_mixed", s);
-        hipLaunchKernelGGL(k_ex_mixed, dim3(nsplit * nd * pk), dim3(TileS::NTHR), SPingPong<TileS>::LDS_BYTES, s, Xp,
+        hipLaunchKernelGGL(k_ex_mixed, dim3(nsplit * nd * pk), dim3(TileS::NTHR), PipeEx::LDS_BYTES, s, Xp,
                            Yp, pstride, kbstride, eX, eY, Kp, nao, nd, mp, nkb, kbl, accumulate, sym,
                            scale);
     }

@@ -150,18 +150,11 @@ struct SAccW {
 // holds one wave of each group, so its matrix core is fed by one group while
 // the other waits on LDS.  A workgroup barrier separates the phases.
 //
-// Three LDS stage buffers: the blocks of stage s are copied global -> LDS
-// (direct, 16 bytes per lane) in phase 2s - 4 and must have landed by the end
-// of phase 2s - 1, before group 0 reads them in phase 2s.  Stage s's buffer
-// is refilled with stage s + 3 in phase 2s + 2, after the barrier that ends
-// group 1's read of stage s (phase 2s + 1).
-template <class TL>
-struct SPingPong {
-    static_assert(TL::NWAVE == 8 && TL::WROWS == 4 && TL::WCOLS == 2, "two groups of four waves");
-    static constexpr int NBUF = 3;
-    static constexpr int LDS_BYTES = NBUF * TL::STAGE_BYTES;
-};
-
+// NBUF LDS stage buffers: the blocks of stage s are copied global -> LDS
+// (direct, 16 bytes per lane) in phase 2 (s - NBUF + 1) and must have landed
+// by the end of phase 2s - 1, before group 0 reads them in phase 2s.  Stage
+// s's buffer is refilled with stage s + NBUF in phase 2s + 2, after the
+// barrier that ends group 1's read of stage s (phase 2s + 1).
 // s_waitcnt with vmcnt <= n and the other counters unconstrained (gfx9
 // encoding: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
 template <int N>
@@ -169,6 +162,29 @@ __device__ __forceinline__ void wait_vmcnt()
 {
     __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
 }
+
+// LDS of a GEMM pipeline with NB stage buffers.
+template <class TL, int NB = 3>
+struct SPipe {
+    static_assert(NB >= 3 && NB <= 5, "LDS stage buffers");
+    static constexpr int NBUF = NB;
+    static constexpr int LDS_BYTES = NBUF * TL::STAGE_BYTES;
+};
+
+// s_waitcnt vmcnt(n * PER) for a run-time n in [0, NMAX].
+template <int PER, int NMAX>
+__device__ __forceinline__ void wait_vm_stages(int n)
+{
+    if (NMAX >= 3 && n >= 3)
+        wait_vmcnt<3 * PER>();
+    else if (NMAX >= 2 && n == 2)
+        wait_vmcnt<2 * PER>();
+    else if (NMAX >= 1 && n == 1)
+        wait_vmcnt<PER>();
+    else
+        wait_vmcnt<0>();
+}
+
 
 // A pointer that is the same for every lane of the wave, kept in scalar
 // registers.
@@ -195,14 +211,15 @@ __device__ __forceinline__ void wg_barrier()
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <class TL, int NS>
+template <class TL, int NS, int NSTAGEBUF = 3>
 __device__ __forceinline__ void stile_gemm_pp(const SPlanes &A, const SPlanes &B, int m0, int n0,
                                               int kb_begin, int kb_end, char *lds, SAccW<TL> &acc)
 {
     constexpr int BM = TL::WROWS * 32, BN = TL::WCOLS * 32 * TL::TN, WTN = TL::TN;
     constexpr int NBA = NS * (BM / 32), NB = NBA + NS * (BN / 32);
     constexpr int NW = TL::NWAVE, PER = (NB + NW - 1) / NW;
-    constexpr int NBUF = SPingPong<TL>::NBUF;
+    static_assert(TL::NWAVE == 8 && TL::WROWS == 4 && TL::WCOLS == 2, "two groups of four waves");
+    constexpr int NBUF = SPipe<TL, NSTAGEBUF>::NBUF;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
@@ -271,50 +288,124 @@ __device__ __forceinline__ void stile_gemm_pp(const SPlanes &A, const SPlanes &B
     // each); the workgroup barriers pair up phase by phase:
     //   phase 2s      group 0 reads stage s,       group 1 multiplies stage s - 1
     //   phase 2s + 1  group 0 multiplies stage s,  group 1 reads stage s
-    // Both groups issue their copies of stage s in phase 2s - 4 and wait for
-    // them at the end of phase 2s - 1.
-    issue(kb_begin, 0);
-    if (nst > 1) {
-        issue(kb_begin + 1, 1);
-        wait_vmcnt<PER>();
-    } else {
-        wait_vmcnt<0>();
-    }
+    // Both groups issue their copies of stage s in phase 2 (s - NBUF + 1) and
+    // wait for them at the end of phase 2s - 1, when the copies of the
+    // NBUF - 2 later stages may still be in flight.
+    constexpr int AHEAD = NBUF - 1;
+    for (int s0 = 0; s0 < AHEAD; s0++)
+        if (s0 < nst)
+            issue(kb_begin + s0, s0);
+    wait_vm_stages<PER, NBUF - 2>(min(nst - 1, AHEAD - 1));
     wg_barrier();
     if (grp == 0) {
 #pragma clang loop unroll(disable)
         for (int st = 0; st < nst; st++) {
-            if (st + 2 < nst)
-                issue(kb_begin + st + 2, (st + 2) % NBUF);
+            if (st + AHEAD < nst)
+                issue(kb_begin + st + AHEAD, (st + AHEAD) % NBUF);
             read(st);
             __builtin_amdgcn_s_waitcnt(0xC07F);     // lgkmcnt(0): fragments in registers
             wg_barrier();
             mult();
-            if (st + 2 < nst)
-                wait_vmcnt<PER>();                  // stage st + 1 landed
-            else
-                wait_vmcnt<0>();
+            // stage st + 1 landed; stages st + 2 .. st + AHEAD may be in flight
+            wait_vm_stages<PER, NBUF - 2>(min(nst - st - 2, AHEAD - 1));
             wg_barrier();
         }
     } else {
-        if (nst > 2)
-            issue(kb_begin + 2, 2);
+        if (AHEAD < nst)
+            issue(kb_begin + AHEAD, AHEAD % NBUF);
         wg_barrier();
 #pragma clang loop unroll(disable)
         for (int st = 0; st < nst; st++) {
             read(st);
             __builtin_amdgcn_s_waitcnt(0xC07F);
-            if (st + 2 < nst)
-                wait_vmcnt<PER>();
-            else
-                wait_vmcnt<0>();
+            wait_vm_stages<PER, NBUF - 2>(min(nst - st - 2, AHEAD - 1));
             wg_barrier();
-            if (st + 3 < nst)
-                issue(kb_begin + st + 3, (st + 3) % NBUF);
+            if (st + AHEAD + 1 < nst)
+                issue(kb_begin + st + AHEAD + 1, (st + AHEAD + 1) % NBUF);
             mult();
             if (st + 1 < nst)
                 wg_barrier();
         }
+    }
+}
+
+// ---------------------------------------------------------------- four-wave GEMM
+// The same product for a workgroup of (BM/32) x (BN/64) = four waves of
+// 32 x 64 outputs, small enough for two workgroups per CU: while one
+// workgroup waits on LDS, a prologue or its epilogue, the other's products
+// keep the matrix cores busy.  All waves read a stage's fragments, multiply,
+// then meet at one barrier; NBUF LDS stage buffers, stage s copied
+// global -> LDS NBUF - 1 stages ahead.
+template <class TL, int NS, int NBUF>
+__device__ __forceinline__ void stile_gemm_w4(const SPlanes &A, const SPlanes &B, int m0, int n0,
+                                              int kb_begin, int kb_end, char *lds, SAccW<TL> &acc)
+{
+    static_assert(TL::NWAVE == 4, "four waves");
+    constexpr int BM = TL::WROWS * 32, BN = TL::WCOLS * 32 * TL::TN, WTN = TL::TN;
+    constexpr int NBA = NS * (BM / 32), NB = NBA + NS * (BN / 32);
+    constexpr int NW = TL::NWAVE, PER = (NB + NW - 1) / NW;
+    static_assert(NB % NW == 0, "whole blocks per wave");
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
+    const int nst = kb_end - kb_begin;
+    if (nst <= 0)
+        return;
+    const uint32_t lane_off = (lane >> 1) * kSliceKB + (((lane & 1) ^ ((lane >> 4) & 1)) << 4);
+    const int8_t *ub[PER];
+    int loff[PER];
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        const int b = wave + u * NW;
+        const bool isA = b < NBA;
+        const int bl = isA ? b : b - NBA;
+        const int T = isA ? BM : BN;
+        const int p = bl / (T / 32), rh = bl % (T / 32);
+        const SPlanes &op = isA ? A : B;
+        ub[u] = uniform_ptr(op.base + p * op.pstride + (i64)((isA ? m0 : n0) + rh * 32) * kSliceKB);
+        loff[u] = (isA ? 0 : TL::A_BYTES) + p * T * kSliceKB + rh * 32 * kSliceKB;
+    }
+    const i64 akbs = A.kbstride, bkbs = B.kbstride;
+    auto issue = [&](int kb, int buf) {
+#pragma unroll
+        for (int u = 0; u < PER; u++)
+            global_to_lds16(ub[u] + (i64)kb * (wave + u * NW < NBA ? akbs : bkbs) + lane_off,
+                            lds + buf * TL::STAGE_BYTES + loff[u]);
+    };
+    const int aoff = slds_off(wr * 32 + (lane & 31), lane >> 5);
+    int boff[WTN];
+#pragma unroll
+    for (int t = 0; t < WTN; t++)
+        boff[t] = slds_off((wc * WTN + t) * 32 + (lane & 31), lane >> 5);
+    constexpr int AHEAD = NBUF - 1;
+    for (int s0 = 0; s0 < AHEAD; s0++)
+        if (s0 < nst)
+            issue(kb_begin + s0, s0);
+#pragma clang loop unroll(disable)
+    for (int st = 0; st < nst; st++) {
+        // stage st landed (this wave's copies), then every wave's (barrier)
+        wait_vm_stages<PER, NBUF - 2>(min(nst - st - 1, AHEAD - 1));
+        wg_barrier();
+        if (st + AHEAD < nst)
+            issue(kb_begin + st + AHEAD, (st + AHEAD) % NBUF);
+        const char *sa = lds + (st % NBUF) * TL::STAGE_BYTES;
+        const char *sb = sa + TL::A_BYTES;
+        v4i fa[NS], fb[WTN][NS];
+#pragma unroll
+        for (int p = 0; p < NS; p++) {
+            fa[p] = *(const v4i *)(sa + p * BM * kSliceKB + aoff);
+#pragma unroll
+            for (int t = 0; t < WTN; t++)
+                fb[t][p] = *(const v4i *)(sb + p * BN * kSliceKB + boff[t]);
+        }
+#pragma unroll
+        for (int i = 0; i < NS; i++)
+#pragma unroll
+            for (int t = 0; t < WTN; t++)
+#pragma unroll
+                for (int j = 0; j < NS; j++)
+                    if (i + j + 2 <= kSliceLevel)
+                        acc.c[t][i + j] = mfma_i8(fa[i], fb[t][j], acc.c[t][i + j]);
     }
 }
 

@@ -88,8 +88,26 @@ def _shapes(B, CL, CR):
     return nao, naux, CL.shape[0], CL.shape[2]
 
 
-def jk_build(B, CL, CR, precision="fp64", want_j=True, want_k=True, nslice=0, out=None, ws=None):
-    """J_k = sum_Q <B^Q, D_k> B^Q and K_k = sum_Q B^Q D_k B^Q for D_k = CL_k CR_k^T."""
+def slice_b(B, nao, out=None):
+    """Digit planes of B for the mixed precision (jk_slice_b), made once and
+    passed to jk_build(..., precision="mixed", slices=...) for every build
+    over the same B.  Returns a uint8 tensor on B's device."""
+    _check_tensor(B, "B")
+    packed = is_packed(B, nao)
+    prob = make_problem(nao, B.shape[0], 1, 1, "mixed", packed=packed)
+    n = int(_lib.lib().jk_slices_bytes(ctypes.byref(prob)))
+    if n == 0:
+        raise _lib.JKError(_lib.JK_EINVAL, "jk_slices_bytes")
+    S = out if out is not None else _workspace(n, B.device)
+    st = _lib.lib().jk_slice_b(ctypes.byref(prob), _ptr(B), _ptr(S), S.numel(), _stream())
+    _lib.check(st, "jk_slice_b")
+    return S
+
+
+def jk_build(B, CL, CR, precision="fp64", want_j=True, want_k=True, nslice=0, out=None, ws=None,
+             slices=None):
+    """J_k = sum_Q <B^Q, D_k> B^Q and K_k = sum_Q B^Q D_k B^Q for D_k = CL_k CR_k^T.
+    slices: B's digit planes from slice_b (precision "mixed" only)."""
     nao, naux, nd, r = _shapes(B, CL, CR)
     prob = make_problem(nao, naux, nd, r, precision, want_j, want_k, nslice, is_packed(B, nao))
     if out is None:
@@ -105,6 +123,12 @@ def jk_build(B, CL, CR, precision="fp64", want_j=True, want_k=True, nslice=0, ou
         raise _lib.JKError(_lib.JK_EINVAL, "jk_build")
     if ws is None:
         ws = _workspace(nbytes, B.device)
+    if slices is not None:
+        st = _lib.lib().jk_build_sliced(ctypes.byref(prob), _ptr(B), _ptr(slices), slices.numel(),
+                                        _ptr(CL), _ptr(CR), _ptr(J), _ptr(K), _ptr(ws), ws.numel(),
+                                        _stream())
+        _lib.check(st, "jk_build_sliced")
+        return J, K
     st = _lib.lib().jk_build(ctypes.byref(prob), _ptr(B), _ptr(CL), _ptr(CR), _ptr(J), _ptr(K),
                              _ptr(ws), ws.numel(), _stream())
     _lib.check(st, "jk_build")

@@ -238,3 +238,31 @@ def test_tuning_validation():
     assert L.jk_autotune(ctypes.byref(p), None, 8, 8, 8, 8, 256, need, None, 2,
                          None) == _lib.JK_EINVAL
     L.jk_tuning_clear()
+
+
+def test_slices_validation():
+    # prepared digit planes of B (jk_slice_b / jk_build_sliced): JK_MIXED only,
+    # sizes and pointers checked before any launch
+    L = _lib.lib()
+    p64 = _prob()
+    pm = _prob(precision=1)
+    assert L.jk_slices_bytes(ctypes.byref(p64)) == 0
+    n = L.jk_slices_bytes(ctypes.byref(pm))
+    assert n > 0 and n % 256 == 0
+    # the planes depend on nao and naux only
+    assert L.jk_slices_bytes(ctypes.byref(_prob(precision=1, ndens=5, rank=7))) == n
+    assert L.jk_slice_b(ctypes.byref(p64), 8, 256, n, None) == _lib.JK_EINVAL
+    assert L.jk_slice_b(ctypes.byref(pm), 8, None, n, None) == _lib.JK_EINVAL
+    assert L.jk_slice_b(ctypes.byref(pm), 8, 264, n, None) == _lib.JK_EINVAL       # misaligned
+    assert L.jk_slice_b(ctypes.byref(pm), 8, 256, n - 1, None) == _lib.JK_EWORKSPACE
+    assert L.jk_slice_b(ctypes.byref(_prob(precision=1, nslice=5)), 8, 256, n,
+                        None) == _lib.JK_EUNSUPPORTED
+    need = L.jk_workspace_bytes(ctypes.byref(pm))
+    assert L.jk_build_sliced(ctypes.byref(p64), 8, 256, n, 8, 8, 8, 8, 256, need,
+                             None) == _lib.JK_EINVAL
+    assert L.jk_build_sliced(ctypes.byref(pm), 8, 256, n - 1, 8, 8, 8, 8, 256, need,
+                             None) == _lib.JK_EWORKSPACE
+    assert L.jk_build_sliced(ctypes.byref(pm), 8, 256, n, 8, 8, 8, 8, 256, need - 1,
+                             None) == _lib.JK_EWORKSPACE
+    assert L.jk_build_sliced(ctypes.byref(pm), 8, None, n, 8, 8, 8, 8, 256, need,
+                             None) == _lib.JK_EINVAL

@@ -108,3 +108,53 @@ def test_config4_mixed_sampled():
     ms[:4] = p.nao - 1
     _, Ke = oracle.jk_entries(B, CL, CR, ks, ms, ns)
     assert np.max(np.abs(Km[ks, ms, ns] - Ke)) <= TOL * np.max(np.abs(Km))
+
+
+@pytest.mark.parametrize("nao,naux,nd,r,packed,sym", [(48, 192, 1, 8, False, False),
+                                                      (130, 37, 3, 13, False, True),
+                                                      (300, 1200, 4, 30, False, False),
+                                                      (200, 50, 5, 17, True, False)])
+def test_prepared_slices_bit_identical(nao, naux, nd, r, packed, sym):
+    # B's digit planes made once (jk_slice_b) and reused by builds with
+    # different factors: each build equals jk_build of the same inputs bit for bit
+    from paper_2608_06536_amd import jk
+    p = synth.Problem(nao=nao, naux=naux, nd=nd, r=r, ell=10.0, tau=naux / 4 + 1, n_ground=1,
+                      seed=7700 + nao)
+    B, CL, CR = synth.make_problem(p)
+    if packed:
+        iu = np.triu_indices(nao)
+        B = np.ascontiguousarray(B[:, iu[0], iu[1]])
+    Bd = _dev(B)[0]
+    S = jk.slice_b(Bd, nao)
+    for rep in range(2):
+        Ld, Rd = _dev(CL * (1.0 + rep), CR)
+        if sym:
+            Rd = Ld
+        J1, K1 = jk.jk_build(Bd, Ld, Rd, precision="mixed")
+        J2, K2 = jk.jk_build(Bd, Ld, Rd, precision="mixed", slices=S)
+        torch.cuda.synchronize()
+        assert torch.equal(J1, J2) and torch.equal(K1, K2), rep
+
+
+def test_prepared_slices_many_chunks():
+    # a 64 MB plan: config 2's 1200 slabs in many chunks, each chunk's planes
+    # read at its own offset of the prepared buffer
+    from paper_2608_06536_amd import jk
+    p = synth.config(2)
+    B, CL, CR = synth.make_problem(p)
+    Bd, Ld, Rd = _dev(B, CL, CR)
+    prob = jk.make_problem(p.nao, p.naux, p.nd, p.r, "mixed")
+    try:
+        jk.tuning_set(prob, 4, 64)
+        assert jk.plan_describe(prob)["chunk_slabs"] < p.naux // 4
+        S = jk.slice_b(Bd, p.nao)
+        J1, K1 = jk.jk_build(Bd, Ld, Rd, precision="mixed")
+        J2, K2 = jk.jk_build(Bd, Ld, Rd, precision="mixed", slices=S)
+        torch.cuda.synchronize()
+    finally:
+        jk.tuning_clear()
+    assert torch.equal(J1, J2) and torch.equal(K1, K2)
+    Jr, Kr, _ = oracle.jk_factored(B, CL, CR)
+    Kh = K2.cpu().numpy()
+    for k in range(p.nd):
+        assert rel_err(Kh[k], Kr[k]) <= TOL

@@ -710,11 +710,12 @@ jk_status build_plain(const jk_problem *p, const double *B, const double *CL, co
 }
 
 // ------------------------------------------------------------------ batched
-// Schedule of a batched FP64 build: the launches (phase, chunk step, tiles,
-// table offset) and the host image of the workspace header (member
-// descriptors, then the member tables of every launch).
+// Schedule of a batched build: the launches (phase, chunk step, tiles, table
+// offset, argument) and the host image of the workspace header (member
+// descriptors, then the member tables of every launch).  Each phase of the
+// build is one launch over the members that take part in it.
 struct BLaunch {
-    int phase, step, ntiles;
+    int phase, step, ntiles, arg;
     size_t tab_off;     // byte offset of the launch's table in the workspace
 };
 
@@ -727,48 +728,101 @@ struct BSchedule {
     std::string key;                 // shape signature
 };
 
+// The plan of one batched member: the single-build plan for its class's
+// chunk budget capped at 256 MB (members own their chunk buffers).
+struct BPlan {
+    FwdPlan f;
+    MixPlan x;           // JK_MIXED members
+    int tile = 0;        // FP64 half-transform: 0, 1 (4x4x4) or 4 (16x16x4, stacked slabs)
+    int sym = 0;         // symmetric densities routed to the X-only path
+    int nsplit = 1;      // exchange splits of the path taken
+    size_t total = 0;
+};
+
+size_t batched_budget(const jk_problem *p) { return std::min(kChunkBudgetBatched, tuned_budget(p)); }
+
+BPlan batched_plan(const jk_problem *p, bool sym_in)
+{
+    BPlan b;
+    const size_t budget = batched_budget(p);
+    if (p->precision == JK_MIXED) {
+        b.x = plan_mixed(p, budget);
+        b.f = b.x.f;
+        b.sym = sym_in ? 1 : 0;
+        b.nsplit = b.sym ? b.x.nsplit_sym : b.x.nsplit;
+        b.total = b.x.total;
+        return b;
+    }
+    b.f = plan_forward(p, budget);
+    // tiles 3 and 4 run as the 16x16x4 tile over stacked slabs when the
+    // chunk's slabs stay within a buffer resource's reach; 2 runs as 0
+    const int t = plan_tuning(p).ht_tile;
+    const bool fits = jk::buf_extent_ok((i64)b.f.qc * p->nao * p->nao);
+    b.tile = t == 1 ? 1 : (t >= 3 && fits) ? 4 : 0;
+    b.sym = (sym_in && b.tile == 4) ? 1 : 0;     // the X-only path needs the 16x16x4 tile
+    b.nsplit = b.sym ? b.f.nsplit_sym : b.f.nsplit;
+    b.total = b.f.total;
+    return b;
+}
+
+// Register blocks of the mixed B slicer for rows of kp inner bytes (0 if
+// rows are longer than the one-pass slicer takes).
+int slicer_blocks(int kp)
+{
+    const int nj = (kp / jk::mixed_k_block() + 7) / 8;
+    return nj <= 1 ? 1 : nj <= 2 ? 2 : nj <= 4 ? 4 : nj <= 8 ? 8 : 0;
+}
+
+bool batched_mixed_ok(int32_t nprob, const jk_problem *p)
+{
+    for (int g = 0; g < nprob; g++) {
+        const MixPlan x = plan_mixed(&p[g], batched_budget(&p[g]));
+        if (slicer_blocks(x.kp) == 0 || !jk::mixed_rowmax_ok(2 * (int)(p[g].ndens * p[g].rank)))
+            return false;
+    }
+    return true;
+}
+
 // Per-member cost of one tile of a phase (larger first in the tables).
-double tile_cost(int phase, const FwdPlan &f, const jk_problem &p)
+double tile_cost(int phase, const BPlan &b, const jk_problem &p)
 {
     switch (phase) {
-    case jk::kPhaseProject: return (double)f.plen;
-    case jk::kPhaseReduce: return (double)f.npb;
+    case jk::kPhaseProject: return (double)b.f.plen;
+    case jk::kPhaseReduce: return (double)b.f.npb;
     case jk::kPhaseCoulomb: return (double)p.naux;
     case jk::kPhaseHalf:
     case jk::kPhaseHalf64:
-    case jk::kPhaseHalf16: return (double)p.nao;
-    case jk::kPhaseExchange: return (double)f.qc * p.rank / f.nsplit;
+    case jk::kPhaseHalf16:
+    case jk::kPhaseMHalf: return (double)p.nao;
+    case jk::kPhaseExchange:
+    case jk::kPhaseMExchange: return (double)b.f.qc * p.rank / b.nsplit;
     default: return (double)p.nao;
     }
 }
 
-BSchedule make_schedule(int32_t nprob, const jk_problem *p)
+// sym: one flag per member (C_L and C_R one buffer), or empty for the
+// workspace size (which does not depend on it).
+BSchedule make_schedule(int32_t nprob, const jk_problem *p, const std::vector<char> &sym)
 {
     BSchedule S;
     const int G = nprob;
-    std::vector<FwdPlan> plans(G);
-    std::vector<int> tile_of(G);
+    const bool mixed = p[0].precision == JK_MIXED;
+    std::vector<BPlan> plans(G);
     int maxsteps = 0;
     for (int g = 0; g < G; g++) {
-        plans[g] = plan_forward(&p[g], std::min(kChunkBudgetBatched, tuned_budget(&p[g])));
-        // the batch runs tile 2 as 0 and tile 3 as 4; tiles 3 and 4 need the chunk's
-        // slabs within a buffer resource's reach
-        const int t = plan_tuning(&p[g]).ht_tile;
-        const bool fits = jk::buf_extent_ok((i64)plans[g].qc * p[g].nao * p[g].nao);
-        tile_of[g] = t == 1 ? 1 : (t >= 3 && fits) ? 4 : 0;
-        const int st = (int)((p[g].naux + plans[g].qc - 1) / plans[g].qc);
+        plans[g] = batched_plan(&p[g], !sym.empty() && sym[g]);
+        const int st = (int)((p[g].naux + plans[g].f.qc - 1) / plans[g].f.qc);
         maxsteps = std::max(maxsteps, st);
     }
     const int w = want(&p[0]);
-    // member lists per launch
     struct Pending {
-        int phase, step;
+        int phase, step, arg;
         std::vector<int> members;
         std::vector<int> tiles;
     };
     std::vector<Pending> pend;
-    auto add = [&](int phase, int step, auto tiles_of, auto takes_part) {
-        Pending L{phase, step, {}, {}};
+    auto add = [&](int phase, int step, auto tiles_of, auto takes_part, int arg = 0) {
+        Pending L{phase, step, arg, {}, {}};
         for (int g = 0; g < G; g++)
             if (takes_part(g)) {
                 L.members.push_back(g);
@@ -782,7 +836,7 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p)
             return tile_cost(phase, plans[L.members[a]], p[L.members[a]]) >
                    tile_cost(phase, plans[L.members[b]], p[L.members[b]]);
         });
-        Pending O{phase, step, {}, {}};
+        Pending O{phase, step, arg, {}, {}};
         for (int i : idx) {
             O.members.push_back(L.members[i]);
             O.tiles.push_back(L.tiles[i]);
@@ -794,7 +848,7 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p)
     if (w & JK_WANT_J) {
         add(jk::kPhaseDensity, 0, [&](int g) { return jk::density_tiles((int)p[g].nao, (int)p[g].ndens); }, all);
         add(jk::kPhaseProject, 0,
-            [&](int g) { return jk::project_tiles((int)p[g].naux, (int)p[g].ndens, plans[g].npb); }, all);
+            [&](int g) { return jk::project_tiles((int)p[g].naux, (int)p[g].ndens, plans[g].f.npb); }, all);
         add(jk::kPhaseReduce, 0, [&](int g) { return jk::reduce_tiles((int)p[g].naux, (int)p[g].ndens); },
             all);
         add(jk::kPhaseCoulomb, 0,
@@ -803,33 +857,77 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p)
     if (w & JK_WANT_K) {
         add(jk::kPhasePack, 0,
             [&](int g) { return jk::pack_tiles((int)p[g].nao, (int)p[g].ndens, (int)p[g].rank); }, all);
+        if (mixed)
+            add(jk::kPhaseMSliceC, 0, [&](int g) { return (plans[g].x.cp + 31) / 32; }, all);
         for (int c = 0; c < maxsteps; c++) {
-            auto in_step = [&](int g) { return (i64)c * plans[g].qc < p[g].naux; };
+            auto in_step = [&](int g) { return (i64)c * plans[g].f.qc < p[g].naux; };
             auto nq_of = [&](int g) {
-                const i64 q0 = (i64)c * plans[g].qc;
-                return (int)std::min<i64>(plans[g].qc, p[g].naux - q0);
+                const i64 q0 = (i64)c * plans[g].f.qc;
+                return (int)std::min<i64>(plans[g].f.qc, p[g].naux - q0);
             };
+            if (mixed) {
+                int nj = 1, ldsb = 0;
+                for (int g = 0; g < G; g++) {
+                    nj = std::max(nj, slicer_blocks(plans[g].x.kp));
+                    const int nkey = plans[g].sym ? (int)p[g].ndens : 2 * (int)p[g].ndens;
+                    ldsb = std::max(ldsb, (int)sizeof(double) * nkey * (int)p[g].rank);
+                }
+                add(jk::kPhaseMSliceB, c,
+                    [&](int g) { return (int)(((i64)nq_of(g) * plans[g].x.mp + 3) / 4); }, in_step, nj);
+                add(jk::kPhaseMHalf, c,
+                    [&](int g) {
+                        return jk::mixed_ht_tiles(plans[g].x.mp,
+                                                  plans[g].sym ? plans[g].x.cp_sym : plans[g].x.cp,
+                                                  nq_of(g));
+                    },
+                    in_step);
+                add(jk::kPhaseMRowmax, c, [&](int g) { return (int)p[g].nao; }, in_step, ldsb);
+                add(jk::kPhaseMSliceXY, c,
+                    [&](int g) {
+                        const int nkey = plans[g].sym ? (int)p[g].ndens : 2 * (int)p[g].ndens;
+                        const int nkb = (int)(((i64)nq_of(g) * p[g].rank + 31) / 32);
+                        return (int)(((i64)nkey * plans[g].x.mp + 31) / 32) * nkb;
+                    },
+                    in_step);
+                add(jk::kPhaseMExchange, c,
+                    [&](int g) {
+                        return jk::mixed_ex_tiles(plans[g].x.mp, (int)p[g].ndens, plans[g].nsplit,
+                                                  plans[g].sym);
+                    },
+                    in_step);
+                continue;
+            }
             // members whose plan chose 64 x 64 half-transform tiles get a launch of their own
             add(jk::kPhaseHalf, c,
                 [&](int g) { return jk::ht_tiles((int)p[g].nao, (int)p[g].ndens, (int)p[g].rank, nq_of(g)); },
-                [&](int g) { return in_step(g) && tile_of[g] == 0; });
+                [&](int g) { return in_step(g) && plans[g].tile == 0; });
             add(jk::kPhaseHalf64, c,
                 [&](int g) { return jk::ht64_tiles((int)p[g].nao, (int)p[g].ndens, (int)p[g].rank, nq_of(g)); },
-                [&](int g) { return in_step(g) && tile_of[g] == 1; });
+                [&](int g) { return in_step(g) && plans[g].tile == 1; });
             add(jk::kPhaseHalf16, c,
                 [&](int g) {
-                    return jk::ht_flat_tiles<jk::TileHalf16>((int)p[g].nao, 2 * (int)(p[g].ndens * p[g].rank),
+                    const int R = (int)(p[g].ndens * p[g].rank);
+                    return jk::ht_flat_tiles<jk::TileHalf16>((int)p[g].nao, plans[g].sym ? R : 2 * R,
                                                            nq_of(g));
                 },
-                [&](int g) { return in_step(g) && tile_of[g] == 4; });
+                [&](int g) { return in_step(g) && plans[g].tile == 4; });
             add(jk::kPhaseExchange, c,
-                [&](int g) { return jk::ex_tiles((int)p[g].nao, (int)p[g].ndens, plans[g].nsplit); },
+                [&](int g) {
+                    return plans[g].sym
+                               ? plans[g].nsplit * (int)p[g].ndens * jk::ex_tri_tiles((int)p[g].nao)
+                               : jk::ex_tiles((int)p[g].nao, (int)p[g].ndens, plans[g].nsplit);
+                },
                 in_step);
         }
         add(jk::kPhaseSum, 0, [&](int g) { return jk::sum_tiles(p[g].ndens * p[g].nao * p[g].nao); },
             [&](int g) { return plans[g].nsplit > 1; });
+        add(jk::kPhaseMirror, 0, [&](int g) { return (int)p[g].ndens * jk::mirror_blocks((int)p[g].nao); },
+            [&](int g) { return plans[g].sym != 0; });
     }
-    // header: descriptors, then tables
+    // header: descriptors, then tables.  Its size is a bound that holds for
+    // every pattern of symmetric members (the workspace query does not know
+    // it): at most one more launch than the non-symmetric schedule, and at
+    // most 2 G + 3 entries per table.
     Carve c;
     const size_t o_mem = c.take(sizeof(jk::BMember) * G);
     for (const Pending &L : pend) {
@@ -837,6 +935,7 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p)
         BLaunch bl;
         bl.phase = L.phase;
         bl.step = L.step;
+        bl.arg = L.arg;
         bl.ntiles = 0;
         for (int t : L.tiles)
             bl.ntiles += t;
@@ -852,7 +951,13 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p)
             S.tabs.push_back(g);
         S.launches.push_back(bl);
     }
-    c.take(sizeof(int) * S.tabs.size());
+    size_t nlaunch_bound = 0;
+    {
+        // the non-symmetric schedule's launch count, plus the mirror launch
+        const int per_step = mixed ? 5 : 4;
+        nlaunch_bound = 4 + 2 + (size_t)maxsteps * per_step + 2;
+    }
+    c.take(sizeof(int) * std::max(S.tabs.size(), nlaunch_bound * (2 * (size_t)G + 3)));
     S.header_bytes = c.off;
     S.mem.resize(G);
     S.region.resize(G);
@@ -865,20 +970,35 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p)
         m.naux = (int)p[g].naux;
         m.nd = (int)p[g].ndens;
         m.r = (int)p[g].rank;
-        m.qc = plans[g].qc;
-        m.ldw = plans[g].ldw;
+        m.qc = plans[g].f.qc;
+        m.ldw = plans[g].f.ldw;
         m.nsplit = plans[g].nsplit;
-        m.npb = plans[g].npb;
-        m.plen = plans[g].plen;
+        m.npb = plans[g].f.npb;
+        m.plen = plans[g].f.plen;
+        m.sym = plans[g].sym;
+        if (mixed) {
+            const MixPlan &x = plans[g].x;
+            const int KB = jk::mixed_k_block();
+            m.mp = x.mp;
+            m.kp = x.kp;
+            m.cp = x.cp;
+            m.cpx = m.sym ? x.cp_sym : x.cp;
+            m.bkb = (i64)x.f.qc * x.mp * KB;
+            m.bps = m.bkb * (x.kp / KB);
+            m.ckb = (i64)x.cp * KB;
+            m.cps = m.ckb * (x.kp / KB);
+            m.xkb = (i64)2 * m.nd * x.mp * KB;
+            m.xps = m.xkb * (x.jp / KB);
+        }
     }
     S.total_bytes = c.off;
     // shape signature
     S.key.reserve(64 + 48 * G);
     for (int g = 0; g < G; g++) {
-        char buf[128];
-        snprintf(buf, sizeof buf, "%lld,%lld,%lld,%lld,%d,%d,%d,%d;", (long long)p[g].nao,
+        char buf[160];
+        snprintf(buf, sizeof buf, "%lld,%lld,%lld,%lld,%d,%d,%d,%d,%d;", (long long)p[g].nao,
                  (long long)p[g].naux, (long long)p[g].ndens, (long long)p[g].rank, p[g].precision,
-                 p[g].flags, plans[g].qc, tile_of[g]);
+                 p[g].flags, plans[g].f.qc, plans[g].tile, plans[g].sym);
         S.key += buf;
     }
     return S;
@@ -990,22 +1110,27 @@ jk_status enqueue_batched(const BSchedule &S, char *ws, hipStream_t s)
     const jk::BMember *M = (const jk::BMember *)ws;
     for (const BLaunch &L : S.launches) {
         hipError_t e = jk::launch_batched_phase(L.phase, M, (const int *)(ws + L.tab_off), L.ntiles,
-                                                L.step, s);
+                                                L.step, s, L.arg);
         if (e != hipSuccess)
             return JK_EHIP;
     }
     return JK_OK;
 }
 
-jk_status build_batched_fp64(int32_t nprob, const jk_problem *p, const double *const *B,
-                             const double *const *CL, const double *const *CR, double *const *J,
-                             double *const *K, char *ws, hipStream_t s)
+jk_status build_batched(int32_t nprob, const jk_problem *p, const double *const *B,
+                        const double *const *CL, const double *const *CR, double *const *J,
+                        double *const *K, char *ws, hipStream_t s)
 {
-    BSchedule S = make_schedule(nprob, p);
+    const bool mixed = p[0].precision == JK_MIXED;
+    std::vector<char> sym(nprob);
+    for (int g = 0; g < nprob; g++)
+        sym[g] = CL[g] == CR[g];
+    BSchedule S = make_schedule(nprob, p, sym);
     // the header: descriptors with this call's pointers, then the tables
     for (int g = 0; g < nprob; g++) {
         jk::BMember &m = S.mem[g];
-        const FwdPlan f = plan_forward(&p[g], std::min(kChunkBudgetBatched, tuned_budget(&p[g])));
+        const BPlan b = batched_plan(&p[g], sym[g] != 0);
+        const FwdPlan &f = b.f;
         char *base = ws + S.region[g];
         m.B = B[g];
         m.CL = CL[g];
@@ -1018,12 +1143,23 @@ jk_status build_batched_fp64(int32_t nprob, const jk_problem *p, const double *c
         m.g = (double *)(base + f.o_g);
         m.Xw = (double *)(base + f.o_x);
         m.Yw = (double *)(base + f.o_y);
-        m.Kp = (double *)(base + f.o_kp);
+        m.Kp = (double *)(base + (mixed ? b.x.o_kp : f.o_kp));
+        if (mixed) {
+            m.Bp = (int8_t *)(base + b.x.o_bp[0]);
+            m.eB = (int *)(base + b.x.o_eb[0]);
+            m.Cp = (int8_t *)(base + b.x.o_cp);
+            m.eC = (int *)(base + b.x.o_ec);
+            m.XY = (double *)(base + b.x.o_xy[0]);
+            m.XYp = (int8_t *)(base + b.x.o_xyp[0]);
+            m.eXY = (int *)(base + b.x.o_exy[0]);
+        }
     }
     if (copy_header(S.mem.data(), nprob, S.tabs, S.header_bytes, ws, s) != hipSuccess)
         return JK_EHIP;
 
     if (jk::prepare_batched_kernels() != hipSuccess)
+        return JK_EHIP;
+    if (mixed && jk::prepare_batched_mixed_kernels() != hipSuccess)
         return JK_EHIP;
     if (s == nullptr || !graphs_enabled())
         return enqueue_batched(S, ws, s);
@@ -1334,9 +1470,11 @@ static size_t jk_batched_workspace_bytes_impl(int32_t nprob, const jk_problem *p
         if (b > mx)
             mx = b;
     }
-    if (p[0].precision == JK_FP64) {
-        // every member owns its single-build workspace, plus the header
-        size_t t = make_schedule(nprob, p).total_bytes;
+    // every member owns its plan's workspace, plus the header (the mixed form
+    // falls back to one build after another, in a single-build workspace,
+    // when a member's rows are too long for the batched slicer)
+    if (p[0].precision == JK_FP64 || batched_mixed_ok(nprob, p)) {
+        size_t t = make_schedule(nprob, p, std::vector<char>()).total_bytes;
         return t > mx ? t : mx;
     }
     return mx;
@@ -1372,8 +1510,8 @@ static jk_status jk_build_batched_impl(int32_t nprob, const jk_problem *p, const
         return JK_EWORKSPACE;
     if (packed_b(&p[0]))
         return JK_EUNSUPPORTED;
-    if (p[0].precision == JK_FP64)
-        return build_batched_fp64(nprob, p, B, CL, CR, J, K, (char *)ws, (hipStream_t)stream);
+    if (p[0].precision == JK_FP64 || batched_mixed_ok(nprob, p))
+        return build_batched(nprob, p, B, CL, CR, J, K, (char *)ws, (hipStream_t)stream);
     for (int32_t g = 0; g < nprob; g++) {
         jk_status st = build_plain(&p[g], B[g], CL[g], CR[g], J[g], K[g], (char *)ws,
                                    (hipStream_t)stream);

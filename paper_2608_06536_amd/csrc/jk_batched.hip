@@ -20,31 +20,6 @@
 
 namespace jk {
 
-// Table layout: tab[0] = n entries, tab[1 .. n+1] = start offsets (n+1
-// values), tab[n+2 .. 2n+2) = member indices.
-__device__ __forceinline__ int find_member(const int *__restrict__ tab, int t, int &local)
-{
-    const int n = tab[0];
-    const int *start = tab + 1;
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (start[mid] <= t)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    local = t - start[lo];
-    return tab[n + 2 + lo];
-}
-
-// Chunk of member m at step c: first slab and slab count.
-__device__ __forceinline__ void chunk_of(const BMember &m, int c, int &q0, int &nq)
-{
-    q0 = c * m.qc;
-    nq = (m.naux - q0) < m.qc ? (m.naux - q0) : m.qc;
-}
-
 __global__ void __launch_bounds__(256) k_b_pack(const BMember *__restrict__ M, const int *__restrict__ tab)
 {
     int loc;
@@ -120,7 +95,8 @@ __global__ void __launch_bounds__(256, 3) k_b_half_transform16(const BMember *__
     const BMember &m = M[find_member(tab, blockIdx.x, loc)];
     int q0, nq;
     chunk_of(m, c, q0, nq);
-    ht_tile_flat<TileB16>(m.B, m.Cc, m.Xw, m.Yw, m.nao, m.nd, m.r, q0, nq, m.ldw, loc, lds, -1);
+    ht_tile_flat<TileB16>(m.B, m.Cc, m.Xw, m.Yw, m.nao, m.nd, m.r, q0, nq, m.ldw, loc, lds,
+                          m.sym ? m.nd * m.r : -1);
 }
 
 // The exchange on the 16 x 16 x 4 engine (member chunk workspaces are capped
@@ -136,8 +112,18 @@ __global__ void __launch_bounds__(256, 3) k_b_exchange(const BMember *__restrict
     const int nj = nq * m.r;
     int jlen = cdiv_i(nj, m.nsplit);
     jlen = ((jlen + 15) / 16) * 16;
-    ex_tile<TileB16>(m.Xw, m.Yw, m.nsplit > 1 ? m.Kp : m.K, m.nao, m.nd, nj, m.ldw, jlen, c > 0, loc,
-                     lds);
+    ex_tile<TileB16>(m.Xw, m.sym ? m.Xw : m.Yw, m.nsplit > 1 ? m.Kp : m.K, m.nao, m.nd, nj, m.ldw,
+                     jlen, c > 0, loc, lds, m.sym);
+}
+
+__global__ void __launch_bounds__(256) k_b_mirror(const BMember *__restrict__ M,
+                                                  const int *__restrict__ tab)
+{
+    __shared__ double t[32][33];
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    const int nb = mirror_blocks(m.nao);
+    mirror_tile(m.K + (i64)(loc / nb) * m.npos, m.nao, loc % nb, t);
 }
 
 __global__ void __launch_bounds__(256) k_b_sum_splits(const BMember *__restrict__ M,
@@ -160,12 +146,19 @@ hipError_t prepare_batched_kernels()
 }
 
 hipError_t launch_batched_phase(int phase, const BMember *M, const int *tab, int ntiles, int step,
-                                hipStream_t s)
+                                hipStream_t s, int arg)
 {
     if (ntiles <= 0)
         return hipSuccess;
+    if (phase >= kPhaseMSliceC)
+        return launch_batched_mixed_phase(phase, M, tab, ntiles, step, s, arg);
     const dim3 g(ntiles);
     switch (phase) {
+    case kPhaseMirror: {
+        ProfScope ps_("b_mirror", s);
+        hipLaunchKernelGGL(k_b_mirror, g, dim3(256), 0, s, M, tab);
+        break;
+    }
     case kPhasePack: {
         ProfScope ps_("b_pack", s);
         hipLaunchKernelGGL(k_b_pack, g, dim3(256), 0, s, M, tab);

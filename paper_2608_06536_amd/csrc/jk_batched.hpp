@@ -13,8 +13,42 @@ struct BMember {
     double *Cc, *D, *part, *g, *Xw, *Yw, *Kp;
     long long npos;
     int nao, naux, nd, r;
-    int qc, ldw, nsplit, npb, plen, pad_;
+    int qc, ldw, nsplit, npb, plen;
+    int sym;            // C_L and C_R are one buffer: X only, K on the upper triangle
+    // JK_MIXED members: digit planes (single-buffered), their row exponents
+    // and strides (slice_core.hpp layout), the FP64 half-transform chunk XY
+    int8_t *Bp, *Cp, *XYp;
+    int *eB, *eC, *eXY;
+    double *XY;
+    long long bkb, bps, ckb, cps, xkb, xps;
+    int mp, kp, cp, cpx;    // padded rows / inner bytes; cpx: [C_L | C_R] rows the products use
 };
+
+// Table layout: tab[0] = n entries, tab[1 .. n+1] = start offsets (n+1
+// values), tab[n+2 .. 2n+2) = member indices.  Returns the member of tile t
+// and its tile index within the member.
+__device__ __forceinline__ int find_member(const int *__restrict__ tab, int t, int &local)
+{
+    const int n = tab[0];
+    const int *start = tab + 1;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    local = t - start[lo];
+    return tab[n + 2 + lo];
+}
+
+// Chunk of member m at step c: first slab and slab count.
+__device__ __forceinline__ void chunk_of(const BMember &m, int c, int &q0, int &nq)
+{
+    q0 = c * m.qc;
+    nq = (m.naux - q0) < m.qc ? (m.naux - q0) : m.qc;
+}
 
 enum {
     kPhasePack = 0,
@@ -26,7 +60,15 @@ enum {
     kPhaseExchange = 6,
     kPhaseSum = 7,
     kPhaseHalf64 = 8,    // the half-transform with 64 x 64 tiles (members whose plan chose them)
-    kPhaseHalf16 = 9     // the half-transform on the 16 x 16 x 4 engine over stacked slabs
+    kPhaseHalf16 = 9,    // the half-transform on the 16 x 16 x 4 engine over stacked slabs
+    kPhaseMirror = 10,   // lower triangle of K from the upper (symmetric members)
+    // JK_MIXED phases (jk_mixed.hip)
+    kPhaseMSliceC = 20,  // digit planes of [C_L | C_R]
+    kPhaseMSliceB = 21,  // digit planes of the chunk's slabs of B
+    kPhaseMHalf = 22,    // INT8 half-transform of the chunk
+    kPhaseMRowmax = 23,  // row exponents of the chunk's X and Y
+    kPhaseMSliceXY = 24, // digit planes of the chunk's X and Y
+    kPhaseMExchange = 25 // INT8 exchange of the chunk
 };
 
 // Sets the dynamic LDS size of the batched kernels that need it on the
@@ -34,8 +76,12 @@ enum {
 hipError_t prepare_batched_kernels();
 
 // One launch of a phase over the members listed in tab (device pointer):
-// ntiles workgroups, step = chunk index for the chunked phases.
+// ntiles workgroups, step = chunk index for the chunked phases.  arg: the
+// slicer's register blocks (kPhaseMSliceB) or the LDS bytes (kPhaseMRowmax).
 hipError_t launch_batched_phase(int phase, const BMember *M, const int *tab, int ntiles, int step,
-                                hipStream_t s);
+                                hipStream_t s, int arg = 0);
+hipError_t launch_batched_mixed_phase(int phase, const BMember *M, const int *tab, int ntiles,
+                                      int step, hipStream_t s, int arg);
+hipError_t prepare_batched_mixed_kernels();
 
 } // namespace jk

@@ -203,36 +203,12 @@ __global__ void __launch_bounds__(512, 4) k_exchange(const double *__restrict__ 
             scale);
 }
 
-// K[k][m][n] = K[k][n][m] for m > n: fills the lower triangle from the upper
-// one through a 32 x 32 LDS transpose (block (bi, bj), bi >= bj).
 __global__ void __launch_bounds__(256) k_mirror_upper(double *__restrict__ K, int nao, int nd)
 {
     __shared__ double t[32][33];
-    const int nb = cdiv_i(nao, 32);
-    int b = blockIdx.x, bi = 0;
-    while (b > bi) {     // lower-triangle block index -> (bi, bj)
-        b -= bi + 1;
-        bi++;
-    }
-    const int bj = b;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     // densities k = blockIdx.y, + gridDim.y, ... (grid y is capped at 65535)
-    for (int k = blockIdx.y; k < nd; k += gridDim.y) {
-        double *Kk = K + (i64)k * nao * nao;
-        for (int y = ty; y < 32; y += 8) {
-            const int row = bj * 32 + y, col = bi * 32 + tx;       // upper source
-            if (row < nao && col < nao)
-                t[y][tx] = Kk[(i64)row * nao + col];
-        }
-        __syncthreads();
-        for (int y = ty; y < 32; y += 8) {
-            const int m = bi * 32 + y, n = bj * 32 + tx;           // lower target
-            if (m < nao && n < nao && m > n)
-                Kk[(i64)m * nao + n] = t[tx][y];
-        }
-        __syncthreads();
-    }
-    (void)nb;
+    for (int k = blockIdx.y; k < nd; k += gridDim.y)
+        mirror_tile(K + (i64)k * nao * nao, nao, blockIdx.x, t);
 }
 
 __global__ void __launch_bounds__(256) k_sum_splits(const double *__restrict__ part,

@@ -114,6 +114,10 @@ hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, i64 bkbstride, const 
 // inner indices at most).
 int ex_mixed_nsplit(int mp, int nd, int nkb, int sym = 0);
 int mixed_max_depth();
+// Workgroups of the mixed half-transform of nq slabs (cpx padded factor
+// columns) and of the mixed exchange with nsplit splits.
+int mixed_ht_tiles(int mp, int cpx, int nq);
+int mixed_ex_tiles(int mp, int nd, int nsplit, int sym);
 // B digit planes from packed slabs (slab stride bs = nao (nao + 1) / 2);
 // mixed_packed_ok tells whether the packed slicer covers rows of kp inner
 // elements (kp <= 2048).

@@ -12,6 +12,7 @@
 #include <set>
 #include <utility>
 
+#include "jk_batched.hpp"
 #include "jk_kernels.hpp"
 #include "jk_tiles.hpp"
 #include "slice_core.hpp"
@@ -51,17 +52,12 @@ __device__ __forceinline__ void write_digits(int8_t *dst, i64 pstride, const int
 // k in [nk, 32 nkb) get zero digits.
 
 // Generic two-pass slicer (any strides; used for the small [C_L | C_R]
-// operand): 8 threads per row, 32 rows per workgroup, exps[b * rp + m] = row
-// exponent.
-__global__ void __launch_bounds__(256) k_slice_rows(const double *__restrict__ src, i64 bs, i64 rs,
-                                                    i64 ks, int nb, int nr, int nk, int rp, int nkb,
-                                                    int8_t *__restrict__ out, i64 pstride,
-                                                    i64 kbstride, int *__restrict__ exps)
+// operand): 8 threads per row (sub = lane & 7), exps[row] = row exponent.
+__device__ __forceinline__ void slice_row8(const double *__restrict__ src, i64 bs, i64 rs, i64 ks,
+                                           int nr, int nk, int rp, int nkb,
+                                           int8_t *__restrict__ out, i64 pstride, i64 kbstride,
+                                           int *__restrict__ exps, i64 row, int sub)
 {
-    const int t = threadIdx.x, sub = t & 7;
-    const i64 row = (i64)blockIdx.x * 32 + (t >> 3);
-    if (row >= (i64)nb * rp)        // whole 8-lane row groups leave together
-        return;
     const int b = (int)(row / rp), m = (int)(row % rp);
     const bool live = m < nr;
     const double *s = src + (i64)b * bs + (i64)m * rs;
@@ -88,20 +84,29 @@ __global__ void __launch_bounds__(256) k_slice_rows(const double *__restrict__ s
     }
 }
 
+// 32 rows per workgroup.
+__global__ void __launch_bounds__(256) k_slice_rows(const double *__restrict__ src, i64 bs, i64 rs,
+                                                    i64 ks, int nb, int nr, int nk, int rp, int nkb,
+                                                    int8_t *__restrict__ out, i64 pstride,
+                                                    i64 kbstride, int *__restrict__ exps)
+{
+    const int t = threadIdx.x;
+    const i64 row = (i64)blockIdx.x * 32 + (t >> 3);
+    if (row >= (i64)nb * rp)        // whole 8-lane row groups leave together
+        return;
+    slice_row8(src, bs, rs, ks, nr, nk, rp, nkb, out, pstride, kbstride, exps, row, t & 7);
+}
+
 // One-pass slicer for unit-stride rows of at most 256 * NJ elements: one wave
 // per row holds the row in registers (lane l: elements 4 l + 256 j + u),
 // reduces the maximum across the wave, then writes the digits.
 template <int NJ>
-__global__ void __launch_bounds__(256) k_slice_rows_wave(const double *__restrict__ src, i64 bs,
-                                                         i64 rs, int nb, int nr, int nk, int rp,
-                                                         int nkb, int8_t *__restrict__ out,
-                                                         i64 pstride, i64 kbstride,
-                                                         int *__restrict__ exps)
+__device__ __forceinline__ void slice_row_wave(const double *__restrict__ src, i64 bs, i64 rs,
+                                               int nr, int nk, int rp, int nkb,
+                                               int8_t *__restrict__ out, i64 pstride, i64 kbstride,
+                                               int *__restrict__ exps, i64 row)
 {
     const int lane = threadIdx.x & 63;
-    const i64 row = (i64)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= (i64)nb * rp)        // whole waves leave together
-        return;
     const int b = (int)(row / rp), m = (int)(row % rp);
     const bool live = m < nr;
     // loads are unconditional (clamped addresses), masked afterwards; rows
@@ -150,6 +155,19 @@ __global__ void __launch_bounds__(256) k_slice_rows_wave(const double *__restric
             write_digits(dst + (i64)kb * kbstride, pstride, d);
         }
     }
+}
+
+template <int NJ>
+__global__ void __launch_bounds__(256) k_slice_rows_wave(const double *__restrict__ src, i64 bs,
+                                                         i64 rs, int nb, int nr, int nk, int rp,
+                                                         int nkb, int8_t *__restrict__ out,
+                                                         i64 pstride, i64 kbstride,
+                                                         int *__restrict__ exps)
+{
+    const i64 row = (i64)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= (i64)nb * rp)        // whole waves leave together
+        return;
+    slice_row_wave<NJ>(src, bs, rs, nr, nk, rp, nkb, out, pstride, kbstride, exps, row);
 }
 
 // The same for packed symmetric slabs (jk.h JK_B_PACKED).  A workgroup takes
@@ -290,18 +308,15 @@ __global__ void __launch_bounds__(256) k_slice_xy(const double *__restrict__ XY,
 // For slab ql of the chunk: XY[ql][m][c] = 2^(eB + eC - 14) * sum_l S_l 2^(-8 (l - 2))
 // (c < R: X = B^Q C_L, c >= R: Y = B^Q C_R).  A planes: rows ql * mp + m;
 // B planes: rows c.  Each workgroup writes whole 1 KB row segments.
-__global__ void __launch_bounds__(256, 2) k_ht_mixed(const int8_t *__restrict__ Bp, i64 bpstride,
-                                                  i64 bkbstride, const int *__restrict__ eB,
-                                                  const int8_t *__restrict__ Cp, i64 cpstride,
-                                                  i64 ckbstride, const int *__restrict__ eC,
-                                                  double *__restrict__ XY, int nao, int R2, int mp,
-                                                  int cp, int nkb)
+__device__ __forceinline__ void ht_mixed_tile(const int8_t *__restrict__ Bp, i64 bpstride,
+                                              i64 bkbstride, const int *__restrict__ eB,
+                                              const int8_t *__restrict__ Cp, i64 cpstride,
+                                              i64 ckbstride, const int *__restrict__ eC,
+                                              double *__restrict__ XY, int nao, int R2, int mp,
+                                              int cp, int nkb, int t, char *lds)
 {
-    extern __shared__ char lds[];
     typedef TileH TL;
     const int nmt = mp / kHtMT, nct = cp / kNT;
-    // consecutive tiles (the column tiles of a row panel) on one XCD, sharing its L2
-    const int t = xcd_swizzle(blockIdx.x, gridDim.x);
     const int ql = t / (nmt * nct), rem = t % (nmt * nct);
     const int mb = rem / nct, cb = rem % nct;
     SPlanes a{Bp + (i64)ql * mp * kSliceKB, bpstride, bkbstride};
@@ -323,15 +338,27 @@ __global__ void __launch_bounds__(256, 2) k_ht_mixed(const int8_t *__restrict__ 
         }
 }
 
+__global__ void __launch_bounds__(256, 2) k_ht_mixed(const int8_t *__restrict__ Bp, i64 bpstride,
+                                                     i64 bkbstride, const int *__restrict__ eB,
+                                                     const int8_t *__restrict__ Cp, i64 cpstride,
+                                                     i64 ckbstride, const int *__restrict__ eC,
+                                                     double *__restrict__ XY, int nao, int R2, int mp,
+                                                     int cp, int nkb)
+{
+    extern __shared__ char lds[];
+    // consecutive tiles (the column tiles of a row panel) on one XCD, sharing its L2
+    ht_mixed_tile(Bp, bpstride, bkbstride, eB, Cp, cpstride, ckbstride, eC, XY, nao, R2, mp, cp, nkb,
+                  xcd_swizzle(blockIdx.x, gridDim.x), lds);
+}
+
 // Row exponents of X/Y over the chunk: exps[key * mp + m] for key = side * nd
 // + k, the maximum over slabs ql < nq and i < r of |XY[ql][m][key * r + i]|.
 // One workgroup per m: column maxima over the slabs (coalesced along c), then
 // the maximum over each key's r columns through LDS (2R doubles).
-__global__ void __launch_bounds__(256) k_xy_rowmax(const double *__restrict__ XY, int nao, int nq,
-                                                   int nkey, int r, int mp, int *__restrict__ exps)
+__device__ __forceinline__ void xy_rowmax_row(const double *__restrict__ XY, int nao, int nq, int nkey,
+                                              int r, int mp, int *__restrict__ exps, int m,
+                                              double *colmax)
 {
-    extern __shared__ double colmax[];
-    const int m = blockIdx.x;
     const int R2 = nkey * r;
     const i64 qs = (i64)nao * R2;
     const double *s = XY + (i64)m * R2;
@@ -366,25 +393,30 @@ __global__ void __launch_bounds__(256) k_xy_rowmax(const double *__restrict__ XY
     }
 }
 
+__global__ void __launch_bounds__(256) k_xy_rowmax(const double *__restrict__ XY, int nao, int nq,
+                                                   int nkey, int r, int mp, int *__restrict__ exps)
+{
+    extern __shared__ double colmax[];
+    xy_rowmax_row(XY, nao, nq, nkey, r, mp, exps, blockIdx.x, colmax);
+}
+
 // ------------------------------------------------------------------ exchange
 // Kp[s][k][m][n] (+)= scale 2^(eX + eY - 14) * sum_l S_l 2^(-8 (l - 2)) over the inner
 // blocks [s * kbl, (s + 1) * kbl) of split s.  X/Y planes: rows k * mp + m
 // from Xp / Yp (same strides); row exponents eX[k * mp + m], eY[k * mp + n].
-__global__ void __launch_bounds__(512) k_ex_mixed(const int8_t *__restrict__ Xp,
-                                                  const int8_t *__restrict__ Yp, i64 pstride,
-                                                  i64 kbstride, const int *__restrict__ eX,
-                                                  const int *__restrict__ eY,
-                                                  double *__restrict__ Kp, int nao, int nd, int mp,
-                                                  int nkb, int kbl, int accumulate, int sym,
-                                                  double scale)
+__device__ __forceinline__ void ex_mixed_tile(const int8_t *__restrict__ Xp,
+                                              const int8_t *__restrict__ Yp, i64 pstride,
+                                              i64 kbstride, const int *__restrict__ eX,
+                                              const int *__restrict__ eY, double *__restrict__ Kp,
+                                              int nao, int nd, int mp, int nkb, int kbl,
+                                              int accumulate, int sym, double scale, int t,
+                                              char *lds)
 {
-    extern __shared__ char lds[];
     typedef TileS TL;
     const int nmt = mp / kMT, nnt = mp / kNT;
     // sym: Y = X, only the square tiles with nb >= mb (upper triangle)
     const int pk = sym ? nmt * (nmt + 1) / 2 : nmt * nnt;
     const int per = nd * pk;
-    const int t = xcd_swizzle(blockIdx.x, gridDim.x);
     const int sp = t / per, rem0 = t % per;
     const int k = rem0 / pk, rem = rem0 % pk;
     int mb, nb;
@@ -422,6 +454,108 @@ __global__ void __launch_bounds__(512) k_ex_mixed(const int8_t *__restrict__ Xp,
                 Kk[o] = accumulate ? Kk[o] + v : v;
             }
         }
+}
+
+__global__ void __launch_bounds__(512) k_ex_mixed(const int8_t *__restrict__ Xp,
+                                                  const int8_t *__restrict__ Yp, i64 pstride,
+                                                  i64 kbstride, const int *__restrict__ eX,
+                                                  const int *__restrict__ eY,
+                                                  double *__restrict__ Kp, int nao, int nd, int mp,
+                                                  int nkb, int kbl, int accumulate, int sym,
+                                                  double scale)
+{
+    extern __shared__ char lds[];
+    ex_mixed_tile(Xp, Yp, pstride, kbstride, eX, eY, Kp, nao, nd, mp, nkb, kbl, accumulate, sym,
+                  scale, xcd_swizzle(blockIdx.x, gridDim.x), lds);
+}
+
+// ------------------------------------------------------------------ batched
+// The mixed phases over many members (jk_batched.hpp): the launch's table maps
+// each workgroup to (member, tile); every member runs its own plan's chunk c
+// with single-buffered planes, so a batched member is the same arithmetic as
+// a single build of the same plan.
+
+__global__ void __launch_bounds__(256) k_bm_slice_c(const BMember *__restrict__ M,
+                                                    const int *__restrict__ tab)
+{
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    const i64 row = (i64)loc * 32 + (threadIdx.x >> 3);
+    if (row >= m.cp)                 // whole 8-lane row groups leave together
+        return;
+    const int R2 = 2 * m.nd * m.r;
+    slice_row8(m.Cc, 0, 1, R2, R2, m.nao, m.cp, m.kp / kSliceKB, m.Cp, m.cps, m.ckb, m.eC, row,
+               threadIdx.x & 7);
+}
+
+template <int NJ>
+__global__ void __launch_bounds__(256) k_bm_slice_b(const BMember *__restrict__ M,
+                                                    const int *__restrict__ tab, int c)
+{
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    int q0, nq;
+    chunk_of(m, c, q0, nq);
+    const i64 row = (i64)loc * 4 + (threadIdx.x >> 6);
+    if (row >= (i64)nq * m.mp)       // whole waves leave together
+        return;
+    slice_row_wave<NJ>(m.B + (i64)q0 * m.npos, m.npos, m.nao, m.nao, m.nao, m.mp, m.kp / kSliceKB,
+                       m.Bp, m.bps, m.bkb, m.eB, row);
+}
+
+__global__ void __launch_bounds__(256, 2) k_bm_ht(const BMember *__restrict__ M,
+                                                  const int *__restrict__ tab, int c)
+{
+    extern __shared__ char lds[];
+    int loc;
+    const BMember &m = M[find_member(tab, xcd_swizzle(blockIdx.x, gridDim.x), loc)];
+    (void)c;
+    const int ncol = m.sym ? m.nd * m.r : 2 * m.nd * m.r;
+    ht_mixed_tile(m.Bp, m.bps, m.bkb, m.eB, m.Cp, m.cps, m.ckb, m.eC, m.XY, m.nao, ncol, m.mp, m.cpx,
+                  m.kp / kSliceKB, loc, lds);
+}
+
+__global__ void __launch_bounds__(256) k_bm_rowmax(const BMember *__restrict__ M,
+                                                   const int *__restrict__ tab, int c)
+{
+    extern __shared__ double colmax[];
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    int q0, nq;
+    chunk_of(m, c, q0, nq);
+    xy_rowmax_row(m.XY, m.nao, nq, m.sym ? m.nd : 2 * m.nd, m.r, m.mp, m.eXY, loc, colmax);
+}
+
+__global__ void __launch_bounds__(256) k_bm_slice_xy(const BMember *__restrict__ M,
+                                                     const int *__restrict__ tab, int c)
+{
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    int q0, nq;
+    chunk_of(m, c, q0, nq);
+    const int nkey = m.sym ? m.nd : 2 * m.nd;
+    const int ngroup = cdiv_i((i64)nkey * m.mp, 32);
+    const int row = (loc % ngroup) * 32 + (threadIdx.x >> 3);
+    if (row >= nkey * m.mp)
+        return;
+    slice_xy_block(m.XY, m.nao, nkey, m.r, m.mp, nq * m.r, m.XYp, m.xps, m.xkb, m.eXY, row,
+                   threadIdx.x & 7, loc / ngroup);
+}
+
+__global__ void __launch_bounds__(512) k_bm_ex(const BMember *__restrict__ M,
+                                               const int *__restrict__ tab, int c)
+{
+    extern __shared__ char lds[];
+    int loc;
+    const BMember &m = M[find_member(tab, xcd_swizzle(blockIdx.x, gridDim.x), loc)];
+    int q0, nq;
+    chunk_of(m, c, q0, nq);
+    const int nkb = cdiv_i((i64)nq * m.r, kSliceKB);
+    const int kbl = cdiv_i(nkb, m.nsplit);
+    const int8_t *Xp = m.XYp, *Yp = m.sym ? Xp : m.XYp + (i64)m.nd * m.mp * kSliceKB;
+    const int *eX = m.eXY, *eY = m.sym ? eX : m.eXY + (i64)m.nd * m.mp;
+    ex_mixed_tile(Xp, Yp, m.xps, m.xkb, eX, eY, m.nsplit > 1 ? m.Kp : m.K, m.nao, m.nd, m.mp, nkb,
+                  kbl, c > 0, m.sym, 1.0, loc, lds);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -601,6 +735,74 @@ hipError_t launch_ex_mixed(const int8_t *Xp, const int8_t *Yp, i64 pstride, i64 
                            scale);
     }
     return hipGetLastError();
+}
+
+// Dynamic LDS of the batched mixed kernels above 64 KB, set once per device
+// before a launch sequence is captured.
+hipError_t prepare_batched_mixed_kernels()
+{
+    hipError_t e = set_lds((const void *)k_bm_ht, PipeHt::LDS_BYTES);
+    if (e == hipSuccess)
+        e = set_lds((const void *)k_bm_ex, PipeEx::LDS_BYTES);
+    return e;
+}
+
+hipError_t launch_batched_mixed_phase(int phase, const BMember *M, const int *tab, int ntiles,
+                                      int step, hipStream_t s, int arg)
+{
+    const dim3 g(ntiles);
+    switch (phase) {
+    case kPhaseMSliceC: {
+        ProfScope ps_("bm_slice_c", s);
+        hipLaunchKernelGGL(k_bm_slice_c, g, dim3(256), 0, s, M, tab);
+        break;
+    }
+    case kPhaseMSliceB: {
+        ProfScope ps_("bm_slice_b", s);
+        if (arg <= 1)
+            hipLaunchKernelGGL(k_bm_slice_b<1>, g, dim3(256), 0, s, M, tab, step);
+        else if (arg <= 2)
+            hipLaunchKernelGGL(k_bm_slice_b<2>, g, dim3(256), 0, s, M, tab, step);
+        else if (arg <= 4)
+            hipLaunchKernelGGL(k_bm_slice_b<4>, g, dim3(256), 0, s, M, tab, step);
+        else if (arg <= 8)
+            hipLaunchKernelGGL(k_bm_slice_b<8>, g, dim3(256), 0, s, M, tab, step);
+        else
+            return hipErrorInvalidValue;
+        break;
+    }
+    case kPhaseMHalf: {
+        ProfScope ps_("bm_ht_mixed", s);
+        hipLaunchKernelGGL(k_bm_ht, g, dim3(TileH::NTHR), PipeHt::LDS_BYTES, s, M, tab, step);
+        break;
+    }
+    case kPhaseMRowmax: {
+        ProfScope ps_("bm_xy_rowmax", s);
+        hipLaunchKernelGGL(k_bm_rowmax, g, dim3(256), (size_t)arg, s, M, tab, step);
+        break;
+    }
+    case kPhaseMSliceXY: {
+        ProfScope ps_("bm_slice_xy", s);
+        hipLaunchKernelGGL(k_bm_slice_xy, g, dim3(256), 0, s, M, tab, step);
+        break;
+    }
+    case kPhaseMExchange: {
+        ProfScope ps_("bm_ex_mixed", s);
+        hipLaunchKernelGGL(k_bm_ex, g, dim3(TileS::NTHR), PipeEx::LDS_BYTES, s, M, tab, step);
+        break;
+    }
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Tile counts of the batched mixed phases for one member (host).
+int mixed_ht_tiles(int mp, int cpx, int nq) { return nq * (mp / kHtMT) * (cpx / kNT); }
+int mixed_ex_tiles(int mp, int nd, int nsplit, int sym)
+{
+    const int nmt = mp / kMT;
+    return nsplit * nd * (sym ? nmt * (nmt + 1) / 2 : nmt * (mp / kNT));
 }
 
 } // namespace jk

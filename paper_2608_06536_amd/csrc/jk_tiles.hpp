@@ -143,6 +143,39 @@ __host__ __device__ inline void ex_tri_coords(int t, int nao, int &mb, int &nb)
 }
 __host__ __device__ inline int sum_tiles(i64 n) { return cdiv_i(n, kElemTile); }
 
+// Kk[m][n] = Kk[n][m] for m > n in lower-triangle block b of 32 x 32 (blocks
+// (bi, bj), bi >= bj, numbered row by row): fills the lower triangle from the
+// upper one through an LDS transpose.  256 threads; t is 32 x 33 doubles.
+__device__ __forceinline__ void mirror_tile(double *__restrict__ Kk, int nao, int b,
+                                            double (*t)[33])
+{
+    int bi = 0;
+    while (b > bi) {
+        b -= bi + 1;
+        bi++;
+    }
+    const int bj = b;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int y = ty; y < 32; y += 8) {
+        const int row = bj * 32 + y, col = bi * 32 + tx;       // upper source
+        if (row < nao && col < nao)
+            t[y][tx] = Kk[(i64)row * nao + col];
+    }
+    __syncthreads();
+    for (int y = ty; y < 32; y += 8) {
+        const int m = bi * 32 + y, n = bj * 32 + tx;           // lower target
+        if (m < nao && n < nao && m > n)
+            Kk[(i64)m * nao + n] = t[tx][y];
+    }
+    __syncthreads();
+}
+
+__host__ __device__ inline int mirror_blocks(int nao)
+{
+    const int nb = cdiv_i(nao, 32);
+    return nb * (nb + 1) / 2;
+}
+
 // ------------------------------------------------------------------ pack
 __device__ inline void pack_tile(const double *__restrict__ CL, const double *__restrict__ CR,
                                  double *__restrict__ Cc, int nao, int nd, int r, int tile)

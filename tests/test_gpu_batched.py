@@ -151,3 +151,61 @@ def test_batched_graph_cache_eviction():
         stream.synchronize()
         for (J, K), (Js, Ks) in zip(res, singles):
             assert torch.equal(J, Js) and torch.equal(K, Ks), g
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_symmetric_members_and_single_plans(precision):
+    # Members whose C_L and C_R are one buffer take the X-only path (upper
+    # triangle, mirrored).  Every member equals a single jk_build of it bit
+    # for bit under a plan whose chunks match the batch's (256 MiB), and the
+    # oracle to the path's tolerance.
+    from paper_2608_06536_amd import jk
+    tol = TOL if precision == "fp64" else 1e-8
+    probs = _problems([70, 150, 33, 260, 9], seed=91, naux_mult=3)
+    items, host = _make(probs)
+    sym = [True, False, True, True, False]
+    items = [(B, L, L if s else R) for (B, L, R), s in zip(items, sym)]
+    res = jk.jk_build_batched(items, precision=precision)
+    torch.cuda.synchronize()
+    try:
+        for g, ((Bd, Ld, Rd), (J, K), (B, CL, CR), p, s) in enumerate(zip(items, res, host, probs, sym)):
+            jk.tuning_set(jk.make_problem(p.nao, p.naux, p.nd, p.r, precision), 4, 256)
+            Js, Ks = jk.jk_build(Bd, Ld, Rd, precision=precision)
+            torch.cuda.synchronize()
+            assert torch.equal(J, Js), g
+            assert torch.equal(K, Ks), g
+            CRh = CL if s else CR
+            Jr, Kr, _ = oracle.jk_factored(B, CL, CRh)
+            assert rel_err(J.cpu().numpy(), Jr) <= TOL
+            for k in range(p.nd):
+                assert rel_err(K[k].cpu().numpy(), Kr[k]) <= tol, (g, k)
+            if s:
+                assert torch.equal(K, K.transpose(1, 2)), g
+    finally:
+        jk.tuning_clear()
+
+
+def test_batched_mixed_graph_replays():
+    # the mixed batch on a non-default stream: captured once, replayed with
+    # new inputs and eager single builds between the replays
+    from paper_2608_06536_amd import jk
+    probs = _problems([31, 77, 140, 5, 64], seed=33)
+    stream = torch.cuda.Stream()
+    nbytes = jk.batched_workspace_bytes([jk.make_problem(p.nao, p.naux, p.nd, p.r, "mixed")
+                                         for p in probs])
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    try:
+        for p in probs:
+            jk.tuning_set(jk.make_problem(p.nao, p.naux, p.nd, p.r, "mixed"), 4, 256)
+        for rep in range(3):
+            items, _ = _make(probs, scale=1.0 + 0.5 * rep)
+            torch.cuda.synchronize()
+            with torch.cuda.stream(stream):
+                res = jk.jk_build_batched(items, precision="mixed", ws=ws)
+                singles = [jk.jk_build(*it, precision="mixed") for it in items]
+            stream.synchronize()
+            for (J, K), (Js, Ks) in zip(res, singles):
+                assert torch.equal(J, Js), rep
+                assert torch.equal(K, Ks), rep
+    finally:
+        jk.tuning_clear()

@@ -93,6 +93,10 @@ def main():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision build")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the candidate plans instead of loading the committed plan table")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 64-geometry batched leg")
     ap.add_argument("--plan", default="",
                     help="TILE,CHUNK_MB: use this plan instead of autotuning (profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -126,13 +130,20 @@ def main():
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     # plan of this shape: from the autotuner (untimed; jk_tune.h), or given
+    # (the committed table by default, so that every run times the same plan)
     t_tune = time.perf_counter()
+    plan_src = "paper_2608_06536_amd/tuned_plans.json"
     if args.plan:
         tile, mb = (int(v) for v in args.plan.split(","))
         jk.tuning_set(jk.make_problem(nao, naux, nd, r), tile, mb)
-        plan_fp64 = {"ht_tile": tile, "chunk_mb": mb}
+        plan_src = "--plan"
+    elif args.autotune:
+        jk.autotune(Bd, Ld, Rd, reps=5, out=(J, K), ws=ws)
+        plan_src = "autotuned on this device"
     else:
-        _, _, plan_fp64 = jk.autotune(Bd, Ld, Rd, reps=5, out=(J, K), ws=ws)
+        with open(os.path.join(ROOT, plan_src)) as fh:
+            jk.tuning_load(fh.read())
+    plan_fp64 = jk.tuning_get(jk.make_problem(nao, naux, nd, r))
     t_tune = time.perf_counter() - t_tune
 
     def build():
@@ -344,6 +355,95 @@ def main():
     except _lib.JKError as e:
         lap_res = {"laplace": f"unavailable: {e}"}
 
+    # ---- the 64-geometry batch: nao uniform in [100, 500], naux = 4 nao, one
+    # ground and five transition densities of rank nao / 10 (B totals 91 GB,
+    # drawn on the device), one jk_build_batched call per precision, replayed
+    # from its captured graph; beside it one jk_build per geometry
+    batched = {"batched": "skipped"}
+    if not args.no_batched:
+        try:
+            bprobs = synth.batched_problems()
+            items = []
+            for bp in bprobs:
+                cl, cr = synth.make_factors(bp)
+                items.append((synth.make_B_device(bp, dev), torch.from_numpy(cl).to(dev),
+                              torch.from_numpy(cr).to(dev)))
+            nd_tot = sum(bp.nd for bp in bprobs)
+            bstream = torch.cuda.Stream()
+            batched = {"workload": f"{len(bprobs)} geometries, nao uniform in [100, 500], naux = 4 nao, "
+                                   "6 densities of rank nao/10 (1 ground + 5 transition); inputs drawn "
+                                   "on the device", "densities": nd_tot,
+                       "B_bytes": int(sum(8 * bp.naux * bp.nao ** 2 for bp in bprobs))}
+            outs = [(torch.empty((bp.nd, bp.nao, bp.nao), dtype=torch.float64, device=dev),
+                     torch.empty((bp.nd, bp.nao, bp.nao), dtype=torch.float64, device=dev))
+                    for bp in bprobs]
+            for prec in ("fp64",) + (() if args.no_mixed else ("mixed",)):
+                nbb = jk.batched_workspace_bytes([jk.make_problem(bp.nao, bp.naux, bp.nd, bp.r, prec)
+                                                  for bp in bprobs])
+                wsb = torch.empty(nbb, dtype=torch.uint8, device=dev)
+                torch.cuda.synchronize()
+                with torch.cuda.stream(bstream):
+                    t_b = rate(lambda: jk.jk_build_batched(items, precision=prec, outs=outs, ws=wsb),
+                               n=5)
+                batched[f"batch_ms_{prec}"] = round(1e3 * t_b, 2)
+                batched[f"densities_per_s_{prec}"] = round(nd_tot / t_b, 1)
+                del wsb
+                torch.cuda.empty_cache()
+            wsg = torch.empty(max(jk.workspace_bytes(jk.make_problem(bp.nao, bp.naux, bp.nd, bp.r))
+                                  for bp in bprobs), dtype=torch.uint8, device=dev)
+
+            def singles():
+                for (Bg, Lg, Rg), og in zip(items, outs):
+                    jk.jk_build(Bg, Lg, Rg, out=og, ws=wsg)
+
+            t_s = rate(singles, n=3)
+            batched["one_build_per_geometry_ms_fp64"] = round(1e3 * t_s, 2)
+            if "batch_ms_mixed" in batched:
+                batched["speedup_mixed_batch_vs_fp64_batch"] = round(
+                    batched["batch_ms_fp64"] / batched["batch_ms_mixed"], 3)
+            del items, outs, wsg
+            torch.cuda.empty_cache()
+        except (_lib.JKError, torch.cuda.OutOfMemoryError) as e:
+            batched = {"batched": f"unavailable: {e}"}
+
+    # ---- measured matrix-core peaks (the microbenchmark of jk_prof.h)
+    peaks = {"int8_pops_random": round(_lib.peak_mfma("int8", True) / 1e15, 3),
+             "int8_pops_constant": round(_lib.peak_mfma("int8", False) / 1e15, 3),
+             "fp64_tflops_random": round(_lib.peak_mfma("fp64", True) / 1e12, 2),
+             "note": "INT8 in the slice engine's 13-product pattern; random = uniform bytes per lane"}
+
+    # ---- INT8 roofline of the mixed build's dominant kernel (event times of
+    # the presliced build; the aux stream's slicing runs beside it, so the
+    # rate is a lower bound)
+    roof_mixed = None
+    if isinstance(mixed, dict) and "build_ms_mixed_presliced" in mixed:
+        wsm = torch.empty(jk.workspace_bytes(jk.make_problem(nao, naux, nd, r, "mixed")),
+                          dtype=torch.uint8, device=dev)
+        S = jk.slice_b(Bd, nao)
+        for _ in range(2):
+            jk.jk_build(Bd, Ld, Rd, precision="mixed", out=(Jm, Km), ws=wsm, slices=S)
+        torch.cuda.synchronize()
+        _lib.prof_enable(4096)
+        _lib.prof_reset()
+        nrep = 10
+        for _ in range(nrep):
+            jk.jk_build(Bd, Ld, Rd, precision="mixed", out=(Jm, Km), ws=wsm, slices=S)
+        kmix = _lib.prof_collect()
+        _lib.prof_disable()
+        ops = {"ht_mixed": 13 * 4.0 * naux * nao * nao * R, "ex_mixed": 13 * 2.0 * naux * nao * nao * R}
+        roof_mixed = {}
+        for kname, kops in ops.items():
+            if kname in kmix:
+                kms, kcnt = kmix[kname]
+                ach = kops * nrep / (kms * 1e-3) / 1e15
+                roof_mixed[kname] = {"achieved": round(ach, 3), "unit": "int8 POP/s (13 digit-pair products)",
+                                     "peak_nominal": 5.0, "frac_nominal": round(ach / 5.0, 3),
+                                     "peak_measured_random": peaks["int8_pops_random"],
+                                     "frac_measured": round(ach / peaks["int8_pops_random"], 3),
+                                     "avg_launch_us": round(1e3 * kms / kcnt, 1),
+                                     "overlapped": True}
+        del wsm, S
+
     # ---- roofline of the dominant kernel
     models = kernel_models(p, nd, nao, naux, R)
     per_kernel = {}
@@ -400,13 +500,16 @@ def main():
         "vjps_per_s_fp64": round(nd / t_vjp, 2),
         "build_ms_fp64": round(1e3 * t_build, 3),
         "vjp_ms_fp64": round(1e3 * t_vjp, 3),
-        "plan": {"fp64": plan_fp64, "autotune_s": round(t_tune, 2)},
+        "plan": {"fp64": plan_fp64, "source": plan_src, "plan_s": round(t_tune, 2)},
         "mixed": mixed,
         "symmetric_densities": sym,
         "packed_b": packed,
         "fock": fock,
         "laplace": lap_res,
+        "batched": batched,
         "roofline": roof,
+        "roofline_mixed": roof_mixed,
+        "peaks_measured": peaks,
         "kernels": per_kernel,
         "prof_dropped": dropped,
     }
@@ -450,12 +553,23 @@ def main():
         tf, tv = cpu_time(ns) if ns > 2 else (tf1, tv1)
         scale = naux / ns
         t_cpu = (tf + tv) * scale
+        # the nao=300 workload (naux=1200, 4 densities of rank 30) in full,
+        # median of 3 builds
+        p2 = synth.config(2)
+        B2, CL2, CR2 = synth.make_problem(p2)
+        t2 = []
+        for _ in range(3):
+            a = time.perf_counter()
+            oracle.jk_factored(B2, CL2, CR2)
+            t2.append(time.perf_counter() - a)
         out["cpu_baseline"] = {
             "value": round(nd / t_cpu, 5), "unit": "densities/s (FP64 build + VJP)",
             "cores": nthr, "kind": "oracle",
             "sample": f"factored oracle (build + derivative) on the first {ns} of {naux} slabs of "
                       f"the same workload, time scaled by {scale:.1f}",
             "build_s_est": round(tf * scale, 2), "vjp_s_est": round(tv * scale, 2),
+            "nao300_build_s_median_of_3": round(float(np.median(t2)), 3),
+            "nao300_densities_per_s": round(p2.nd / float(np.median(t2)), 4),
         }
     print(json.dumps(out), flush=True)
 

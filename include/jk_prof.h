@@ -36,6 +36,15 @@ int jk_prof_entry(int32_t i, const char **name, double *total_ms, int64_t *launc
 /* Launches not recorded because the pool was full. */
 int64_t jk_prof_dropped(void);
 
+/* Matrix-core peak microbenchmark on the current device (allocates a small
+ * buffer, launches on the default stream and synchronises; not for use in a
+ * timed region).  kind 0: V_MFMA_I32_32X32X32_I8 in the slice engine's
+ * pattern (13 digit-pair products per two output tiles), in int8 ops/s;
+ * kind 1: V_MFMA_F64_16X16X4_F64, in flop/s.  random != 0: operands drawn per
+ * lane (uniform bytes, like the digits), else constants; the sustained INT8
+ * rate depends on the data.  Returns -1 on an error. */
+double jk_peak_mfma(int32_t kind, int32_t random);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,7 @@ LAPLACE_MAX_POINTS = 20
 TUNE_EXPORTS = ("jk_autotune", "jk_tuning_get", "jk_tuning_set", "jk_tuning_clear",
                 "jk_tuning_save", "jk_tuning_load", "jk_plan_describe")
 PROF_EXPORTS = ("jk_prof_enable", "jk_prof_reset", "jk_prof_collect", "jk_prof_entry",
-                "jk_prof_dropped")
+                "jk_prof_dropped", "jk_peak_mfma")
 
 
 class Problem(ctypes.Structure):
@@ -130,6 +130,8 @@ def lib():
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.jk_prof_dropped.restype = ctypes.c_int64
         L.jk_prof_dropped.argtypes = []
+        L.jk_peak_mfma.restype = ctypes.c_double
+        L.jk_peak_mfma.argtypes = [ctypes.c_int32, ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -175,3 +177,13 @@ def prof_collect() -> dict:
 
 def prof_dropped() -> int:
     return int(lib().jk_prof_dropped())
+
+
+def peak_mfma(kind: str, random: bool = True) -> float:
+    """Measured matrix-core rate: kind "int8" (int8 ops/s in the slice
+    engine's pattern) or "fp64" (flop/s); random per-lane operands or
+    constants (include/jk_prof.h)."""
+    v = float(lib().jk_peak_mfma({"int8": 0, "fp64": 1}[kind], 1 if random else 0))
+    if v < 0:
+        raise RuntimeError("jk_peak_mfma failed")
+    return v

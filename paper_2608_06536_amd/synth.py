@@ -34,7 +34,8 @@ import os
 import numpy as np
 
 __all__ = [
-    "Problem", "CONFIGS", "config", "make_B", "make_B_slabs", "make_B_parallel", "make_factors",
+    "Problem", "CONFIGS", "config", "make_B", "make_B_slabs", "make_B_parallel", "make_B_device",
+    "make_factors",
     "make_cotangents", "make_problem", "batched_problems", "Orbitals", "make_orbitals",
     "make_amplitudes", "LAPLACE_BENCH",
 ]
@@ -126,6 +127,22 @@ def make_B_parallel(p: Problem, workers: int = 16, step: int = 32) -> np.ndarray
                                            out=B[a:min(a + step, p.naux)]),
                     range(0, p.naux, step)))
     return B
+
+
+def make_B_device(p: Problem, device):
+    """The make_B recipe drawn on a GPU from torch's seeded generator: the
+    same distribution and structure (symmetric slabs, exp(-|m-n|/ell) decay
+    across a slab, exp(-Q/tau) across slabs), a different random stream from
+    the host generator.  For timing batches too large to draw on the host;
+    parity tests use make_B."""
+    import torch
+    g = torch.Generator(device=device).manual_seed(p.seed)
+    B = torch.randn((p.naux, p.nao, p.nao), generator=g, dtype=torch.float64, device=device)
+    B = torch.triu(B) + torch.triu(B, 1).transpose(1, 2)
+    idx = torch.arange(p.nao, device=device, dtype=torch.float64)
+    B *= torch.exp(-(idx[:, None] - idx[None, :]).abs() / p.ell)
+    B *= torch.exp(-torch.arange(p.naux, device=device, dtype=torch.float64) / p.tau)[:, None, None]
+    return B.contiguous()
 
 
 def _orth(rng: np.random.Generator, nao: int, r: int) -> np.ndarray:

@@ -160,6 +160,7 @@ int chunk_slabs_vjp(const jk_problem *p)
 
 struct VjpPlan {
     int qc, ldw, npb, plen, ndp, nsplit_c;
+    bool paired;        // omega and gamma in one pass over B (2 nd <= 16)
     size_t o_cc, o_d, o_e, o_part, o_g, o_om, o_omx, o_x, o_y, o_pr, o_dcp, total;
 };
 
@@ -173,13 +174,24 @@ VjpPlan plan_vjp(const jk_problem *p)
     f.ndp = (int)(((nd + 7) / 8) * 8);
     f.npb = jk::project_nblocks(npos, (int)naux, (int)nd, &f.plen);
     f.nsplit_c = jk::vjp_stage_c_nsplit((int)nao, (int)R, f.qc);
+    f.paired = 2 * nd <= 16;
+    size_t part = (size_t)f.npb * naux * f.ndp;
+    if (f.paired) {
+        // 2 nd <= 8: one group of the 8-wide projection; else the 16-wide one
+        int plen2;
+        const size_t p2 = 2 * nd <= 8
+                              ? (size_t)jk::project_nblocks(npos, (int)naux, (int)(2 * nd), &plen2) * naux * 8
+                              : (size_t)jk::project16_nblocks(npos, (int)naux, &plen2) * naux * 16;
+        part = part > p2 ? part : p2;
+    }
     Carve c;
     f.o_cc = c.take(sizeof(double) * nao * 2 * R);
-    f.o_d = c.take(sizeof(double) * nd * npos);
+    // paired: [W | D], the cotangent copied in front of the densities
+    f.o_d = c.take(sizeof(double) * (f.paired ? 2 : 1) * nd * npos);
     f.o_e = c.take(sizeof(double) * nd * npos);
-    f.o_part = c.take(sizeof(double) * (size_t)f.npb * naux * f.ndp);
+    f.o_part = c.take(sizeof(double) * part);
     f.o_g = c.take(sizeof(double) * nd * naux);
-    f.o_om = c.take(sizeof(double) * nd * naux);
+    f.o_om = c.take(sizeof(double) * (f.paired ? 2 : 1) * nd * naux);   // paired: [omega | gamma]
     f.o_omx = c.take(sizeof(double) * naux * R);
     f.o_x = c.take(sizeof(double) * nd * nao * (size_t)f.ldw);
     f.o_y = c.take(sizeof(double) * nd * nao * (size_t)f.ldw);
@@ -417,7 +429,21 @@ jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const
     double *dCp = (double *)(ws + f.o_dcp);
 
     JK_TRY(jk::launch_pack_c(CL, CR, Cc, nao, nd, r, s));
-    if (has_w) {
+    if (has_w && want_db && f.paired) {
+        // omega_kQ = <W_k, B^Q> and gamma_kQ = <D_k, B^Q> in one pass over B:
+        // the 2 nd matrices [W | D] against each slab; E = D - 2 D^T.
+        double *WD = D;
+        D = WD + (i64)nd * npos;
+        g = om + (i64)nd * naux;
+        JK_TRY(hipMemcpyAsync(WD, W, sizeof(double) * (size_t)nd * npos, hipMemcpyDeviceToDevice, s));
+        JK_TRY(jk::launch_density(CL, CR, D, nao, nd, r, s));
+        if (2 * nd <= 8)
+            JK_TRY(jk::launch_project(B, WD, part, om, naux, 2 * nd, npos, s));
+        else
+            JK_TRY(jk::launch_project16(B, WD, part, om, naux, 2 * nd, npos, s));
+        JK_TRY(jk::launch_omega_expand(om, omx, naux, nd, r, s));
+        JK_TRY(jk::launch_vjp_e_matrix(D, E, nao, nd, s));
+    } else if (has_w) {
         // omega_kQ = <W_k, B^Q>; for dB also gamma_kQ = <D_k, B^Q> and E = D - 2 D^T.
         JK_TRY(jk::launch_project(B, W, part, om, naux, nd, npos, s));
         JK_TRY(jk::launch_omega_expand(om, omx, naux, nd, r, s));

@@ -32,6 +32,15 @@ __global__ void __launch_bounds__(256) k_project(const double *__restrict__ B,
     project_tile(B, A, part, naux, nd, npos, plen, blockIdx.x, lds);
 }
 
+__global__ void __launch_bounds__(256) k_project16(const double *__restrict__ B,
+                                                   const double *__restrict__ A,
+                                                   double *__restrict__ part, int naux, int nd,
+                                                   i64 npos, int plen)
+{
+    __shared__ double lds[TileProject16::LDS_DOUBLES];
+    project16_tile(B, A, part, naux, nd, npos, plen, blockIdx.x, lds);
+}
+
 __global__ void __launch_bounds__(256) k_project_reduce(const double *__restrict__ part,
                                                         double *__restrict__ g, int naux, int nd,
                                                         int npb)
@@ -302,6 +311,31 @@ hipError_t launch_project(const double *B, const double *A, double *part, double
         ProfScope ps_("project", s);
         hipLaunchKernelGGL(k_project, dim3(project_tiles(naux, nd, npb)), dim3(256), 0, s, B, A, part,
                            naux, nd, npos, plen);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    {
+        ProfScope ps_("project_reduce", s);
+        hipLaunchKernelGGL(k_project_reduce, dim3(reduce_tiles(naux, nd)), dim3(256), 0, s, part, g,
+                           naux, nd, npb);
+    }
+    return hipGetLastError();
+}
+
+int project16_nblocks(i64 npos, int naux, int *plen) { return project_nblocks(npos, naux, 8, plen); }
+
+hipError_t launch_project16(const double *B, const double *A, double *part, double *g, int naux,
+                            int nd, i64 npos, hipStream_t s)
+{
+    if (nd <= 8 || nd > 16)
+        return hipErrorInvalidValue;
+    int plen;
+    const int npb = project16_nblocks(npos, naux, &plen);
+    {
+        ProfScope ps_("project16", s);
+        hipLaunchKernelGGL(k_project16, dim3(project16_tiles(naux, npb)), dim3(256), 0, s, B, A,
+                           part, naux, nd, npos, plen);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)

@@ -40,6 +40,11 @@ hipError_t launch_pack_c(const double *CL, const double *CR, double *Cc, int nao
 hipError_t launch_density(const double *CL, const double *CR, double *D, int nao, int nd, int r,
                           hipStream_t s);
 int project_nblocks(int64_t npos, int naux, int nd, int *plen);
+// 9 to 16 matrices A_k (contiguous, npos apart) projected in one pass over B
+// into g[k][Q]; part holds project16_nblocks x naux x 16 doubles.
+int project16_nblocks(int64_t npos, int naux, int *plen);
+hipError_t launch_project16(const double *B, const double *A, double *part, double *g, int naux,
+                            int nd, int64_t npos, hipStream_t s);
 hipError_t launch_project(const double *B, const double *A, double *part, double *g, int naux,
                           int nd, int64_t npos, hipStream_t s);
 // J (+)= scale * sum_Q g B^Q; accumulate adds to what J holds.

@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(512) k_peak_i8(int iters, int *__restrict__ si
 constexpr int kF64Chains = 16;
 
 template <int RANDOM>
-__global__ void __launch_bounds__(256) k_peak_f64(int iters, double *__restrict__ sink)
+__global__ void __launch_bounds__(256, 2) k_peak_f64(int iters, double *__restrict__ sink)
 {
     unsigned h = (blockIdx.x * 256u + threadIdx.x) * 2654435761u + 0x7f4a7c15u;
     double a[4], b[4];

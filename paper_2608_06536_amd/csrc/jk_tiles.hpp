@@ -35,6 +35,7 @@ constexpr int kElemTile = 1024;
 typedef Tile<kHtM, kHtN, 64, 32, 16> TileHalf;
 typedef Tile<kExM, kExN, 64, 16, 16> TileExch;
 typedef Tile<kProjRows, 8, 64, 8, 16> TileProject;
+typedef Tile<kProjRows, 16, 64, 16, 16> TileProject16;
 typedef Tile<64, 64, 32, 32, 16> TileDensity;
 // The half-transform's second tile shape (a plan choice, jk_tune.h): 64 x 64,
 // four workgroups per CU; wins at small nao where 128-row tiles waste rows.
@@ -240,6 +241,31 @@ __device__ inline void project_tile(const double *__restrict__ B, const double *
     tile_foreach(acc, qt * kProjRows, 0, [&](int q, int kk, double v) {
         if (q < naux && kk < 8)
             out[(i64)q * ndp + kg * 8 + kk] = v;
+    });
+}
+
+// The same product for 9 to 16 matrices A_k in one group (two sets of
+// projections paired in one pass over B): part[pb][Q][k], k < 16, one tile per
+// (position block, Q-tile).
+__host__ __device__ inline int project16_tiles(int naux, int npb) { return cdiv_i(naux, kProjRows) * npb; }
+__device__ inline void project16_tile(const double *__restrict__ B, const double *__restrict__ A,
+                                      double *__restrict__ part, int naux, int nd, i64 npos,
+                                      int plen, int tile, double *lds)
+{
+    typedef TileProject16 TL;
+    const int nqt = cdiv_i(naux, kProjRows);
+    const int pb = tile / nqt, qt = tile % nqt;
+    const i64 p0 = (i64)pb * plen;
+    const int len = (int)((npos - p0) < plen ? (npos - p0) : plen);
+    OpKC a{B + p0, npos, naux, len};
+    OpKC b{A + p0, npos, nd, len};
+    Acc<TL> acc;
+    acc.zero();
+    tile_gemm<TL>(a, b, qt * kProjRows, 0, 0, len, lds, acc);
+    double *out = part + (i64)pb * naux * 16;
+    tile_foreach(acc, qt * kProjRows, 0, [&](int q, int kk, double v) {
+        if (q < naux && kk < 16)
+            out[(i64)q * 16 + kk] = v;
     });
 }
 

@@ -44,6 +44,9 @@ def _prob(nao, naux, nd, r, seed):
     (70, 11, 3, 7),
     (131, 21, 2, 20),     # 3R = 120: inner dimension not a multiple of 16
     (48, 192, 1, 8),      # the nao=48 workload shape
+    (50, 30, 8, 5),       # omega and gamma as 16 projections in one pass over B
+    (45, 20, 5, 4),       # 10 of the 16 projection columns used
+    (40, 15, 9, 3),       # 18 projections: omega and gamma in passes of their own
 ])
 def test_vjp_vs_oracle(nao, naux, nd, r):
     B, CL, CR, W, V = _prob(nao, naux, nd, r, 300 + nao)

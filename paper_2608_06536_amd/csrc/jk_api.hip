@@ -218,11 +218,12 @@ struct MixPlan {
     int cp_sym, nsplit_sym;   // X-only columns and triangle splits (C_L = C_R)
     size_t bp_bytes, xy_bytes, xyp_bytes;
     size_t o_bp[2], o_eb[2], o_xy[2], o_xyp[2], o_exy[2], o_cp, o_ec, o_kp, total;
+    size_t o_pm[2];           // the half-transform's row maxima per tile (single builds)
 };
 
 inline i64 pad_to(i64 x, i64 m) { return ((x + m - 1) / m) * m; }
 
-MixPlan plan_mixed(const jk_problem *p, size_t budget = kChunkBudget)
+MixPlan plan_mixed(const jk_problem *p, size_t budget = kChunkBudget, bool rowmax_tiles = true)
 {
     MixPlan x;
     x.f = plan_forward(p, budget);
@@ -254,6 +255,10 @@ MixPlan plan_mixed(const jk_problem *p, size_t budget = kChunkBudget)
     x.o_cp = c.take((size_t)x.ns * x.cp * x.kp);
     x.o_ec = c.take(sizeof(int) * (size_t)x.cp);
     x.o_kp = c.take(sizeof(double) * (size_t)nsmax * nd * nao * nao);
+    // sized for both sides (the X-only case has fewer column tiles and keys)
+    const size_t pm = rowmax_tiles ? jk::xy_rowmax_pm_doubles(x.f.qc, x.mp, x.cp, (int)r, (int)(2 * nd)) : 0;
+    for (int b = 0; b < 2; b++)
+        x.o_pm[b] = c.take(sizeof(double) * pm);
     x.total = c.off;
     return x;
 }
@@ -598,13 +603,14 @@ jk_status build_mixed(const jk_problem *p, const double *B, const KSeg *seg, int
     auto XY = [&](int c) { return (double *)(ws + x.o_xy[c & 1]); };
     auto XYp = [&](int c) { return (int8_t *)(ws + x.o_xyp[c & 1]); };
     auto eXY = [&](int c) { return (int *)(ws + x.o_exy[c & 1]); };
+    auto PM = [&](int c) { return (double *)(ws + x.o_pm[c & 1]); };
 
     // Two streams.  Main stream s: the MFMA-bound products, ht(c + 1) then
     // ex(c).  Auxiliary stream a: the HBM-bound slicing, slice_b(c + 2), then
     // rowmax / slice_xy(c + 1).  Buffers are double-buffered by chunk parity;
     // every reuse waits for the last reader of the previous occupant:
     //   Bp/eB[c]   written by slice_b(c),  read by ht(c)
-    //   XY[c]      written by ht(c),       read by rowmax/slice_xy(c)
+    //   XY/PM[c]   written by ht(c),       read by rowmax/slice_xy(c)
     //   XYp/eXY[c] written by slice_xy(c), read by ex(c)
     hipStream_t a = nullptr;
     JK_TRY(aux_stream(&a));
@@ -627,7 +633,7 @@ jk_status build_mixed(const jk_problem *p, const double *B, const KSeg *seg, int
         return JK_OK;
     };
     auto slice_xy = [&](int c) -> jk_status {
-        JK_TRY(jk::launch_xy_rowmax(XY(c), nao, nq_of(c), nkey, r, x.mp, eXY(c), a));
+        JK_TRY(jk::launch_xy_rowmax_pm(PM(c), nao, nq_of(c), nkey, r, x.mp, cpx, eXY(c), a));
         JK_TRY(jk::launch_slice_xy(XY(c), nao, nkey, r, x.mp, nq_of(c) * r, nkb_of(c), XYp(c), xps, xkb,
                                    eXY(c), a));
         JK_TRY(hipEventRecord(sx[c & 1], a));
@@ -638,7 +644,7 @@ jk_status build_mixed(const jk_problem *p, const double *B, const KSeg *seg, int
         if (c >= 2)
             JK_TRY(hipStreamWaitEvent(s, sx[c & 1], 0));    // XY[c] free
         JK_TRY(jk::launch_ht_mixed(Bp(c), bps, bkb, eB(c), Cp, cps, ckb, eC, XY(c), nao, ncol, nq_of(c),
-                                   x.mp, cpx, x.kp / KB, s));
+                                   x.mp, cpx, x.kp / KB, s, PM(c), r));
         JK_TRY(hipEventRecord(ht[c & 1], s));
         return JK_OK;
     };
@@ -772,7 +778,7 @@ BPlan batched_plan(const jk_problem *p, bool sym_in)
     BPlan b;
     const size_t budget = batched_budget(p);
     if (p->precision == JK_MIXED) {
-        b.x = plan_mixed(p, budget);
+        b.x = plan_mixed(p, budget, false);
         b.f = b.x.f;
         b.sym = sym_in ? 1 : 0;
         b.nsplit = b.sym ? b.x.nsplit_sym : b.x.nsplit;
@@ -802,7 +808,7 @@ int slicer_blocks(int kp)
 bool batched_mixed_ok(int32_t nprob, const jk_problem *p)
 {
     for (int g = 0; g < nprob; g++) {
-        const MixPlan x = plan_mixed(&p[g], batched_budget(&p[g]));
+        const MixPlan x = plan_mixed(&p[g], batched_budget(&p[g]), false);
         if (slicer_blocks(x.kp) == 0 || !jk::mixed_rowmax_ok(2 * (int)(p[g].ndens * p[g].rank)))
             return false;
     }

@@ -111,9 +111,16 @@ hipError_t launch_xy_rowmax(const double *XY, int nao, int nq, int nkey, int r, 
                             hipStream_t s);
 hipError_t launch_slice_xy(const double *XY, int nao, int nkey, int r, int mp, int nj, int nkb,
                            int8_t *out, i64 pstride, i64 kbstride, const int *exps, hipStream_t s);
+// pm (optional): the row maxima of the chunk's X and Y per tile
+// (xy_rowmax_pm_doubles doubles), reduced into exponents by launch_xy_rowmax_pm.
 hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, i64 bkbstride, const int *eB,
                            const int8_t *Cp, i64 cpstride, i64 ckbstride, const int *eC, double *XY,
-                           int nao, int R2, int nq, int mp, int cp, int nkb, hipStream_t s);
+                           int nao, int R2, int nq, int mp, int cp, int nkb, hipStream_t s,
+                           double *pm = nullptr, int r = 1);
+int xy_rowmax_slots(int r, int nkey);
+size_t xy_rowmax_pm_doubles(int nq, int mp, int cp, int r, int nkey);
+hipError_t launch_xy_rowmax_pm(const double *pm, int nao, int nq, int nkey, int r, int mp, int cp,
+                               int *exps, hipStream_t s);
 // Exchange splits of a chunk of nkb inner blocks: chosen for occupancy, and
 // never fewer than keep each split's int32 sums exact (mixed_max_depth()
 // inner indices at most).

@@ -308,12 +308,24 @@ __global__ void __launch_bounds__(256) k_slice_xy(const double *__restrict__ XY,
 // For slab ql of the chunk: XY[ql][m][c] = 2^(eB + eC - 14) * sum_l S_l 2^(-8 (l - 2))
 // (c < R: X = B^Q C_L, c >= R: Y = B^Q C_R).  A planes: rows ql * mp + m;
 // B planes: rows c.  Each workgroup writes whole 1 KB row segments.
+//
+// With pm set, the tile also leaves the row maxima the exponents of X and Y
+// need: for each of its rows m and each key (c / r) its columns meet, the
+// largest |XY[ql][m][c]| over those columns, at
+//     pm[((ql nct + cb) nslot + key - key0) mp + m]
+// (cb = column tile, key0 = its first key, nslot >= the keys a tile meets).
+// They are gathered in LDS (the pipeline's buffers, free after the products)
+// with atomic maxima on the bit patterns, which order like the values for
+// non-negative doubles; the maximum is exact, so the exponents equal those
+// of a pass over XY.
 __device__ __forceinline__ void ht_mixed_tile(const int8_t *__restrict__ Bp, i64 bpstride,
                                               i64 bkbstride, const int *__restrict__ eB,
                                               const int8_t *__restrict__ Cp, i64 cpstride,
                                               i64 ckbstride, const int *__restrict__ eC,
                                               double *__restrict__ XY, int nao, int R2, int mp,
-                                              int cp, int nkb, int t, char *lds)
+                                              int cp, int nkb, int t, char *lds,
+                                              double *__restrict__ pm = nullptr, int r = 1,
+                                              int nslot = 0)
 {
     typedef TileH TL;
     const int nmt = mp / kHtMT, nct = cp / kNT;
@@ -325,6 +337,14 @@ __device__ __forceinline__ void ht_mixed_tile(const int8_t *__restrict__ Bp, i64
     acc.zero();
     stile_gemm_w4<TL, kNS, kNbHt>(a, b, mb * kHtMT, cb * kNT, 0, nkb, lds, acc);
     double *out = XY + (i64)ql * nao * R2;
+    unsigned long long *cell = (unsigned long long *)lds;
+    const int key0 = pm ? cb * kNT / r : 0;
+    if (pm) {
+        __syncthreads();                      // every wave past its last stage
+        for (int e = threadIdx.x; e < kHtMT * nslot; e += TL::NTHR)
+            cell[e] = 0ull;
+        __syncthreads();
+    }
 #pragma unroll
     for (int tt = 0; tt < kWTN; tt++)
 #pragma unroll
@@ -332,10 +352,22 @@ __device__ __forceinline__ void ht_mixed_tile(const int8_t *__restrict__ Bp, i64
             int row, col;
             stile_coord_wide<TL>(tt, e, row, col);
             const int m = mb * kHtMT + row, c = cb * kNT + col;
-            if (m < nao && c < R2)
-                out[(i64)m * R2 + c] =
+            if (m < nao && c < R2) {
+                const double v =
                     ldexp(combine_levels_wide<TL>(acc, tt, e), eB[(i64)ql * mp + m] + eC[c] + kSliceProdShift);
+                out[(i64)m * R2 + c] = v;
+                if (pm)
+                    atomicMax(&cell[(c / r - key0) * kHtMT + row],
+                              (unsigned long long)__double_as_longlong(fabs(v)));
+            }
         }
+    if (pm) {
+        __syncthreads();
+        const int nct = cp / kNT;
+        double *dst = pm + (i64)(ql * nct + cb) * nslot * mp + mb * kHtMT;
+        for (int e = threadIdx.x; e < kHtMT * nslot; e += TL::NTHR)
+            dst[(i64)(e / kHtMT) * mp + e % kHtMT] = __longlong_as_double((long long)cell[e]);
+    }
 }
 
 __global__ void __launch_bounds__(256, 2) k_ht_mixed(const int8_t *__restrict__ Bp, i64 bpstride,
@@ -343,12 +375,53 @@ __global__ void __launch_bounds__(256, 2) k_ht_mixed(const int8_t *__restrict__ 
                                                      const int8_t *__restrict__ Cp, i64 cpstride,
                                                      i64 ckbstride, const int *__restrict__ eC,
                                                      double *__restrict__ XY, int nao, int R2, int mp,
-                                                     int cp, int nkb)
+                                                     int cp, int nkb, double *__restrict__ pm, int r,
+                                                     int nslot)
 {
     extern __shared__ char lds[];
     // consecutive tiles (the column tiles of a row panel) on one XCD, sharing its L2
     ht_mixed_tile(Bp, bpstride, bkbstride, eB, Cp, cpstride, ckbstride, eC, XY, nao, R2, mp, cp, nkb,
-                  xcd_swizzle(blockIdx.x, gridDim.x), lds);
+                  xcd_swizzle(blockIdx.x, gridDim.x), lds, pm, r, nslot);
+}
+
+// exps[key mp + m] from the half-transform's partial maxima: the largest over
+// the chunk's slabs and over the (one or two) column tiles that meet key's
+// columns [key r, key r + r).  Workgroup: 64 rows of one key, 16 waves; wave
+// w takes the slabs ql = w, w + 16, ... (coalesced 512-byte reads); the wave
+// maxima meet in LDS.
+constexpr int kPmWaves = 16;
+__global__ void __launch_bounds__(64 * kPmWaves) k_xy_rowmax_pm(const double *__restrict__ pm, int nao,
+                                                               int nq, int nct, int mp, int nslot,
+                                                               int r, int *__restrict__ exps)
+{
+    __shared__ double red[kPmWaves][64];
+    const int key = blockIdx.y, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = blockIdx.x * 64 + lane;
+    const int mc = m < nao ? m : nao - 1;
+    const int cb0 = key * r / kNT, cb1 = (key * r + r - 1) / kNT;
+    const i64 qs = (i64)nct * nslot * mp;
+    double mx = 0.0;
+    for (int cb = cb0; cb <= cb1; cb++) {
+        const int slot = key - cb * kNT / r;
+        const double *p = pm + ((i64)cb * nslot + slot) * mp + mc;
+        int ql = w;
+        for (; ql + 3 * kPmWaves < nq; ql += 4 * kPmWaves) {
+            const double v0 = p[(i64)ql * qs], v1 = p[(i64)(ql + kPmWaves) * qs];
+            const double v2 = p[(i64)(ql + 2 * kPmWaves) * qs], v3 = p[(i64)(ql + 3 * kPmWaves) * qs];
+            mx = fmax(mx, fmax(fmax(v0, v1), fmax(v2, v3)));
+        }
+        for (; ql < nq; ql += kPmWaves)
+            mx = fmax(mx, p[(i64)ql * qs]);
+    }
+    red[w][lane] = mx;
+    __syncthreads();
+    if (w == 0 && m < nao) {
+        double v = red[0][lane];
+#pragma unroll
+        for (int u = 1; u < kPmWaves; u++)
+            v = fmax(v, red[u][lane]);
+        exps[(i64)key * mp + m] = row_exponent(v);
+    }
 }
 
 // Row exponents of X/Y over the chunk: exps[key * mp + m] for key = side * nd
@@ -685,18 +758,44 @@ hipError_t launch_slice_xy(const double *XY, int nao, int nkey, int r, int mp, i
 }
 
 
+int xy_rowmax_slots(int r, int nkey)
+{
+    const int n = (kNT - 1) / r + 2;
+    return n < nkey ? n : nkey;
+}
+
+size_t xy_rowmax_pm_doubles(int nq, int mp, int cp, int r, int nkey)
+{
+    return (size_t)nq * (cp / kNT) * xy_rowmax_slots(r, nkey) * mp;
+}
+
 hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, i64 bkbstride, const int *eB,
                            const int8_t *Cp, i64 cpstride, i64 ckbstride, const int *eC, double *XY,
-                           int nao, int R2, int nq, int mp, int cp, int nkb, hipStream_t s)
+                           int nao, int R2, int nq, int mp, int cp, int nkb, hipStream_t s,
+                           double *pm, int r)
 {
     hipError_t e = set_lds((const void *)k_ht_mixed, PipeHt::LDS_BYTES);
     if (e != hipSuccess)
         return e;
+    const int nslot = pm ? xy_rowmax_slots(r, R2 / r) : 0;
+    if (pm && (size_t)kHtMT * nslot * sizeof(double) > (size_t)PipeHt::LDS_BYTES)
+        return hipErrorInvalidValue;
     {
         ProfScope ps_("ht_mixed", s);
         hipLaunchKernelGGL(k_ht_mixed, dim3(nq * (mp / kHtMT) * (cp / kNT)), dim3(TileH::NTHR),
                            PipeHt::LDS_BYTES, s, Bp, bpstride, bkbstride, eB, Cp, cpstride, ckbstride,
-                           eC, XY, nao, R2, mp, cp, nkb);
+                           eC, XY, nao, R2, mp, cp, nkb, pm, r, nslot);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_xy_rowmax_pm(const double *pm, int nao, int nq, int nkey, int r, int mp, int cp,
+                               int *exps, hipStream_t s)
+{
+    {
+        ProfScope ps_("xy_rowmax_pm", s);
+        hipLaunchKernelGGL(k_xy_rowmax_pm, dim3(cdiv(nao, 64), nkey), dim3(64 * kPmWaves), 0, s, pm, nao, nq,
+                           cp / kNT, mp, xy_rowmax_slots(r, nkey), r, exps);
     }
     return hipGetLastError();
 }

@@ -314,10 +314,16 @@ __global__ void __launch_bounds__(256) k_slice_xy(const double *__restrict__ XY,
 // largest |XY[ql][m][c]| over those columns, at
 //     pm[((ql nct + cb) nslot + key - key0) mp + m]
 // (cb = column tile, key0 = its first key, nslot >= the keys a tile meets).
-// They are gathered in LDS (the pipeline's buffers, free after the products)
-// with atomic maxima on the bit patterns, which order like the values for
-// non-negative doubles; the maximum is exact, so the exponents equal those
-// of a pass over XY.
+// The tile's |XY| values go to LDS (the pipeline's buffers, free after the
+// products), rows kPmLd doubles apart, and one thread per (row, key) takes the
+// maximum over the key's columns.  The maximum is exact, so the exponents
+// equal those of a pass over XY.
+//
+// The row and column exponents a lane needs (16 rows, 2 columns) are loaded
+// before the products, so that their latency is hidden behind them.
+constexpr int kPmLd = kNT + 1;      // LDS row stride of the |XY| tile (doubles)
+static_assert(kHtMT * kPmLd * 8 <= PipeHt::LDS_BYTES, "|XY| tile in the pipeline's LDS");
+
 __device__ __forceinline__ void ht_mixed_tile(const int8_t *__restrict__ Bp, i64 bpstride,
                                               i64 bkbstride, const int *__restrict__ eB,
                                               const int8_t *__restrict__ Cp, i64 cpstride,
@@ -331,20 +337,30 @@ __device__ __forceinline__ void ht_mixed_tile(const int8_t *__restrict__ Bp, i64
     const int nmt = mp / kHtMT, nct = cp / kNT;
     const int ql = t / (nmt * nct), rem = t % (nmt * nct);
     const int mb = rem / nct, cb = rem % nct;
+    // exponents of this lane's rows (element e of either tile) and columns
+    // (rows < mp and columns < cp always have one)
+    int eb[16], ec[kWTN];
+#pragma unroll
+    for (int e = 0; e < 16; e++) {
+        int row, col;
+        stile_coord_wide<TL>(0, e, row, col);
+        eb[e] = eB[(i64)ql * mp + mb * kHtMT + row];
+    }
+#pragma unroll
+    for (int tt = 0; tt < kWTN; tt++) {
+        int row, col;
+        stile_coord_wide<TL>(tt, 0, row, col);
+        ec[tt] = eC[cb * kNT + col] + kSliceProdShift;
+    }
     SPlanes a{Bp + (i64)ql * mp * kSliceKB, bpstride, bkbstride};
     SPlanes b{Cp, cpstride, ckbstride};
     SAccW<TL> acc;
     acc.zero();
     stile_gemm_w4<TL, kNS, kNbHt>(a, b, mb * kHtMT, cb * kNT, 0, nkb, lds, acc);
     double *out = XY + (i64)ql * nao * R2;
-    unsigned long long *cell = (unsigned long long *)lds;
-    const int key0 = pm ? cb * kNT / r : 0;
-    if (pm) {
+    double *tile = (double *)lds;
+    if (pm)
         __syncthreads();                      // every wave past its last stage
-        for (int e = threadIdx.x; e < kHtMT * nslot; e += TL::NTHR)
-            cell[e] = 0ull;
-        __syncthreads();
-    }
 #pragma unroll
     for (int tt = 0; tt < kWTN; tt++)
 #pragma unroll
@@ -352,21 +368,26 @@ __device__ __forceinline__ void ht_mixed_tile(const int8_t *__restrict__ Bp, i64
             int row, col;
             stile_coord_wide<TL>(tt, e, row, col);
             const int m = mb * kHtMT + row, c = cb * kNT + col;
-            if (m < nao && c < R2) {
-                const double v =
-                    ldexp(combine_levels_wide<TL>(acc, tt, e), eB[(i64)ql * mp + m] + eC[c] + kSliceProdShift);
+            const double v = ldexp(combine_levels_wide<TL>(acc, tt, e), eb[e] + ec[tt]);
+            if (m < nao && c < R2)
                 out[(i64)m * R2 + c] = v;
-                if (pm)
-                    atomicMax(&cell[(c / r - key0) * kHtMT + row],
-                              (unsigned long long)__double_as_longlong(fabs(v)));
-            }
+            if (pm)
+                tile[row * kPmLd + col] = fabs(v);
         }
     if (pm) {
         __syncthreads();
-        const int nct = cp / kNT;
+        const int c0 = cb * kNT, key0 = c0 / r;
+        const int cend = (c0 + kNT) < R2 ? (c0 + kNT) : R2;
         double *dst = pm + (i64)(ql * nct + cb) * nslot * mp + mb * kHtMT;
-        for (int e = threadIdx.x; e < kHtMT * nslot; e += TL::NTHR)
-            dst[(i64)(e / kHtMT) * mp + e % kHtMT] = __longlong_as_double((long long)cell[e]);
+        for (int e = threadIdx.x; e < kHtMT * nslot; e += TL::NTHR) {
+            const int slot = e / kHtMT, row = e % kHtMT, key = key0 + slot;
+            const int ca = key * r > c0 ? key * r - c0 : 0;
+            const int cz = ((key + 1) * r < cend ? (key + 1) * r : cend) - c0;
+            double mx = 0.0;
+            for (int c = ca; c < cz; c++)
+                mx = fmax(mx, tile[row * kPmLd + c]);
+            dst[(i64)slot * mp + row] = mx;
+        }
     }
 }
 

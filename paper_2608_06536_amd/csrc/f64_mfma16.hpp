@@ -521,4 +521,39 @@ __device__ __forceinline__ void tile_foreach16(const Acc16<TL> &acc, int m0, int
                 f(rb + 16 * i + 4 * v, cb + 16 * j, acc.c[i][j][v]);
 }
 
+// out[m ld + n] = (accumulate ? out[m ld + n] : 0) + scale * value for every
+// output element (m, n) this lane holds with m < mlim and n < nlim.  The four
+// elements of an accumulator are read together before any of them is
+// written, so that the reads' latencies overlap instead of following each
+// other.
+template <class TL>
+__device__ __forceinline__ void tile_update16(const Acc16<TL> &acc, int m0, int n0,
+                                              double *__restrict__ out, i64 ld, int mlim, int nlim,
+                                              int accumulate, double scale)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave / TL::WCOLS, wc = wave % TL::WCOLS;
+    const int rb = m0 + wr * TL::WM + (lane >> 4);
+    const int cb = n0 + wc * TL::WN + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < TL::MA; i++)
+#pragma unroll
+        for (int j = 0; j < TL::NB; j++) {
+            const int n = cb + 16 * j;
+            double old[4];
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int m = rb + 16 * i + 4 * v;
+                old[v] = (accumulate && m < mlim && n < nlim) ? out[(i64)m * ld + n] : 0.0;
+            }
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int m = rb + 16 * i + 4 * v;
+                if (m < mlim && n < nlim)
+                    out[(i64)m * ld + n] =
+                        accumulate ? old[v] + scale * acc.c[i][j][v] : scale * acc.c[i][j][v];
+            }
+        }
+}
+
 } // namespace jk

@@ -534,20 +534,43 @@ __device__ __forceinline__ void ex_mixed_tile(const int8_t *__restrict__ Xp,
     acc.zero();
     stile_gemm_pp<TL, kNS, kNbEx>(a, b, mb * kMT, nb * kNT, kb0, kb1, lds, acc);
     double *Kk = Kp + ((i64)sp * nd + k) * nao * nao;
+    // The lane's row and column exponents (rows and columns < mp all have
+    // one), and per tile the partial sums it adds to, each loaded in one
+    // batch so that their latencies overlap.
+    int ex[16], ey[kWTN];
 #pragma unroll
-    for (int tt = 0; tt < kWTN; tt++)
+    for (int e = 0; e < 16; e++) {
+        int row, col;
+        stile_coord_wide<TL>(0, e, row, col);
+        ex[e] = eX[(i64)k * mp + mb * kMT + row];
+    }
+#pragma unroll
+    for (int tt = 0; tt < kWTN; tt++) {
+        int row, col;
+        stile_coord_wide<TL>(tt, 0, row, col);
+        ey[tt] = eY[(i64)k * mp + nb * kNT + col] + kSliceProdShift;
+    }
+#pragma unroll
+    for (int tt = 0; tt < kWTN; tt++) {
+        double old[16];
+#pragma unroll
+        for (int e = 0; e < 16; e++) {
+            int row, col;
+            stile_coord_wide<TL>(tt, e, row, col);
+            const int m = mb * kMT + row, n = nb * kNT + col;
+            old[e] = (accumulate && m < nao && n < nao) ? Kk[(i64)m * nao + n] : 0.0;
+        }
 #pragma unroll
         for (int e = 0; e < 16; e++) {
             int row, col;
             stile_coord_wide<TL>(tt, e, row, col);
             const int m = mb * kMT + row, n = nb * kNT + col;
             if (m < nao && n < nao) {
-                const double v = scale * ldexp(combine_levels_wide<TL>(acc, tt, e),
-                                               eX[(i64)k * mp + m] + eY[(i64)k * mp + n] + kSliceProdShift);
-                const i64 o = (i64)m * nao + n;
-                Kk[o] = accumulate ? Kk[o] + v : v;
+                const double v = scale * ldexp(combine_levels_wide<TL>(acc, tt, e), ex[e] + ey[tt]);
+                Kk[(i64)m * nao + n] = accumulate ? old[e] + v : v;
             }
         }
+    }
 }
 
 __global__ void __launch_bounds__(512) k_ex_mixed(const int8_t *__restrict__ Xp,

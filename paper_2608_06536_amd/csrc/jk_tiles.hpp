@@ -580,7 +580,7 @@ __device__ inline void ex_tile(const double *__restrict__ Xw, const double *__re
         Acc16<TL> acc;
         acc.zero();
         tile_gemm16<TL, MASK>(a, b, mb * kExM, nb * kExN, j0, j1, lds, acc);
-        tile_foreach16(acc, mb * kExM, nb * kExN, out);
+        tile_update16(acc, mb * kExM, nb * kExN, Kk, nao, nao, nao, accumulate, scale);
     } else {
         OpKC a{Xw + (i64)k * nao * ldw, ldw, nao, j1};
         OpKC b{Yw + (i64)k * nao * ldw, ldw, nao, j1};

@@ -149,13 +149,7 @@ __global__ void __launch_bounds__(256, 3) k_vjp_stage_c(const double *__restrict
         BufIC b{L + (i64)qa * nao * R2, R2, R2, nao};
         tile_gemm16_seg<TL>(a, b, n2, (i64)nao * R2, qb - qa, mb * kTM, cb * kTN, nao, lds, acc);
     }
-    double *out = dCp + (i64)sp * nao * R2;
-    tile_foreach16(acc, mb * kTM, cb * kTN, [&](int m, int c, double v) {
-        if (m < nao && c < R2) {
-            i64 o = (i64)m * R2 + c;
-            out[o] = accumulate ? out[o] + v : v;
-        }
-    });
+    tile_update16(acc, mb * kTM, cb * kTN, dCp + (i64)sp * nao * R2, R2, nao, R2, accumulate, 1.0);
 }
 
 // dCL[k][m][i] = sum_sp dCp[sp][m][k*r+i];  dCR[k][m][i] = sum_sp dCp[sp][m][R+k*r+i]

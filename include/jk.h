@@ -208,8 +208,11 @@ size_t jk_batched_workspace_bytes(int32_t nprob, const jk_problem *p);
  * above.  Every problem must share one precision and one flags value.  Each
  * member's outputs agree with a jk_build call of that member alone to
  * rounding, and are bit-identical to it when that build's plan (jk_tune.h)
- * has a chunk budget of at most 256 MiB: each member's Q-chunks are capped
- * at 256 MiB, and K sums its chunks in order.  With a non-default stream the
+ * has a chunk budget of at most 1 GiB (JK_FP64) or 256 MiB (JK_MIXED): each
+ * member's Q-chunks are capped at that budget, and K sums its chunks in
+ * order.  Every member owns its chunk buffers, so the workspace grows with
+ * the members (53 GiB for 64 FP64 geometries of nao 100..500, naux = 4 nao,
+ * 6 densities of rank nao/10).  With a non-default stream the
  * launch sequence is captured once per shape signature, workspace and device
  * and replayed (at most 32 such graphs are kept; the oldest is destroyed,
  * after a device synchronisation, when a new one is made).  The member

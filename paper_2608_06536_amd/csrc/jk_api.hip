@@ -34,8 +34,13 @@ constexpr i64 kMaxCols = 1 << 20;       // 2 * ndens * rank
 // Chunk workspace target (X/Y of the build, X/Y and slab blocks of the
 // derivative): fewer, longer launches; 1 GB is small next to HBM3E.
 constexpr size_t kChunkBudget = (size_t)1 << 30;
-// Members of a batched build each own their chunk buffers: a smaller target.
-constexpr size_t kChunkBudgetBatched = (size_t)256 << 20;
+// Members of a batched build each own their chunk buffers.  FP64 members
+// take the single build's 1 GB target (fewer chunk steps, each launch over
+// every member's chunk; 355 against 377 ms with 256 MB on the 64-geometry
+// batch); JK_MIXED members, whose chunk buffers also hold digit planes and a
+// second X/Y buffer, take 256 MB.
+constexpr size_t kChunkBudgetBatched = (size_t)1 << 30;
+constexpr size_t kChunkBudgetBatchedMixed = (size_t)256 << 20;
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -771,7 +776,11 @@ struct BPlan {
     size_t total = 0;
 };
 
-size_t batched_budget(const jk_problem *p) { return std::min(kChunkBudgetBatched, tuned_budget(p)); }
+size_t batched_budget(const jk_problem *p)
+{
+    return std::min(p->precision == JK_MIXED ? kChunkBudgetBatchedMixed : kChunkBudgetBatched,
+                    tuned_budget(p));
+}
 
 BPlan batched_plan(const jk_problem *p, bool sym_in)
 {

@@ -105,32 +105,37 @@ def test_batched_mixed():
 
 
 def test_batched_member_over_several_chunks():
-    # nao = 300, naux = 1200, 6 densities of rank 30: 4 chunks of 256 MiB in
-    # the batch.  Bit-identical to a single build under a 256 MiB plan, and
-    # equal to rounding under the default 1024 MiB plan (one chunk).
+    # nao = 300, naux = 1200, 6 densities of rank 30.  Under a 256 MiB plan
+    # the member runs as 4 chunks in the batch and is bit-identical to a single
+    # build under that plan; under the default 1 GiB plan it is one chunk and
+    # bit-identical to the default single build.  Both agree to rounding.
     from paper_2608_06536_amd import jk
     probs = [synth.Problem(nao=300, naux=1200, nd=6, r=30, ell=20.0, tau=300.0, n_ground=1,
                            seed=8801),
              synth.Problem(nao=90, naux=360, nd=6, r=9, ell=20.0, tau=90.0, n_ground=1, seed=8802)]
     items, host = _make(probs)
-    res = jk.jk_build_batched(items)
     p0 = probs[0]
     prob = jk.make_problem(p0.nao, p0.naux, p0.nd, p0.r)
-    Jd, Kd = jk.jk_build(*items[0])
     try:
         jk.tuning_set(prob, 4, 256)
         assert jk.plan_describe(prob)["chunk_slabs"] < p0.naux
+        res_c = jk.jk_build_batched(items)
         Js, Ks = jk.jk_build(*items[0])
     finally:
         jk.tuning_clear()
+    assert jk.plan_describe(prob)["chunk_slabs"] == p0.naux
+    res = jk.jk_build_batched(items)
+    Jd, Kd = jk.jk_build(*items[0])
     torch.cuda.synchronize()
-    assert torch.equal(res[0][0], Js) and torch.equal(res[0][1], Ks)
-    assert torch.equal(res[0][0], Jd)
-    assert rel_err(res[0][1].cpu().numpy(), Kd.cpu().numpy()) <= TOL
+    assert torch.equal(res_c[0][0], Js) and torch.equal(res_c[0][1], Ks)
+    assert torch.equal(res[0][0], Jd) and torch.equal(res[0][1], Kd)
+    assert torch.equal(res_c[0][0], res[0][0])
+    assert rel_err(res_c[0][1].cpu().numpy(), res[0][1].cpu().numpy()) <= TOL
     B, CL, CR = host[0]
     Jr, Kr, _ = oracle.jk_factored(B, CL, CR)
-    assert rel_err(res[0][0].cpu().numpy(), Jr) <= TOL
-    assert rel_err(res[0][1].cpu().numpy(), Kr) <= TOL
+    for J, K in (res_c[0], res[0]):
+        assert rel_err(J.cpu().numpy(), Jr) <= TOL
+        assert rel_err(K.cpu().numpy(), Kr) <= TOL
 
 
 def test_batched_graph_cache_eviction():
@@ -157,10 +162,11 @@ def test_batched_graph_cache_eviction():
 def test_batched_symmetric_members_and_single_plans(precision):
     # Members whose C_L and C_R are one buffer take the X-only path (upper
     # triangle, mirrored).  Every member equals a single jk_build of it bit
-    # for bit under a plan whose chunks match the batch's (256 MiB), and the
-    # oracle to the path's tolerance.
+    # for bit under a plan whose chunks match the batch's (1 GiB for FP64,
+    # 256 MiB for mixed members), and the oracle to the path's tolerance.
     from paper_2608_06536_amd import jk
     tol = TOL if precision == "fp64" else 1e-8
+    chunk_mb = 1024 if precision == "fp64" else 256
     probs = _problems([70, 150, 33, 260, 9], seed=91, naux_mult=3)
     items, host = _make(probs)
     sym = [True, False, True, True, False]
@@ -169,7 +175,7 @@ def test_batched_symmetric_members_and_single_plans(precision):
     torch.cuda.synchronize()
     try:
         for g, ((Bd, Ld, Rd), (J, K), (B, CL, CR), p, s) in enumerate(zip(items, res, host, probs, sym)):
-            jk.tuning_set(jk.make_problem(p.nao, p.naux, p.nd, p.r, precision), 4, 256)
+            jk.tuning_set(jk.make_problem(p.nao, p.naux, p.nd, p.r, precision), 4, chunk_mb)
             Js, Ks = jk.jk_build(Bd, Ld, Rd, precision=precision)
             torch.cuda.synchronize()
             assert torch.equal(J, Js), g

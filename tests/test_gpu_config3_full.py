@@ -6,7 +6,7 @@ Every member is checked against oracle entries computed one by one (J and K,
 FP64 1e-12 and mixed 1e-8, normwise against the member's own largest entry),
 J of the mixed build equals the FP64 J bit for bit, and a spread of members
 (smallest, largest and two between) is bit-identical to a jk_build of that
-member alone under a plan whose chunks match the batch's (256 MiB).  Inputs
+member alone under a plan whose chunks match the batch's (1 GiB).  Inputs
 come from the host generator (each slab has its own seeded stream).
 """
 import numpy as np
@@ -69,7 +69,7 @@ def test_config3_fp64_batched(batch):
     try:
         for g in (order[0], order[len(order) // 3], order[2 * len(order) // 3], order[-1]):
             p = probs[g]
-            jk.tuning_set(jk.make_problem(p.nao, p.naux, p.nd, p.r), 4, 256)
+            jk.tuning_set(jk.make_problem(p.nao, p.naux, p.nd, p.r), 4, 1024)
             Js, Ks = jk.jk_build(*items[g])
             torch.cuda.synchronize()
             assert torch.equal(res[g][0], Js), g

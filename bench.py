@@ -79,7 +79,8 @@ def kernel_models(p, nd, nao, naux, R):
         "vjp_stage_c": ("mfma", 4.0 * naux * n2 * R, "flop"),
         "vjp_stage_d": ("mfma", 4.0 * naux * n2 * R, "flop"),
         "coulomb": ("hbm", 8.0 * naux * n2, "byte"),
-        "project": ("hbm", 3 * 8.0 * naux * n2, "byte"),   # gamma (build), omega, gamma (derivative)
+        "project": ("hbm", 8.0 * naux * n2, "byte"),       # gamma (build)
+        "project16": ("hbm", 8.0 * naux * n2, "byte"),     # omega and gamma (derivative), one pass
     }
 
 

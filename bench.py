@@ -413,6 +413,23 @@ def main():
              "fp64_tflops_random": round(_lib.peak_mfma("fp64", True) / 1e12, 2),
              "note": "INT8 in the slice engine's 13-product pattern; random = uniform bytes per lane"}
 
+    # ---- a library DGEMM of the half-transform's shape, for comparison: one
+    # chunk of the plan as one (nq nao) x nao by nao x 2R product (torch.matmul
+    # in FP64, served by the ROCm BLAS libraries); the kernel also writes the
+    # per-slab X/Y layout, the library product one plain matrix
+    try:
+        nqc = jk.plan_describe(jk.make_problem(nao, naux, nd, r))["chunk_slabs"]
+        A2 = Bd[:nqc].reshape(nqc * nao, nao)
+        C2 = torch.randn((nao, 2 * R), dtype=torch.float64, device=dev)
+        O2 = torch.empty((nqc * nao, 2 * R), dtype=torch.float64, device=dev)
+        t_g = rate(lambda: torch.matmul(A2, C2, out=O2))
+        peaks["library_dgemm_half_transform_shape"] = {
+            "shape": [nqc * nao, nao, 2 * R], "ms": round(1e3 * t_g, 3),
+            "tflops": round(2.0 * nqc * nao * nao * 2 * R / t_g / 1e12, 2)}
+        del A2, C2, O2
+    except (RuntimeError, torch.cuda.OutOfMemoryError) as e:
+        peaks["library_dgemm_half_transform_shape"] = f"unavailable: {e}"
+
     # ---- INT8 roofline of the mixed build's dominant kernel (event times of
     # the presliced build; the aux stream's slicing runs beside it, so the
     # rate is a lower bound)

@@ -80,5 +80,21 @@ def test_config5_full_forward_and_derivative():
     assert np.max(np.abs(got - ref)) <= TOL * float(dB.abs().max())
     # dC_L, dC_R at full size: the one-density oracle would cost ~1e12 CPU flops
     # here; they are checked entry for entry on the 500-slab share
-    # (test_gpu_large.py) and the same kernels run at every slab count.
+    # (test_gpu_large.py), and here through the self-adjoint identity
+    # (Sec. 2.1, Eq. (1)): with A_k = J[W_k] + K[V_k],
+    #     dC_Lk = A_k C_Rk,   dC_Rk = A_k^T C_Lk,
+    # where J[W] and K[V] come from forward builds whose densities are W_k and
+    # V_k themselves (left factor W_k or V_k, right factor the identity), a
+    # path that shares no kernel with the derivative's stages.
     assert bool(torch.isfinite(dCL).all()) and bool(torch.isfinite(dCR).all())
+    del dB
+    torch.cuda.empty_cache()
+    eye = torch.eye(p.nao, dtype=torch.float64, device=dev)
+    for k in (0, p.nd - 1):
+        F = torch.stack([Wd[k], Vd[k]])                 # densities W_k and V_k
+        Jf, Kf = jk.jk_build(Bd, F, torch.stack([eye, eye]))
+        A = Jf[0] + Kf[1]
+        torch.cuda.synchronize()
+        assert rel_err(dCL[k].cpu().numpy(), (A @ Rd[k]).cpu().numpy()) <= TOL, k
+        assert rel_err(dCR[k].cpu().numpy(), (A.T.contiguous() @ Ld[k]).cpu().numpy()) <= TOL, k
+        del Jf, Kf, A

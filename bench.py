@@ -247,8 +247,16 @@ def main():
             jk.jk_build(Bd, Ld, Ld, out=(Js, Ks), ws=ws)
 
         t_sym = rate(build_sym)
+
+        def vjp_sym():
+            jk.jk_vjp(Bd, Ld, Ld, Wd, Vd, out=(dB, dCL, dCR), ws=ws)
+
+        t_vjp_sym = rate(vjp_sym)
+        vjp()                      # the general adjoints again, for the sampled check below
         sym = {"builds_per_s_fp64_sym": round(nd / t_sym, 2), "build_ms_fp64_sym": round(1e3 * t_sym, 3),
-               "speedup_vs_general_fp64": round(t_build / t_sym, 3)}
+               "speedup_vs_general_fp64": round(t_build / t_sym, 3),
+               "vjp_ms_fp64_sym": round(1e3 * t_vjp_sym, 3),
+               "vjp_speedup_vs_general_fp64": round(t_vjp / t_vjp_sym, 3)}
         if not args.no_mixed:
             wsm = torch.empty(jk.workspace_bytes(jk.make_problem(nao, naux, nd, r, "mixed")),
                               dtype=torch.uint8, device=dev)

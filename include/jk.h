@@ -236,7 +236,13 @@ jk_status jk_build_batched(int32_t nprob, const jk_problem *p,
  * dCL and dCR are both NULL (not computed) or both non-NULL (else
  * JK_EINVAL).  Only JK_FP64 with full slabs is supported, and one slab's
  * block of factor columns must stay below 4 GiB: 16 nao ndens rank < 2^32
- * bytes (else JK_EUNSUPPORTED). */
+ * bytes (else JK_EUNSUPPORTED).
+ * Symmetric densities: when CL and CR are the same pointer (the C_L = C_R
+ * case of Sec. 2.3), Y^Q_k = X^Q_k, so only X is recomputed and both products
+ * V_k Y and V_k^T X read it.  dCL and dCR are still the two separate
+ * gradients (their sum is the gradient with respect to the shared factor),
+ * bit-identical to those of the general path given equal contents behind two
+ * pointers. */
 jk_status jk_vjp(const jk_problem *p, const double *B, const double *CL,
                  const double *CR, const double *Jbar, const double *Kbar,
                  double *dB, double *dCL, double *dCR, void *ws,

@@ -437,6 +437,10 @@ jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const
     double *Yw = (double *)(ws + f.o_y);
     double *L = (double *)(ws + f.o_pr);
     double *dCp = (double *)(ws + f.o_dcp);
+    // The same factor for both sides (C_L = C_R, symmetric densities): Y = X,
+    // so the half-transforms form X only and both stage-B products read it.
+    const bool sym = CL == CR;
+    double *Yx = sym ? Xw : Yw;
 
     JK_TRY(jk::launch_pack_c(CL, CR, Cc, nao, nd, r, s));
     if (has_w && want_db && f.paired) {
@@ -480,15 +484,15 @@ jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const
     for (int q0 = 0; q0 < naux; q0 += f.qc) {
         const int nq = (naux - q0) < f.qc ? (naux - q0) : f.qc;
         if (has_v)
-            JK_TRY(jk::launch_half_transform(B, Cc, Xw, Yw, nao, nd, r, q0, nq, f.ldw, s, -1, 0,
-                                             tile, "vjp_half_transform"));
+            JK_TRY(jk::launch_half_transform(B, Cc, Xw, Yw, nao, nd, r, q0, nq, f.ldw, s,
+                                             sym ? R : 2 * R, 0, tile, "vjp_half_transform"));
         JK_TRY(hipEventRecord(ev_x, s));         // X, Y of this chunk; D of the last done
         JK_TRY(hipStreamWaitEvent(a, ev_x, 0));
         JK_TRY(jk::launch_vjp_stage_b_one(1, V, Xw, Cc, omx, L, nao, nd, r, q0, nq * r, f.ldw, has_v,
                                           has_w, a));
         JK_TRY(hipEventRecord(ev_br, a));
         JK_TRY(hipStreamWaitEvent(s, ev_aux, 0)); // C of the last chunk done with the blocks
-        JK_TRY(jk::launch_vjp_stage_b_one(0, V, Yw, Cc, omx, L, nao, nd, r, q0, nq * r, f.ldw, has_v,
+        JK_TRY(jk::launch_vjp_stage_b_one(0, V, Yx, Cc, omx, L, nao, nd, r, q0, nq * r, f.ldw, has_v,
                                           has_w, s));
         JK_TRY(hipStreamWaitEvent(s, ev_br, 0));
         JK_TRY(hipEventRecord(ev_b, s));

@@ -93,6 +93,36 @@ def test_vjp_dot_product_with_oracle_jvp():
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
 
 
+@pytest.mark.parametrize("nao,naux,nd,r", [(70, 11, 3, 7), (131, 21, 2, 20), (50, 30, 8, 5)])
+def test_vjp_symmetric_densities(nao, naux, nd, r):
+    # C_L and C_R one buffer: the X-only recomputation (Y = X) gives the
+    # general path's adjoints bit for bit, and the oracle's for C_R = C_L.
+    from paper_2608_06536_amd import jk
+    B, CL, _, W, V = _prob(nao, naux, nd, r, 400 + nao)
+    Bd, Ld, Wd, Vd = _dev(B, CL, W, V)
+    sym = [_np(t) for t in jk.jk_vjp(Bd, Ld, Ld, Wd, Vd)]
+    gen = [_np(t) for t in jk.jk_vjp(Bd, Ld, Ld.clone(), Wd, Vd)]
+    torch.cuda.synchronize()
+    for a, b in zip(sym, gen):
+        assert np.array_equal(a, b)
+    rB, rL, rR = oracle.vjp(B, CL, CL, W, V)
+    assert rel_err(sym[0], rB) <= TOL
+    assert rel_err(sym[1], rL) <= TOL
+    assert rel_err(sym[2], rR) <= TOL
+
+
+def test_autograd_shared_factor():
+    # J, K of D = C C^T through one leaf C: its gradient is dC_L + dC_R.
+    from paper_2608_06536_amd import jk
+    B, CL, _, W, V = _prob(33, 9, 2, 4, 18)
+    C = torch.from_numpy(CL).cuda().requires_grad_(True)
+    Bd, Wd, Vd = _dev(B, W, V)
+    J, K = jk.jk(Bd, C, C)
+    ((Wd * J).sum() + (Vd * K).sum()).backward()
+    _, rL, rR = oracle.vjp(B, CL, CL, W, V)
+    assert rel_err(C.grad.cpu().numpy(), rL + rR) <= TOL
+
+
 def test_vjp_self_adjoint_gpu_forward():
     # dC_L = (J[W] + K[V]) C_R and dC_R = (J[W] + K[V])^T C_L, with J[W] and
     # K[V] from the GPU forward itself (C_L = W, C_R = I).

@@ -290,8 +290,21 @@ def main():
             t_p = rate(build_packed)
             packed[f"build_ms_{prec}"] = round(1e3 * t_p, 3)
             packed[f"builds_per_s_{prec}"] = round(nd / t_p, 2)
+            if prec == "fp64":
+                # the derivative with packed B gives dB packed (half the bytes)
+                dBpk = torch.empty_like(Bpk)
+
+                def vjp_packed():
+                    jk.jk_vjp(Bpk, Ld, Rd, Wd, Vd, out=(dBpk, dCL, dCR), ws=wsp)
+
+                t_pv = rate(vjp_packed)
+                packed["vjp_ms_fp64"] = round(1e3 * t_pv, 3)
+                packed["vjps_per_s_fp64"] = round(nd / t_pv, 2)
+                packed["vjp_workspace_bytes"] = int(wsp.numel())
+                del dBpk
             del wsp
         del Bpk, Jp, Kp_
+        vjp()                      # the general adjoints again, for the sampled check below
     except _lib.JKError as e:
         packed = {"packed": f"unavailable: {e}"}
 

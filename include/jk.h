@@ -89,8 +89,9 @@ typedef enum {
  * naux nao (nao + 1) / 2 doubles, half the full square.  gamma and J stream
  * the packed positions (half the bytes); the half-transforms read each
  * element (m, n) at its packed place.  Accepted by jk_build, jk_fock and
- * jk_laplace_build (FP64 and JK_MIXED; mixed needs nao <= 2048);
- * jk_build_batched and jk_vjp return JK_EUNSUPPORTED. */
+ * jk_laplace_build (FP64 and JK_MIXED; mixed needs nao <= 2048) and by
+ * jk_vjp (FP64; dB then comes back packed too); jk_build_batched returns
+ * JK_EUNSUPPORTED. */
 enum { JK_WANT_J = 1, JK_WANT_K = 2, JK_B_PACKED = 4 };
 
 typedef struct {
@@ -234,9 +235,15 @@ jk_status jk_build_batched(int32_t nprob, const jk_problem *p,
  * given symmetric B (its symmetric part is convention-free).  The
  * half-transforms are recomputed, not stored.  dB may be NULL (not computed);
  * dCL and dCR are both NULL (not computed) or both non-NULL (else
- * JK_EINVAL).  Only JK_FP64 with full slabs is supported, and one slab's
- * block of factor columns must stay below 4 GiB: 16 nao ndens rank < 2^32
- * bytes (else JK_EUNSUPPORTED).
+ * JK_EINVAL).  Only JK_FP64 is supported, and one slab's block of factor
+ * columns must stay below 4 GiB: 16 nao ndens rank < 2^32 bytes (else
+ * JK_EUNSUPPORTED).
+ * Packed B (JK_B_PACKED): dB has B's packed layout and holds the gradient
+ * with respect to the packed elements, dB[m][n] + dB[n][m] at (m, n), m < n,
+ * and dB[m][m] on the diagonal.  The projections stream the packed slabs;
+ * each Q-chunk is unpacked into two workspace buffers of full squares that
+ * the half-transforms and the products B^Q [P' | R'] read (the workspace
+ * grows by 2 x chunk slabs x 8 nao^2 bytes).
  * Symmetric densities: when CL and CR are the same pointer (the C_L = C_R
  * case of Sec. 2.3), Y^Q_k = X^Q_k, so only X is recomputed and both products
  * V_k Y and V_k^T X read it.  dCL and dCR are still the two separate

@@ -155,7 +155,13 @@ constexpr size_t kChunkBudgetVjp = (size_t)4 << 30;
 int chunk_slabs_vjp(const jk_problem *p)
 {
     size_t per = 4 * (size_t)p->nao * (size_t)(p->ndens * p->rank) * sizeof(double);
-    i64 qc = (i64)(kChunkBudgetVjp / (per ? per : 1));
+    size_t budget = kChunkBudgetVjp;
+    if (p->flags & JK_B_PACKED) {
+        // two unpacked full squares per slab of the chunk, on a budget of their own
+        per += 2 * (size_t)p->nao * (size_t)p->nao * sizeof(double);
+        budget *= 2;
+    }
+    i64 qc = (i64)(budget / (per ? per : 1));
     if (qc < 1)
         qc = 1;
     if (qc > p->naux)
@@ -166,14 +172,18 @@ int chunk_slabs_vjp(const jk_problem *p)
 struct VjpPlan {
     int qc, ldw, npb, plen, ndp, nsplit_c;
     bool paired;        // omega and gamma in one pass over B (2 nd <= 16)
-    size_t o_cc, o_d, o_e, o_part, o_g, o_om, o_omx, o_x, o_y, o_pr, o_dcp, total;
+    bool packed;        // JK_B_PACKED: chunks unpacked into o_bu, packed W, D, E
+    size_t o_cc, o_d, o_e, o_part, o_g, o_om, o_omx, o_x, o_y, o_pr, o_dcp;
+    size_t o_bu, o_wdp, o_ep, total;
 };
 
 VjpPlan plan_vjp(const jk_problem *p)
 {
     VjpPlan f;
     const i64 nao = p->nao, nd = p->ndens, r = p->rank, R = nd * r, naux = p->naux;
-    const i64 npos = nao * nao;
+    f.packed = packed_b(p);
+    // positions per slab of B as stored (the projections stream them)
+    const i64 npos = f.packed ? nao * (nao + 1) / 2 : nao * nao;
     f.qc = chunk_slabs_vjp(p);
     f.ldw = (int)(f.qc * r);
     f.ndp = (int)(((nd + 7) / 8) * 8);
@@ -190,10 +200,11 @@ VjpPlan plan_vjp(const jk_problem *p)
         part = part > p2 ? part : p2;
     }
     Carve c;
+    const i64 nsq = nao * nao;
     f.o_cc = c.take(sizeof(double) * nao * 2 * R);
     // paired: [W | D], the cotangent copied in front of the densities
-    f.o_d = c.take(sizeof(double) * (f.paired ? 2 : 1) * nd * npos);
-    f.o_e = c.take(sizeof(double) * nd * npos);
+    f.o_d = c.take(sizeof(double) * (f.paired ? 2 : 1) * nd * nsq);
+    f.o_e = c.take(sizeof(double) * nd * nsq);
     f.o_part = c.take(sizeof(double) * part);
     f.o_g = c.take(sizeof(double) * nd * naux);
     f.o_om = c.take(sizeof(double) * (f.paired ? 2 : 1) * nd * naux);   // paired: [omega | gamma]
@@ -202,6 +213,16 @@ VjpPlan plan_vjp(const jk_problem *p)
     f.o_y = c.take(sizeof(double) * nd * nao * (size_t)f.ldw);
     f.o_pr = c.take(sizeof(double) * (size_t)f.qc * nao * 2 * R);
     f.o_dcp = c.take(sizeof(double) * (size_t)f.nsplit_c * nao * 2 * R);
+    if (f.packed) {
+        // two chunk buffers of full squares (stage C of one chunk may still
+        // read one while the next chunk is unpacked into the other); W, D and
+        // E as packed sums over each symmetric pair of positions
+        f.o_bu = c.take(sizeof(double) * 2 * (size_t)f.qc * nsq);
+        f.o_wdp = c.take(sizeof(double) * 2 * nd * npos);
+        f.o_ep = c.take(sizeof(double) * nd * npos);
+    } else {
+        f.o_bu = f.o_wdp = f.o_ep = 0;
+    }
     f.total = c.off;
     return f;
 }
@@ -424,6 +445,15 @@ jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const
     const int nao = (int)p->nao, naux = (int)p->naux, nd = (int)p->ndens, r = (int)p->rank;
     const int R = nd * r;
     const i64 npos = (i64)nao * nao;
+    // Packed B: the projections and the affine term run over the packed
+    // positions, with W, D and E folded onto them (each symmetric pair of
+    // positions summed: <W, B^Q> over the square is the packed dot product);
+    // every chunk is unpacked to full squares for the half-transform and
+    // stage C, and stage D writes the packed gradient.
+    const bool pk = f.packed;
+    const i64 npk = pk ? (i64)nao * (nao + 1) / 2 : npos;
+    double *WDp = pk ? (double *)(ws + f.o_wdp) : nullptr;
+    double *Ep = pk ? (double *)(ws + f.o_ep) : nullptr;
     const int has_w = W != nullptr, has_v = V != nullptr;
     const bool want_db = dB != nullptr, want_dc = dCL != nullptr;
     double *Cc = (double *)(ws + f.o_cc);
@@ -451,21 +481,43 @@ jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const
         g = om + (i64)nd * naux;
         JK_TRY(hipMemcpyAsync(WD, W, sizeof(double) * (size_t)nd * npos, hipMemcpyDeviceToDevice, s));
         JK_TRY(jk::launch_density(CL, CR, D, nao, nd, r, s));
+        const double *A = WD;
+        if (pk) {
+            JK_TRY(jk::launch_sym_pack(WD, WDp, nao, 2 * nd, s));
+            A = WDp;
+        }
         if (2 * nd <= 8)
-            JK_TRY(jk::launch_project(B, WD, part, om, naux, 2 * nd, npos, s));
+            JK_TRY(jk::launch_project(B, A, part, om, naux, 2 * nd, npk, s));
         else
-            JK_TRY(jk::launch_project16(B, WD, part, om, naux, 2 * nd, npos, s));
+            JK_TRY(jk::launch_project16(B, A, part, om, naux, 2 * nd, npk, s));
         JK_TRY(jk::launch_omega_expand(om, omx, naux, nd, r, s));
         JK_TRY(jk::launch_vjp_e_matrix(D, E, nao, nd, s));
     } else if (has_w) {
         // omega_kQ = <W_k, B^Q>; for dB also gamma_kQ = <D_k, B^Q> and E = D - 2 D^T.
-        JK_TRY(jk::launch_project(B, W, part, om, naux, nd, npos, s));
+        const double *Wq = W;
+        if (pk) {
+            JK_TRY(jk::launch_sym_pack(W, WDp, nao, nd, s));
+            Wq = WDp;
+        }
+        JK_TRY(jk::launch_project(B, Wq, part, om, naux, nd, npk, s));
         JK_TRY(jk::launch_omega_expand(om, omx, naux, nd, r, s));
         if (want_db) {
             JK_TRY(jk::launch_density(CL, CR, D, nao, nd, r, s));
-            JK_TRY(jk::launch_project(B, D, part, g, naux, nd, npos, s));
+            const double *Dq = D;
+            if (pk) {
+                JK_TRY(jk::launch_sym_pack(D, WDp + (i64)nd * npk, nao, nd, s));
+                Dq = WDp + (i64)nd * npk;
+            }
+            JK_TRY(jk::launch_project(B, Dq, part, g, naux, nd, npk, s));
             JK_TRY(jk::launch_vjp_e_matrix(D, E, nao, nd, s));
         }
+    }
+    // the affine term's matrices as the positions of dB are stored
+    const double *Wa = W, *Ea = E;
+    if (pk && has_w && want_db) {
+        JK_TRY(jk::launch_sym_pack(E, Ep, nao, nd, s));
+        Wa = WDp;                                 // [W | D] packed, W first
+        Ea = Ep;
     }
     // Two streams, so that one launch's last partial round of workgroups
     // overlaps another launch:
@@ -481,10 +533,21 @@ jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const
     hipEvent_t ev_x = ev.ev[0], ev_br = ev.ev[1], ev_b = ev.ev[2], ev_aux = ev.ev[3];
     JK_TRY(hipEventRecord(ev_aux, s));           // aux starts after the prologue
     const int tile = plan_tuning(p).ht_tile;
-    for (int q0 = 0; q0 < naux; q0 += f.qc) {
+    for (int q0 = 0, c = 0; q0 < naux; q0 += f.qc, c++) {
         const int nq = (naux - q0) < f.qc ? (naux - q0) : f.qc;
+        // the slabs the half-transform and stage C read: B itself, or this
+        // chunk unpacked (buffer c % 2; stage C of chunk c - 2, the last
+        // reader of that buffer, finished before main's stage B of chunk c - 1)
+        const double *Bs = B;
+        int qs = q0;
+        if (pk && (has_v || want_dc)) {
+            double *Bu = (double *)(ws + f.o_bu) + (size_t)(c & 1) * f.qc * npos;
+            JK_TRY(jk::launch_unpack_slabs(B, Bu, nao, q0, nq, s));
+            Bs = Bu;
+            qs = 0;
+        }
         if (has_v)
-            JK_TRY(jk::launch_half_transform(B, Cc, Xw, Yw, nao, nd, r, q0, nq, f.ldw, s,
+            JK_TRY(jk::launch_half_transform(Bs, Cc, Xw, Yw, nao, nd, r, qs, nq, f.ldw, s,
                                              sym ? R : 2 * R, 0, tile, "vjp_half_transform"));
         JK_TRY(hipEventRecord(ev_x, s));         // X, Y of this chunk; D of the last done
         JK_TRY(hipStreamWaitEvent(a, ev_x, 0));
@@ -498,13 +561,16 @@ jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const
         JK_TRY(hipEventRecord(ev_b, s));
         if (want_dc) {
             JK_TRY(hipStreamWaitEvent(a, ev_b, 0));
-            JK_TRY(jk::launch_vjp_stage_c(B, L, dCp, nao, R, q0, nq, f.nsplit_c, q0 > 0, a));
+            JK_TRY(jk::launch_vjp_stage_c(Bs, L, dCp, nao, R, qs, nq, f.nsplit_c, q0 > 0, a));
         }
         JK_TRY(hipEventRecord(ev_aux, a));
         if (want_db) {
-            JK_TRY(jk::launch_vjp_stage_d(L, Cc, dB, nao, R, q0, nq, s));
+            if (pk)
+                JK_TRY(jk::launch_vjp_stage_d_packed(L, Cc, dB, nao, R, q0, nq, s));
+            else
+                JK_TRY(jk::launch_vjp_stage_d(L, Cc, dB, nao, R, q0, nq, s));
             if (has_w)
-                JK_TRY(jk::launch_vjp_db_affine(g, om, W, E, dB, nd, naux, npos, q0, nq, s));
+                JK_TRY(jk::launch_vjp_db_affine(g, om, Wa, Ea, dB, nd, naux, npk, q0, nq, s));
         }
     }
     JK_TRY(hipStreamWaitEvent(s, ev_aux, 0));
@@ -1655,7 +1721,7 @@ static jk_status jk_vjp_impl(const jk_problem *p, const double *B, const double 
         return JK_EINVAL;
     if (ws_bytes < jk_workspace_bytes(p))
         return JK_EWORKSPACE;
-    if (p->precision != JK_FP64 || packed_b(p))
+    if (p->precision != JK_FP64)
         return JK_EUNSUPPORTED;
     // stages C and D read a slab's block [P' | R'] (nao x 2R) through one buffer
     // resource, whose offsets stop at 4 GiB

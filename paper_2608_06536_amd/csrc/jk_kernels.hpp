@@ -92,6 +92,13 @@ hipError_t launch_vjp_dc_finish(const double *dCp, double *dCL, double *dCR, int
 hipError_t launch_vjp_e_matrix(const double *D, double *E, int nao, int nd, hipStream_t s);
 hipError_t launch_vjp_stage_d(const double *L, const double *Cc, double *dB, int nao, int R,
                               int q0, int nq, hipStream_t s);
+// Packed B (jk.h JK_B_PACKED): full squares of slabs q0 .. q0 + nq - 1 into
+// out[nq][nao][nao]; stage D writing the packed gradient of those slabs
+// (dB[a][b] + dB[b][a] for a < b, dB[a][a] on the diagonal).
+hipError_t launch_unpack_slabs(const double *Bp, double *out, int nao, int q0, int nq,
+                               hipStream_t s);
+hipError_t launch_vjp_stage_d_packed(const double *L, const double *Cc, double *dB, int nao, int R,
+                                     int q0, int nq, hipStream_t s);
 hipError_t launch_vjp_db_affine(const double *gam, const double *om, const double *W,
                                 const double *E, double *dB, int nd, int naux, i64 npos, int q0,
                                 int nq, hipStream_t s);

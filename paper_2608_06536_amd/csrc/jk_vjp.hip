@@ -220,6 +220,116 @@ __global__ void __launch_bounds__(256, 3) k_vjp_stage_d(const double *__restrict
     });
 }
 
+// ------------------------------------------------------------------ packed B
+// Packed-triangular slabs (jk.h JK_B_PACKED): element (a, b), a <= b, of slab
+// Q at Q np + a nao - a (a - 1) / 2 + (b - a), np = nao (nao + 1) / 2.
+__device__ __forceinline__ i64 pk_at(int a, int b, int nao)
+{
+    return (i64)a * (2 * (i64)nao - a + 1) / 2 + (b - a);
+}
+
+// Full squares of the chunk's packed slabs: out[ql][m][n] = B^{q0+ql}(min,
+// max of m, n).  A workgroup takes one 32 x 32 tile pair (I <= J) of one
+// slab through LDS, so that the tile and its mirror image are both written
+// as coalesced rows.  grid.x = nq * ntri (ntri = nb (nb + 1) / 2 tile pairs).
+constexpr int kUt = 32;
+__global__ void __launch_bounds__(256) k_unpack_slabs(const double *__restrict__ Bp,
+                                                      double *__restrict__ out, int nao, int q0,
+                                                      int ntri)
+{
+    __shared__ double T[kUt][kUt + 1];
+    const int nb = (nao + kUt - 1) / kUt;
+    const int ql = blockIdx.x / ntri;
+    int t = blockIdx.x % ntri, I = 0;
+    while (t >= nb - I) {                      // row-major over the upper triangle
+        t -= nb - I;
+        I++;
+    }
+    const int J = I + t, m0 = I * kUt, n0 = J * kUt;
+    const double *src = Bp + (i64)(q0 + ql) * ((i64)nao * (nao + 1) / 2);
+    double *dst = out + (i64)ql * nao * nao;
+    for (int e = threadIdx.x; e < kUt * kUt; e += 256) {
+        const int i = e / kUt, j = e % kUt, m = m0 + i, n = n0 + j;
+        if (m < nao && n < nao && m <= n)
+            T[i][j] = src[pk_at(m, n, nao)];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kUt * kUt; e += 256) {
+        const int i = e / kUt, j = e % kUt, m = m0 + i, n = n0 + j;
+        if (m < nao && n < nao)
+            dst[(i64)m * nao + n] = (I == J && j < i) ? T[j][i] : T[i][j];
+    }
+    if (I < J)
+        for (int e = threadIdx.x; e < kUt * kUt; e += 256) {
+            const int jj = e / kUt, ii = e % kUt, n = n0 + jj, m = m0 + ii;
+            if (n < nao && m < nao)
+                dst[(i64)n * nao + m] = T[ii][jj];
+        }
+}
+
+// Upper-triangle tiles of the 128 x 64 grid: row tile ab covers column tiles
+// 2 ab .. nnt - 1 (the first that meets columns >= its first row).
+__device__ __forceinline__ int tri_first(int ab) { return ab * kTM / kTN; }
+__host__ __device__ inline int vjp_tri_tiles(int nao)
+{
+    const int nmt = (nao + kTM - 1) / kTM, nnt = (nao + kTN - 1) / kTN;
+    int n = 0;
+    for (int ab = 0; ab < nmt; ab++)
+        n += ab * kTM / kTN < nnt ? nnt - ab * kTM / kTN : 0;
+    return n;
+}
+
+// Stage D for packed B.  The gradient with respect to the packed element
+// (a, b), a < b, is dB[a][b] + dB[b][a], and dB[a][a] on the diagonal.  With
+// A = [C_R | P'] and M = [R' | C_L] (dB = A M^T) the sum dB + dB^T =
+// A M^T + M A^T is the product [A | M] [M | A]^T of depth 4R: the two
+// products of the full stage D, then R' C_R^T + C_L P'^T, over the
+// upper-triangle tiles only (the flops of the full dB), written to the packed
+// positions; the diagonal is halved.  grid.x = nq * vjp_tri_tiles(nao).
+__global__ void __launch_bounds__(256, 2) k_vjp_stage_d_packed(const double *__restrict__ L,
+                                                               const double *__restrict__ Cc,
+                                                               double *__restrict__ dB, int nao,
+                                                               int R, int q0, int nq, int ntri)
+{
+    typedef TileV TL;
+    extern __shared__ double lds[];
+    const int R2 = 2 * R;
+    const int t = xcd_swizzle(blockIdx.x, nq * ntri);
+    const int ql = t / ntri;
+    const int nnt = (nao + kTN - 1) / kTN;
+    int tt = t % ntri, ab = 0;
+    while (tt >= nnt - tri_first(ab)) {
+        tt -= nnt - tri_first(ab);
+        ab++;
+    }
+    const int bb = tri_first(ab) + tt;
+    const double *Lq = L + (i64)ql * nao * R2;
+    Acc16<TL> acc;
+    acc.zero();
+    {
+        const double *a0 = Cc + R, *a1 = Lq, *b0 = Lq + R, *b1 = Cc;   // C_R R'^T + P' C_L^T
+        BufKC a{a0, R2, nao, R};
+        BufKC b{b0, R2, nao, R};
+        tile_gemm16_seg<TL>(a, b, ((i64)(intptr_t)a1 - (i64)(intptr_t)a0) / 8,
+                            ((i64)(intptr_t)b1 - (i64)(intptr_t)b0) / 8, 2, ab * kTM, bb * kTN, R,
+                            lds, acc);
+    }
+    __syncthreads();                // the second pipeline refills the buffers the first read last
+    {
+        const double *a0 = Lq + R, *a1 = Cc, *b0 = Cc + R, *b1 = Lq;   // R' C_R^T + C_L P'^T
+        BufKC a{a0, R2, nao, R};
+        BufKC b{b0, R2, nao, R};
+        tile_gemm16_seg<TL>(a, b, ((i64)(intptr_t)a1 - (i64)(intptr_t)a0) / 8,
+                            ((i64)(intptr_t)b1 - (i64)(intptr_t)b0) / 8, 2, ab * kTM, bb * kTN, R,
+                            lds, acc);
+    }
+    double *out = dB + (i64)(q0 + ql) * ((i64)nao * (nao + 1) / 2);
+    tile_foreach16(acc, ab * kTM, bb * kTN, [&](int ia, int ib, double v) {
+        if (ia <= ib && ib < nao)
+            out[pk_at(ia, ib, nao)] = ia == ib ? 0.5 * v : v;
+    });
+}
+
 // dB[Q][p] += sum_k gamma[k][Q] W[k][p] + omega[k][Q] E[k][p] for Q in
 // [q0, q0 + nq): each thread keeps the W and E values of its two positions in
 // registers across its slabs (densities in groups of 8) and updates four
@@ -429,6 +539,33 @@ hipError_t launch_vjp_stage_d(const double *L, const double *Cc, double *dB, int
         ProfScope ps_("vjp_stage_d", s);
         const dim3 g(nq * cdiv(nao, kTM) * cdiv(nao, kTN));
         hipLaunchKernelGGL(k_vjp_stage_d, g, dim3(TileV::NTHR), lds, s, L, Cc, dB, nao, R, q0, nq);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_slabs(const double *Bp, double *out, int nao, int q0, int nq,
+                               hipStream_t s)
+{
+    const int nb = cdiv(nao, kUt), ntri = nb * (nb + 1) / 2;
+    {
+        ProfScope ps_("vjp_unpack_slabs", s);
+        hipLaunchKernelGGL(k_unpack_slabs, dim3(nq * ntri), dim3(256), 0, s, Bp, out, nao, q0, ntri);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp_stage_d_packed(const double *L, const double *Cc, double *dB, int nao, int R,
+                                     int q0, int nq, hipStream_t s)
+{
+    const int lds = (int)sizeof(double) * TileV::LDS_DOUBLES;
+    hipError_t e = set_dynamic_lds((const void *)k_vjp_stage_d_packed, lds);
+    if (e != hipSuccess)
+        return e;
+    const int ntri = vjp_tri_tiles(nao);
+    {
+        ProfScope ps_("vjp_stage_d", s);
+        hipLaunchKernelGGL(k_vjp_stage_d_packed, dim3(nq * ntri), dim3(TileV::NTHR), lds, s, L, Cc, dB,
+                           nao, R, q0, nq, ntri);
     }
     return hipGetLastError();
 }

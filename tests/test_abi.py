@@ -154,13 +154,13 @@ def test_vjp_block_beyond_buffer_reach_unsupported():
 
 
 def test_packed_b_unsupported_paths():
-    # packed slabs are valid for jk_build / jk_fock, but the derivative and the
-    # batched form refuse them before any launch
+    # packed slabs are valid for jk_build, jk_fock and jk_vjp, but the batched
+    # form refuses them before any launch
     L = _lib.lib()
     p = _prob(flags=_lib.JK_B_PACKED)
     need = L.jk_workspace_bytes(ctypes.byref(p))
     assert need > 0
-    assert L.jk_vjp(ctypes.byref(p), 8, 8, 8, 8, 8, 8, 8, 8, 256, need, None) == _lib.JK_EUNSUPPORTED
+    assert L.jk_vjp(ctypes.byref(p), 8, 8, 8, 8, 8, 8, 8, 8, 256, need - 1, None) == _lib.JK_EWORKSPACE
     arr = (_lib.Problem * 2)(_prob(flags=_lib.JK_B_PACKED), _prob(nao=20, flags=_lib.JK_B_PACKED))
     nb = L.jk_batched_workspace_bytes(2, arr)
     assert nb > 0

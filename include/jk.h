@@ -89,9 +89,8 @@ typedef enum {
  * naux nao (nao + 1) / 2 doubles, half the full square.  gamma and J stream
  * the packed positions (half the bytes); the half-transforms read each
  * element (m, n) at its packed place.  Accepted by jk_build, jk_fock and
- * jk_laplace_build (FP64 and JK_MIXED; mixed needs nao <= 2048) and by
- * jk_vjp (FP64; dB then comes back packed too); jk_build_batched returns
- * JK_EUNSUPPORTED. */
+ * jk_laplace_build and jk_build_batched (FP64 and JK_MIXED; mixed needs
+ * nao <= 2048) and by jk_vjp (FP64; dB then comes back packed too). */
 enum { JK_WANT_J = 1, JK_WANT_K = 2, JK_B_PACKED = 4 };
 
 typedef struct {

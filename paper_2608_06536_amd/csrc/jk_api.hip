@@ -866,10 +866,11 @@ BPlan batched_plan(const jk_problem *p, bool sym_in)
     }
     b.f = plan_forward(p, budget);
     // tiles 3 and 4 run as the 16x16x4 tile over stacked slabs when the
-    // chunk's slabs stay within a buffer resource's reach; 2 runs as 0
+    // chunk's slabs stay within a buffer resource's reach; 2 runs as 0.
+    // Packed slabs always take the 16x16x4 engine's per-slab tile.
     const int t = plan_tuning(p).ht_tile;
     const bool fits = jk::buf_extent_ok((i64)b.f.qc * p->nao * p->nao);
-    b.tile = t == 1 ? 1 : (t >= 3 && fits) ? 4 : 0;
+    b.tile = b.f.packed ? 4 : t == 1 ? 1 : (t >= 3 && fits) ? 4 : 0;
     b.sym = (sym_in && b.tile == 4) ? 1 : 0;     // the X-only path needs the 16x16x4 tile
     b.nsplit = b.sym ? b.f.nsplit_sym : b.f.nsplit;
     b.total = b.f.total;
@@ -889,6 +890,8 @@ bool batched_mixed_ok(int32_t nprob, const jk_problem *p)
     for (int g = 0; g < nprob; g++) {
         const MixPlan x = plan_mixed(&p[g], batched_budget(&p[g]), false);
         if (slicer_blocks(x.kp) == 0 || !jk::mixed_rowmax_ok(2 * (int)(p[g].ndens * p[g].rank)))
+            return false;
+        if (packed_b(&p[g]) && !jk::mixed_packed_ok((int)p[g].nao, x.kp))
             return false;
     }
     return true;
@@ -956,14 +959,20 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p, const std::vector<ch
             pend.push_back(O);
     };
     auto all = [](int) { return true; };
+    const bool packed = packed_b(&p[0]);
+    auto rows = [&](int g) { return (int)(p[g].ndens * p[g].nao); };
     if (w & JK_WANT_J) {
         add(jk::kPhaseDensity, 0, [&](int g) { return jk::density_tiles((int)p[g].nao, (int)p[g].ndens); }, all);
+        if (packed)
+            add(jk::kPhaseSymPack, 0, rows, all);
         add(jk::kPhaseProject, 0,
             [&](int g) { return jk::project_tiles((int)p[g].naux, (int)p[g].ndens, plans[g].f.npb); }, all);
         add(jk::kPhaseReduce, 0, [&](int g) { return jk::reduce_tiles((int)p[g].naux, (int)p[g].ndens); },
             all);
         add(jk::kPhaseCoulomb, 0,
-            [&](int g) { return jk::coulomb_tiles((int)p[g].ndens, p[g].nao * p[g].nao); }, all);
+            [&](int g) { return jk::coulomb_tiles((int)p[g].ndens, plans[g].f.slab); }, all);
+        if (packed)
+            add(jk::kPhaseUnpackJ, 0, rows, all);
     }
     if (w & JK_WANT_K) {
         add(jk::kPhasePack, 0,
@@ -977,14 +986,21 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p, const std::vector<ch
                 return (int)std::min<i64>(plans[g].f.qc, p[g].naux - q0);
             };
             if (mixed) {
-                int nj = 1, ldsb = 0;
+                int nj = 1, ldsb = 0, maxnao = 1;
                 for (int g = 0; g < G; g++) {
                     nj = std::max(nj, slicer_blocks(plans[g].x.kp));
                     const int nkey = plans[g].sym ? (int)p[g].ndens : 2 * (int)p[g].ndens;
                     ldsb = std::max(ldsb, (int)sizeof(double) * nkey * (int)p[g].rank);
+                    maxnao = std::max(maxnao, (int)p[g].nao);
                 }
-                add(jk::kPhaseMSliceB, c,
-                    [&](int g) { return (int)(((i64)nq_of(g) * plans[g].x.mp + 3) / 4); }, in_step, nj);
+                if (packed)      // bands of 8 rows through LDS; arg = 16 x LDS bytes + blocks
+                    add(jk::kPhaseMSliceBPacked, c,
+                        [&](int g) { return nq_of(g) * ((plans[g].x.mp + 7) / 8); }, in_step,
+                        16 * (int)sizeof(double) * 8 * maxnao + nj);
+                else
+                    add(jk::kPhaseMSliceB, c,
+                        [&](int g) { return (int)(((i64)nq_of(g) * plans[g].x.mp + 3) / 4); }, in_step,
+                        nj);
                 add(jk::kPhaseMHalf, c,
                     [&](int g) {
                         return jk::mixed_ht_tiles(plans[g].x.mp,
@@ -1021,7 +1037,14 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p, const std::vector<ch
                     return jk::ht_flat_tiles<jk::TileHalf16>((int)p[g].nao, plans[g].sym ? R : 2 * R,
                                                            nq_of(g));
                 },
-                [&](int g) { return in_step(g) && plans[g].tile == 4; });
+                [&](int g) { return in_step(g) && plans[g].tile == 4 && !packed; });
+            add(jk::kPhaseHalf16Packed, c,
+                [&](int g) {
+                    const int R = (int)(p[g].ndens * p[g].rank);
+                    return nq_of(g) * jk::cdiv_i(p[g].nao, jk::TileHalf16::BM) *
+                           jk::cdiv_i(plans[g].sym ? R : 2 * R, jk::TileHalf16::BN);
+                },
+                [&](int g) { return in_step(g) && packed; });
             add(jk::kPhaseExchange, c,
                 [&](int g) {
                     return plans[g].sym
@@ -1065,8 +1088,9 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p, const std::vector<ch
     size_t nlaunch_bound = 0;
     {
         // the non-symmetric schedule's launch count, plus the mirror launch
+        // (J: four phases, six with packed B)
         const int per_step = mixed ? 5 : 4;
-        nlaunch_bound = 4 + 2 + (size_t)maxsteps * per_step + 2;
+        nlaunch_bound = 6 + 2 + (size_t)maxsteps * per_step + 2;
     }
     c.take(sizeof(int) * std::max(S.tabs.size(), nlaunch_bound * (2 * (size_t)G + 3)));
     S.header_bytes = c.off;
@@ -1077,6 +1101,8 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p, const std::vector<ch
         jk::BMember &m = S.mem[g];
         memset(&m, 0, sizeof(m));
         m.npos = p[g].nao * p[g].nao;
+        m.bslab = plans[g].f.slab;
+        m.packed = plans[g].f.packed ? 1 : 0;
         m.nao = (int)p[g].nao;
         m.naux = (int)p[g].naux;
         m.nd = (int)p[g].ndens;
@@ -1250,6 +1276,7 @@ jk_status build_batched(int32_t nprob, const jk_problem *p, const double *const 
         m.K = K[g];
         m.Cc = (double *)(base + f.o_cc);
         m.D = (double *)(base + f.o_d);
+        m.S = f.packed ? (double *)(base + f.o_s) : nullptr;
         m.part = (double *)(base + f.o_part);
         m.g = (double *)(base + f.o_g);
         m.Xw = (double *)(base + f.o_x);
@@ -1619,8 +1646,6 @@ static jk_status jk_build_batched_impl(int32_t nprob, const jk_problem *p, const
         return JK_EINVAL;
     if (ws_bytes < jk_batched_workspace_bytes(nprob, p))
         return JK_EWORKSPACE;
-    if (packed_b(&p[0]))
-        return JK_EUNSUPPORTED;
     if (p[0].precision == JK_FP64 || batched_mixed_ok(nprob, p))
         return build_batched(nprob, p, B, CL, CR, J, K, (char *)ws, (hipStream_t)stream);
     for (int32_t g = 0; g < nprob; g++) {

@@ -36,13 +36,41 @@ __global__ void __launch_bounds__(256) k_b_density(const BMember *__restrict__ M
     density_tile(m.CL, m.CR, m.D, m.nao, m.r, loc, lds);
 }
 
+// S_k = D_k + D_k^T on the packed positions (D_k[m][m] on the diagonal):
+// one row m of one k per workgroup.
+__global__ void __launch_bounds__(256) k_b_sym_pack(const BMember *__restrict__ M,
+                                                    const int *__restrict__ tab)
+{
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    const int k = loc / m.nao, a = loc % m.nao;
+    const double *Dk = m.D + (i64)k * m.npos;
+    double *row = m.S + (i64)k * m.bslab + pk_row(a, m.nao) - a;
+    for (int b = a + threadIdx.x; b < m.nao; b += 256)
+        row[b] = b == a ? Dk[(i64)a * m.nao + a] : Dk[(i64)a * m.nao + b] + Dk[(i64)b * m.nao + a];
+}
+
+// J_k[a][b] from the packed J_k the Coulomb phase left in D: one row per
+// workgroup.
+__global__ void __launch_bounds__(256) k_b_unpack_j(const BMember *__restrict__ M,
+                                                    const int *__restrict__ tab)
+{
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    const int k = loc / m.nao, a = loc % m.nao;
+    const double *Pk = m.D + (i64)k * m.bslab;
+    double *o = m.J + ((i64)k * m.nao + a) * m.nao;
+    for (int b = threadIdx.x; b < m.nao; b += 256)
+        o[b] = Pk[pk_index(a, b, m.nao)];
+}
+
 __global__ void __launch_bounds__(256) k_b_project(const BMember *__restrict__ M,
                                                    const int *__restrict__ tab)
 {
     __shared__ double lds[TileProject::LDS_DOUBLES];
     int loc;
     const BMember &m = M[find_member(tab, blockIdx.x, loc)];
-    project_tile(m.B, m.D, m.part, m.naux, m.nd, m.npos, m.plen, loc, lds);
+    project_tile(m.B, m.packed ? m.S : m.D, m.part, m.naux, m.nd, m.bslab, m.plen, loc, lds);
 }
 
 __global__ void __launch_bounds__(256) k_b_reduce(const BMember *__restrict__ M,
@@ -58,7 +86,7 @@ __global__ void __launch_bounds__(256) k_b_coulomb(const BMember *__restrict__ M
 {
     int loc;
     const BMember &m = M[find_member(tab, blockIdx.x, loc)];
-    coulomb_tile(m.B, m.g, m.J, m.naux, m.nd, m.npos, loc);
+    coulomb_tile(m.B, m.g, m.packed ? m.D : m.J, m.naux, m.nd, m.bslab, loc);
 }
 
 __global__ void __launch_bounds__(256, 3) k_b_half_transform(const BMember *__restrict__ M,
@@ -97,6 +125,20 @@ __global__ void __launch_bounds__(256, 3) k_b_half_transform16(const BMember *__
     chunk_of(m, c, q0, nq);
     ht_tile_flat<TileB16>(m.B, m.Cc, m.Xw, m.Yw, m.nao, m.nd, m.r, q0, nq, m.ldw, loc, lds,
                           m.sym ? m.nd * m.r : -1);
+}
+
+// Packed slabs on the 16 x 16 x 4 engine: 128 x 64 tiles per slab.
+__global__ void __launch_bounds__(256, 3) k_b_half_transform16_packed(const BMember *__restrict__ M,
+                                                                      const int *__restrict__ tab,
+                                                                      int c)
+{
+    extern __shared__ double lds[];
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    int q0, nq;
+    chunk_of(m, c, q0, nq);
+    ht_tile16_packed<TileB16>(m.B, m.Cc, m.Xw, m.Yw, m.nao, m.nd, m.r, q0, m.ldw, loc, lds,
+                              m.sym ? m.nd * m.r : -1);
 }
 
 // The exchange on the 16 x 16 x 4 engine (member chunk workspaces are capped
@@ -140,6 +182,8 @@ static constexpr int kLds16 = (int)sizeof(double) * TileB16::LDS_DOUBLES;
 hipError_t prepare_batched_kernels()
 {
     hipError_t e = set_dynamic_lds((const void *)k_b_half_transform16, kLds16);
+    if (e == hipSuccess)
+        e = set_dynamic_lds((const void *)k_b_half_transform16_packed, kLds16);
     if (e == hipSuccess)
         e = set_dynamic_lds((const void *)k_b_exchange, kLds16);
     return e;
@@ -197,6 +241,22 @@ hipError_t launch_batched_phase(int phase, const BMember *M, const int *tab, int
     case kPhaseHalf16: {
         ProfScope ps_("b_half_transform", s);
         hipLaunchKernelGGL(k_b_half_transform16, g, dim3(TileB16::NTHR), kLds16, s, M, tab, step);
+        break;
+    }
+    case kPhaseHalf16Packed: {
+        ProfScope ps_("b_half_transform", s);
+        hipLaunchKernelGGL(k_b_half_transform16_packed, g, dim3(TileB16::NTHR), kLds16, s, M, tab,
+                           step);
+        break;
+    }
+    case kPhaseSymPack: {
+        ProfScope ps_("b_sym_pack", s);
+        hipLaunchKernelGGL(k_b_sym_pack, g, dim3(256), 0, s, M, tab);
+        break;
+    }
+    case kPhaseUnpackJ: {
+        ProfScope ps_("b_unpack_j", s);
+        hipLaunchKernelGGL(k_b_unpack_j, g, dim3(256), 0, s, M, tab);
         break;
     }
     case kPhaseExchange: {

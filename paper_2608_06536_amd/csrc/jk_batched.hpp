@@ -22,6 +22,12 @@ struct BMember {
     double *XY;
     long long bkb, bps, ckb, cps, xkb, xps;
     int mp, kp, cp, cpx;    // padded rows / inner bytes; cpx: [C_L | C_R] rows the products use
+    // Packed-triangular B (jk.h JK_B_PACKED): bslab doubles per slab of B
+    // (npos for full squares); gamma pairs B with S = D + D^T folded onto the
+    // packed positions, and J is formed packed in D, then written out in full.
+    double *S;
+    long long bslab;
+    int packed;
 };
 
 // Table layout: tab[0] = n entries, tab[1 .. n+1] = start offsets (n+1
@@ -62,13 +68,17 @@ enum {
     kPhaseHalf64 = 8,    // the half-transform with 64 x 64 tiles (members whose plan chose them)
     kPhaseHalf16 = 9,    // the half-transform on the 16 x 16 x 4 engine over stacked slabs
     kPhaseMirror = 10,   // lower triangle of K from the upper (symmetric members)
+    kPhaseSymPack = 11,  // packed B: S = D + D^T on the packed positions
+    kPhaseUnpackJ = 12,  // packed B: J in full from its packed form
+    kPhaseHalf16Packed = 13,  // packed B: the 16 x 16 x 4 half-transform, tiles per slab
     // JK_MIXED phases (jk_mixed.hip)
     kPhaseMSliceC = 20,  // digit planes of [C_L | C_R]
     kPhaseMSliceB = 21,  // digit planes of the chunk's slabs of B
     kPhaseMHalf = 22,    // INT8 half-transform of the chunk
     kPhaseMRowmax = 23,  // row exponents of the chunk's X and Y
     kPhaseMSliceXY = 24, // digit planes of the chunk's X and Y
-    kPhaseMExchange = 25 // INT8 exchange of the chunk
+    kPhaseMExchange = 25, // INT8 exchange of the chunk
+    kPhaseMSliceBPacked = 26  // digit planes of the chunk's packed slabs
 };
 
 // Sets the dynamic LDS size of the batched kernels that need it on the
@@ -77,7 +87,9 @@ hipError_t prepare_batched_kernels();
 
 // One launch of a phase over the members listed in tab (device pointer):
 // ntiles workgroups, step = chunk index for the chunked phases.  arg: the
-// slicer's register blocks (kPhaseMSliceB) or the LDS bytes (kPhaseMRowmax).
+// slicer's register blocks (kPhaseMSliceB, kPhaseMSliceBPacked: 8 x that
+// plus the LDS bytes / 8 x 1024, see launch_batched_mixed_phase) or the LDS
+// bytes (kPhaseMRowmax).
 hipError_t launch_batched_phase(int phase, const BMember *M, const int *tab, int ntiles, int step,
                                 hipStream_t s, int arg = 0);
 hipError_t launch_batched_mixed_phase(int phase, const BMember *M, const int *tab, int ntiles,

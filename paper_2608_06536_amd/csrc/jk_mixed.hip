@@ -178,17 +178,15 @@ __global__ void __launch_bounds__(256) k_slice_rows_wave(const double *__restric
 // of the band from LDS exactly as the one-pass slicer does.  nk = nr = nao.
 constexpr int kBand = 8;
 
+// Band [m0, m0 + kBand) of packed slab P, plane rows b * rp + m; T holds
+// kBand x nao doubles of LDS.
 template <int NJ>
-__global__ void __launch_bounds__(256) k_slice_band_packed(const double *__restrict__ src, i64 bs,
-                                                           int nb, int nao, int rp, int nkb,
-                                                           int8_t *__restrict__ out, i64 pstride,
-                                                           i64 kbstride, int *__restrict__ exps)
+__device__ __forceinline__ void slice_band_packed(const double *__restrict__ P, int b, int m0,
+                                                  int nao, int rp, int nkb,
+                                                  int8_t *__restrict__ out, i64 pstride,
+                                                  i64 kbstride, int *__restrict__ exps, double *T)
 {
-    extern __shared__ double T[];              // [kBand][ld]
     const int ld = nao;
-    const int nband = (rp + kBand - 1) / kBand;
-    const int b = blockIdx.x / nband, m0 = (blockIdx.x % nband) * kBand;
-    const double *P = src + (i64)b * bs;
     const int tid = threadIdx.x;
 #pragma unroll 1
     for (int r = 0; r < kBand; r++) {          // n >= m: packed row m
@@ -245,6 +243,18 @@ __global__ void __launch_bounds__(256) k_slice_band_packed(const double *__restr
             }
         }
     }
+}
+
+template <int NJ>
+__global__ void __launch_bounds__(256) k_slice_band_packed(const double *__restrict__ src, i64 bs,
+                                                           int nb, int nao, int rp, int nkb,
+                                                           int8_t *__restrict__ out, i64 pstride,
+                                                           i64 kbstride, int *__restrict__ exps)
+{
+    extern __shared__ double T[];              // [kBand][nao]
+    const int nband = (rp + kBand - 1) / kBand;
+    const int b = blockIdx.x / nband, m0 = (blockIdx.x % nband) * kBand;
+    slice_band_packed<NJ>(src + (i64)b * bs, b, m0, nao, rp, nkb, out, pstride, kbstride, exps, T);
 }
 
 // Elementwise slicer of the half-transformed factors.  Source XY[ql][m][c]
@@ -620,6 +630,23 @@ __global__ void __launch_bounds__(256) k_bm_slice_b(const BMember *__restrict__ 
                        m.Bp, m.bps, m.bkb, m.eB, row);
 }
 
+// The chunk's packed slabs (jk.h JK_B_PACKED), bands of kBand rows; the
+// dynamic LDS covers the largest member's band.
+template <int NJ>
+__global__ void __launch_bounds__(256) k_bm_slice_b_packed(const BMember *__restrict__ M,
+                                                           const int *__restrict__ tab, int c)
+{
+    extern __shared__ double T[];
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    int q0, nq;
+    chunk_of(m, c, q0, nq);
+    const int nband = (m.mp + kBand - 1) / kBand;
+    const int b = loc / nband, m0 = (loc % nband) * kBand;
+    slice_band_packed<NJ>(m.B + (i64)(q0 + b) * m.bslab, b, m0, m.nao, m.mp, m.kp / kSliceKB, m.Bp,
+                          m.bps, m.bkb, m.eB, T);
+}
+
 __global__ void __launch_bounds__(256, 2) k_bm_ht(const BMember *__restrict__ M,
                                                   const int *__restrict__ tab, int c)
 {
@@ -887,6 +914,16 @@ hipError_t prepare_batched_mixed_kernels()
     hipError_t e = set_lds((const void *)k_bm_ht, PipeHt::LDS_BYTES);
     if (e == hipSuccess)
         e = set_lds((const void *)k_bm_ex, PipeEx::LDS_BYTES);
+    // the packed slicer's band of the longest rows the packed path takes
+    const int band = (int)sizeof(double) * kBand * 2048;
+    if (e == hipSuccess)
+        e = set_lds((const void *)k_bm_slice_b_packed<1>, band);
+    if (e == hipSuccess)
+        e = set_lds((const void *)k_bm_slice_b_packed<2>, band);
+    if (e == hipSuccess)
+        e = set_lds((const void *)k_bm_slice_b_packed<4>, band);
+    if (e == hipSuccess)
+        e = set_lds((const void *)k_bm_slice_b_packed<8>, band);
     return e;
 }
 
@@ -910,6 +947,25 @@ hipError_t launch_batched_mixed_phase(int phase, const BMember *M, const int *ta
             hipLaunchKernelGGL(k_bm_slice_b<4>, g, dim3(256), 0, s, M, tab, step);
         else if (arg <= 8)
             hipLaunchKernelGGL(k_bm_slice_b<8>, g, dim3(256), 0, s, M, tab, step);
+        else
+            return hipErrorInvalidValue;
+        break;
+    }
+    case kPhaseMSliceBPacked: {
+        // arg = 16 x (dynamic LDS bytes) + register blocks
+        const int nj = arg & 15;
+        const size_t lds = (size_t)(arg >> 4);
+        if (lds > sizeof(double) * kBand * 2048)
+            return hipErrorInvalidValue;
+        ProfScope ps_("bm_slice_b_packed", s);
+        if (nj <= 1)
+            hipLaunchKernelGGL(k_bm_slice_b_packed<1>, g, dim3(256), lds, s, M, tab, step);
+        else if (nj <= 2)
+            hipLaunchKernelGGL(k_bm_slice_b_packed<2>, g, dim3(256), lds, s, M, tab, step);
+        else if (nj <= 4)
+            hipLaunchKernelGGL(k_bm_slice_b_packed<4>, g, dim3(256), lds, s, M, tab, step);
+        else if (nj <= 8)
+            hipLaunchKernelGGL(k_bm_slice_b_packed<8>, g, dim3(256), lds, s, M, tab, step);
         else
             return hipErrorInvalidValue;
         break;

@@ -153,21 +153,23 @@ def test_vjp_block_beyond_buffer_reach_unsupported():
     assert L.jk_vjp(ctypes.byref(p), 8, 8, 8, 8, 8, 8, 8, 8, 256, need, None) == _lib.JK_EUNSUPPORTED
 
 
-def test_packed_b_unsupported_paths():
-    # packed slabs are valid for jk_build, jk_fock and jk_vjp, but the batched
-    # form refuses them before any launch
+def test_packed_b_paths_validate():
+    # packed slabs are valid for every entry point; each still refuses a
+    # workspace one byte short before any launch
     L = _lib.lib()
     p = _prob(flags=_lib.JK_B_PACKED)
     need = L.jk_workspace_bytes(ctypes.byref(p))
     assert need > 0
     assert L.jk_vjp(ctypes.byref(p), 8, 8, 8, 8, 8, 8, 8, 8, 256, need - 1, None) == _lib.JK_EWORKSPACE
-    arr = (_lib.Problem * 2)(_prob(flags=_lib.JK_B_PACKED), _prob(nao=20, flags=_lib.JK_B_PACKED))
-    nb = L.jk_batched_workspace_bytes(2, arr)
-    assert nb > 0
-    VP = ctypes.c_void_p * 2
-    ptrs = VP(8, 8)
-    assert L.jk_build_batched(2, arr, ptrs, ptrs, ptrs, ptrs, ptrs, 256, nb,
-                              None) == _lib.JK_EUNSUPPORTED
+    for prec in (0, 1):
+        arr = (_lib.Problem * 2)(_prob(flags=_lib.JK_B_PACKED, precision=prec),
+                                 _prob(nao=20, flags=_lib.JK_B_PACKED, precision=prec))
+        nb = L.jk_batched_workspace_bytes(2, arr)
+        assert nb > 0
+        VP = ctypes.c_void_p * 2
+        ptrs = VP(8, 8)
+        assert L.jk_build_batched(2, arr, ptrs, ptrs, ptrs, ptrs, ptrs, 256, nb - 1,
+                                  None) == _lib.JK_EWORKSPACE
     # flags: both-or-neither of J and K for jk_fock, packed allowed
     c = (ctypes.c_double * 3)(2.0, -1.0, 0.0)
     pj = _prob(flags=_lib.JK_WANT_J | _lib.JK_B_PACKED)

@@ -215,3 +215,67 @@ def test_batched_mixed_graph_replays():
                 assert torch.equal(K, Ks), rep
     finally:
         jk.tuning_clear()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_packed_members(precision):
+    # Every member's B packed (jk.h JK_B_PACKED), general and symmetric
+    # densities mixed: each member equals a single packed jk_build of it bit
+    # for bit under a plan whose chunks match the batch's, and the oracle to
+    # the path's tolerance.
+    from paper_2608_06536_amd import jk
+    tol = TOL if precision == "fp64" else 1e-8
+    chunk_mb = 1024 if precision == "fp64" else 256
+    probs = _problems([70, 150, 33, 260, 9], seed=95, naux_mult=3)
+    items, host = _make(probs)
+    sym = [False, True, False, True, True]
+    packed = []
+    for (Bd, Ld, Rd), s in zip(items, sym):
+        iu = torch.triu_indices(Bd.shape[1], Bd.shape[1], device="cuda")
+        packed.append((Bd[:, iu[0], iu[1]].contiguous(), Ld, Ld if s else Rd))
+    res = jk.jk_build_batched(packed, precision=precision)
+    torch.cuda.synchronize()
+    try:
+        for g, ((Bp, Ld, Rd), (J, K), (B, CL, CR), p, s) in enumerate(zip(packed, res, host, probs, sym)):
+            jk.tuning_set(jk.make_problem(p.nao, p.naux, p.nd, p.r, precision, packed=True), 4,
+                          chunk_mb)
+            Js, Ks = jk.jk_build(Bp, Ld, Rd, precision=precision)
+            torch.cuda.synchronize()
+            assert torch.equal(J, Js), g
+            assert torch.equal(K, Ks), g
+            Jr, Kr, _ = oracle.jk_factored(B, CL, CL if s else CR)
+            assert rel_err(J.cpu().numpy(), Jr) <= TOL
+            for k in range(p.nd):
+                assert rel_err(K[k].cpu().numpy(), Kr[k]) <= tol, (g, k)
+    finally:
+        jk.tuning_clear()
+
+
+def test_batched_packed_graph_replays():
+    # packed members on a non-default stream: captured once, replayed with new
+    # inputs, each replay equal to the eager single builds between them
+    from paper_2608_06536_amd import jk
+    probs = _problems([31, 77, 140, 5], seed=37)
+    stream = torch.cuda.Stream()
+    nbytes = jk.batched_workspace_bytes([jk.make_problem(p.nao, p.naux, p.nd, p.r, packed=True)
+                                         for p in probs])
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    try:
+        for p in probs:
+            jk.tuning_set(jk.make_problem(p.nao, p.naux, p.nd, p.r, packed=True), 4, 1024)
+        for rep in range(3):
+            items, _ = _make(probs, scale=1.0 + 0.5 * rep)
+            pk = []
+            for Bd, Ld, Rd in items:
+                iu = torch.triu_indices(Bd.shape[1], Bd.shape[1], device="cuda")
+                pk.append((Bd[:, iu[0], iu[1]].contiguous(), Ld, Rd))
+            torch.cuda.synchronize()
+            with torch.cuda.stream(stream):
+                res = jk.jk_build_batched(pk, ws=ws)
+                singles = [jk.jk_build(*it) for it in pk]
+            stream.synchronize()
+            for (J, K), (Js, Ks) in zip(res, singles):
+                assert torch.equal(J, Js), rep
+                assert torch.equal(K, Ks), rep
+    finally:
+        jk.tuning_clear()

@@ -423,7 +423,28 @@ def main():
             if "batch_ms_mixed" in batched:
                 batched["speedup_mixed_batch_vs_fp64_batch"] = round(
                     batched["batch_ms_fp64"] / batched["batch_ms_mixed"], 3)
-            del items, outs, wsg
+            del wsg
+            # the same batch with every B packed (each full square freed as
+            # its packed copy is made)
+            for g in range(len(items)):
+                Bg, Lg, Rg = items[g]
+                iu = torch.triu_indices(Bg.shape[1], Bg.shape[1], device=dev)
+                items[g] = (Bg[:, iu[0], iu[1]].contiguous(), Lg, Rg)
+                del Bg, iu
+            torch.cuda.empty_cache()
+            batched["B_bytes_packed"] = int(sum(it[0].numel() * 8 for it in items))
+            for prec in ("fp64",) + (() if args.no_mixed else ("mixed",)):
+                nbb = jk.batched_workspace_bytes([jk.make_problem(bp.nao, bp.naux, bp.nd, bp.r, prec,
+                                                                  packed=True) for bp in bprobs])
+                wsb = torch.empty(nbb, dtype=torch.uint8, device=dev)
+                torch.cuda.synchronize()
+                with torch.cuda.stream(bstream):
+                    t_b = rate(lambda: jk.jk_build_batched(items, precision=prec, outs=outs, ws=wsb),
+                               n=5)
+                batched[f"batch_ms_{prec}_packed"] = round(1e3 * t_b, 2)
+                del wsb
+                torch.cuda.empty_cache()
+            del items, outs
             torch.cuda.empty_cache()
         except (_lib.JKError, torch.cuda.OutOfMemoryError) as e:
             batched = {"batched": f"unavailable: {e}"}

@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(256, 3) k_b_half_transform(const BMember *__re
 {
     __shared__ double lds[TileHalf::LDS_DOUBLES];
     int loc;
-    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    const BMember &m = M[find_member(tab, xcd_local(blockIdx.x, gridDim.x), loc)];
     int q0, nq;
     chunk_of(m, c, q0, nq);
     ht_tile(m.B, m.Cc, m.Xw, m.Yw, m.nao, m.nd, m.r, q0, m.ldw, loc, lds);
@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(256, 4) k_b_half_transform64(const BMember *__
 {
     __shared__ double lds[TileHalf64::LDS_DOUBLES];
     int loc;
-    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    const BMember &m = M[find_member(tab, xcd_local(blockIdx.x, gridDim.x), loc)];
     int q0, nq;
     chunk_of(m, c, q0, nq);
     ht_tile_tl<TileHalf64>(m.B, m.Cc, m.Xw, m.Yw, m.nao, m.nd, m.r, q0, m.ldw, loc, lds, -1);
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(256, 3) k_b_half_transform16(const BMember *__
 {
     extern __shared__ double lds[];
     int loc;
-    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    const BMember &m = M[find_member(tab, xcd_local(blockIdx.x, gridDim.x), loc)];
     int q0, nq;
     chunk_of(m, c, q0, nq);
     ht_tile_flat<TileB16>(m.B, m.Cc, m.Xw, m.Yw, m.nao, m.nd, m.r, q0, nq, m.ldw, loc, lds,
@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(256, 3) k_b_half_transform16_packed(const BMem
 {
     extern __shared__ double lds[];
     int loc;
-    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    const BMember &m = M[find_member(tab, xcd_local(blockIdx.x, gridDim.x), loc)];
     int q0, nq;
     chunk_of(m, c, q0, nq);
     ht_tile16_packed<TileB16>(m.B, m.Cc, m.Xw, m.Yw, m.nao, m.nd, m.r, q0, m.ldw, loc, lds,
@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(256, 3) k_b_exchange(const BMember *__restrict
 {
     extern __shared__ double lds[];
     int loc;
-    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    const BMember &m = M[find_member(tab, xcd_local(blockIdx.x, gridDim.x), loc)];
     int q0, nq;
     chunk_of(m, c, q0, nq);
     const int nj = nq * m.r;

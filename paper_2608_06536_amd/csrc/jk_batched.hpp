@@ -49,6 +49,24 @@ __device__ __forceinline__ int find_member(const int *__restrict__ tab, int t, i
     return tab[n + 2 + lo];
 }
 
+// Workgroup index remapped so that runs of kXcdRun consecutive table tiles
+// (the column tiles of one row panel, the tiles of one exchange row) land on
+// one XCD and share its L2, while the table's order (larger tiles first)
+// holds at the scale of 8 kXcdRun tiles.  Within each full block of
+// 8 kXcdRun indices, logical = block start + (hw % 8) kXcdRun + (hw / 8) %
+// kXcdRun (the hardware deals workgroups round-robin over the 8 XCDs); the
+// indices of a last, partial block keep their place.
+constexpr int kXcdRun = 16;
+__device__ __forceinline__ int xcd_local(int hw, int n)
+{
+    const int blk = 8 * kXcdRun;
+    const int b0 = hw - hw % blk;
+    if (b0 + blk > n)
+        return hw;
+    const int r = hw - b0;
+    return b0 + (r & 7) * kXcdRun + (r >> 3);
+}
+
 // Chunk of member m at step c: first slab and slab count.
 __device__ __forceinline__ void chunk_of(const BMember &m, int c, int &q0, int &nq)
 {

@@ -652,7 +652,7 @@ __global__ void __launch_bounds__(256, 2) k_bm_ht(const BMember *__restrict__ M,
 {
     extern __shared__ char lds[];
     int loc;
-    const BMember &m = M[find_member(tab, xcd_swizzle(blockIdx.x, gridDim.x), loc)];
+    const BMember &m = M[find_member(tab, xcd_local(blockIdx.x, gridDim.x), loc)];
     (void)c;
     const int ncol = m.sym ? m.nd * m.r : 2 * m.nd * m.r;
     ht_mixed_tile(m.Bp, m.bps, m.bkb, m.eB, m.Cp, m.cps, m.ckb, m.eC, m.XY, m.nao, ncol, m.mp, m.cpx,
@@ -691,7 +691,7 @@ __global__ void __launch_bounds__(512) k_bm_ex(const BMember *__restrict__ M,
 {
     extern __shared__ char lds[];
     int loc;
-    const BMember &m = M[find_member(tab, xcd_swizzle(blockIdx.x, gridDim.x), loc)];
+    const BMember &m = M[find_member(tab, xcd_local(blockIdx.x, gridDim.x), loc)];
     int q0, nq;
     chunk_of(m, c, q0, nq);
     const int nkb = cdiv_i((i64)nq * m.r, kSliceKB);

@@ -14,6 +14,7 @@
 #include "../../include/jk.h"
 #include "jk_batched.hpp"
 #include "jk_kernels.hpp"
+#include "coulomb_upper.hpp"
 #include "jk_tiles.hpp"
 #include "jk_tune.hpp"
 
@@ -365,7 +366,7 @@ jk_status coulomb_part(const FwdPlan &f, int nao, int naux, int nd, int r, const
     JK_TRY(jk::launch_density(CL, CR, D, nao, nd, r, s));
     if (!f.packed) {
         JK_TRY(jk::launch_project(B, D, part, g, naux, nd, f.slab, s));
-        JK_TRY(jk::launch_coulomb(B, g, out, naux, nd, f.slab, s, scale, accumulate));
+        JK_TRY(jk::launch_coulomb_upper(B, g, out, nao, naux, nd, s, scale, accumulate));
         return JK_OK;
     }
     double *S = (double *)(ws + f.o_s);
@@ -970,7 +971,11 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p, const std::vector<ch
         add(jk::kPhaseReduce, 0, [&](int g) { return jk::reduce_tiles((int)p[g].naux, (int)p[g].ndens); },
             all);
         add(jk::kPhaseCoulomb, 0,
-            [&](int g) { return jk::coulomb_tiles((int)p[g].ndens, plans[g].f.slab); }, all);
+            [&](int g) {
+                return packed ? jk::coulomb_tiles((int)p[g].ndens, plans[g].f.slab)
+                              : jk::cu_tiles((int)p[g].nao, (int)p[g].ndens);
+            },
+            all);
         if (packed)
             add(jk::kPhaseUnpackJ, 0, rows, all);
     }

@@ -17,6 +17,7 @@
 #include "jk_batched.hpp"
 #include "jk_kernels.hpp"
 #include "jk_tiles.hpp"
+#include "coulomb_upper.hpp"
 
 namespace jk {
 
@@ -86,7 +87,10 @@ __global__ void __launch_bounds__(256) k_b_coulomb(const BMember *__restrict__ M
 {
     int loc;
     const BMember &m = M[find_member(tab, blockIdx.x, loc)];
-    coulomb_tile(m.B, m.g, m.packed ? m.D : m.J, m.naux, m.nd, m.bslab, loc);
+    if (m.packed)
+        coulomb_tile(m.B, m.g, m.D, m.naux, m.nd, m.bslab, loc);
+    else
+        coulomb_upper_tile(m.B, m.g, m.J, m.nao, m.naux, m.nd, loc);
 }
 
 __global__ void __launch_bounds__(256, 3) k_b_half_transform(const BMember *__restrict__ M,

@@ -50,6 +50,10 @@ hipError_t launch_project(const double *B, const double *A, double *part, double
 // J (+)= scale * sum_Q g B^Q; accumulate adds to what J holds.
 hipError_t launch_coulomb(const double *B, const double *g, double *J, int naux, int nd,
                           int64_t npos, hipStream_t s, double scale = 1.0, int accumulate = 0);
+// The same for full-square symmetric slabs from their upper triangles (half
+// the bytes of B; J bit-identical to launch_coulomb's).
+hipError_t launch_coulomb_upper(const double *B, const double *g, double *J, int nao, int naux,
+                                int nd, hipStream_t s, double scale = 1.0, int accumulate = 0);
 // packed: B holds packed upper-triangle slabs (nao (nao + 1) / 2 doubles).
 // tile (full slabs only; jk_tune.h): 0 = 128 x 64 workgroup tiles of four
 // waves, 1 = 64 x 64, 2 = 128 x 64 of eight waves (4x4x4 engine); 3 = 128 x 128,

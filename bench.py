@@ -68,8 +68,8 @@ OVERLAPPED = {"vjp_half_transform", "vjp_stage_b_p", "vjp_stage_b_r", "vjp_stage
 
 def kernel_models(p, nd, nao, naux, R):
     """Algorithmic work of each kernel over ONE step: (bound, amount, unit).
-    Flops count the method's own products; bytes count one read of B (of its
-    upper triangles for the Coulomb stream, which needs no more)."""
+    Flops count the method's own products; bytes count one read of B's upper
+    triangles for the HBM streams (gamma, omega, J), which need no more."""
     n2 = float(nao) * nao
     return {
         "half_transform": ("mfma", 4.0 * naux * n2 * R, "flop"),       # the build's
@@ -80,8 +80,8 @@ def kernel_models(p, nd, nao, naux, R):
         "vjp_stage_c": ("mfma", 4.0 * naux * n2 * R, "flop"),
         "vjp_stage_d": ("mfma", 4.0 * naux * n2 * R, "flop"),
         "coulomb": ("hbm", 8.0 * naux * nao * (nao + 1) / 2, "byte"),   # B's upper triangles
-        "project": ("hbm", 8.0 * naux * n2, "byte"),       # gamma (build)
-        "project16": ("hbm", 8.0 * naux * n2, "byte"),     # omega and gamma (derivative), one pass
+        "project": ("hbm", 8.0 * naux * nao * (nao + 1) / 2, "byte"),   # gamma (build)
+        "project16": ("hbm", 8.0 * naux * nao * (nao + 1) / 2, "byte"), # omega, gamma (derivative)
     }
 
 

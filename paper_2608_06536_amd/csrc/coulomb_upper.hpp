@@ -1,4 +1,5 @@
-// coulomb_upper.hpp -- the Coulomb matrix from the upper triangle of B.
+// coulomb_upper.hpp -- the HBM streams over B (gamma and J) from the upper
+// triangles of the slabs.
 //
 // J_k = sum_Q gamma_kQ B^Q (Sec. 2.3, Eq. (4)) with every slab B^Q symmetric
 // (a precondition of the engine): each J_k[m][n], m <= n, is a sum over the
@@ -10,6 +11,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "jk_tiles.hpp"
 
 namespace jk {
 
@@ -82,6 +85,79 @@ __device__ inline void coulomb_upper_tile(const double *__restrict__ B, const do
             if (n != m)
                 Jk[t] = accumulate ? Jk[t] + scale * a[k] : scale * a[k];
         }
+}
+
+// ------------------------------------------------------------------ gamma
+// gamma_kQ = <B^Q, A_k> = sum_{m <= n} B^Q[m][n] S_k[m][n] with S_k the fold
+// of A_k onto its upper triangle: A_k[m][n] + A_k[n][m] above the diagonal,
+// A_k[m][m] on it, zero below (fold_upper_row, in place).  A product with
+// M = naux, N = the matrices, inner = the upper-triangle positions: row m
+// contributes columns m .. nao - 1.
+//
+// Rows go in groups of G consecutive rows m0 .. m0 + G - 1, each row one
+// segment of the 4x4x4 engine's segmented pipeline starting at column m0 (a
+// uniform stride of nao between segments) with depth nao - m0: the few
+// positions left of a row's diagonal multiply the zeros of S, and every read
+// stays in its row.  Groups are paired (g with ng - 1 - g) so that the tiles
+// weigh the same; part[pair][Q][k] holds each pair's sums, added in a fixed
+// order by reduce_tile.  About 2048 workgroups in all.
+__host__ __device__ inline int pu_group_rows(int nao, int naux, int nkg)
+{
+    const int nqt = (naux + kProjRows - 1) / kProjRows;
+    int want = 2048 / (nqt * nkg);
+    if (want < 1)
+        want = 1;
+    const int g = (nao + 2 * want - 1) / (2 * want);
+    return g < 1 ? 1 : g;
+}
+__host__ __device__ inline int pu_pairs(int nao, int G) { return ((nao + G - 1) / G + 1) / 2; }
+
+// In-place fold of row a of matrix k (nmat matrices of nao x nao): for
+// b > a, A[a][b] += A[b][a] and A[b][a] = 0.  Each pair belongs to one row.
+__device__ inline void fold_upper_row(double *__restrict__ A, int nao, int k, int a)
+{
+    double *Ak = A + (int64_t)k * nao * nao;
+    for (int b = a + 1 + (int)threadIdx.x; b < nao; b += 256) {
+        const double x = Ak[(int64_t)a * nao + b], y = Ak[(int64_t)b * nao + a];
+        Ak[(int64_t)a * nao + b] = x + y;
+        Ak[(int64_t)b * nao + a] = 0.0;
+    }
+}
+
+// One tile: a pair of row groups, one Q-tile of kProjRows slabs, one group of
+// 8 matrices (TL = TileProject, NK = 8: nd in groups of 8) or all of up to 16
+// (TL = TileProject16, NK = 16: nd <= 16 in one group).
+template <class TL, int NK>
+__device__ inline void project_upper_tile(const double *__restrict__ B, const double *__restrict__ S,
+                                          double *__restrict__ part, int naux, int nd, int nao,
+                                          int G, int tile, double *lds)
+{
+    const int ng = (nao + G - 1) / G;
+    const int nqt = cdiv_i(naux, kProjRows), nkg = NK == 8 ? cdiv_i(nd, 8) : 1;
+    const int pb = tile / (nqt * nkg), rem = tile % (nqt * nkg);
+    const int kg = rem / nqt, qt = rem % nqt;
+    const int ndg = NK == 8 ? ((nd - kg * 8) < 8 ? (nd - kg * 8) : 8) : nd;
+    const int64_t npos = (int64_t)nao * nao;
+    Acc<TL> acc;
+    acc.zero();
+#pragma unroll 1
+    for (int h = 0; h < 2; h++) {
+        const int grp = h == 0 ? pb : ng - 1 - pb;
+        if (h == 1 && grp <= pb)
+            break;                                 // the middle group of an odd count
+        const int m0 = grp * G;
+        const int rows = (nao - m0) < G ? (nao - m0) : G;
+        const int kdepth = nao - m0;
+        OpKC a{B + (int64_t)m0 * nao + m0, npos, naux, kdepth};
+        OpKC b{S + (int64_t)kg * 8 * npos + (int64_t)m0 * nao + m0, npos, ndg, kdepth};
+        tile_gemm_seg<TL>(a, b, nao, nao, rows, qt * kProjRows, 0, kdepth, lds, acc);
+    }
+    const int ndp = NK == 8 ? nkg * 8 : 16;
+    double *out = part + (int64_t)pb * naux * ndp;
+    tile_foreach(acc, qt * kProjRows, 0, [&](int q, int kk, double v) {
+        if (q < naux && kk < NK)
+            out[(int64_t)q * ndp + kg * 8 + kk] = v;
+    });
 }
 
 } // namespace jk

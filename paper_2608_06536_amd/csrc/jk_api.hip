@@ -132,7 +132,13 @@ FwdPlan plan_forward(const jk_problem *p, size_t budget = kChunkBudget)
     f.packed = packed_b(p);
     f.slab = f.packed ? jk::pk_size((int)nao) : npos;
     // gamma runs over the stored positions of a slab
-    f.npb = jk::project_nblocks(f.slab, (int)p->naux, (int)nd, &f.plen);
+    // gamma: packed slabs stream their positions in blocks of plen; full
+    // squares read their upper triangles in row groups of plen rows, npb
+    // pairs of groups (coulomb_upper.hpp)
+    if (f.packed)
+        f.npb = jk::project_nblocks(f.slab, (int)p->naux, (int)nd, &f.plen);
+    else
+        f.npb = jk::project_upper_blocks((int)nao, (int)p->naux, (int)((nd + 7) / 8), &f.plen);
     Carve c;
     f.o_cc = c.take(sizeof(double) * nao * 2 * R);
     f.o_d = c.take(sizeof(double) * nd * npos);
@@ -199,12 +205,27 @@ VjpPlan plan_vjp(const jk_problem *p)
                               ? (size_t)jk::project_nblocks(npos, (int)naux, (int)(2 * nd), &plen2) * naux * 8
                               : (size_t)jk::project16_nblocks(npos, (int)naux, &plen2) * naux * 16;
         part = part > p2 ? part : p2;
+        if (!f.packed) {
+            // full squares: [W | D] folded onto the upper triangles
+            int G;
+            const size_t p3 = (size_t)jk::project_upper_blocks((int)nao, (int)naux, 1, &G) * naux *
+                              (2 * nd <= 8 ? 8 : 16);
+            part = part > p3 ? part : p3;
+        }
+    }
+    if (!f.packed) {
+        // full squares, W and D projected on their own (groups of 8)
+        int G;
+        const size_t p4 = (size_t)jk::project_upper_blocks((int)nao, (int)naux, (int)((nd + 7) / 8), &G) *
+                          naux * f.ndp;
+        part = part > p4 ? part : p4;
     }
     Carve c;
     const i64 nsq = nao * nao;
     f.o_cc = c.take(sizeof(double) * nao * 2 * R);
-    // paired: [W | D], the cotangent copied in front of the densities
-    f.o_d = c.take(sizeof(double) * (f.paired ? 2 : 1) * nd * nsq);
+    // [W | D]: the cotangent copied in front of the densities (folded in
+    // place for full squares; paired, the two in one pass over B)
+    f.o_d = c.take(sizeof(double) * (f.paired || !f.packed ? 2 : 1) * nd * nsq);
     f.o_e = c.take(sizeof(double) * nd * nsq);
     f.o_part = c.take(sizeof(double) * part);
     f.o_g = c.take(sizeof(double) * nd * naux);
@@ -365,7 +386,9 @@ jk_status coulomb_part(const FwdPlan &f, int nao, int naux, int nd, int r, const
     double *g = (double *)(ws + f.o_g);
     JK_TRY(jk::launch_density(CL, CR, D, nao, nd, r, s));
     if (!f.packed) {
-        JK_TRY(jk::launch_project(B, D, part, g, naux, nd, f.slab, s));
+        // the upper triangles of the symmetric slabs: D folded onto its own
+        JK_TRY(jk::launch_fold_upper(D, nao, nd, s));
+        JK_TRY(jk::launch_project_upper(B, D, part, g, nao, naux, nd, s));
         JK_TRY(jk::launch_coulomb_upper(B, g, out, nao, naux, nd, s, scale, accumulate));
         return JK_OK;
     }
@@ -482,35 +505,45 @@ jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const
         g = om + (i64)nd * naux;
         JK_TRY(hipMemcpyAsync(WD, W, sizeof(double) * (size_t)nd * npos, hipMemcpyDeviceToDevice, s));
         JK_TRY(jk::launch_density(CL, CR, D, nao, nd, r, s));
-        const double *A = WD;
+        JK_TRY(jk::launch_vjp_e_matrix(D, E, nao, nd, s));
         if (pk) {
             JK_TRY(jk::launch_sym_pack(WD, WDp, nao, 2 * nd, s));
-            A = WDp;
+            if (2 * nd <= 8)
+                JK_TRY(jk::launch_project(B, WDp, part, om, naux, 2 * nd, npk, s));
+            else
+                JK_TRY(jk::launch_project16(B, WDp, part, om, naux, 2 * nd, npk, s));
+        } else {
+            // the upper triangles of the symmetric slabs: [W | D] folded onto
+            // their own (E is formed from D above, before the fold)
+            JK_TRY(jk::launch_fold_upper(WD, nao, 2 * nd, s));
+            JK_TRY(jk::launch_project_upper(B, WD, part, om, nao, naux, 2 * nd, s, 2 * nd > 8));
         }
-        if (2 * nd <= 8)
-            JK_TRY(jk::launch_project(B, A, part, om, naux, 2 * nd, npk, s));
-        else
-            JK_TRY(jk::launch_project16(B, A, part, om, naux, 2 * nd, npk, s));
         JK_TRY(jk::launch_omega_expand(om, omx, naux, nd, r, s));
-        JK_TRY(jk::launch_vjp_e_matrix(D, E, nao, nd, s));
-    } else if (has_w) {
+    } else if (has_w && pk) {
         // omega_kQ = <W_k, B^Q>; for dB also gamma_kQ = <D_k, B^Q> and E = D - 2 D^T.
-        const double *Wq = W;
-        if (pk) {
-            JK_TRY(jk::launch_sym_pack(W, WDp, nao, nd, s));
-            Wq = WDp;
-        }
-        JK_TRY(jk::launch_project(B, Wq, part, om, naux, nd, npk, s));
+        JK_TRY(jk::launch_sym_pack(W, WDp, nao, nd, s));
+        JK_TRY(jk::launch_project(B, WDp, part, om, naux, nd, npk, s));
         JK_TRY(jk::launch_omega_expand(om, omx, naux, nd, r, s));
         if (want_db) {
             JK_TRY(jk::launch_density(CL, CR, D, nao, nd, r, s));
-            const double *Dq = D;
-            if (pk) {
-                JK_TRY(jk::launch_sym_pack(D, WDp + (i64)nd * npk, nao, nd, s));
-                Dq = WDp + (i64)nd * npk;
-            }
-            JK_TRY(jk::launch_project(B, Dq, part, g, naux, nd, npk, s));
+            JK_TRY(jk::launch_sym_pack(D, WDp + (i64)nd * npk, nao, nd, s));
+            JK_TRY(jk::launch_project(B, WDp + (i64)nd * npk, part, g, naux, nd, npk, s));
             JK_TRY(jk::launch_vjp_e_matrix(D, E, nao, nd, s));
+        }
+    } else if (has_w) {
+        // The same from a folded copy of W (then D), in the row groups of the
+        // paired pass: omega comes out bit for bit as there.
+        double *Wc = D;
+        D = Wc + (i64)nd * npos;
+        JK_TRY(hipMemcpyAsync(Wc, W, sizeof(double) * (size_t)nd * npos, hipMemcpyDeviceToDevice, s));
+        JK_TRY(jk::launch_fold_upper(Wc, nao, nd, s));
+        JK_TRY(jk::launch_project_upper(B, Wc, part, om, nao, naux, nd, s));
+        JK_TRY(jk::launch_omega_expand(om, omx, naux, nd, r, s));
+        if (want_db) {
+            JK_TRY(jk::launch_density(CL, CR, D, nao, nd, r, s));
+            JK_TRY(jk::launch_vjp_e_matrix(D, E, nao, nd, s));
+            JK_TRY(jk::launch_fold_upper(D, nao, nd, s));
+            JK_TRY(jk::launch_project_upper(B, D, part, g, nao, naux, nd, s));
         }
     }
     // the affine term's matrices as the positions of dB are stored
@@ -902,7 +935,7 @@ bool batched_mixed_ok(int32_t nprob, const jk_problem *p)
 double tile_cost(int phase, const BPlan &b, const jk_problem &p)
 {
     switch (phase) {
-    case jk::kPhaseProject: return (double)b.f.plen;
+    case jk::kPhaseProject: return (double)b.f.plen * (b.f.packed ? 1 : p.nao);
     case jk::kPhaseReduce: return (double)b.f.npb;
     case jk::kPhaseCoulomb: return (double)p.naux;
     case jk::kPhaseHalf:
@@ -964,8 +997,7 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p, const std::vector<ch
     auto rows = [&](int g) { return (int)(p[g].ndens * p[g].nao); };
     if (w & JK_WANT_J) {
         add(jk::kPhaseDensity, 0, [&](int g) { return jk::density_tiles((int)p[g].nao, (int)p[g].ndens); }, all);
-        if (packed)
-            add(jk::kPhaseSymPack, 0, rows, all);
+        add(packed ? jk::kPhaseSymPack : jk::kPhaseFoldUpper, 0, rows, all);
         add(jk::kPhaseProject, 0,
             [&](int g) { return jk::project_tiles((int)p[g].naux, (int)p[g].ndens, plans[g].f.npb); }, all);
         add(jk::kPhaseReduce, 0, [&](int g) { return jk::reduce_tiles((int)p[g].naux, (int)p[g].ndens); },

@@ -51,6 +51,16 @@ __global__ void __launch_bounds__(256) k_b_sym_pack(const BMember *__restrict__ 
         row[b] = b == a ? Dk[(i64)a * m.nao + a] : Dk[(i64)a * m.nao + b] + Dk[(i64)b * m.nao + a];
 }
 
+// D_k folded onto its upper triangle in place (coulomb_upper.hpp): one row
+// per workgroup.
+__global__ void __launch_bounds__(256) k_b_fold_upper(const BMember *__restrict__ M,
+                                                      const int *__restrict__ tab)
+{
+    int loc;
+    const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    fold_upper_row(m.D, m.nao, loc / m.nao, loc % m.nao);
+}
+
 // J_k[a][b] from the packed J_k the Coulomb phase left in D: one row per
 // workgroup.
 __global__ void __launch_bounds__(256) k_b_unpack_j(const BMember *__restrict__ M,
@@ -71,7 +81,10 @@ __global__ void __launch_bounds__(256) k_b_project(const BMember *__restrict__ M
     __shared__ double lds[TileProject::LDS_DOUBLES];
     int loc;
     const BMember &m = M[find_member(tab, blockIdx.x, loc)];
-    project_tile(m.B, m.packed ? m.S : m.D, m.part, m.naux, m.nd, m.bslab, m.plen, loc, lds);
+    if (m.packed)
+        project_tile(m.B, m.S, m.part, m.naux, m.nd, m.bslab, m.plen, loc, lds);
+    else
+        project_upper_tile<TileProject, 8>(m.B, m.D, m.part, m.naux, m.nd, m.nao, m.plen, loc, lds);
 }
 
 __global__ void __launch_bounds__(256) k_b_reduce(const BMember *__restrict__ M,
@@ -251,6 +264,11 @@ hipError_t launch_batched_phase(int phase, const BMember *M, const int *tab, int
         ProfScope ps_("b_half_transform", s);
         hipLaunchKernelGGL(k_b_half_transform16_packed, g, dim3(TileB16::NTHR), kLds16, s, M, tab,
                            step);
+        break;
+    }
+    case kPhaseFoldUpper: {
+        ProfScope ps_("b_fold_upper", s);
+        hipLaunchKernelGGL(k_b_fold_upper, g, dim3(256), 0, s, M, tab);
         break;
     }
     case kPhaseSymPack: {

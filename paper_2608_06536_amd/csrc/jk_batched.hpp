@@ -89,6 +89,7 @@ enum {
     kPhaseSymPack = 11,  // packed B: S = D + D^T on the packed positions
     kPhaseUnpackJ = 12,  // packed B: J in full from its packed form
     kPhaseHalf16Packed = 13,  // packed B: the 16 x 16 x 4 half-transform, tiles per slab
+    kPhaseFoldUpper = 14,     // full squares: D folded onto its upper triangle (gamma)
     // JK_MIXED phases (jk_mixed.hip)
     kPhaseMSliceC = 20,  // digit planes of [C_L | C_R]
     kPhaseMSliceB = 21,  // digit planes of the chunk's slabs of B

@@ -50,8 +50,16 @@ hipError_t launch_project(const double *B, const double *A, double *part, double
 // J (+)= scale * sum_Q g B^Q; accumulate adds to what J holds.
 hipError_t launch_coulomb(const double *B, const double *g, double *J, int naux, int nd,
                           int64_t npos, hipStream_t s, double scale = 1.0, int accumulate = 0);
-// The same for full-square symmetric slabs from their upper triangles (half
-// the bytes of B; J bit-identical to launch_coulomb's).
+// Full-square symmetric slabs read on their upper triangles (half the bytes
+// of B).  fold_upper: A_k[m][n] += A_k[n][m], A_k[n][m] = 0 for n > m, in
+// place (nmat matrices).  project_upper: g[k][Q] = <B^Q, A_k> from the folded
+// A; part holds project_upper_blocks pairs x naux x (8 groups, or 16) doubles;
+// sixteen: 9 to 16 matrices in one pass (else groups of 8).
+hipError_t launch_fold_upper(double *A, int nao, int nmat, hipStream_t s);
+int project_upper_blocks(int nao, int naux, int nkg, int *G);
+hipError_t launch_project_upper(const double *B, const double *S, double *part, double *g, int nao,
+                                int naux, int nd, hipStream_t s, bool sixteen = false);
+// J (bit-identical to launch_coulomb's for symmetric slabs).
 hipError_t launch_coulomb_upper(const double *B, const double *g, double *J, int nao, int naux,
                                 int nd, hipStream_t s, double scale = 1.0, int accumulate = 0);
 // packed: B holds packed upper-triangle slabs (nao (nao + 1) / 2 doubles).

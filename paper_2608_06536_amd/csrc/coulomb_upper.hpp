@@ -100,11 +100,13 @@ __device__ inline void coulomb_upper_tile(const double *__restrict__ B, const do
 // positions left of a row's diagonal multiply the zeros of S, and every read
 // stays in its row.  Groups are paired (g with ng - 1 - g) so that the tiles
 // weigh the same; part[pair][Q][k] holds each pair's sums, added in a fixed
-// order by reduce_tile.  About 2048 workgroups in all.
+// order by reduce_tile.  About 512 workgroups in all: at nao 500 these tiles
+// (groups of 4 rows) ran at 4.4 TB/s, groups of 1 and 2 rows (2000 and 1000
+// tiles) at 4.1-4.2.
 __host__ __device__ inline int pu_group_rows(int nao, int naux, int nkg)
 {
     const int nqt = (naux + kProjRows - 1) / kProjRows;
-    int want = 2048 / (nqt * nkg);
+    int want = 512 / (nqt * nkg);
     if (want < 1)
         want = 1;
     const int g = (nao + 2 * want - 1) / (2 * want);

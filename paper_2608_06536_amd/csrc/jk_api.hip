@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
+#include <cstring>
 
 #include <algorithm>
 #include <cmath>
@@ -1845,7 +1846,11 @@ jk_status jk_plan_describe(const jk_problem *p, const jk_tuning *t, jk_plan_info
 
 const char *jk_status_str(jk_status s)
 {
-    switch (s) {
+    // A C caller may pass any int; read it as one (a load of an enum object
+    // outside the enumerators' range is undefined in C++).
+    int v = 0;
+    std::memcpy(&v, &s, sizeof v < sizeof s ? sizeof v : sizeof s);
+    switch (v) {
     case JK_OK: return "ok";
     case JK_EINVAL: return "invalid argument";
     case JK_EWORKSPACE: return "workspace too small";

@@ -165,8 +165,8 @@ int chunk_slabs_vjp(const jk_problem *p)
     size_t per = 4 * (size_t)p->nao * (size_t)(p->ndens * p->rank) * sizeof(double);
     size_t budget = kChunkBudgetVjp;
     if (p->flags & JK_B_PACKED) {
-        // two unpacked full squares per slab of the chunk, on a budget of their own
-        per += 2 * (size_t)p->nao * (size_t)p->nao * sizeof(double);
+        // the chunk's slabs unpacked to full squares, on a budget of their own
+        per += (size_t)p->nao * (size_t)p->nao * sizeof(double);
         budget *= 2;
     }
     i64 qc = (i64)(budget / (per ? per : 1));
@@ -237,10 +237,10 @@ VjpPlan plan_vjp(const jk_problem *p)
     f.o_pr = c.take(sizeof(double) * (size_t)f.qc * nao * 2 * R);
     f.o_dcp = c.take(sizeof(double) * (size_t)f.nsplit_c * nao * 2 * R);
     if (f.packed) {
-        // two chunk buffers of full squares (stage C of one chunk may still
-        // read one while the next chunk is unpacked into the other); W, D and
-        // E as packed sums over each symmetric pair of positions
-        f.o_bu = c.take(sizeof(double) * 2 * (size_t)f.qc * nsq);
+        // the chunk's slabs as full squares (stage C, their last reader, runs
+        // on the stream that unpacks the next chunk); W, D and E as packed
+        // sums over each symmetric pair of positions
+        f.o_bu = c.take(sizeof(double) * (size_t)f.qc * nsq);
         f.o_wdp = c.take(sizeof(double) * 2 * nd * npos);
         f.o_ep = c.take(sizeof(double) * nd * npos);
     } else {
@@ -554,29 +554,27 @@ jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const
         Wa = WDp;                                 // [W | D] packed, W first
         Ea = Ep;
     }
-    // Two streams, so that one launch's last partial round of workgroups
-    // overlaps another launch:
-    //   main: HT(c), B[P'](c), D(c), affine(c)
-    //   aux:  B[R'](c), C(c)
-    // Order: aux's B[R'](c) after HT(c) (reads X) and after D(c - 1) (R' of
-    // the slab blocks); main's B[P'](c) after C(c - 1) (reads the blocks);
-    // C(c) and D(c) after both B's; main ends after aux's last work.
+    // Stage B's two products run side by side on two streams:
+    //   main: HT(c), B[P'](c), C(c), D(c), affine(c)
+    //   aux:  B[R'](c)
+    // aux's B[R'](c) waits for HT(c) (it reads X), whose event main records
+    // after every reader of chunk c - 1's slab blocks; main waits for B[R'](c)
+    // before stage C.  Stage C beside stage D (on the second stream) took 2%
+    // longer than the two in sequence.
     hipStream_t a = nullptr;
     JK_TRY(aux_stream(&a));
     EventSet ev;
-    JK_TRY(ev.create(4));
-    hipEvent_t ev_x = ev.ev[0], ev_br = ev.ev[1], ev_b = ev.ev[2], ev_aux = ev.ev[3];
-    JK_TRY(hipEventRecord(ev_aux, s));           // aux starts after the prologue
+    JK_TRY(ev.create(2));
+    hipEvent_t ev_x = ev.ev[0], ev_br = ev.ev[1];
     const int tile = plan_tuning(p).ht_tile;
-    for (int q0 = 0, c = 0; q0 < naux; q0 += f.qc, c++) {
+    for (int q0 = 0; q0 < naux; q0 += f.qc) {
         const int nq = (naux - q0) < f.qc ? (naux - q0) : f.qc;
         // the slabs the half-transform and stage C read: B itself, or this
-        // chunk unpacked (buffer c % 2; stage C of chunk c - 2, the last
-        // reader of that buffer, finished before main's stage B of chunk c - 1)
+        // chunk unpacked
         const double *Bs = B;
         int qs = q0;
         if (pk && (has_v || want_dc)) {
-            double *Bu = (double *)(ws + f.o_bu) + (size_t)(c & 1) * f.qc * npos;
+            double *Bu = (double *)(ws + f.o_bu);
             JK_TRY(jk::launch_unpack_slabs(B, Bu, nao, q0, nq, s));
             Bs = Bu;
             qs = 0;
@@ -589,16 +587,11 @@ jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const
         JK_TRY(jk::launch_vjp_stage_b_one(1, V, Xw, Cc, omx, L, nao, nd, r, q0, nq * r, f.ldw, has_v,
                                           has_w, a));
         JK_TRY(hipEventRecord(ev_br, a));
-        JK_TRY(hipStreamWaitEvent(s, ev_aux, 0)); // C of the last chunk done with the blocks
         JK_TRY(jk::launch_vjp_stage_b_one(0, V, Yx, Cc, omx, L, nao, nd, r, q0, nq * r, f.ldw, has_v,
                                           has_w, s));
         JK_TRY(hipStreamWaitEvent(s, ev_br, 0));
-        JK_TRY(hipEventRecord(ev_b, s));
-        if (want_dc) {
-            JK_TRY(hipStreamWaitEvent(a, ev_b, 0));
-            JK_TRY(jk::launch_vjp_stage_c(Bs, L, dCp, nao, R, qs, nq, f.nsplit_c, q0 > 0, a));
-        }
-        JK_TRY(hipEventRecord(ev_aux, a));
+        if (want_dc)
+            JK_TRY(jk::launch_vjp_stage_c(Bs, L, dCp, nao, R, qs, nq, f.nsplit_c, q0 > 0, s));
         if (want_db) {
             if (pk)
                 JK_TRY(jk::launch_vjp_stage_d_packed(L, Cc, dB, nao, R, q0, nq, s));
@@ -608,7 +601,6 @@ jk_status vjp_fp64(const jk_problem *p, const double *B, const double *CL, const
                 JK_TRY(jk::launch_vjp_db_affine(g, om, Wa, Ea, dB, nd, naux, npk, q0, nq, s));
         }
     }
-    JK_TRY(hipStreamWaitEvent(s, ev_aux, 0));
     if (want_dc)
         JK_TRY(jk::launch_vjp_dc_finish(dCp, dCL, dCR, nao, nd, r, f.nsplit_c, s));
     return JK_OK;

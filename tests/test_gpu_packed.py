@@ -173,10 +173,10 @@ def test_packed_vjp_single_cotangent(which):
     assert rel_err(dCR.cpu().numpy(), rR) <= TOL
 
 
-def test_packed_vjp_three_chunks_vs_full():
-    # 27000 slabs at nao 200: the packed derivative takes three chunks of
-    # unpacked slabs (13158, 13158, 684), so both chunk buffers are used and
-    # the first is reused.  Against the full-square derivative of the same B
+def test_packed_vjp_two_chunks_vs_full():
+    # 27000 slabs at nao 200: the packed derivative takes two chunks of
+    # unpacked slabs (25811, 1189), so the chunk buffer of unpacked slabs is
+    # reused.  Against the full-square derivative of the same B
     # (generated on the device; that path is checked against the oracle):
     # dB packed from its symmetric sums, dC_L and dC_R to rounding.
     from paper_2608_06536_amd import jk

@@ -272,7 +272,7 @@ struct MixPlan {
 
 inline i64 pad_to(i64 x, i64 m) { return ((x + m - 1) / m) * m; }
 
-MixPlan plan_mixed(const jk_problem *p, size_t budget = kChunkBudget, bool rowmax_tiles = true)
+MixPlan plan_mixed(const jk_problem *p, size_t budget = kChunkBudget)
 {
     MixPlan x;
     x.f = plan_forward(p, budget);
@@ -305,7 +305,7 @@ MixPlan plan_mixed(const jk_problem *p, size_t budget = kChunkBudget, bool rowma
     x.o_ec = c.take(sizeof(int) * (size_t)x.cp);
     x.o_kp = c.take(sizeof(double) * (size_t)nsmax * nd * nao * nao);
     // sized for both sides (the X-only case has fewer column tiles and keys)
-    const size_t pm = rowmax_tiles ? jk::xy_rowmax_pm_doubles(x.f.qc, x.mp, x.cp, (int)r, (int)(2 * nd)) : 0;
+    const size_t pm = jk::xy_rowmax_pm_doubles(x.f.qc, x.mp, x.cp, (int)r, (int)(2 * nd));
     for (int b = 0; b < 2; b++)
         x.o_pm[b] = c.take(sizeof(double) * pm);
     x.total = c.off;
@@ -884,7 +884,7 @@ BPlan batched_plan(const jk_problem *p, bool sym_in)
     BPlan b;
     const size_t budget = batched_budget(p);
     if (p->precision == JK_MIXED) {
-        b.x = plan_mixed(p, budget, false);
+        b.x = plan_mixed(p, budget);
         b.f = b.x.f;
         b.sym = sym_in ? 1 : 0;
         b.nsplit = b.sym ? b.x.nsplit_sym : b.x.nsplit;
@@ -915,7 +915,7 @@ int slicer_blocks(int kp)
 bool batched_mixed_ok(int32_t nprob, const jk_problem *p)
 {
     for (int g = 0; g < nprob; g++) {
-        const MixPlan x = plan_mixed(&p[g], batched_budget(&p[g]), false);
+        const MixPlan x = plan_mixed(&p[g], batched_budget(&p[g]));
         if (slicer_blocks(x.kp) == 0 || !jk::mixed_rowmax_ok(2 * (int)(p[g].ndens * p[g].rank)))
             return false;
         if (packed_b(&p[g]) && !jk::mixed_packed_ok((int)p[g].nao, x.kp))
@@ -1016,11 +1016,9 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p, const std::vector<ch
                 return (int)std::min<i64>(plans[g].f.qc, p[g].naux - q0);
             };
             if (mixed) {
-                int nj = 1, ldsb = 0, maxnao = 1;
+                int nj = 1, maxnao = 1;
                 for (int g = 0; g < G; g++) {
                     nj = std::max(nj, slicer_blocks(plans[g].x.kp));
-                    const int nkey = plans[g].sym ? (int)p[g].ndens : 2 * (int)p[g].ndens;
-                    ldsb = std::max(ldsb, (int)sizeof(double) * nkey * (int)p[g].rank);
                     maxnao = std::max(maxnao, (int)p[g].nao);
                 }
                 if (packed)      // bands of 8 rows through LDS; arg = 16 x LDS bytes + blocks
@@ -1038,7 +1036,13 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p, const std::vector<ch
                                                   nq_of(g));
                     },
                     in_step);
-                add(jk::kPhaseMRowmax, c, [&](int g) { return (int)p[g].nao; }, in_step, ldsb);
+                // one tile per (64-row block, key) of X/Y
+                add(jk::kPhaseMRowmax, c,
+                    [&](int g) {
+                        const int nkey = plans[g].sym ? (int)p[g].ndens : 2 * (int)p[g].ndens;
+                        return jk::cdiv_i(p[g].nao, 64) * nkey;
+                    },
+                    in_step);
                 add(jk::kPhaseMSliceXY, c,
                     [&](int g) {
                         const int nkey = plans[g].sym ? (int)p[g].ndens : 2 * (int)p[g].ndens;
@@ -1320,6 +1324,7 @@ jk_status build_batched(int32_t nprob, const jk_problem *p, const double *const 
             m.XY = (double *)(base + b.x.o_xy[0]);
             m.XYp = (int8_t *)(base + b.x.o_xyp[0]);
             m.eXY = (int *)(base + b.x.o_exy[0]);
+            m.pm = (double *)(base + b.x.o_pm[0]);
         }
     }
     if (copy_header(S.mem.data(), nprob, S.tabs, S.header_bytes, ws, s) != hipSuccess)

@@ -20,6 +20,7 @@ struct BMember {
     int8_t *Bp, *Cp, *XYp;
     int *eB, *eC, *eXY;
     double *XY;
+    double *pm;         // the half-transform's partial row maxima of X/Y
     long long bkb, bps, ckb, cps, xkb, xps;
     int mp, kp, cp, cpx;    // padded rows / inner bytes; cpx: [C_L | C_R] rows the products use
     // Packed-triangular B (jk.h JK_B_PACKED): bslab doubles per slab of B
@@ -106,9 +107,8 @@ hipError_t prepare_batched_kernels();
 
 // One launch of a phase over the members listed in tab (device pointer):
 // ntiles workgroups, step = chunk index for the chunked phases.  arg: the
-// slicer's register blocks (kPhaseMSliceB, kPhaseMSliceBPacked: 8 x that
-// plus the LDS bytes / 8 x 1024, see launch_batched_mixed_phase) or the LDS
-// bytes (kPhaseMRowmax).
+// slicer's register blocks (kPhaseMSliceB), or 16 x the dynamic LDS bytes
+// plus the register blocks (kPhaseMSliceBPacked).
 hipError_t launch_batched_phase(int phase, const BMember *M, const int *tab, int ntiles, int step,
                                 hipStream_t s, int arg = 0);
 hipError_t launch_batched_mixed_phase(int phase, const BMember *M, const int *tab, int ntiles,

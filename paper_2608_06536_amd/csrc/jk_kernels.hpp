@@ -125,9 +125,8 @@ hipError_t launch_slice_rows(const double *src, i64 bs, i64 rs, i64 ks, int nb, 
                              hipStream_t s);
 hipError_t launch_slice_b(const double *src, i64 bs, i64 rs, int nb, int nr, int nk, int rp, int nkb,
                           int8_t *out, i64 pstride, i64 kbstride, int *exps, hipStream_t s);
+// widths 2 nd r of X/Y the mixed path takes
 int mixed_rowmax_ok(int R2);
-hipError_t launch_xy_rowmax(const double *XY, int nao, int nq, int nkey, int r, int mp, int *exps,
-                            hipStream_t s);
 hipError_t launch_slice_xy(const double *XY, int nao, int nkey, int r, int mp, int nj, int nkb,
                            int8_t *out, i64 pstride, i64 kbstride, const int *exps, hipStream_t s);
 // pm (optional): the row maxima of the chunk's X and Y per tile

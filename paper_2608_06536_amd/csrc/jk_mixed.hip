@@ -415,19 +415,27 @@ __global__ void __launch_bounds__(256, 2) k_ht_mixed(const int8_t *__restrict__ 
                   xcd_swizzle(blockIdx.x, gridDim.x), lds, pm, r, nslot);
 }
 
+// Partial-maximum slots per (row, column tile): the keys a column tile of
+// kNT columns can meet.
+__host__ __device__ inline int pm_slots(int r, int nkey)
+{
+    const int n = (kNT - 1) / r + 2;
+    return n < nkey ? n : nkey;
+}
+
 // exps[key mp + m] from the half-transform's partial maxima: the largest over
 // the chunk's slabs and over the (one or two) column tiles that meet key's
-// columns [key r, key r + r).  Workgroup: 64 rows of one key, 16 waves; wave
-// w takes the slabs ql = w, w + 16, ... (coalesced 512-byte reads); the wave
-// maxima meet in LDS.
-constexpr int kPmWaves = 16;
-__global__ void __launch_bounds__(64 * kPmWaves) k_xy_rowmax_pm(const double *__restrict__ pm, int nao,
-                                                               int nq, int nct, int mp, int nslot,
-                                                               int r, int *__restrict__ exps)
+// columns [key r, key r + r), for the 64 rows of row block mblk.  NW waves;
+// wave w takes the slabs ql = w, w + NW, ... (coalesced 512-byte reads); the
+// wave maxima meet in red.
+template <int NW>
+__device__ __forceinline__ void rowmax_pm_block(const double *__restrict__ pm, int nao, int nq,
+                                                int nct, int mp, int nslot, int r,
+                                                int *__restrict__ exps, int mblk, int key,
+                                                double (*red)[64])
 {
-    __shared__ double red[kPmWaves][64];
-    const int key = blockIdx.y, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int m = blockIdx.x * 64 + lane;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = mblk * 64 + lane;
     const int mc = m < nao ? m : nao - 1;
     const int cb0 = key * r / kNT, cb1 = (key * r + r - 1) / kNT;
     const i64 qs = (i64)nct * nslot * mp;
@@ -436,12 +444,12 @@ __global__ void __launch_bounds__(64 * kPmWaves) k_xy_rowmax_pm(const double *__
         const int slot = key - cb * kNT / r;
         const double *p = pm + ((i64)cb * nslot + slot) * mp + mc;
         int ql = w;
-        for (; ql + 3 * kPmWaves < nq; ql += 4 * kPmWaves) {
-            const double v0 = p[(i64)ql * qs], v1 = p[(i64)(ql + kPmWaves) * qs];
-            const double v2 = p[(i64)(ql + 2 * kPmWaves) * qs], v3 = p[(i64)(ql + 3 * kPmWaves) * qs];
+        for (; ql + 3 * NW < nq; ql += 4 * NW) {
+            const double v0 = p[(i64)ql * qs], v1 = p[(i64)(ql + NW) * qs];
+            const double v2 = p[(i64)(ql + 2 * NW) * qs], v3 = p[(i64)(ql + 3 * NW) * qs];
             mx = fmax(mx, fmax(fmax(v0, v1), fmax(v2, v3)));
         }
-        for (; ql < nq; ql += kPmWaves)
+        for (; ql < nq; ql += NW)
             mx = fmax(mx, p[(i64)ql * qs]);
     }
     red[w][lane] = mx;
@@ -449,59 +457,20 @@ __global__ void __launch_bounds__(64 * kPmWaves) k_xy_rowmax_pm(const double *__
     if (w == 0 && m < nao) {
         double v = red[0][lane];
 #pragma unroll
-        for (int u = 1; u < kPmWaves; u++)
+        for (int u = 1; u < NW; u++)
             v = fmax(v, red[u][lane]);
         exps[(i64)key * mp + m] = row_exponent(v);
     }
 }
 
-// Row exponents of X/Y over the chunk: exps[key * mp + m] for key = side * nd
-// + k, the maximum over slabs ql < nq and i < r of |XY[ql][m][key * r + i]|.
-// One workgroup per m: column maxima over the slabs (coalesced along c), then
-// the maximum over each key's r columns through LDS (2R doubles).
-__device__ __forceinline__ void xy_rowmax_row(const double *__restrict__ XY, int nao, int nq, int nkey,
-                                              int r, int mp, int *__restrict__ exps, int m,
-                                              double *colmax)
+// Workgroup: 64 rows of one key, 16 waves.
+constexpr int kPmWaves = 16;
+__global__ void __launch_bounds__(64 * kPmWaves) k_xy_rowmax_pm(const double *__restrict__ pm, int nao,
+                                                               int nq, int nct, int mp, int nslot,
+                                                               int r, int *__restrict__ exps)
 {
-    const int R2 = nkey * r;
-    const i64 qs = (i64)nao * R2;
-    const double *s = XY + (i64)m * R2;
-    for (int c = threadIdx.x; c < R2; c += 256) {
-        double mx[16];
-#pragma unroll
-        for (int u = 0; u < 16; u++)
-            mx[u] = 0.0;
-        int q = 0;
-        for (; q + 16 <= nq; q += 16) {
-            double v[16];
-#pragma unroll
-            for (int u = 0; u < 16; u++)
-                v[u] = __builtin_nontemporal_load(s + (i64)(q + u) * qs + c);
-#pragma unroll
-            for (int u = 0; u < 16; u++)
-                mx[u] = fmax(mx[u], fabs(v[u]));
-        }
-        for (; q < nq; q++)
-            mx[0] = fmax(mx[0], fabs(s[(i64)q * qs + c]));
-#pragma unroll
-        for (int u = 1; u < 16; u++)
-            mx[0] = fmax(mx[0], mx[u]);
-        colmax[c] = mx[0];
-    }
-    __syncthreads();
-    for (int key = threadIdx.x; key < nkey; key += 256) {
-        double mx = 0.0;
-        for (int i = 0; i < r; i++)
-            mx = fmax(mx, colmax[key * r + i]);
-        exps[(i64)key * mp + m] = row_exponent(mx);
-    }
-}
-
-__global__ void __launch_bounds__(256) k_xy_rowmax(const double *__restrict__ XY, int nao, int nq,
-                                                   int nkey, int r, int mp, int *__restrict__ exps)
-{
-    extern __shared__ double colmax[];
-    xy_rowmax_row(XY, nao, nq, nkey, r, mp, exps, blockIdx.x, colmax);
+    __shared__ double red[kPmWaves][64];
+    rowmax_pm_block<kPmWaves>(pm, nao, nq, nct, mp, nslot, r, exps, blockIdx.x, blockIdx.y, red);
 }
 
 // ------------------------------------------------------------------ exchange
@@ -654,20 +623,24 @@ __global__ void __launch_bounds__(256, 2) k_bm_ht(const BMember *__restrict__ M,
     int loc;
     const BMember &m = M[find_member(tab, xcd_local(blockIdx.x, gridDim.x), loc)];
     (void)c;
-    const int ncol = m.sym ? m.nd * m.r : 2 * m.nd * m.r;
-    ht_mixed_tile(m.Bp, m.bps, m.bkb, m.eB, m.Cp, m.cps, m.ckb, m.eC, m.XY, m.nao, ncol, m.mp, m.cpx,
-                  m.kp / kSliceKB, loc, lds);
+    const int nkey = m.sym ? m.nd : 2 * m.nd;
+    ht_mixed_tile(m.Bp, m.bps, m.bkb, m.eB, m.Cp, m.cps, m.ckb, m.eC, m.XY, m.nao, nkey * m.r, m.mp,
+                  m.cpx, m.kp / kSliceKB, loc, lds, m.pm, m.r, pm_slots(m.r, nkey));
 }
 
+// Row exponents from the half-transform's partial maxima: tile loc of a
+// member is (row block loc % nmb, key loc / nmb), 64 rows, four waves.
 __global__ void __launch_bounds__(256) k_bm_rowmax(const BMember *__restrict__ M,
                                                    const int *__restrict__ tab, int c)
 {
-    extern __shared__ double colmax[];
+    __shared__ double red[4][64];
     int loc;
     const BMember &m = M[find_member(tab, blockIdx.x, loc)];
     int q0, nq;
     chunk_of(m, c, q0, nq);
-    xy_rowmax_row(m.XY, m.nao, nq, m.sym ? m.nd : 2 * m.nd, m.r, m.mp, m.eXY, loc, colmax);
+    const int nkey = m.sym ? m.nd : 2 * m.nd, nmb = (m.nao + 63) / 64;
+    rowmax_pm_block<4>(m.pm, m.nao, nq, m.cpx / kNT, m.mp, pm_slots(m.r, nkey), m.r, m.eXY, loc % nmb,
+                       loc / nmb, red);
 }
 
 __global__ void __launch_bounds__(256) k_bm_slice_xy(const BMember *__restrict__ M,
@@ -805,17 +778,6 @@ int mixed_packed_ok(int nao, int kp) { return cdiv(kp / kSliceKB, 8) <= 8 && nao
 
 int mixed_rowmax_ok(int R2) { return R2 <= 8192; }
 
-hipError_t launch_xy_rowmax(const double *XY, int nao, int nq, int nkey, int r, int mp, int *exps,
-                            hipStream_t s)
-{
-    {
-        ProfScope ps_("xy_rowmax", s);
-        hipLaunchKernelGGL(k_xy_rowmax, dim3(nao), dim3(256), sizeof(double) * nkey * r, s, XY, nao,
-                           nq, nkey, r, mp, exps);
-    }
-    return hipGetLastError();
-}
-
 hipError_t launch_slice_xy(const double *XY, int nao, int nkey, int r, int mp, int nj, int nkb,
                            int8_t *out, i64 pstride, i64 kbstride, const int *exps, hipStream_t s)
 {
@@ -829,11 +791,7 @@ hipError_t launch_slice_xy(const double *XY, int nao, int nkey, int r, int mp, i
 }
 
 
-int xy_rowmax_slots(int r, int nkey)
-{
-    const int n = (kNT - 1) / r + 2;
-    return n < nkey ? n : nkey;
-}
+int xy_rowmax_slots(int r, int nkey) { return pm_slots(r, nkey); }
 
 size_t xy_rowmax_pm_doubles(int nq, int mp, int cp, int r, int nkey)
 {
@@ -977,7 +935,7 @@ hipError_t launch_batched_mixed_phase(int phase, const BMember *M, const int *ta
     }
     case kPhaseMRowmax: {
         ProfScope ps_("bm_xy_rowmax", s);
-        hipLaunchKernelGGL(k_bm_rowmax, g, dim3(256), (size_t)arg, s, M, tab, step);
+        hipLaunchKernelGGL(k_bm_rowmax, g, dim3(256), 0, s, M, tab, step);
         break;
     }
     case kPhaseMSliceXY: {

@@ -1313,6 +1313,7 @@ jk_status build_batched(int32_t nprob, const jk_problem *p, const double *const 
         m.S = f.packed ? (double *)(base + f.o_s) : nullptr;
         m.part = (double *)(base + f.o_part);
         m.g = (double *)(base + f.o_g);
+        m.goff = (long long)((S.region[g] + f.o_g) / sizeof(double));
         m.Xw = (double *)(base + f.o_x);
         m.Yw = (double *)(base + f.o_y);
         m.Kp = (double *)(base + (mixed ? b.x.o_kp : f.o_kp));

@@ -95,15 +95,18 @@ __global__ void __launch_bounds__(256) k_b_reduce(const BMember *__restrict__ M,
     reduce_tile(m.part, m.g, m.naux, m.nd, m.npb, loc);
 }
 
+// ws: the workspace start (where M lies), as doubles; g is read at ws + goff.
 __global__ void __launch_bounds__(256) k_b_coulomb(const BMember *__restrict__ M,
-                                                   const int *__restrict__ tab)
+                                                   const int *__restrict__ tab,
+                                                   const double *__restrict__ ws)
 {
     int loc;
     const BMember &m = M[find_member(tab, blockIdx.x, loc)];
+    const double *g = ws + m.goff;
     if (m.packed)
-        coulomb_tile(m.B, m.g, m.D, m.naux, m.nd, m.bslab, loc);
+        coulomb_tile(m.B, g, m.D, m.naux, m.nd, m.bslab, loc);
     else
-        coulomb_upper_tile(m.B, m.g, m.J, m.nao, m.naux, m.nd, loc);
+        coulomb_upper_tile(m.B, g, m.J, m.nao, m.naux, m.nd, loc);
 }
 
 __global__ void __launch_bounds__(256, 3) k_b_half_transform(const BMember *__restrict__ M,
@@ -242,7 +245,7 @@ hipError_t launch_batched_phase(int phase, const BMember *M, const int *tab, int
     }
     case kPhaseCoulomb: {
         ProfScope ps_("b_coulomb", s);
-        hipLaunchKernelGGL(k_b_coulomb, g, dim3(256), 0, s, M, tab);
+        hipLaunchKernelGGL(k_b_coulomb, g, dim3(256), 0, s, M, tab, (const double *)M);
         break;
     }
     case kPhaseHalf: {

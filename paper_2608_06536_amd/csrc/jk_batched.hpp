@@ -12,6 +12,11 @@ struct BMember {
     double *J, *K;
     double *Cc, *D, *part, *g, *Xw, *Yw, *Kp;
     long long npos;
+    // g as an offset in doubles from the start of the workspace (the batch's
+    // descriptors): the Coulomb pass reads g through a kernel argument, whose
+    // read-only, unaliased loads the compiler makes scalar (one load per
+    // wave, not per lane)
+    long long goff;
     int nao, naux, nd, r;
     int qc, ldw, nsplit, npb, plen;
     int sym;            // C_L and C_R are one buffer: X only, K on the upper triangle

@@ -541,6 +541,12 @@ def main():
                 "byte_per_launch": amount * args.steps / dom_cnt,
                 "avg_launch_us": round(1e3 * dom_ms / dom_cnt, 1)}
 
+    # the batched target as a rate ratio: densities/s of the mixed batched
+    # build (members of nao 100-500) over densities/s of the FP64 build at
+    # nao=500 (different workloads, compared per density)
+    if "densities_per_s_mixed" in batched:
+        batched["mixed_batch_rate_vs_fp64_build_rate"] = round(
+            batched["densities_per_s_mixed"] / (nd / t_build), 3)
     out = {
         "metric": "J/K builds/s + VJPs/s at nao=500 (FP64 vs mixed), max err vs FP64 oracle",
         "value": round(value, 3),

@@ -60,10 +60,11 @@ def measured_traffic(kernel, plan):
 
 
 # Derivative launches that run concurrently on two streams (stage B's two
-# products; stage C beside stage D, the affine term and the next chunk's
-# half-transform): their HIP-event times include the concurrent launch.
-OVERLAPPED = {"vjp_half_transform", "vjp_stage_b_p", "vjp_stage_b_r", "vjp_stage_c",
-              "vjp_stage_d", "vjp_db_affine"}
+# products): their HIP-event times include the concurrent launch.
+OVERLAPPED = {"vjp_stage_b_p", "vjp_stage_b_r"}
+# Launch names of one kernel function: the derivative's half-transforms are
+# the build's kernel on chunks of their own.
+SAME_KERNEL = {"vjp_half_transform": "half_transform"}
 
 
 def kernel_models(p, nd, nao, naux, R):
@@ -520,10 +521,16 @@ def main():
         if name in OVERLAPPED:
             ent["overlapped"] = True
         per_kernel[name] = ent
-    # The roofline kernel: the one with the most time among those that never
-    # share the GPU with another launch (an overlapped launch's event time
-    # includes the other launch's work).
-    dom = max((kv for kv in kern.items() if kv[0] not in OVERLAPPED), key=lambda kv: kv[1][0])[0]
+    # The roofline kernel: the kernel function with the most time among those
+    # that never share the GPU with another launch (an overlapped launch's
+    # event time includes the other launch's work); its build launches (one
+    # fixed chunk plan, the one the counter records cover) give the figures.
+    fn_ms = {}
+    for name, (ms, _) in kern.items():
+        if name not in OVERLAPPED:
+            fn = SAME_KERNEL.get(name, name)
+            fn_ms[fn] = fn_ms.get(fn, 0.0) + ms
+    dom = max(fn_ms, key=fn_ms.get)
     bound, amount, unit = models.get(dom, ("mfma", float("nan"), "flop"))
     dom_ms, dom_cnt = kern[dom]
     if unit == "flop":

@@ -240,9 +240,9 @@ jk_status jk_build_batched(int32_t nprob, const jk_problem *p,
  * Packed B (JK_B_PACKED): dB has B's packed layout and holds the gradient
  * with respect to the packed elements, dB[m][n] + dB[n][m] at (m, n), m < n,
  * and dB[m][m] on the diagonal.  The projections stream the packed slabs;
- * each Q-chunk is unpacked into two workspace buffers of full squares that
- * the half-transforms and the products B^Q [P' | R'] read (the workspace
- * grows by 2 x chunk slabs x 8 nao^2 bytes).
+ * each Q-chunk is unpacked into a workspace buffer of full squares that the
+ * half-transforms and the products B^Q [P' | R'] read (the workspace grows by
+ * chunk slabs x 8 nao^2 bytes).
  * Symmetric densities: when CL and CR are the same pointer (the C_L = C_R
  * case of Sec. 2.3), Y^Q_k = X^Q_k, so only X is recomputed and both products
  * V_k Y and V_k^T X read it.  dCL and dCR are still the two separate

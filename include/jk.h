@@ -130,7 +130,7 @@ jk_status jk_build(const jk_problem *p, const double *B, const double *CL,
  * writing the integer planes) need not be repeated.
  *   jk_slices_bytes   size of the buffer for problem *p (0 if *p is invalid
  *                     or not JK_MIXED).  It depends on nao and naux only:
- *                     about 4 bytes per element of B plus padding to 128
+ *                     about 4 bytes per element of B plus padding to 64
  *                     rows and 32 columns per slab.
  *   jk_slice_b        writes the planes of B (full or packed slabs, as
  *                     p->flags says) into `slices` (DEVICE, 256-byte aligned,

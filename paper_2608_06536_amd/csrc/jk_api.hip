@@ -264,6 +264,7 @@ VjpPlan plan_vjp(const jk_problem *p)
 struct MixPlan {
     FwdPlan f;
     int ns, mp, kp, cp, jp, nsplit;
+    int mpb;                  // rows per slab of B's planes (X/Y planes: mp)
     int cp_sym, nsplit_sym;   // X-only columns and triangle splits (C_L = C_R)
     size_t bp_bytes, xy_bytes, xyp_bytes;
     size_t o_bp[2], o_eb[2], o_xy[2], o_xyp[2], o_exy[2], o_cp, o_ec, o_kp, total;
@@ -279,6 +280,7 @@ MixPlan plan_mixed(const jk_problem *p, size_t budget = kChunkBudget)
     const i64 nao = p->nao, nd = p->ndens, r = p->rank, R = nd * r;
     x.ns = jk::mixed_nslice();
     x.mp = (int)pad_to(nao, jk::mixed_row_pad());
+    x.mpb = (int)pad_to(nao, jk::mixed_b_row_pad());
     x.kp = (int)pad_to(nao, jk::mixed_k_pad());
     x.cp = (int)pad_to(2 * R, jk::mixed_row_pad());
     x.jp = (int)pad_to((i64)x.f.qc * r, jk::mixed_k_pad());
@@ -286,7 +288,7 @@ MixPlan plan_mixed(const jk_problem *p, size_t budget = kChunkBudget)
     x.cp_sym = (int)pad_to(R, jk::mixed_row_pad());
     x.nsplit_sym = jk::ex_mixed_nsplit(x.mp, (int)nd, x.jp / jk::mixed_k_block(), 1);
     const int nsmax = x.nsplit > x.nsplit_sym ? x.nsplit : x.nsplit_sym;
-    x.bp_bytes = (size_t)x.ns * x.f.qc * x.mp * x.kp;
+    x.bp_bytes = (size_t)x.ns * x.f.qc * x.mpb * x.kp;
     x.xy_bytes = sizeof(double) * (size_t)x.f.qc * nao * 2 * R;
     x.xyp_bytes = (size_t)x.ns * 2 * nd * x.mp * x.jp;
     Carve c;
@@ -297,7 +299,7 @@ MixPlan plan_mixed(const jk_problem *p, size_t budget = kChunkBudget)
     x.o_xy[1] = c.take(x.xy_bytes);
     for (int b = 0; b < 2; b++) {
         x.o_bp[b] = c.take(x.bp_bytes);
-        x.o_eb[b] = c.take(sizeof(int) * (size_t)x.f.qc * x.mp);
+        x.o_eb[b] = c.take(sizeof(int) * (size_t)x.f.qc * x.mpb);
         x.o_xyp[b] = c.take(x.xyp_bytes);
         x.o_exy[b] = c.take(sizeof(int) * (size_t)2 * nd * x.mp);
     }
@@ -305,7 +307,7 @@ MixPlan plan_mixed(const jk_problem *p, size_t budget = kChunkBudget)
     x.o_ec = c.take(sizeof(int) * (size_t)x.cp);
     x.o_kp = c.take(sizeof(double) * (size_t)nsmax * nd * nao * nao);
     // sized for both sides (the X-only case has fewer column tiles and keys)
-    const size_t pm = jk::xy_rowmax_pm_doubles(x.f.qc, x.mp, x.cp, (int)r, (int)(2 * nd));
+    const size_t pm = jk::xy_rowmax_pm_doubles(x.f.qc, x.mpb, x.cp, (int)r, (int)(2 * nd));
     for (int b = 0; b < 2; b++)
         x.o_pm[b] = c.take(sizeof(double) * pm);
     x.total = c.off;
@@ -617,7 +619,7 @@ struct SliceLayout {
 SliceLayout slice_layout(const jk_problem *p)
 {
     SliceLayout L;
-    L.mp = (int)pad_to(p->nao, jk::mixed_row_pad());
+    L.mp = (int)pad_to(p->nao, jk::mixed_b_row_pad());
     L.kp = (int)pad_to(p->nao, jk::mixed_k_pad());
     const int KB = jk::mixed_k_block();
     L.kbstride = (i64)p->naux * L.mp * KB;
@@ -688,7 +690,7 @@ jk_status build_mixed(const jk_problem *p, const double *B, const KSeg *seg, int
     double *Kp = nsplit > 1 ? (double *)(ws + x.o_kp) : K;
     const int KB = jk::mixed_k_block();
     // K-blocked plane strides (slice_core.hpp): kbstride = rows * 32 bytes
-    const i64 bkb = pre ? SL.kbstride : (i64)f.qc * x.mp * KB;
+    const i64 bkb = pre ? SL.kbstride : (i64)f.qc * x.mpb * KB;
     const i64 bps = pre ? SL.pstride : bkb * (x.kp / KB);
     const i64 ckb = (i64)x.cp * KB, cps = ckb * (x.kp / KB);
     const i64 xkb = (i64)2 * nd * x.mp * KB, xps = xkb * (x.jp / KB);
@@ -696,11 +698,11 @@ jk_status build_mixed(const jk_problem *p, const double *B, const KSeg *seg, int
     auto nq_of = [&](int c) { return chunks[c].nq; };
     auto nkb_of = [&](int c) { return (int)(pad_to((i64)nq_of(c) * r, jk::mixed_k_pad()) / KB); };
     auto Bp = [&](int c) {
-        return pre ? (int8_t *)(pre + SL.o_planes) + (i64)chunks[c].q0 * x.mp * KB
+        return pre ? (int8_t *)(pre + SL.o_planes) + (i64)chunks[c].q0 * x.mpb * KB
                    : (int8_t *)(ws + x.o_bp[c & 1]);
     };
     auto eB = [&](int c) {
-        return pre ? (int *)(pre + SL.o_exp) + (i64)chunks[c].q0 * x.mp : (int *)(ws + x.o_eb[c & 1]);
+        return pre ? (int *)(pre + SL.o_exp) + (i64)chunks[c].q0 * x.mpb : (int *)(ws + x.o_eb[c & 1]);
     };
     auto XY = [&](int c) { return (double *)(ws + x.o_xy[c & 1]); };
     auto XYp = [&](int c) { return (int8_t *)(ws + x.o_xyp[c & 1]); };
@@ -726,16 +728,16 @@ jk_status build_mixed(const jk_problem *p, const double *B, const KSeg *seg, int
             return JK_OK;
         }
         if (f.packed)
-            JK_TRY(jk::launch_slice_b_packed(chunks[c].B, f.slab, nq_of(c), nao, x.mp, x.kp / KB,
+            JK_TRY(jk::launch_slice_b_packed(chunks[c].B, f.slab, nq_of(c), nao, x.mpb, x.kp / KB,
                                              Bp(c), bps, bkb, eB(c), a));
         else
-            JK_TRY(jk::launch_slice_b(chunks[c].B, npos, nao, nq_of(c), nao, nao, x.mp,
+            JK_TRY(jk::launch_slice_b(chunks[c].B, npos, nao, nq_of(c), nao, nao, x.mpb,
                                       x.kp / KB, Bp(c), bps, bkb, eB(c), a));
         JK_TRY(hipEventRecord(sb[c & 1], a));
         return JK_OK;
     };
     auto slice_xy = [&](int c) -> jk_status {
-        JK_TRY(jk::launch_xy_rowmax_pm(PM(c), nao, nq_of(c), nkey, r, x.mp, cpx, eXY(c), a));
+        JK_TRY(jk::launch_xy_rowmax_pm(PM(c), nao, nq_of(c), nkey, r, x.mpb, x.mp, cpx, eXY(c), a));
         JK_TRY(jk::launch_slice_xy(XY(c), nao, nkey, r, x.mp, nq_of(c) * r, nkb_of(c), XYp(c), xps, xkb,
                                    eXY(c), a));
         JK_TRY(hipEventRecord(sx[c & 1], a));
@@ -746,7 +748,7 @@ jk_status build_mixed(const jk_problem *p, const double *B, const KSeg *seg, int
         if (c >= 2)
             JK_TRY(hipStreamWaitEvent(s, sx[c & 1], 0));    // XY[c] free
         JK_TRY(jk::launch_ht_mixed(Bp(c), bps, bkb, eB(c), Cp, cps, ckb, eC, XY(c), nao, ncol, nq_of(c),
-                                   x.mp, cpx, x.kp / KB, s, PM(c), r));
+                                   x.mpb, cpx, x.kp / KB, s, PM(c), r));
         JK_TRY(hipEventRecord(ht[c & 1], s));
         return JK_OK;
     };
@@ -1023,15 +1025,15 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p, const std::vector<ch
                 }
                 if (packed)      // bands of 8 rows through LDS; arg = 16 x LDS bytes + blocks
                     add(jk::kPhaseMSliceBPacked, c,
-                        [&](int g) { return nq_of(g) * ((plans[g].x.mp + 7) / 8); }, in_step,
+                        [&](int g) { return nq_of(g) * ((plans[g].x.mpb + 7) / 8); }, in_step,
                         16 * (int)sizeof(double) * 8 * maxnao + nj);
                 else
                     add(jk::kPhaseMSliceB, c,
-                        [&](int g) { return (int)(((i64)nq_of(g) * plans[g].x.mp + 3) / 4); }, in_step,
+                        [&](int g) { return (int)(((i64)nq_of(g) * plans[g].x.mpb + 3) / 4); }, in_step,
                         nj);
                 add(jk::kPhaseMHalf, c,
                     [&](int g) {
-                        return jk::mixed_ht_tiles(plans[g].x.mp,
+                        return jk::mixed_ht_tiles(plans[g].x.mpb,
                                                   plans[g].sym ? plans[g].x.cp_sym : plans[g].x.cp,
                                                   nq_of(g));
                     },
@@ -1151,10 +1153,11 @@ BSchedule make_schedule(int32_t nprob, const jk_problem *p, const std::vector<ch
             const MixPlan &x = plans[g].x;
             const int KB = jk::mixed_k_block();
             m.mp = x.mp;
+            m.mpb = x.mpb;
             m.kp = x.kp;
             m.cp = x.cp;
             m.cpx = m.sym ? x.cp_sym : x.cp;
-            m.bkb = (i64)x.f.qc * x.mp * KB;
+            m.bkb = (i64)x.f.qc * x.mpb * KB;
             m.bps = m.bkb * (x.kp / KB);
             m.ckb = (i64)x.cp * KB;
             m.cps = m.ckb * (x.kp / KB);

@@ -28,6 +28,7 @@ struct BMember {
     double *pm;         // the half-transform's partial row maxima of X/Y
     long long bkb, bps, ckb, cps, xkb, xps;
     int mp, kp, cp, cpx;    // padded rows / inner bytes; cpx: [C_L | C_R] rows the products use
+    int mpb;                // rows per slab of B's planes (the half-transform's row tiles)
     // Packed-triangular B (jk.h JK_B_PACKED): bslab doubles per slab of B
     // (npos for full squares); gamma pairs B with S = D + D^T folded onto the
     // packed positions, and J is formed packed in D, then written out in full.

@@ -118,6 +118,9 @@ hipError_t launch_vjp_db_affine(const double *gam, const double *om, const doubl
 // mixed precision (jk_mixed.hip)
 int mixed_nslice();
 int mixed_row_pad();
+// rows per slab of B's digit planes (a multiple of the INT8 half-transform's
+// row tile; X/Y planes keep mixed_row_pad)
+int mixed_b_row_pad();
 int mixed_k_pad();
 int mixed_k_block();
 hipError_t launch_slice_rows(const double *src, i64 bs, i64 rs, i64 ks, int nb, int nr, int nk,
@@ -137,8 +140,9 @@ hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, i64 bkbstride, const 
                            double *pm = nullptr, int r = 1);
 int xy_rowmax_slots(int r, int nkey);
 size_t xy_rowmax_pm_doubles(int nq, int mp, int cp, int r, int nkey);
-hipError_t launch_xy_rowmax_pm(const double *pm, int nao, int nq, int nkey, int r, int mp, int cp,
-                               int *exps, hipStream_t s);
+// pm rows mp per slab (the half-transform's row pitch); exps[key mpe + m]
+hipError_t launch_xy_rowmax_pm(const double *pm, int nao, int nq, int nkey, int r, int mp, int mpe,
+                               int cp, int *exps, hipStream_t s);
 // Exchange splits of a chunk of nkb inner blocks: chosen for occupancy, and
 // never fewer than keep each split's int32 sums exact (mixed_max_depth()
 // inner indices at most).

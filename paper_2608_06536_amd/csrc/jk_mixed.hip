@@ -423,14 +423,15 @@ __host__ __device__ inline int pm_slots(int r, int nkey)
     return n < nkey ? n : nkey;
 }
 
-// exps[key mp + m] from the half-transform's partial maxima: the largest over
-// the chunk's slabs and over the (one or two) column tiles that meet key's
-// columns [key r, key r + r), for the 64 rows of row block mblk.  NW waves;
-// wave w takes the slabs ql = w, w + NW, ... (coalesced 512-byte reads); the
-// wave maxima meet in red.
+// exps[key mpe + m] from the half-transform's partial maxima (rows of mp per
+// slab, the half-transform's row pitch): the largest over the chunk's slabs
+// and over the (one or two) column tiles that meet key's columns [key r,
+// key r + r), for the 64 rows of row block mblk.  NW waves; wave w takes the
+// slabs ql = w, w + NW, ... (coalesced 512-byte reads); the wave maxima meet
+// in red.
 template <int NW>
 __device__ __forceinline__ void rowmax_pm_block(const double *__restrict__ pm, int nao, int nq,
-                                                int nct, int mp, int nslot, int r,
+                                                int nct, int mp, int mpe, int nslot, int r,
                                                 int *__restrict__ exps, int mblk, int key,
                                                 double (*red)[64])
 {
@@ -459,18 +460,19 @@ __device__ __forceinline__ void rowmax_pm_block(const double *__restrict__ pm, i
 #pragma unroll
         for (int u = 1; u < NW; u++)
             v = fmax(v, red[u][lane]);
-        exps[(i64)key * mp + m] = row_exponent(v);
+        exps[(i64)key * mpe + m] = row_exponent(v);
     }
 }
 
 // Workgroup: 64 rows of one key, 16 waves.
 constexpr int kPmWaves = 16;
 __global__ void __launch_bounds__(64 * kPmWaves) k_xy_rowmax_pm(const double *__restrict__ pm, int nao,
-                                                               int nq, int nct, int mp, int nslot,
-                                                               int r, int *__restrict__ exps)
+                                                               int nq, int nct, int mp, int mpe,
+                                                               int nslot, int r,
+                                                               int *__restrict__ exps)
 {
     __shared__ double red[kPmWaves][64];
-    rowmax_pm_block<kPmWaves>(pm, nao, nq, nct, mp, nslot, r, exps, blockIdx.x, blockIdx.y, red);
+    rowmax_pm_block<kPmWaves>(pm, nao, nq, nct, mp, mpe, nslot, r, exps, blockIdx.x, blockIdx.y, red);
 }
 
 // ------------------------------------------------------------------ exchange
@@ -593,9 +595,9 @@ __global__ void __launch_bounds__(256) k_bm_slice_b(const BMember *__restrict__ 
     int q0, nq;
     chunk_of(m, c, q0, nq);
     const i64 row = (i64)loc * 4 + (threadIdx.x >> 6);
-    if (row >= (i64)nq * m.mp)       // whole waves leave together
+    if (row >= (i64)nq * m.mpb)      // whole waves leave together
         return;
-    slice_row_wave<NJ>(m.B + (i64)q0 * m.npos, m.npos, m.nao, m.nao, m.nao, m.mp, m.kp / kSliceKB,
+    slice_row_wave<NJ>(m.B + (i64)q0 * m.npos, m.npos, m.nao, m.nao, m.nao, m.mpb, m.kp / kSliceKB,
                        m.Bp, m.bps, m.bkb, m.eB, row);
 }
 
@@ -610,9 +612,9 @@ __global__ void __launch_bounds__(256) k_bm_slice_b_packed(const BMember *__rest
     const BMember &m = M[find_member(tab, blockIdx.x, loc)];
     int q0, nq;
     chunk_of(m, c, q0, nq);
-    const int nband = (m.mp + kBand - 1) / kBand;
+    const int nband = (m.mpb + kBand - 1) / kBand;
     const int b = loc / nband, m0 = (loc % nband) * kBand;
-    slice_band_packed<NJ>(m.B + (i64)(q0 + b) * m.bslab, b, m0, m.nao, m.mp, m.kp / kSliceKB, m.Bp,
+    slice_band_packed<NJ>(m.B + (i64)(q0 + b) * m.bslab, b, m0, m.nao, m.mpb, m.kp / kSliceKB, m.Bp,
                           m.bps, m.bkb, m.eB, T);
 }
 
@@ -624,7 +626,7 @@ __global__ void __launch_bounds__(256, 2) k_bm_ht(const BMember *__restrict__ M,
     const BMember &m = M[find_member(tab, xcd_local(blockIdx.x, gridDim.x), loc)];
     (void)c;
     const int nkey = m.sym ? m.nd : 2 * m.nd;
-    ht_mixed_tile(m.Bp, m.bps, m.bkb, m.eB, m.Cp, m.cps, m.ckb, m.eC, m.XY, m.nao, nkey * m.r, m.mp,
+    ht_mixed_tile(m.Bp, m.bps, m.bkb, m.eB, m.Cp, m.cps, m.ckb, m.eC, m.XY, m.nao, nkey * m.r, m.mpb,
                   m.cpx, m.kp / kSliceKB, loc, lds, m.pm, m.r, pm_slots(m.r, nkey));
 }
 
@@ -639,8 +641,8 @@ __global__ void __launch_bounds__(256) k_bm_rowmax(const BMember *__restrict__ M
     int q0, nq;
     chunk_of(m, c, q0, nq);
     const int nkey = m.sym ? m.nd : 2 * m.nd, nmb = (m.nao + 63) / 64;
-    rowmax_pm_block<4>(m.pm, m.nao, nq, m.cpx / kNT, m.mp, pm_slots(m.r, nkey), m.r, m.eXY, loc % nmb,
-                       loc / nmb, red);
+    rowmax_pm_block<4>(m.pm, m.nao, nq, m.cpx / kNT, m.mpb, m.mp, pm_slots(m.r, nkey), m.r, m.eXY,
+                       loc % nmb, loc / nmb, red);
 }
 
 __global__ void __launch_bounds__(256) k_bm_slice_xy(const BMember *__restrict__ M,
@@ -678,6 +680,7 @@ __global__ void __launch_bounds__(512) k_bm_ex(const BMember *__restrict__ M,
 // ------------------------------------------------------------------ launchers
 int mixed_nslice() { return kNS; }
 int mixed_row_pad() { return kRowPad; }
+int mixed_b_row_pad() { return kHtMT; }
 int mixed_k_pad() { return kKPad; }
 int mixed_k_block() { return kSliceKB; }
 
@@ -818,13 +821,13 @@ hipError_t launch_ht_mixed(const int8_t *Bp, i64 bpstride, i64 bkbstride, const 
     return hipGetLastError();
 }
 
-hipError_t launch_xy_rowmax_pm(const double *pm, int nao, int nq, int nkey, int r, int mp, int cp,
-                               int *exps, hipStream_t s)
+hipError_t launch_xy_rowmax_pm(const double *pm, int nao, int nq, int nkey, int r, int mp, int mpe,
+                               int cp, int *exps, hipStream_t s)
 {
     {
         ProfScope ps_("xy_rowmax_pm", s);
         hipLaunchKernelGGL(k_xy_rowmax_pm, dim3(cdiv(nao, 64), nkey), dim3(64 * kPmWaves), 0, s, pm, nao, nq,
-                           cp / kNT, mp, xy_rowmax_slots(r, nkey), r, exps);
+                           cp / kNT, mp, mpe, xy_rowmax_slots(r, nkey), r, exps);
     }
     return hipGetLastError();
 }
